@@ -1,0 +1,149 @@
+"""Seeded synthetic initial conditions for the QED event-generator workloads.
+
+This module is shared by the tests, the benchmark and the oracle runs.  It only
+draws random numbers and lays them out; it holds none of the generator's
+arithmetic (no rates, no bounds, no quantum parameter).  Each workload mirrors
+the regime a QED-PIC push stage sees (Sec. 2.2 and 3.1 of the paper):
+
+* ``c1``  16,384 electrons, gamma log-uniform in [1e2, 1e4], isotropic, uniform
+          static B = 1e-3 (Schwinger units) along z; chi spans about [1e-2, 10].
+* ``c2``  1,048,576 electrons + 262,144 photons in a uniform E field of amplitude
+          1e-3 rotating in the xy plane with period 200 dt; chi and gamma drawn
+          jointly (chi log-uniform in [1e-3, 1e2], gamma log-uniform in
+          [max(10, 1e3 chi), 1e5], pitch angle to E from sin(theta) = chi/(E gamma)).
+* ``c3``  16,777,216 electrons, gamma log-uniform in [1e3, 1e4], isotropic; 90% in
+          a weak field B = 5e-7 z (chi < 5e-3, one sub-step), 10% in a Gaussian
+          hot spot B = 1e-2 exp(-r^2/2) z with r ~ N(0, I_3) in units of the spot
+          size; fields are per particle and static.
+* ``c4``  log-uniform x in [1e-4, 50] for the synchrotron-function microbenchmark.
+
+All species arrays are float64 numpy arrays (``x, y, z, ux, uy, uz, w``) plus
+uint64 ``id``; photon momenta are stored in ``ux, uy, uz`` as k = hbar k/(m c).
+Ids are unique across species.  Sizes can be scaled down with ``scale`` (tests).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Global steps (units hbar/(m c^2)).  Fixed here; how each value was chosen is
+# stated beside it.
+DT_C1 = 8.37e4         # mean emission probability per step about 0.5
+DT_C2 = 10358.420305623711   # (0.8 um laser period) / 200
+DT_C3 = 2.0696e5       # hot-spot particles need at most 1000 sub-steps
+E0_C2 = 1.0e-3
+B_C1 = 1.0e-3
+P_MAX = 0.01
+
+
+def _isotropic(rng, n):
+    cth = rng.uniform(-1.0, 1.0, n)
+    phi = rng.uniform(0.0, 2.0 * math.pi, n)
+    sth = np.sqrt(np.maximum(0.0, 1.0 - cth * cth))
+    return sth * np.cos(phi), sth * np.sin(phi), cth
+
+
+def _species(n, id0, rng, pos_scale=1.0e4):
+    return {
+        "x": rng.uniform(-pos_scale, pos_scale, n),
+        "y": rng.uniform(-pos_scale, pos_scale, n),
+        "z": rng.uniform(-pos_scale, pos_scale, n),
+        "w": np.ones(n),
+        "id": np.arange(id0, id0 + n, dtype=np.uint64),
+    }
+
+
+def _empty():
+    s = {k: np.zeros(0) for k in ("x", "y", "z", "ux", "uy", "uz", "w")}
+    s["id"] = np.zeros(0, np.uint64)
+    return s
+
+
+def uniform_field(ex=0.0, ey=0.0, ez=0.0, bx=0.0, by=0.0, bz=0.0):
+    return {k: np.array([v], np.float64) for k, v in
+            zip(("ex", "ey", "ez", "bx", "by", "bz"), (ex, ey, ez, bx, by, bz))}
+
+
+def c1(n=16384, seed=1):
+    """Emission only, FP64 path: electrons in a uniform static magnetic field."""
+    rng = np.random.default_rng(seed)
+    e = _species(n, 0, rng)
+    gamma = 10.0 ** rng.uniform(2.0, 4.0, n)
+    u = np.sqrt(gamma * gamma - 1.0)
+    dx, dy, dz = _isotropic(rng, n)
+    e["ux"], e["uy"], e["uz"] = u * dx, u * dy, u * dz
+    return {"electrons": e, "positrons": _empty(), "photons": _empty(),
+            "fields": uniform_field(bz=B_C1), "dt": DT_C1, "steps": 100, "seed": 1,
+            "p_max": P_MAX}
+
+
+def _joint_chi_energy(rng, n, e0):
+    """chi log-uniform in [1e-3, 1e2]; energy log-uniform in [max(10, 1e3 chi), 1e5];
+    direction at angle theta to x with sin(theta) = chi / (e0 * energy)."""
+    chi = 10.0 ** rng.uniform(-3.0, 2.0, n)
+    lo = np.log10(np.maximum(10.0, 1.0e3 * chi))
+    energy = 10.0 ** (lo + (5.0 - lo) * rng.uniform(0.0, 1.0, n))
+    sth = np.clip(chi / (e0 * energy), 0.0, 1.0)
+    cth = np.sqrt(1.0 - sth * sth) * np.where(rng.uniform(0, 1, n) < 0.5, -1.0, 1.0)
+    phi = rng.uniform(0.0, 2.0 * math.pi, n)
+    # axis x is the field direction at step 0
+    return energy, (cth, sth * np.cos(phi), sth * np.sin(phi))
+
+
+def c2(n_e=1048576, n_g=262144, seed=2):
+    """Emission + pair creation, mixed precision, rotating uniform E field."""
+    rng = np.random.default_rng(seed)
+    e = _species(n_e, 0, rng)
+    gamma, (dx, dy, dz) = _joint_chi_energy(rng, n_e, E0_C2)
+    u = np.sqrt(np.maximum(gamma * gamma - 1.0, 0.0))
+    e["ux"], e["uy"], e["uz"] = u * dx, u * dy, u * dz
+    g = _species(n_g, n_e, rng)
+    eps, (dx, dy, dz) = _joint_chi_energy(rng, n_g, E0_C2)
+    g["ux"], g["uy"], g["uz"] = eps * dx, eps * dy, eps * dz
+    return {"electrons": e, "positrons": _empty(), "photons": g,
+            "fields": c2_field(0), "dt": DT_C2, "steps": 200, "seed": 1, "p_max": P_MAX}
+
+
+def c2_field(step, steps_per_turn=200):
+    """E(t) = E0 (cos 2 pi s/200, sin 2 pi s/200, 0), frozen over global step s."""
+    ph = 2.0 * math.pi * step / steps_per_turn
+    return uniform_field(ex=E0_C2 * math.cos(ph), ey=E0_C2 * math.sin(ph))
+
+
+def c3(n=16777216, seed=3, hot_fraction=0.1, shuffle=True):
+    """Uneven batch: weak-field bulk plus a Gaussian hot spot (per-particle fields)."""
+    rng = np.random.default_rng(seed)
+    e = _species(n, 0, rng)
+    gamma = 10.0 ** rng.uniform(3.0, 4.0, n)
+    u = np.sqrt(gamma * gamma - 1.0)
+    dx, dy, dz = _isotropic(rng, n)
+    e["ux"], e["uy"], e["uz"] = u * dx, u * dy, u * dz
+    n_hot = int(round(hot_fraction * n))
+    hot = np.zeros(n, bool)
+    hot[:n_hot] = True
+    if shuffle:
+        rng.shuffle(hot)
+    r2 = np.sum(rng.standard_normal((3, n)) ** 2, axis=0)
+    bz = np.where(hot, 1.0e-2 * np.exp(-0.5 * r2), 5.0e-7)
+    zeros = np.zeros(n)
+    fields = {"ex": zeros, "ey": zeros, "ez": zeros, "bx": zeros, "by": zeros, "bz": bz}
+    return {"electrons": e, "positrons": _empty(), "photons": _empty(), "fields": fields,
+            "hot": hot, "dt": DT_C3, "steps": 50, "seed": 1, "p_max": P_MAX}
+
+
+def c4_host(n, seed=4):
+    """log-uniform x in [1e-4, 50] (host, float64)."""
+    rng = np.random.default_rng(seed)
+    return 10.0 ** rng.uniform(-4.0, math.log10(50.0), n)
+
+
+def subset(species, idx):
+    return {k: np.ascontiguousarray(v[idx]) for k, v in species.items()}
+
+
+def field_subset(fields, idx):
+    out = {}
+    for k, v in fields.items():
+        out[k] = v if v.size == 1 else np.ascontiguousarray(v[idx])
+    return out
