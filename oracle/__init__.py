@@ -175,7 +175,7 @@ def synchrotron_parallel(x, threads=None):
     def run(ix):
         if ix.size == 0:
             return
-        a, b = ix[0], ix[-1] + 1
+        a, b = int(ix[0]), int(ix[-1]) + 1
         xs = x[a:b]
         lib().orc_synchrotron_vec(b - a, _p(xs, C.c_double),
                                   C.cast(F.ctypes.data + 8 * a, _D), C.cast(G.ctypes.data + 8 * a, _D))

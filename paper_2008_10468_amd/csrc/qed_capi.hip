@@ -1,0 +1,370 @@
+// C ABI of the QED event generator: argument checks, context and scratch
+// management, launch sizing.  All device work is in qed_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/qed.h"
+#include "qed_internal.hpp"
+
+using qed::u64;
+
+struct qed_ctx {
+    qed_config cfg;
+    hipStream_t stream;
+    int num_cu;
+    qed::DevState *st;        // device
+    uint8_t *alive;           // photon scratch, sized by photon_cap
+    u64 *hole_idx, *mover_idx;
+    u64 photon_cap;
+    u64 *last_n[3];           // count pointers of the last step (for qed_sync)
+    bool prof;                // bracket launches with events
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> rec_id;  // kernel id of each recorded launch
+    size_t rec_used;          // event pairs in use
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        if ((expr) != hipSuccess) return QED_ERR_HIP;   \
+    } while (0)
+
+bool species_ok(const qed_species &s) {
+    return s.n && s.x && s.y && s.z && s.ux && s.uy && s.uz && s.w && s.id;
+}
+
+bool field_ok(const qed_field &f) {
+    return f.ex && f.ey && f.ez && f.bx && f.by && f.bz && (f.stride == 0 || f.stride == 1);
+}
+
+qed::SpeciesDev to_dev(const qed_species &s) {
+    qed::SpeciesDev d;
+    d.n = reinterpret_cast<u64 *>(s.n);
+    d.cap = s.capacity;
+    d.x = s.x;
+    d.y = s.y;
+    d.z = s.z;
+    d.ux = s.ux;
+    d.uy = s.uy;
+    d.uz = s.uz;
+    d.w = s.w;
+    d.id = s.id;
+    d.parent = s.parent;
+    d.events = s.events;
+    return d;
+}
+
+qed::FieldDev to_dev(const qed_field &f) {
+    qed::FieldDev d;
+    d.ex = f.ex;
+    d.ey = f.ey;
+    d.ez = f.ez;
+    d.bx = f.bx;
+    d.by = f.by;
+    d.bz = f.bz;
+    d.stride = f.stride;
+    return d;
+}
+
+int grid_for(u64 work, int max_blocks) {
+    u64 b = (work + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > (u64)max_blocks) b = (u64)max_blocks;
+    return (int)b;
+}
+
+qed_status ensure_photon_scratch(qed_ctx *c, u64 cap) {
+    if (cap <= c->photon_cap) return QED_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->alive) (void)hipFree(c->alive);
+    if (c->hole_idx) (void)hipFree(c->hole_idx);
+    if (c->mover_idx) (void)hipFree(c->mover_idx);
+    c->alive = nullptr;
+    c->hole_idx = c->mover_idx = nullptr;
+    c->photon_cap = 0;
+    HIP_TRY(hipMalloc(&c->alive, cap));
+    HIP_TRY(hipMalloc(&c->hole_idx, cap * sizeof(u64)));
+    HIP_TRY(hipMalloc(&c->mover_idx, cap * sizeof(u64)));
+    c->photon_cap = cap;
+    return QED_OK;
+}
+
+const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_end",
+                                         "k_fill",  "k_move",   "k_synchrotron"};
+
+// Event pair for one profiled launch (grown on demand, reused after a read).
+bool prof_pair(qed_ctx *c, int id, hipEvent_t *a, hipEvent_t *b) {
+    if (2 * (c->rec_used + 1) > c->ev_pool.size()) {
+        for (int k = 0; k < 2; ++k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return false;
+            c->ev_pool.push_back(e);
+        }
+    }
+    *a = c->ev_pool[2 * c->rec_used];
+    *b = c->ev_pool[2 * c->rec_used + 1];
+    if (c->rec_id.size() <= c->rec_used) c->rec_id.resize(c->rec_used + 1);
+    c->rec_id[c->rec_used] = id;
+    c->rec_used++;
+    return true;
+}
+
+hipError_t launch(qed_ctx *c, int id, const qed::StepArgs &a, int precision, int blocks) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->prof && prof_pair(c, id, &e0, &e1)) {
+        hipError_t r = hipEventRecord(e0, c->stream);
+        if (r != hipSuccess) return r;
+    }
+    hipError_t r = qed::launch_kernel(id, a, precision, blocks, c->stream);
+    if (r == hipSuccess && e1) r = hipEventRecord(e1, c->stream);
+    return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+qed_status qed_config_default(qed_config *cfg) {
+    if (!cfg) return QED_ERR_INVALID_ARG;
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->device = 0;
+    cfg->stream = nullptr;
+    cfg->precision = QED_PREC_MIXED;
+    cfg->p_max = 0.01;
+    cfg->emission = 1;
+    cfg->pairs = 1;
+    cfg->scheduler = QED_SCHED_NAIVE;
+    cfg->pair_bound_coef = 0.1;
+    cfg->max_substeps = 1u << 24;
+    return QED_OK;
+}
+
+qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
+    if (!out || !cfg) return QED_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (cfg->precision != QED_PREC_F64 && cfg->precision != QED_PREC_MIXED) return QED_ERR_INVALID_ARG;
+    if (!(cfg->p_max > 0.0 && cfg->p_max <= 1.0)) return QED_ERR_INVALID_ARG;
+    if (!(cfg->pair_bound_coef > 0.0) || !isfinite(cfg->pair_bound_coef)) return QED_ERR_INVALID_ARG;
+    if (cfg->max_substeps < 1) return QED_ERR_INVALID_ARG;
+    if (cfg->scheduler != QED_SCHED_NAIVE && cfg->scheduler != QED_SCHED_BINNED) return QED_ERR_INVALID_ARG;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (cfg->device < 0 || cfg->device >= ndev) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(cfg->device));
+    qed_ctx *c = new (std::nothrow) qed_ctx();
+    if (!c) return QED_ERR_HIP;
+    c->cfg = *cfg;
+    c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, cfg->device) != hipSuccess) {
+        delete c;
+        return QED_ERR_HIP;
+    }
+    c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (hipMalloc(&c->st, sizeof(qed::DevState)) != hipSuccess ||
+        hipMemset(c->st, 0, sizeof(qed::DevState)) != hipSuccess) {
+        if (c->st) (void)hipFree(c->st);
+        delete c;
+        return QED_ERR_HIP;
+    }
+    *out = c;
+    return QED_OK;
+}
+
+qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], double dt, uint64_t seed,
+                    uint32_t step) {
+    if (!c || !p || !fields) return QED_ERR_INVALID_ARG;
+    if (!(dt > 0.0) || !isfinite(dt)) return QED_ERR_INVALID_ARG;
+    const bool emission = c->cfg.emission != 0, pairs = c->cfg.pairs != 0;
+    const qed_species *sp[3] = {&p->electrons, &p->positrons, &p->photons};
+    // every species that can be read or appended to must be complete
+    const bool need[3] = {emission || pairs, emission || pairs, emission || pairs};
+    for (int s = 0; s < 3; ++s) {
+        if (!need[s]) continue;
+        if (!species_ok(*sp[s])) return QED_ERR_INVALID_ARG;
+    }
+    if (emission && (!field_ok(fields[0]) || !field_ok(fields[1]))) return QED_ERR_INVALID_ARG;
+    if (pairs && !field_ok(fields[2])) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    if (pairs) {
+        qed_status r = ensure_photon_scratch(c, sp[2]->capacity > 0 ? sp[2]->capacity : 1);
+        if (r != QED_OK) return r;
+    }
+    qed::StepArgs a;
+    memset(&a, 0, sizeof(a));
+    for (int s = 0; s < 3; ++s) {
+        a.sp[s] = to_dev(*sp[s]);
+        a.fl[s] = to_dev(fields[s]);
+        c->last_n[s] = a.sp[s].n;
+    }
+    a.st = c->st;
+    a.dt = dt;
+    a.p_max = c->cfg.p_max;
+    a.pair_coef = c->cfg.pair_bound_coef;
+    a.seed = seed;
+    a.step = step;
+    a.max_sub = c->cfg.max_substeps;
+    a.emission = emission;
+    a.pairs = pairs;
+    a.alive = c->alive;
+    a.hole_idx = c->hole_idx;
+    a.mover_idx = c->mover_idx;
+    const int maxb = c->num_cu * 8;
+    const int lepton_blocks = grid_for(sp[0]->capacity + sp[1]->capacity, maxb);
+    const int photon_blocks = grid_for(sp[2]->capacity, maxb);
+    const int aux_blocks = grid_for(sp[2]->capacity, c->num_cu * 4);
+    const int prec = c->cfg.precision == QED_PREC_F64 ? 0 : 1;
+    hipError_t r = launch(c, qed::K_BEGIN, a, prec, 1);
+    if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON, a, prec, photon_blocks);
+    if (r == hipSuccess && emission) r = launch(c, qed::K_LEPTON, a, prec, lepton_blocks);
+    if (r == hipSuccess) r = launch(c, qed::K_END, a, prec, 1);
+    if (r == hipSuccess && pairs) r = launch(c, qed::K_FILL, a, prec, aux_blocks);
+    if (r == hipSuccess && pairs) r = launch(c, qed::K_MOVE, a, prec, aux_blocks);
+    return r == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
+qed_status qed_sync(qed_ctx *c, qed_report *rep) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    qed::DevState h;
+    HIP_TRY(hipMemcpy(&h, c->st, sizeof(h), hipMemcpyDeviceToHost));
+    qed_status s = QED_OK;
+    if (h.status_bits & 1ull)
+        s = QED_ERR_CAPACITY;
+    else if (h.status_bits & 2ull)
+        s = QED_ERR_NONFINITE;
+    if (rep) {
+        memset(rep, 0, sizeof(*rep));
+        rep->status = s;
+        for (int k = 0; k < 3; ++k) {
+            rep->required_capacity[k] = h.required[k];
+            if (c->last_n[k]) HIP_TRY(hipMemcpy(&rep->n[k], c->last_n[k], sizeof(u64), hipMemcpyDeviceToHost));
+        }
+        rep->nonfinite = h.nonfinite;
+    }
+    // clear the sticky status
+    h.status_bits = 0;
+    h.nonfinite = 0;
+    h.required[0] = h.required[1] = h.required[2] = 0;
+    HIP_TRY(hipMemcpy(&c->st->status_bits, &h.status_bits, sizeof(u64), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(&c->st->nonfinite, &h.nonfinite, sizeof(u64), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(&c->st->required[0], &h.required[0], 3 * sizeof(u64), hipMemcpyHostToDevice));
+    return s;
+}
+
+qed_status qed_synchrotron(qed_ctx *c, const void *x, void *F, void *G, uint64_t n, int dtype) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    if (dtype != QED_F32 && dtype != QED_F64) return QED_ERR_INVALID_ARG;
+    if (n == 0) return QED_OK;
+    if (!x || (!F && !G)) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    const int blocks = grid_for(n, c->num_cu * 16);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->prof && prof_pair(c, qed::K_SYNCHROTRON, &e0, &e1)) HIP_TRY(hipEventRecord(e0, c->stream));
+    if (qed::launch_synchrotron(x, F, G, n, dtype == QED_F32 ? 0 : 1, c->st, blocks, c->stream) != hipSuccess)
+        return QED_ERR_HIP;
+    if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
+    return QED_OK;
+}
+
+qed_status qed_get_stats(qed_ctx *c, qed_stats *out) {
+    if (!c || !out) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    qed::DevState h;
+    HIP_TRY(hipMemcpy(&h, c->st, sizeof(h), hipMemcpyDeviceToHost));
+    memset(out, 0, sizeof(*out));
+    out->steps = h.steps;
+    for (int k = 0; k < 3; ++k) {
+        out->substeps[k] = h.substeps[k];
+        out->particles[k] = h.particles[k];
+    }
+    out->emissions = h.emissions;
+    out->pairs = h.pairs;
+    out->clips = h.clips;
+    out->capped = h.capped;
+    double mp;
+    memcpy(&mp, &h.max_p_bits, sizeof(mp));
+    out->max_p = mp;
+    return QED_OK;
+}
+
+qed_status qed_reset_stats(qed_ctx *c) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    qed::DevState h;
+    HIP_TRY(hipMemcpy(&h, c->st, sizeof(h), hipMemcpyDeviceToHost));
+    h.steps = 0;
+    h.substeps[0] = h.substeps[1] = h.substeps[2] = 0;
+    h.particles[0] = h.particles[1] = h.particles[2] = 0;
+    h.emissions = h.pairs = h.clips = h.capped = 0;
+    h.max_p_bits = 0;
+    HIP_TRY(hipMemcpy(c->st, &h, sizeof(h), hipMemcpyHostToDevice));
+    return QED_OK;
+}
+
+qed_status qed_profile_enable(qed_ctx *c, int on) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    c->prof = on != 0;
+    return QED_OK;
+}
+
+qed_status qed_profile_read(qed_ctx *c, qed_kernel_time *out, int max, int *count) {
+    if (!c || !count || max < 0 || (max > 0 && !out)) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double ms[qed::K_COUNT] = {0};
+    u64 nl[qed::K_COUNT] = {0};
+    for (size_t k = 0; k < c->rec_used; ++k) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, c->ev_pool[2 * k], c->ev_pool[2 * k + 1]));
+        ms[c->rec_id[k]] += t;
+        nl[c->rec_id[k]] += 1;
+    }
+    c->rec_used = 0;
+    int w = 0;
+    for (int id = 0; id < qed::K_COUNT && w < max; ++id) {
+        if (!nl[id]) continue;
+        out[w].name = kKernelName[id];
+        out[w].launches = nl[id];
+        out[w].total_ms = ms[id];
+        ++w;
+    }
+    *count = w;
+    return QED_OK;
+}
+
+void qed_finalize(qed_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->cfg.device);
+    (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->alive) (void)hipFree(c->alive);
+    if (c->hole_idx) (void)hipFree(c->hole_idx);
+    if (c->mover_idx) (void)hipFree(c->mover_idx);
+    if (c->st) (void)hipFree(c->st);
+    delete c;
+}
+
+const char *qed_status_string(qed_status s) {
+    switch (s) {
+        case QED_OK: return "ok";
+        case QED_ERR_INVALID_ARG: return "invalid argument";
+        case QED_ERR_CAPACITY: return "particle buffer capacity exceeded";
+        case QED_ERR_NONFINITE: return "non-finite input";
+        case QED_ERR_HIP: return "HIP runtime error";
+        case QED_ERR_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// Device-side building blocks of the QED event generator (gfx950).
+//
+// Counter-based random numbers, the quantum parameter chi, the sub-step bounds of
+// Sec. 3.1.1, the Boris pusher and the synchrotron-function fits of Sec. 3.2.1.
+// Everything is templated on the working real type R (float for the mixed path,
+// double for the FP64 path); quantities that decide the sub-step count are always
+// formed in double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qed {
+
+constexpr double kAlpha = 7.2973525693e-3;  // fine-structure constant (CODATA 2018)
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrt3 = 1.7320508075688772935;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11).  Round: with (hi, lo) the halves of the
+// 32x32->64 products M0*c0 and M1*c2, the counter becomes
+// (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0); the key advances by the Weyl constants.
+// ---------------------------------------------------------------------------
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// (2k+1) 2^-24 with k the top 23 bits: exact in float, strictly inside (0, 1).
+__device__ __forceinline__ float u24(uint32_t w) { return (float)(((w >> 9) << 1) | 1u) * 0x1p-24f; }
+
+// (2k+1) 2^-53 with k the top 52 bits of (hi:lo): exact in double, inside (0, 1).
+__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
+    const uint64_t k = ((((uint64_t)hi) << 32) | lo) >> 12;
+    return (double)((k << 1) | 1u) * 0x1p-53;
+}
+
+// Id of a child: Philox under the seed key tagged with (0x5851F42D, 0x4C957F2D),
+// counter (parent, step, 2 i + slot); slot 0 = photon or pair electron, 1 = positron.
+__device__ __forceinline__ uint64_t child_id(uint64_t seed, uint64_t parent, uint32_t step,
+                                             uint32_t sub, uint32_t slot) {
+    const u32x4 w = philox10((uint32_t)parent, (uint32_t)(parent >> 32), step, 2u * sub + slot,
+                             (uint32_t)seed ^ 0x5851F42Du, (uint32_t)(seed >> 32) ^ 0x4C957F2Du);
+    return (((uint64_t)w.y) << 32) | w.x;
+}
+
+// ---------------------------------------------------------------------------
+// chi = sqrt((energy E + p x B)^2 - (p . E)^2) (eq. (1) and eq. (2) text), in double.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double chi_def(double en, double px, double py, double pz, double ex,
+                                          double ey, double ez, double bx, double by, double bz) {
+    const double ax = en * ex + (py * bz - pz * by);
+    const double ay = en * ey + (pz * bx - px * bz);
+    const double az = en * ez + (px * by - py * bx);
+    const double pe = px * ex + py * ey + pz * ez;
+    const double s = ax * ax + ay * ay + az * az - pe * pe;
+    return s > 0.0 ? sqrt(s) : 0.0;
+}
+
+// Lepton chi in float for the sub-step loop.  With gamma^2 = 1 + |u|^2 the
+// definition rearranges to |E|^2 + |u x E|^2 + 2 gamma E.(u x B) + |u x B|^2
+// (Lagrange's identity), which has no cancellation in a pure E field.  Only the
+// cross term can cancel (crossed fields with u along E x B); then the value is
+// recomputed in double from the definition.
+__device__ __forceinline__ float chi_lepton_f32(float ux, float uy, float uz, float gamma, float ex,
+                                                float ey, float ez, float bx, float by, float bz,
+                                                float e2) {
+    const float cex = uy * ez - uz * ey, cey = uz * ex - ux * ez, cez = ux * ey - uy * ex;
+    const float cbx = uy * bz - uz * by, cby = uz * bx - ux * bz, cbz = ux * by - uy * bx;
+    const float t = e2 + (cex * cex + cey * cey + cez * cez) + (cbx * cbx + cby * cby + cbz * cbz);
+    const float xt = 2.0f * gamma * (ex * cbx + ey * cby + ez * cbz);
+    if (xt < -0.5f * t) {
+        const double gd = sqrt(1.0 + (double)ux * ux + (double)uy * uy + (double)uz * uz);
+        return (float)chi_def(gd, ux, uy, uz, ex, ey, ez, bx, by, bz);
+    }
+    const float s = t + xt;
+    return s > 0.0f ? sqrtf(s) : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Sub-step bounds (Sec. 3.1.1).  Emission: b = 3 chi/2, c = sqrt(3) alpha dt/(pi gamma),
+// f(b) in four pieces; each printed breakpoint belongs to the piece above it.
+// Pairs: f = coef c b with the photon energy in place of gamma.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double bound_emission(double chi, double gamma, double dt) {
+    const double b = 1.5 * chi;
+    const double c = kSqrt3 * kAlpha * dt / (kPi * gamma);
+    double lead;
+    if (b < 0.1)
+        lead = 0.56 * kPi * c * b;
+    else if (b < 0.5)
+        lead = 0.45 * kPi * c * pow(b, 11.0 / 12.0);
+    else if (b < 10.0)
+        lead = 0.42 * kPi * c * pow(b, 19.0 / 24.0);
+    else
+        lead = 0.55 * kPi * c * pow(b, 2.0 / 3.0);
+    return lead + 0.1 * c * b;
+}
+
+__device__ __forceinline__ double bound_pair(double chi, double eps, double dt, double coef) {
+    return coef * (kSqrt3 * kAlpha * dt / (kPi * eps)) * (1.5 * chi);
+}
+
+// Smallest N >= 1 with f/N <= p_max, capped at cap (sets *capped).
+__device__ __forceinline__ uint32_t nsub(double f, double p_max, uint32_t cap, bool *capped) {
+    double r = ceil(f / p_max);
+    if (!(r >= 1.0)) r = 1.0;
+    *capped = r > (double)cap;
+    if (*capped) r = (double)cap;
+    return (uint32_t)r;
+}
+
+// Float reciprocal, square root and reciprocal square root from the hardware
+// instructions (about 1 ulp); the double versions keep IEEE accuracy.
+__device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double rcp(double v) { return 1.0 / v; }
+__device__ __forceinline__ float sqrt_(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ __forceinline__ double sqrt_(double v) { return sqrt(v); }
+__device__ __forceinline__ float rsqrt_(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ double rsqrt_(double v) { return 1.0 / sqrt(v); }
+
+// ---------------------------------------------------------------------------
+// Boris pusher, du/dt = q (E + u x B / gamma), frozen fields.  hq = q dt / 2 and
+// hex, hey, hez = hq E are precomputed per particle.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void boris(R &ux, R &uy, R &uz, R hex, R hey, R hez, R hq, R bx, R by,
+                                      R bz) {
+    const R mx = ux + hex, my = uy + hey, mz = uz + hez;
+    const R ig = rsqrt_(R(1) + mx * mx + my * my + mz * mz);
+    const R f = hq * ig;
+    const R tx = f * bx, ty = f * by, tz = f * bz;
+    const R s = R(2) * rcp(R(1) + tx * tx + ty * ty + tz * tz);
+    const R px = mx + (my * tz - mz * ty);
+    const R py = my + (mz * tx - mx * tz);
+    const R pz = mz + (mx * ty - my * tx);
+    const R sx = s * tx, sy = s * ty, sz = s * tz;
+    ux = mx + (py * sz - pz * sy) + hex;
+    uy = my + (pz * sx - px * sz) + hey;
+    uz = mz + (px * sy - py * sx) + hez;
+}
+
+}  // namespace qed

@@ -1,0 +1,110 @@
+// Synchrotron functions F(x) = x int_x^inf K_{5/3} and G(x) = x K_{2/3} (Sec. 3.2.1)
+// from the piecewise fits of synchro_coeffs.inc:
+//   F(x) = t e^{-x} H_F(t),  G(x) = t e^{-x} H_G(t),  t = x^(1/3),
+// with H_F, H_G analytic in t and tabulated as one polynomial per uniform segment
+// of t.  F and G share t, e^{-x} and the segment index; the segment's
+// coefficients are gathered from LDS with 128-bit loads (float: 2 loads per
+// function, double: 6).  The tables live in constant memory and are staged into
+// LDS once per block by syn_stage().
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#define QED_SYN_STORAGE static __constant__ const
+#include "synchro_coeffs.inc"
+#undef QED_SYN_STORAGE
+
+namespace qed {
+
+template <class R>
+struct SynTable;
+
+template <>
+struct SynTable<float> {
+    static constexpr int kSeg = QED_SYN_F32_NSEG;
+    static constexpr int kCoef = QED_SYN_F32_NCOEF;   // 8
+    static constexpr float kTmax = (float)QED_SYN_F32_TMAX;
+    static constexpr float kInvHalfWidth = 4.0f;       // 1 / (W/2), W = 0.5
+    static constexpr int kWords = kSeg * 2 * kCoef;    // floats
+    float4 v[kWords / 4];
+};
+
+template <>
+struct SynTable<double> {
+    static constexpr int kSeg = QED_SYN_F64_NSEG;
+    static constexpr int kCoef = QED_SYN_F64_NCOEF;   // 12
+    static constexpr double kTmax = QED_SYN_F64_TMAX;
+    static constexpr double kInvHalfWidth = 8.0;       // 1 / (W/2), W = 0.25
+    static constexpr int kWords = kSeg * 2 * kCoef;    // doubles
+    double2 v[kWords / 2];
+};
+
+static_assert(QED_SYN_F32_NCOEF == 8, "float kernel assumes 8 coefficients");
+static_assert(QED_SYN_F64_NCOEF == 12, "double kernel assumes 12 coefficients");
+
+// Copy the constant table into the block's LDS copy.  All threads of the block
+// must call it before any uses the table.
+__device__ __forceinline__ void syn_stage(SynTable<float> &t) {
+    const float4 *src = reinterpret_cast<const float4 *>(&qed_syn_f32_coef[0][0][0]);
+    for (int i = threadIdx.x; i < SynTable<float>::kWords / 4; i += blockDim.x) t.v[i] = src[i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void syn_stage(SynTable<double> &t) {
+    const double2 *src = reinterpret_cast<const double2 *>(&qed_syn_f64_coef[0][0][0]);
+    for (int i = threadIdx.x; i < SynTable<double>::kWords / 2; i += blockDim.x) t.v[i] = src[i];
+    __syncthreads();
+}
+
+__device__ __forceinline__ float syn_cbrt(float z) { return cbrtf(z); }
+__device__ __forceinline__ double syn_cbrt(double z) { return cbrt(z); }
+__device__ __forceinline__ float syn_expm(float z) { return expf(-z); }
+__device__ __forceinline__ double syn_expm(double z) { return exp(-z); }
+
+// F, G at z >= 0 (z = +inf gives 0).  Caller guarantees z is not NaN / negative.
+__device__ __forceinline__ void syn_eval(float z, const SynTable<float> &tab, float &F, float &G) {
+    const float t = syn_cbrt(z);
+    const float tc = fminf(t, SynTable<float>::kTmax);
+    const int seg = min((int)(tc * 2.0f), SynTable<float>::kSeg - 1);
+    const float s = fmaf(tc, SynTable<float>::kInvHalfWidth, -(float)(2 * seg + 1));
+    const float4 *c = &tab.v[seg * 4];
+    const float4 f0 = c[0], f1 = c[1], g0 = c[2], g1 = c[3];
+    float hf = f1.w, hg = g1.w;
+    hf = fmaf(hf, s, f1.z);
+    hg = fmaf(hg, s, g1.z);
+    hf = fmaf(hf, s, f1.y);
+    hg = fmaf(hg, s, g1.y);
+    hf = fmaf(hf, s, f1.x);
+    hg = fmaf(hg, s, g1.x);
+    hf = fmaf(hf, s, f0.w);
+    hg = fmaf(hg, s, g0.w);
+    hf = fmaf(hf, s, f0.z);
+    hg = fmaf(hg, s, g0.z);
+    hf = fmaf(hf, s, f0.y);
+    hg = fmaf(hg, s, g0.y);
+    hf = fmaf(hf, s, f0.x);
+    hg = fmaf(hg, s, g0.x);
+    const float pre = tc * syn_expm(z);
+    F = pre * hf;
+    G = pre * hg;
+}
+
+__device__ __forceinline__ void syn_eval(double z, const SynTable<double> &tab, double &F, double &G) {
+    const double t = syn_cbrt(z);
+    const double tc = fmin(t, SynTable<double>::kTmax);
+    const int seg = min((int)(tc * 4.0), SynTable<double>::kSeg - 1);
+    const double s = fma(tc, SynTable<double>::kInvHalfWidth, -(double)(2 * seg + 1));
+    const double2 *c = &tab.v[seg * 12];
+    double hf = c[5].y, hg = c[11].y;
+#pragma unroll
+    for (int k = 10; k >= 0; --k) {
+        const double2 cf = c[k >> 1], cg = c[6 + (k >> 1)];
+        hf = fma(hf, s, (k & 1) ? cf.y : cf.x);
+        hg = fma(hg, s, (k & 1) ? cg.y : cg.x);
+    }
+    const double pre = tc * syn_expm(z);
+    F = pre * hf;
+    G = pre * hg;
+}
+
+}  // namespace qed

@@ -141,7 +141,8 @@ def main(out_path=None):
         "// Generated by paper_2008_10468_amd/fitgen/synchro_fit.py -- do not edit.",
         "// F(x) = t e^{-x} H_F(t), G(x) = t e^{-x} H_G(t), t = x^(1/3); per segment j of",
         "// width W in t a degree-D polynomial in s = (t - (j + 1/2) W) / (W / 2).",
-        "// Layout: [segment][function F,G][coefficient c_0..c_D].",
+        "// Layout: [segment][function F,G][coefficient c_0..c_D].  The includer defines",
+        "// QED_SYN_STORAGE (e.g. __constant__ const) before including this file.",
         "",
     ]
     with mpc.Pool(min(16, os.cpu_count() or 1)) as pool:
@@ -157,7 +158,7 @@ def main(out_path=None):
             lines.append(f"#define QED_SYN_{up}_WIDTH {float(width)!r}")
             lines.append(f"#define QED_SYN_{up}_TMAX {float(width * nseg)!r}")
             lines.append(f"// max relative error of H over the table, in {ctype}: {worst:.3e}")
-            lines.append(f"static const {ctype} qed_syn_{name}_coef[{nseg}][2][{deg + 1}] = {{")
+            lines.append(f"QED_SYN_STORAGE {ctype} qed_syn_{name}_coef[{nseg}][2][{deg + 1}] = {{")
             for sgi, (cf, cg) in enumerate(segs):
                 def fmt(v):
                     if ctype == "float":

@@ -1,0 +1,330 @@
+"""ctypes binding of libqed.so (include/qed.h).  Argument marshalling only: every
+step of the generator runs in the library's HIP kernels; torch provides device
+memory and the stream.  Importing this module does not load the library; the
+first call does, and fails loudly if it has not been built."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqed.so")
+
+QED_OK, QED_ERR_INVALID_ARG, QED_ERR_CAPACITY, QED_ERR_NONFINITE, QED_ERR_HIP, QED_ERR_STATE = 0, -1, -2, -3, -4, -5
+QED_F32, QED_F64 = 0, 1
+QED_PREC_F64, QED_PREC_MIXED = 0, 1
+QED_SCHED_NAIVE, QED_SCHED_BINNED = 0, 1
+
+SPECIES = ("electrons", "positrons", "photons")
+
+
+class qed_species(C.Structure):
+    _fields_ = [("n", C.c_void_p), ("capacity", C.c_uint64),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("ux", C.c_void_p), ("uy", C.c_void_p), ("uz", C.c_void_p),
+                ("w", C.c_void_p), ("id", C.c_void_p), ("parent", C.c_void_p),
+                ("events", C.c_void_p)]
+
+
+class qed_particles(C.Structure):
+    _fields_ = [(s, qed_species) for s in SPECIES]
+
+
+class qed_field(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("ex", "ey", "ez", "bx", "by", "bz")] + [("stride", C.c_uint64)]
+
+
+class qed_config(C.Structure):
+    _fields_ = [("device", C.c_int), ("stream", C.c_void_p), ("precision", C.c_int),
+                ("p_max", C.c_double), ("emission", C.c_int), ("pairs", C.c_int),
+                ("scheduler", C.c_int), ("pair_bound_coef", C.c_double),
+                ("max_substeps", C.c_uint32)]
+
+
+class qed_report(C.Structure):
+    _fields_ = [("status", C.c_int32), ("pad", C.c_int32), ("required_capacity", C.c_uint64 * 3),
+                ("nonfinite", C.c_uint64), ("n", C.c_uint64 * 3)]
+
+
+class qed_stats(C.Structure):
+    _fields_ = [("steps", C.c_uint64), ("substeps", C.c_uint64 * 3), ("particles", C.c_uint64 * 3),
+                ("emissions", C.c_uint64),
+                ("pairs", C.c_uint64), ("clips", C.c_uint64), ("capped", C.c_uint64),
+                ("max_p", C.c_double)]
+
+
+class qed_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("launches", C.c_uint64), ("total_ms", C.c_double)]
+
+
+EXPORTS = ("qed_config_default", "qed_init", "qed_step", "qed_sync", "qed_synchrotron",
+           "qed_get_stats", "qed_reset_stats", "qed_profile_enable", "qed_profile_read",
+           "qed_finalize", "qed_status_string")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libqed.so; raise if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2008_10468_amd.build`")
+    L = C.CDLL(path)
+    L.qed_config_default.argtypes = [C.POINTER(qed_config)]
+    L.qed_init.argtypes = [C.POINTER(C.c_void_p), C.POINTER(qed_config)]
+    L.qed_step.argtypes = [C.c_void_p, C.POINTER(qed_particles), C.POINTER(qed_field), C.c_double,
+                           C.c_uint64, C.c_uint32]
+    L.qed_sync.argtypes = [C.c_void_p, C.POINTER(qed_report)]
+    L.qed_synchrotron.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int]
+    L.qed_get_stats.argtypes = [C.c_void_p, C.POINTER(qed_stats)]
+    L.qed_reset_stats.argtypes = [C.c_void_p]
+    L.qed_profile_enable.argtypes = [C.c_void_p, C.c_int]
+    L.qed_profile_read.argtypes = [C.c_void_p, C.POINTER(qed_kernel_time), C.c_int, C.POINTER(C.c_int)]
+    L.qed_finalize.argtypes = [C.c_void_p]
+    L.qed_finalize.restype = None
+    L.qed_status_string.argtypes = [C.c_int]
+    L.qed_status_string.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("qed_finalize", "qed_status_string"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class QedError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+def status_string(s):
+    return load().qed_status_string(int(s)).decode()
+
+
+def _check(st, what):
+    if st != QED_OK:
+        raise QedError(st, what)
+
+
+# ---------------------------------------------------------------- thin wrappers
+
+def qed_config_default():
+    cfg = qed_config()
+    _check(load().qed_config_default(C.byref(cfg)), "qed_config_default")
+    return cfg
+
+
+def qed_init(cfg):
+    ctx = C.c_void_p()
+    _check(load().qed_init(C.byref(ctx), C.byref(cfg)), "qed_init")
+    return ctx
+
+
+def qed_step(ctx, particles, fields, dt, seed, step):
+    arr = (qed_field * 3)(*fields)
+    return load().qed_step(ctx, C.byref(particles), arr, float(dt), int(seed), int(step))
+
+
+def qed_sync(ctx):
+    rep = qed_report()
+    st = load().qed_sync(ctx, C.byref(rep))
+    return st, rep
+
+
+def qed_synchrotron(ctx, x, F, G, n, dtype):
+    return load().qed_synchrotron(ctx, x, F, G, int(n), int(dtype))
+
+
+def qed_get_stats(ctx):
+    s = qed_stats()
+    _check(load().qed_get_stats(ctx, C.byref(s)), "qed_get_stats")
+    return s
+
+
+def qed_reset_stats(ctx):
+    _check(load().qed_reset_stats(ctx), "qed_reset_stats")
+
+
+def qed_profile_enable(ctx, on):
+    _check(load().qed_profile_enable(ctx, int(on)), "qed_profile_enable")
+
+
+def qed_profile_read(ctx):
+    """{kernel name: (launches, total ms)} since the last read."""
+    arr = (qed_kernel_time * 16)()
+    cnt = C.c_int()
+    _check(load().qed_profile_read(ctx, arr, 16, C.byref(cnt)), "qed_profile_read")
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(cnt.value)}
+
+
+def qed_finalize(ctx):
+    load().qed_finalize(ctx)
+
+
+# ---------------------------------------------------------------- torch helpers
+
+def _torch():
+    import torch
+    return torch
+
+
+class SpeciesBuffers:
+    """Device SoA buffers of one species (torch tensors) with a fixed capacity."""
+
+    def __init__(self, capacity, real, device="cuda", parent=True, events=True):
+        torch = _torch()
+        self.capacity = int(capacity)
+        self.real = real
+        cap = max(1, self.capacity)
+        self.n = torch.zeros(1, dtype=torch.int64, device=device)
+        self.x = torch.zeros(cap, dtype=torch.float64, device=device)
+        self.y = torch.zeros(cap, dtype=torch.float64, device=device)
+        self.z = torch.zeros(cap, dtype=torch.float64, device=device)
+        self.ux = torch.zeros(cap, dtype=real, device=device)
+        self.uy = torch.zeros(cap, dtype=real, device=device)
+        self.uz = torch.zeros(cap, dtype=real, device=device)
+        self.w = torch.zeros(cap, dtype=real, device=device)
+        self.id = torch.zeros(cap, dtype=torch.int64, device=device)
+        self.parent = torch.zeros(cap, dtype=torch.int64, device=device) if parent else None
+        self.events = torch.zeros(cap, dtype=torch.int32, device=device) if events else None
+
+    def struct(self):
+        s = qed_species()
+        s.n = self.n.data_ptr()
+        s.capacity = self.capacity
+        for k in ("x", "y", "z", "ux", "uy", "uz", "w", "id"):
+            setattr(s, k, getattr(self, k).data_ptr())
+        s.parent = self.parent.data_ptr() if self.parent is not None else None
+        s.events = self.events.data_ptr() if self.events is not None else None
+        return s
+
+    def upload(self, host):
+        """host: dict of numpy arrays x,y,z,ux,uy,uz,w (float64) and id (uint64)."""
+        torch = _torch()
+        n = int(host["id"].size)
+        if n > self.capacity:
+            raise ValueError("capacity too small")
+        for k in ("x", "y", "z"):
+            getattr(self, k)[:n].copy_(torch.from_numpy(np.ascontiguousarray(host[k], np.float64)))
+        for k in ("ux", "uy", "uz", "w"):
+            getattr(self, k)[:n].copy_(torch.from_numpy(np.ascontiguousarray(host[k], np.float64)).to(self.real))
+        self.id[:n].copy_(torch.from_numpy(np.ascontiguousarray(host["id"]).view(np.int64)))
+        self.n.fill_(n)
+
+    def count(self):
+        return int(self.n.item())
+
+    def download(self):
+        n = self.count()
+        out = {k: getattr(self, k)[:n].double().cpu().numpy() for k in ("x", "y", "z", "ux", "uy", "uz", "w")}
+        out["id"] = self.id[:n].cpu().numpy().view(np.uint64)
+        if self.parent is not None:
+            out["parent"] = self.parent[:n].cpu().numpy().view(np.uint64)
+        return out
+
+    def events_host(self, n):
+        return self.events[:n].cpu().numpy().astype(np.uint32)
+
+
+class FieldBuffers:
+    """Per-species field: either uniform (6 values) or per-slot arrays."""
+
+    def __init__(self, host, real, device="cuda", capacity=None):
+        torch = _torch()
+        self.host = host
+        vals = [np.asarray(host[k], np.float64).ravel() for k in ("ex", "ey", "ez", "bx", "by", "bz")]
+        self.stride = 0 if vals[0].size == 1 else 1
+        size = 1 if self.stride == 0 else max(int(capacity or vals[0].size), vals[0].size)
+        self.t = []
+        for v in vals:
+            t = torch.zeros(size, dtype=real, device=device)
+            t[:v.size].copy_(torch.from_numpy(v).to(real))
+            self.t.append(t)
+
+    def set_uniform(self, host):
+        for t, k in zip(self.t, ("ex", "ey", "ez", "bx", "by", "bz")):
+            t.fill_(float(np.asarray(host[k]).ravel()[0]))
+
+    def struct(self):
+        f = qed_field()
+        for t, k in zip(self.t, ("ex", "ey", "ez", "bx", "by", "bz")):
+            setattr(f, k, t.data_ptr())
+        f.stride = self.stride
+        return f
+
+
+class Generator:
+    """A context plus the three species buffers; convenience for tests and the benchmark."""
+
+    def __init__(self, precision=QED_PREC_MIXED, capacity=(1 << 20, 1 << 20, 1 << 20), emission=True,
+                 pairs=True, p_max=0.01, scheduler=QED_SCHED_NAIVE, pair_bound_coef=0.1,
+                 max_substeps=1 << 24, device=0, stream=None, parent=True, events=True):
+        torch = _torch()
+        self.real = torch.float64 if precision == QED_PREC_F64 else torch.float32
+        self.precision = precision
+        cfg = qed_config_default()
+        cfg.device = device
+        cfg.stream = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        cfg.precision = precision
+        cfg.p_max = p_max
+        cfg.emission = int(emission)
+        cfg.pairs = int(pairs)
+        cfg.scheduler = scheduler
+        cfg.pair_bound_coef = pair_bound_coef
+        cfg.max_substeps = max_substeps
+        self.cfg = cfg
+        self.ctx = qed_init(cfg)
+        self.sp = [SpeciesBuffers(c, self.real, parent=parent, events=events) for c in capacity]
+        self.fields = [None, None, None]
+
+    def load_state(self, state):
+        for s, name in enumerate(SPECIES):
+            self.sp[s].upload(state[name])
+
+    def set_fields(self, fields, per_species=None):
+        """fields: one field dict for all species, or per_species list of three."""
+        fl = per_species or [fields, fields, fields]
+        self.fields = [FieldBuffers(f, self.real, capacity=self.sp[s].capacity) for s, f in enumerate(fl)]
+
+    def particles(self):
+        p = qed_particles()
+        for s, name in enumerate(SPECIES):
+            setattr(p, name, self.sp[s].struct())
+        return p
+
+    def step(self, dt, seed, step):
+        st = qed_step(self.ctx, self.particles(), [f.struct() for f in self.fields], dt, seed, step)
+        _check(st, "qed_step")
+
+    def sync(self):
+        return qed_sync(self.ctx)
+
+    def stats(self):
+        return qed_get_stats(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            qed_finalize(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def synchrotron(ctx, x, F=None, G=None):
+    """F, G of a torch device tensor x (float32 or float64)."""
+    torch = _torch()
+    dtype = QED_F32 if x.dtype == torch.float32 else QED_F64
+    if F is None:
+        F = torch.empty_like(x)
+    if G is None:
+        G = torch.empty_like(x)
+    _check(qed_synchrotron(ctx, x.data_ptr(), F.data_ptr(), G.data_ptr(), x.numel(), dtype), "qed_synchrotron")
+    return F, G

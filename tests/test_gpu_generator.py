@@ -1,0 +1,259 @@
+"""GPU parity of qed_step (Algorithms 1 and 2) against the oracle, particle by particle.
+
+Protocol: the GPU runs a step; the oracle runs the same step from the GPU's
+start-of-step state (float values are exact in double) with the same Philox
+streams; pre-existing leptons are compared slot by slot, photons and children by
+their deterministic ids.  FP64 path: identical event counts.  Mixed path:
+identical event counts on >= 99.99% of particles, momenta to float accuracy."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import as_precision, compare_children, compare_leptons, gpu_step, oracle_step
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _mom(d):
+    return np.stack([d["ux"], d["uy"], d["uz"]])
+
+
+def _gen(precision, capacity, **kw):
+    from paper_2008_10468_amd import qed
+    return qed.Generator(precision=precision, capacity=capacity, **kw)
+
+
+def _check_step(g, fields, dt, seed, step, precision, emission=True, pairs=True, rtol=1e-9, min_agree=1.0,
+                max_missing=0, rtol_per_substep=0.0):
+    """One GPU step checked against the oracle.  Momentum tolerance of a particle:
+    rtol + rtol_per_substep * (its number of sub-steps)."""
+    before, after, events, st, rep = gpu_step(g, fields, dt, seed, step)
+    from paper_2008_10468_amd import qed
+    assert st == qed.QED_OK, qed.status_string(st)
+    fh = [as_precision(f.host, precision) for f in g.fields]
+    res = oracle_step(before, fh, dt, seed, step, precision, emission=emission, pairs=pairs)
+    out = {}
+    child_rtol = rtol
+    if emission:
+        for s, name in ((0, "electron"), (1, "positron")):
+            n0 = before[s]["id"].size
+            ost, och, onsub, onev, otl = res[name]
+            tol = rtol + rtol_per_substep * onsub[:n0].astype(np.float64)
+            out[name] = compare_leptons(after[s], events[s], ost, onev, n0, tol, min_agree)
+            # positions of particles with the same events
+            same = events[s][:n0] == onev[:n0]
+            for k in ("x", "y", "z"):
+                d = np.abs(after[s][k][:n0] - ost[k][:n0])
+                assert np.all(d[same] <= tol[same] * dt + 1e-12 * np.abs(ost[k][:n0][same]))
+            nmax = int(onsub.max()) if onsub.size else 0
+            child_rtol = max(child_rtol, rtol + rtol_per_substep * nmax)
+    # photons: survivors by id, plus emitted photons by id
+    if emission or pairs:
+        gph = after[2]
+        exp_ids, exp_mom, exp_w = [], [], []
+        if pairs:
+            pst, pch, alive, _, pnev, _ = res["photon"]
+            n0 = before[2]["id"].size
+            same = events[2][:n0] == pnev[:n0]
+            assert np.mean(same) >= min_agree if n0 else True
+            keep = alive.astype(bool)
+            exp_ids.append(pst["id"][keep])
+            exp_mom.append(_mom(pst)[:, keep])
+            exp_w.append(pst["w"][keep])
+            # pair children
+            for s, kind in ((0, 1), (1, 2)):
+                n0s = before[s]["id"].size
+                sel = pch["kind"] == kind
+                compare_children(after[s]["id"][n0s:], _mom(after[s])[:, n0s:], after[s]["w"][n0s:],
+                                 pch["id"][sel], np.stack([pch["px"][sel], pch["py"][sel], pch["pz"][sel]]),
+                                 pch["w"][sel], child_rtol, max_missing)
+        else:
+            n0 = before[2]["id"].size
+            exp_ids.append(before[2]["id"])
+            exp_mom.append(_mom(before[2]))
+            exp_w.append(before[2]["w"])
+        if emission:
+            for name in ("electron", "positron"):
+                och = res[name][1]
+                exp_ids.append(och["id"])
+                exp_mom.append(np.stack([och["px"], och["py"], och["pz"]]))
+                exp_w.append(och["w"])
+        nc, miss = compare_children(gph["id"], _mom(gph), gph["w"], np.concatenate(exp_ids),
+                                    np.concatenate(exp_mom, axis=1), np.concatenate(exp_w), child_rtol,
+                                    max_missing)
+        out["photons_matched"] = nc
+    return out, after
+
+
+def test_c1_fp64_steps_match_oracle():
+    """Emission only, FP64, uniform B: 4 steps, identical events every step."""
+    from paper_2008_10468_amd import qed
+    w = workloads.c1(n=3000)
+    g = _gen(qed.QED_PREC_F64, (4096, 16, 1 << 16), pairs=False)
+    g.load_state(w)
+    g.set_fields(w["fields"])
+    for step in range(4):
+        out, _ = _check_step(g, w["fields"], w["dt"], 1, step, qed.QED_PREC_F64, pairs=False, rtol=1e-9)
+        assert out["electron"] == 1.0
+    stats = g.stats()
+    assert stats.substeps[0] > 0 and stats.emissions > 0
+    g.close()
+
+
+def test_c1_fp64_full_run_matches_independent_oracle_run():
+    """The oracle runs all steps on its own (no GPU state in between) on a subset."""
+    from paper_2008_10468_amd import qed
+    w = workloads.c1(n=1024)
+    g = _gen(qed.QED_PREC_F64, (1024, 16, 1 << 16), pairs=False)
+    g.load_state(w)
+    g.set_fields(w["fields"])
+    ost = {k: v.copy() for k, v in w["electrons"].items()}
+    nsteps = 6
+    ev_gpu = np.zeros(1024, np.int64)
+    ev_orc = np.zeros(1024, np.int64)
+    for step in range(nsteps):
+        g.step(w["dt"], 1, step)
+        assert g.sync()[0] == qed.QED_OK
+        ev_gpu += g.sp[0].events_host(1024)
+        _, _, nev, _ = oracle.lepton_step(ost, w["fields"], -1.0, w["dt"], 1, step, rng_bits=53)
+        ev_orc += nev
+    assert np.array_equal(ev_gpu, ev_orc)
+    e = g.sp[0].download()
+    assert np.allclose(_mom(e), _mom(ost), rtol=1e-8, atol=1e-8)
+    g.close()
+
+
+@pytest.mark.parametrize("seed", [1, 7])
+def test_c2_mixed_emission_and_pairs(seed):
+    """Rotating E field, mixed precision, 3 steps with pairs and photon compaction."""
+    from paper_2008_10468_amd import qed
+    w = workloads.c2(n_e=12000, n_g=4000, seed=seed)
+    g = _gen(qed.QED_PREC_MIXED, (1 << 15, 1 << 14, 1 << 16))
+    g.load_state(w)
+    for step in range(3):
+        g.set_fields(workloads.c2_field(step))
+        out, after = _check_step(g, None, w["dt"], seed, step, qed.QED_PREC_MIXED, rtol=2e-5,
+                                 min_agree=0.9999, max_missing=4, rtol_per_substep=2e-7)
+    st = g.stats()
+    assert st.pairs > 0 and st.emissions > 0
+    g.close()
+
+
+def test_per_particle_fields_hot_spot():
+    """Per-particle (stride 1) fields, C3 recipe in miniature, mixed precision."""
+    from paper_2008_10468_amd import qed
+    w = workloads.c3(n=6000, hot_fraction=0.3)
+    g = _gen(qed.QED_PREC_MIXED, (6000, 16, 1 << 17), pairs=False)
+    g.load_state(w)
+    zero = {k: np.zeros(1) for k in ("ex", "ey", "ez", "bx", "by", "bz")}
+    g.set_fields(None, per_species=[w["fields"], zero, zero])
+    out, _ = _check_step(g, None, w["dt"], 1, 0, qed.QED_PREC_MIXED, pairs=False, rtol=2e-5,
+                         min_agree=0.9999, max_missing=4, rtol_per_substep=2e-7)
+    assert g.stats().substeps[0] > 6000
+    g.close()
+
+
+def test_capacity_overflow_then_retry_is_identical():
+    from paper_2008_10468_amd import qed
+    w = workloads.c1(n=2000)
+    small = _gen(qed.QED_PREC_F64, (2048, 16, 64), pairs=False)
+    small.load_state(w)
+    small.set_fields(w["fields"])
+    small.step(w["dt"], 3, 0)
+    st, rep = small.sync()
+    assert st == qed.QED_ERR_CAPACITY
+    need = rep.required_capacity[2]
+    assert need > 64 and rep.n[2] == 64
+    small.close()
+    big = _gen(qed.QED_PREC_F64, (2048, 16, int(need)), pairs=False)
+    big.load_state(w)
+    big.set_fields(w["fields"])
+    big.step(w["dt"], 3, 0)
+    st, rep = big.sync()
+    assert st == qed.QED_OK and rep.n[2] == need
+    ref = _gen(qed.QED_PREC_F64, (2048, 16, 4 * int(need)), pairs=False)
+    ref.load_state(w)
+    ref.set_fields(w["fields"])
+    ref.step(w["dt"], 3, 0)
+    assert ref.sync()[0] == qed.QED_OK
+    a, b = big.sp[2].download(), ref.sp[2].download()
+    ia, ib = np.argsort(a["id"]), np.argsort(b["id"])
+    for k in ("id", "ux", "uy", "uz", "x", "w"):
+        assert np.array_equal(a[k][ia], b[k][ib])
+    big.close()
+    ref.close()
+
+
+def test_nonfinite_and_invalid_arguments():
+    from paper_2008_10468_amd import qed
+    w = workloads.c1(n=64)
+    w["electrons"]["uy"][5] = np.nan
+    g = _gen(qed.QED_PREC_MIXED, (64, 16, 4096), pairs=False)
+    g.load_state(w)
+    g.set_fields(w["fields"])
+    g.step(w["dt"], 1, 0)
+    st, rep = g.sync()
+    assert st == qed.QED_ERR_NONFINITE and rep.nonfinite == 1
+    assert np.isnan(g.sp[0].download()["uy"][5])
+    assert g.sync()[0] == qed.QED_OK
+    p = g.particles()
+    flds = [f.struct() for f in g.fields]
+    assert qed.qed_step(g.ctx, p, flds, 0.0, 1, 0) == qed.QED_ERR_INVALID_ARG
+    assert qed.qed_step(g.ctx, p, flds, float("nan"), 1, 0) == qed.QED_ERR_INVALID_ARG
+    p.electrons.ux = None
+    assert qed.qed_step(g.ctx, p, flds, 1.0, 1, 0) == qed.QED_ERR_INVALID_ARG
+    g.close()
+
+
+def test_empty_and_zero_field():
+    from paper_2008_10468_amd import qed
+    g = _gen(qed.QED_PREC_MIXED, (128, 16, 16))
+    g.set_fields(workloads.uniform_field())
+    g.step(1e4, 1, 0)
+    assert g.sync()[0] == qed.QED_OK
+    assert [g.sp[s].count() for s in range(3)] == [0, 0, 0]
+    w = workloads.c1(n=100)
+    g.load_state(w)
+    g.step(1e4, 1, 0)
+    st, rep = g.sync()
+    assert st == qed.QED_OK and rep.n[2] == 0
+    assert g.stats().substeps[0] == 100
+    g.close()
+
+
+def test_full_c2_size_sampled_against_oracle():
+    """C2 at full size (1,048,576 e- + 262,144 photons) in the benchmark's launch
+    configuration; 4096 sampled electrons and 2048 photons checked by the oracle."""
+    from paper_2008_10468_amd import qed
+    w = workloads.c2()
+    g = _gen(qed.QED_PREC_MIXED, (1 << 22, 1 << 21, 1 << 22))
+    g.load_state(w)
+    g.set_fields(workloads.c2_field(0))
+    before, after, events, st, rep = gpu_step(g, None, w["dt"], 1, 0)
+    assert st == qed.QED_OK
+    rng = np.random.default_rng(0)
+    se = np.sort(rng.choice(before[0]["id"].size, 4096, replace=False))
+    sg = np.sort(rng.choice(before[2]["id"].size, 2048, replace=False))
+    sub_e = workloads.subset(before[0], se)
+    sub_g = workloads.subset(before[2], sg)
+    fh = as_precision(workloads.c2_field(0), qed.QED_PREC_MIXED)
+    och, onsub, onev, _ = oracle.lepton_step(sub_e, fh, -1.0, w["dt"], 1, 0, rng_bits=24)
+    agree = np.mean(onev == events[0][se])
+    assert agree >= 0.9999
+    same = onev == events[0][se]
+    du = np.linalg.norm(_mom(after[0])[:, se] - _mom(sub_e), axis=0) / np.linalg.norm(_mom(sub_e), axis=0)
+    assert np.max(du[same]) < 2e-5
+    pch, alive, _, pnev, _ = oracle.photon_step(sub_g, fh, w["dt"], 1, 0, rng_bits=24)
+    assert np.mean(pnev == events[2][sg]) >= 0.9999
+    # decayed photons' pairs are present in the lepton buffers, survivors in the photon buffer
+    ids_e = set(after[0]["id"][before[0]["id"].size:].tolist())
+    ids_p = set(after[1]["id"].tolist())
+    ids_g = set(after[2]["id"].tolist())
+    for j, k in zip(pch["id"], pch["kind"]):
+        assert int(j) in (ids_e if k == 1 else ids_p)
+    for pid, a in zip(sub_g["id"], alive):
+        assert (int(pid) in ids_g) == bool(a)
+    g.close()
