@@ -29,24 +29,24 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed) peak
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
-# Algorithmic work of the dominant kernel (k_lepton, mixed precision), counted from
-# its source: floating-point operations per lepton sub-step (FMA = 2, each
-# reciprocal / square root / cube root / exponential = 1) and HBM bytes per lepton
-# per step (read u 12 + id 8 + position 24; write u 12 + position 24) plus bytes
-# per emitted photon (weight read 4; position 24 + k 12 + weight 4 + id 8 written).
-FLOPS_PER_LEPTON_SUBSTEP = 170
-BYTES_PER_LEPTON_STEP = 80
-BYTES_PER_EMISSION = 52
-
-
+# Algorithmic work per unit, counted from the kernel source (mixed precision).
+# Floating-point operations: FMA = 2, each reciprocal / square root / cube root /
+# exponential = 1.  HBM bytes: the arrays a kernel must touch for one particle.
+FLOPS_PER_LEPTON_SUBSTEP = 170      # Boris push 52, gamma and move 15, chi 40, candidate 14,
+                                    # F and G 37, acceptance 12
+FLOPS_PER_PHOTON_SUBSTEP = 62       # move 6, candidate 6, F and G 37, acceptance 13
+BYTES_PER_LEPTON_STEP = 80          # read u 12 + id 8 + position 24; write u 12 + position 24
+BYTES_PER_EMISSION = 52             # weight read 4; position 24 + k 12 + weight 4 + id 8 written
+BYTES_PER_PHOTON_STEP = 61          # read k 12 + position 24; write position 24 + flag 1
+BYTES_PER_BINNED_EXTRA = 8          # sub-step count read 4 + queue entry read 4 (heavy pass)
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def c2_setup(torch, qed, workloads, steps_total):
+def c2_setup(torch, qed, workloads, steps_total, sched):
     w = workloads.c2()
     g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 23, 1 << 23, 1 << 25),
-                      parent=False, events=False)
+                      parent=False, events=False, scheduler=sched)
     # one frozen field per global step, resident on the device: step s reads entry s
     E = np.array([[workloads.c2_field(s)[k][0] for k in ("ex", "ey", "ez", "bx", "by", "bz")]
                   for s in range(steps_total)], np.float64)
@@ -118,6 +118,50 @@ def cpu_baseline(workloads, budget_s):
                       f"steps, FP64 oracle with the same random streams, {dt:.1f} s wall"}
 
 
+def roofline(kt, st, K):
+    """Roofline of the kernel with the largest share of the profiled time."""
+    cand = {k: v for k, v in kt.items() if k in ("k_lepton", "k_light", "k_heavy", "k_photon")}
+    name = max(cand, key=lambda k: cand[k][1])
+    nl, tms = cand[name]
+    avg_s = tms * 1e-3 / max(nl, 1)
+    lep_sub = st.substeps[0] + st.substeps[1]
+    lep_part = st.particles[0] + st.particles[1]
+    if name == "k_lepton":
+        sub, part, em = lep_sub, lep_part, st.emissions
+        byts = BYTES_PER_LEPTON_STEP * part + BYTES_PER_EMISSION * em
+        flops = FLOPS_PER_LEPTON_SUBSTEP * sub
+    elif name == "k_heavy":
+        sub, part = st.heavy_substeps, st.heavy_particles
+        em = st.emissions * sub / max(lep_sub, 1)      # emissions shared in proportion to sub-steps
+        byts = (BYTES_PER_LEPTON_STEP + BYTES_PER_BINNED_EXTRA) * part + BYTES_PER_EMISSION * em
+        flops = FLOPS_PER_LEPTON_SUBSTEP * sub
+    elif name == "k_light":
+        sub, part = lep_sub - st.heavy_substeps, lep_part - st.heavy_particles
+        em = st.emissions * sub / max(lep_sub, 1)
+        byts = BYTES_PER_LEPTON_STEP * part + 4 * lep_part + BYTES_PER_EMISSION * em
+        flops = FLOPS_PER_LEPTON_SUBSTEP * sub
+    else:
+        sub, part, em = st.substeps[2], st.particles[2], st.pairs
+        byts = BYTES_PER_PHOTON_STEP * part + 2 * BYTES_PER_EMISSION * em
+        flops = FLOPS_PER_PHOTON_SUBSTEP * sub
+    byts /= max(nl, 1)
+    flops /= max(nl, 1)
+    t_mem = byts / (HBM_PEAK_GBS * 1e9)
+    t_alu = flops / (FP32_VECTOR_PEAK_TFLOPS * 1e12)
+    if t_mem >= t_alu:
+        roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = name
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["per_launch"] = {"particles": part / max(nl, 1), "substeps": sub / max(nl, 1),
+                          "events": em / max(nl, 1), "algorithmic_bytes": byts, "algorithmic_flops": flops}
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +169,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--scheduler", choices=("naive", "binned"), default="binned")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -137,7 +182,8 @@ def main():
 
     torch.cuda.set_device(0)
     K, W = args.steps, args.warmup
-    w, g, field = c2_setup(torch, qed, workloads, max(K, W))
+    sched = qed.QED_SCHED_BINNED if args.scheduler == "binned" else qed.QED_SCHED_NAIVE
+    w, g, field = c2_setup(torch, qed, workloads, max(K, W), sched)
     log(f"bench: C2 workload, {w['electrons']['id'].size} e- + {w['photons']['id'].size} photons, "
         f"dt={w['dt']}, steps={K}, warmup={W}")
 
@@ -177,28 +223,7 @@ def main():
     log("bench: kernel times (profiled pass): " +
         ", ".join(f"{k}: {v[1] / max(v[0], 1) * 1e3:.1f} us x{v[0]}" for k, v in kt.items()))
 
-    # roofline of the dominant kernel (k_lepton) from the profiled pass
-    nl, tl_ms = kt.get("k_lepton", (0, 0.0))
-    avg_s = tl_ms * 1e-3 / max(nl, 1)
-    lep_sub = (stats_p.substeps[0] + stats_p.substeps[1]) / max(nl, 1)
-    lep_part = (stats_p.particles[0] + stats_p.particles[1]) / max(nl, 1)
-    em = stats_p.emissions / max(nl, 1)
-    flops = FLOPS_PER_LEPTON_SUBSTEP * lep_sub
-    byts = BYTES_PER_LEPTON_STEP * lep_part + BYTES_PER_EMISSION * em
-    t_mem = byts / (HBM_PEAK_GBS * 1e9)
-    t_alu = flops / (FP32_VECTOR_PEAK_TFLOPS * 1e12)
-    if t_mem >= t_alu:
-        roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    else:
-        roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = "k_lepton<float>"
-    roof["avg_launch_us"] = avg_s * 1e6
-    roof["per_launch"] = {"leptons": lep_part, "substeps": lep_sub, "emissions": em,
-                          "algorithmic_bytes": byts, "algorithmic_flops": flops}
-
+    roof = roofline(kt, stats_p, K)
     out = {
         "metric": "particle-sub-steps/s",
         "value": value,
@@ -217,7 +242,7 @@ def main():
                         "200 steps, emission + pair creation, mixed precision (f32 push and synchrotron "
                         "functions, f64 sub-step count and positions), buffers growing by appends",
             "steps": K, "p_max": 0.01, "dt_hbar_over_mc2": w["dt"], "seed": w["seed"],
-            "scheduler": "naive",
+            "scheduler": args.scheduler,
         },
         "events_per_s": ev / (ms * 1e-3),
         "roofline": roof,

@@ -114,6 +114,8 @@ typedef struct qed_stats {
     uint64_t steps;
     uint64_t substeps[3]; /* particle-sub-steps of e-, e+, photons */
     uint64_t particles[3];/* particle-steps (particles processed, summed over steps) */
+    uint64_t heavy_particles, heavy_substeps; /* part of the above run by the heavy-queue
+                                                 kernel of the binned scheduler */
     uint64_t emissions;   /* photons emitted */
     uint64_t pairs;       /* photons that decayed into pairs */
     uint64_t clips;       /* sub-steps whose acceptance probability exceeded 1 */
@@ -158,6 +160,23 @@ QED_API qed_status qed_synchrotron(qed_ctx *ctx, const void *x, void *F, void *G
 
 QED_API qed_status qed_get_stats(qed_ctx *ctx, qed_stats *out);
 QED_API qed_status qed_reset_stats(qed_ctx *ctx);
+
+/* Launch shape of the kernels (the autotuner's search space).  Results never
+ * depend on it: random numbers are keyed by particle, not by lane. */
+typedef struct qed_tuning {
+    uint32_t lepton_blocks_per_cu; /* grid of the naive lepton kernel, the light pass and
+                                      the pre-pass, in 256-thread blocks per CU (>= 1) */
+    uint32_t heavy_blocks_per_cu;  /* persistent heavy-queue kernel, blocks per CU (>= 1) */
+    uint32_t photon_blocks_per_cu; /* photon kernel, blocks per CU (>= 1) */
+    uint32_t light_max;            /* binned scheduler: particles with at most this many
+                                      sub-steps run in buffer order (>= 1) */
+    uint32_t chunk;                /* binned scheduler: queue entries a wave claims at once
+                                      (a multiple of 64, >= 64) */
+} qed_tuning;
+
+/* Read / replace the context's launch shape; INVALID_ARG if a field is out of range. */
+QED_API qed_status qed_get_tuning(qed_ctx *ctx, qed_tuning *out);
+QED_API qed_status qed_set_tuning(qed_ctx *ctx, const qed_tuning *t);
 
 /* Per-kernel timing of the library's own launches, for measurement: while
  * enabled, every kernel the context enqueues is bracketed by two HIP events on

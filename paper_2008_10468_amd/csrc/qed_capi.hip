@@ -19,9 +19,12 @@ struct qed_ctx {
     hipStream_t stream;
     int num_cu;
     qed::DevState *st;        // device
+    qed_tuning tune;
     uint8_t *alive;           // photon scratch, sized by photon_cap
-    u64 *hole_idx, *mover_idx;
+    u64 *dead_idx, *hole_idx, *mover_idx;
     u64 photon_cap;
+    uint32_t *nsub[2], *queue[2];  // binned-scheduler scratch, sized by lepton_cap
+    u64 lepton_cap[2];
     u64 *last_n[3];           // count pointers of the last step (for qed_sync)
     bool prof;                // bracket launches with events
     std::vector<hipEvent_t> ev_pool;
@@ -80,24 +83,49 @@ int grid_for(u64 work, int max_blocks) {
     return (int)b;
 }
 
+template <class T>
+void release(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
 qed_status ensure_photon_scratch(qed_ctx *c, u64 cap) {
     if (cap <= c->photon_cap) return QED_OK;
     HIP_TRY(hipStreamSynchronize(c->stream));
-    if (c->alive) (void)hipFree(c->alive);
-    if (c->hole_idx) (void)hipFree(c->hole_idx);
-    if (c->mover_idx) (void)hipFree(c->mover_idx);
-    c->alive = nullptr;
-    c->hole_idx = c->mover_idx = nullptr;
+    release(c->alive);
+    release(c->dead_idx);
+    release(c->hole_idx);
+    release(c->mover_idx);
     c->photon_cap = 0;
     HIP_TRY(hipMalloc(&c->alive, cap));
+    HIP_TRY(hipMalloc(&c->dead_idx, cap * sizeof(u64)));
     HIP_TRY(hipMalloc(&c->hole_idx, cap * sizeof(u64)));
     HIP_TRY(hipMalloc(&c->mover_idx, cap * sizeof(u64)));
     c->photon_cap = cap;
     return QED_OK;
 }
 
-const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_end",
-                                         "k_fill",  "k_move",   "k_synchrotron"};
+qed_status ensure_lepton_scratch(qed_ctx *c, int s, u64 cap) {
+    if (cap <= c->lepton_cap[s]) return QED_OK;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    release(c->nsub[s]);
+    release(c->queue[s]);
+    c->lepton_cap[s] = 0;
+    HIP_TRY(hipMalloc(&c->nsub[s], cap * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&c->queue[s], cap * sizeof(uint32_t)));
+    c->lepton_cap[s] = cap;
+    return QED_OK;
+}
+
+bool tuning_ok(const qed_tuning &t) {
+    return t.lepton_blocks_per_cu >= 1 && t.lepton_blocks_per_cu <= 64 && t.heavy_blocks_per_cu >= 1 &&
+           t.heavy_blocks_per_cu <= 64 && t.photon_blocks_per_cu >= 1 && t.photon_blocks_per_cu <= 64 &&
+           t.light_max >= 1 && t.chunk >= 64 && t.chunk % 64 == 0 && t.chunk <= (1u << 20);
+}
+
+const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_prepass",
+                                         "k_scan",  "k_scatter", "k_light", "k_heavy",
+                                         "k_end",   "k_fill",   "k_move",  "k_synchrotron"};
 
 // Event pair for one profiled launch (grown on demand, reused after a read).
 bool prof_pair(qed_ctx *c, int id, hipEvent_t *a, hipEvent_t *b) {
@@ -168,6 +196,11 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
         return QED_ERR_HIP;
     }
     c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    c->tune.lepton_blocks_per_cu = 8;
+    c->tune.heavy_blocks_per_cu = 4;
+    c->tune.photon_blocks_per_cu = 8;
+    c->tune.light_max = 2;
+    c->tune.chunk = 256;
     if (hipMalloc(&c->st, sizeof(qed::DevState)) != hipSuccess ||
         hipMemset(c->st, 0, sizeof(qed::DevState)) != hipSuccess) {
         if (c->st) (void)hipFree(c->st);
@@ -192,10 +225,19 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
     }
     if (emission && (!field_ok(fields[0]) || !field_ok(fields[1]))) return QED_ERR_INVALID_ARG;
     if (pairs && !field_ok(fields[2])) return QED_ERR_INVALID_ARG;
+    const bool binned = c->cfg.scheduler == QED_SCHED_BINNED && emission;
+    if (binned && (sp[0]->capacity > 0xFFFFFFFFull || sp[1]->capacity > 0xFFFFFFFFull))
+        return QED_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(c->cfg.device));
     if (pairs) {
         qed_status r = ensure_photon_scratch(c, sp[2]->capacity > 0 ? sp[2]->capacity : 1);
         if (r != QED_OK) return r;
+    }
+    if (binned) {
+        for (int s = 0; s < 2; ++s) {
+            qed_status r = ensure_lepton_scratch(c, s, sp[s]->capacity > 0 ? sp[s]->capacity : 1);
+            if (r != QED_OK) return r;
+        }
     }
     qed::StepArgs a;
     memset(&a, 0, sizeof(a));
@@ -213,17 +255,32 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
     a.max_sub = c->cfg.max_substeps;
     a.emission = emission;
     a.pairs = pairs;
+    a.light_max = c->tune.light_max;
+    a.chunk = c->tune.chunk;
     a.alive = c->alive;
+    a.dead_idx = c->dead_idx;
     a.hole_idx = c->hole_idx;
     a.mover_idx = c->mover_idx;
-    const int maxb = c->num_cu * 8;
-    const int lepton_blocks = grid_for(sp[0]->capacity + sp[1]->capacity, maxb);
-    const int photon_blocks = grid_for(sp[2]->capacity, maxb);
+    for (int s = 0; s < 2; ++s) {
+        a.nsub[s] = c->nsub[s];
+        a.queue[s] = c->queue[s];
+    }
+    const u64 lep_cap = sp[0]->capacity > sp[1]->capacity ? sp[0]->capacity : sp[1]->capacity;
+    const int lepton_blocks = grid_for(lep_cap, c->num_cu * (int)c->tune.lepton_blocks_per_cu);
+    const int heavy_blocks = c->num_cu * (int)c->tune.heavy_blocks_per_cu;
+    const int photon_blocks = grid_for(sp[2]->capacity, c->num_cu * (int)c->tune.photon_blocks_per_cu);
     const int aux_blocks = grid_for(sp[2]->capacity, c->num_cu * 4);
     const int prec = c->cfg.precision == QED_PREC_F64 ? 0 : 1;
     hipError_t r = launch(c, qed::K_BEGIN, a, prec, 1);
     if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON, a, prec, photon_blocks);
-    if (r == hipSuccess && emission) r = launch(c, qed::K_LEPTON, a, prec, lepton_blocks);
+    if (r == hipSuccess && emission && !binned) r = launch(c, qed::K_LEPTON, a, prec, lepton_blocks);
+    if (binned) {
+        if (r == hipSuccess) r = launch(c, qed::K_PREPASS, a, prec, lepton_blocks);
+        if (r == hipSuccess) r = launch(c, qed::K_SCAN, a, prec, 1);
+        if (r == hipSuccess) r = launch(c, qed::K_SCATTER, a, prec, lepton_blocks);
+        if (r == hipSuccess) r = launch(c, qed::K_LIGHT, a, prec, lepton_blocks);
+        if (r == hipSuccess) r = launch(c, qed::K_HEAVY, a, prec, heavy_blocks);
+    }
     if (r == hipSuccess) r = launch(c, qed::K_END, a, prec, 1);
     if (r == hipSuccess && pairs) r = launch(c, qed::K_FILL, a, prec, aux_blocks);
     if (r == hipSuccess && pairs) r = launch(c, qed::K_MOVE, a, prec, aux_blocks);
@@ -287,6 +344,8 @@ qed_status qed_get_stats(qed_ctx *c, qed_stats *out) {
         out->substeps[k] = h.substeps[k];
         out->particles[k] = h.particles[k];
     }
+    out->heavy_particles = h.heavy_particles;
+    out->heavy_substeps = h.heavy_substeps;
     out->emissions = h.emissions;
     out->pairs = h.pairs;
     out->clips = h.clips;
@@ -306,9 +365,22 @@ qed_status qed_reset_stats(qed_ctx *c) {
     h.steps = 0;
     h.substeps[0] = h.substeps[1] = h.substeps[2] = 0;
     h.particles[0] = h.particles[1] = h.particles[2] = 0;
+    h.heavy_particles = h.heavy_substeps = 0;
     h.emissions = h.pairs = h.clips = h.capped = 0;
     h.max_p_bits = 0;
     HIP_TRY(hipMemcpy(c->st, &h, sizeof(h), hipMemcpyHostToDevice));
+    return QED_OK;
+}
+
+qed_status qed_get_tuning(qed_ctx *c, qed_tuning *out) {
+    if (!c || !out) return QED_ERR_INVALID_ARG;
+    *out = c->tune;
+    return QED_OK;
+}
+
+qed_status qed_set_tuning(qed_ctx *c, const qed_tuning *t) {
+    if (!c || !t || !tuning_ok(*t)) return QED_ERR_INVALID_ARG;
+    c->tune = *t;
     return QED_OK;
 }
 
@@ -348,10 +420,15 @@ void qed_finalize(qed_ctx *c) {
     (void)hipSetDevice(c->cfg.device);
     (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    if (c->alive) (void)hipFree(c->alive);
-    if (c->hole_idx) (void)hipFree(c->hole_idx);
-    if (c->mover_idx) (void)hipFree(c->mover_idx);
-    if (c->st) (void)hipFree(c->st);
+    release(c->alive);
+    release(c->dead_idx);
+    release(c->hole_idx);
+    release(c->mover_idx);
+    for (int s = 0; s < 2; ++s) {
+        release(c->nsub[s]);
+        release(c->queue[s]);
+    }
+    release(c->st);
     delete c;
 }
 

@@ -9,20 +9,39 @@ namespace qed {
 
 typedef unsigned long long u64;
 
+// Sub-step-count bins of the binned scheduler: bin 0 holds the light particles
+// (N <= light_max), bin j >= 1 the heavy ones with floor(4 log2 N) = j - 1
+// (quarter-octave bins, so the counts in one bin differ by less than 19%).
+constexpr int kBins = 128;
+
 // Per-context device state: step bookkeeping and cumulative counters.
 struct DevState {
     u64 n0[3];        // live counts at step start (clamped to capacity)
-    u64 dead;         // photons that decayed in this step
+    u64 dead;         // photons that decayed in this step (= entries of the dead list)
     u64 ntot;         // photon count after appends (clamped), before compaction
     u64 S;            // photon count after compaction
     u64 holes;        // compaction: holes found in [0, S)
     u64 movers;       // compaction: survivors found in [S, ntot)
-    u64 substeps[3];  // cumulative particle-sub-steps per species
+    u64 heavy[2];     // binned scheduler: heavy particles per lepton species
+    u64 queue[2];     // binned scheduler: next unclaimed entry of each work queue
     u64 particles[3]; // cumulative particle-steps per species
-    u64 emissions, pairs, clips, capped, nonfinite, steps;
-    u64 max_p_bits;   // largest acceptance probability (bits of a non-negative double)
-    u64 status_bits;  // bit 0: capacity exceeded, bit 1: non-finite input
+    u64 steps;
+    // Counters updated by atomics from every block sit on their own 128-byte lines
+    // so that the L2 serves them in parallel.
+    alignas(128) u64 substeps[3];  // cumulative particle-sub-steps per species
+    alignas(128) u64 heavy_particles;  // cumulative work of the heavy-queue kernel
+    alignas(128) u64 heavy_substeps;
+    alignas(128) u64 emissions;
+    alignas(128) u64 pairs;
+    alignas(128) u64 clips;
+    alignas(128) u64 capped;
+    alignas(128) u64 nonfinite;
+    alignas(128) u64 max_p_bits;   // largest acceptance probability (bits of a non-negative double)
+    alignas(128) u64 status_bits;  // bit 0: capacity exceeded, bit 1: non-finite input
     u64 required[3];  // largest count requested per species (capacity errors)
+    uint32_t hist[2][kBins];    // per-bin counts of the current step
+    uint32_t offset[2][kBins];  // start of each heavy bin in the work queue
+    uint32_t cursor[2][kBins];  // fill position inside each bin
 };
 
 struct SpeciesDev {
@@ -46,16 +65,36 @@ struct StepArgs {
     double dt, p_max, pair_coef;
     uint64_t seed;
     uint32_t step, max_sub;
-    int emission, pairs;  // which algorithms run in this step
-    uint8_t *alive;     // photon flags, one per photon slot
-    u64 *hole_idx;      // compaction lists
+    int emission, pairs;   // which algorithms run in this step
+    uint32_t light_max;    // binned scheduler: largest N handled by the light pass
+    uint32_t chunk;        // binned scheduler: queue entries claimed per wave (multiple of 64)
+    uint8_t *alive;        // photon flags, one per photon slot
+    u64 *dead_idx;         // slots of the photons that decayed this step
+    u64 *hole_idx;         // compaction lists
     u64 *mover_idx;
+    uint32_t *nsub[2];     // binned scheduler: sub-step count per lepton slot (0: skipped)
+    uint32_t *queue[2];    // binned scheduler: heavy lepton slots sorted by bin, heaviest first
 };
 
-// Kernels of one step, in launch order, and the standalone synchrotron kernel.
-enum KernelId { K_BEGIN = 0, K_PHOTON, K_LEPTON, K_END, K_FILL, K_MOVE, K_SYNCHROTRON, K_COUNT };
+// Kernels, in launch order, and the standalone synchrotron kernel.
+enum KernelId {
+    K_BEGIN = 0,
+    K_PHOTON,
+    K_LEPTON,   // naive scheduler: one lane per lepton
+    K_PREPASS,  // binned scheduler: sub-step counts and histogram
+    K_SCAN,
+    K_SCATTER,
+    K_LIGHT,
+    K_HEAVY,
+    K_END,
+    K_FILL,
+    K_MOVE,
+    K_SYNCHROTRON,
+    K_COUNT
+};
 
-// Enqueue one kernel of a step (precision: 0 = F64, 1 = MIXED).
+// Enqueue one kernel of a step (precision: 0 = F64, 1 = MIXED).  blocks is the
+// grid size in x; lepton kernels add y = 2 (one row per lepton species).
 hipError_t launch_kernel(int id, const StepArgs &a, int precision, int blocks, hipStream_t s);
 
 // Enqueue the elementwise synchrotron kernel (dtype: 0 = float, 1 = double).

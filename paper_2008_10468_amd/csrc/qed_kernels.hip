@@ -1,33 +1,42 @@
 // Kernels of the QED event generator for gfx950 (wave64).
 //
 // One global step (Sec. 2.2) is the sequence
-//   k_begin   snapshot the live counts (particles appended later in the step wait
-//             for the next step);
-//   k_photon  Algorithm 2 for every photon: straight-line sub-steps, pair creation
-//             with density eq. (2); pairs are appended to the e-/e+ buffers and the
-//             photon is flagged dead;
-//   k_lepton  Algorithm 1 for every electron and positron: Boris sub-steps,
-//             emission with density eq. (1); photons are appended with recoil on
-//             the parent;
-//   k_end     clamp counts to capacity (reporting overflow) and size the
-//             photon compaction;
+//   k_begin    snapshot the live counts (particles appended later in the step wait
+//              for the next step) and clear the per-step counters;
+//   k_photon   Algorithm 2 for every photon: straight-line sub-steps, pair creation
+//              with density eq. (2); pairs are appended to the e-/e+ buffers, the
+//              photon is flagged dead and its slot is put on the dead list;
+//   Algorithm 1 for every electron and positron (Boris sub-steps, emission with
+//   density eq. (1), recoil, photons appended), scheduled one of two ways:
+//     naive:   k_lepton, one lane per particle in buffer order;
+//     binned:  k_prepass computes each particle's sub-step count N and a histogram
+//              over quarter-octave bins of N; k_scan and k_scatter build a work
+//              queue of the heavy particles (N > light_max) sorted by bin, heaviest
+//              first; k_light runs the light particles in buffer order; k_heavy is
+//              a persistent kernel whose waves claim chunks of the queue, so the
+//              64 lanes of a wave carry nearly the same N;
+//   k_end      clamp counts to capacity (reporting overflow), size the compaction;
 //   k_fill / k_move  fill the holes left by decayed photons in [0, S) with the
-//             survivors found in [S, n), so the photon buffer is dense again.
+//              survivors found in [S, n): both scans are O(decays).
 // Appends use one atomic per wavefront: the accepting lanes are found with a
 // ballot, the lowest one reserves popcount slots and each lane takes its rank.
-// The sub-step count of a particle comes from the bounds f(b) of Sec. 3.1.1,
-// evaluated in double from the start-of-step momentum and field.
+// Random numbers are keyed by (seed, id, step, sub-step), so every schedule gives
+// the same per-particle result.  The sub-step count of a particle comes from the
+// bounds f(b) of Sec. 3.1.1, evaluated in double at the step start.
 #include "qed_device.hpp"
 #include "qed_internal.hpp"
 #include "qed_synchro.hpp"
-
-#include <type_traits>
 
 namespace qed {
 
 namespace {
 
 constexpr int kBlock = 256;
+
+// For chi_g below this value the pair density of eq. (2) is below 1e-40 for every
+// candidate x (z_p >= 8/(3 chi_g) > 120), so no uniform y in (0,1) can accept it;
+// such photons only move, which gives the same result as sampling.
+constexpr double kQuietPhotonChi = 0.0222;
 
 __device__ __forceinline__ u64 lanemask_lt() {
     const int l = __lane_id();
@@ -56,27 +65,89 @@ __device__ __forceinline__ bool finite3(R a, R b, R c) {
 template <class R>
 struct Tally {
     u64 substeps = 0;
-    uint32_t events = 0, clips = 0, capped = 0, nonfinite = 0;
+    uint32_t events = 0, clips = 0, capped = 0, nonfinite = 0, particles = 0;
     R max_p = 0;
 };
 
+// Block-wide reduction of the tallies, then one atomic per counter and block.
+// Every thread of the block must call it.
 template <class R>
-__device__ __forceinline__ void flush_tally(const Tally<R> &t, DevState *st, int species) {
-    const u64 sub = wave_sum(t.substeps);
-    const uint32_t ev = wave_sum(t.events), cl = wave_sum(t.clips), cp = wave_sum(t.capped),
-                   nf = wave_sum(t.nonfinite);
+__device__ __forceinline__ void flush_tally(const Tally<R> &t, DevState *st, int species,
+                                            bool heavy = false) {
+    __shared__ u64 red[kBlock / 64][8];
+    const u64 v[7] = {wave_sum(t.substeps), (u64)wave_sum(t.events), (u64)wave_sum(t.clips),
+                      (u64)wave_sum(t.capped), (u64)wave_sum(t.nonfinite),
+                      (u64)wave_sum(t.particles), 0};
     const double mp = wave_max((double)t.max_p);
+    const int wv = threadIdx.x / 64;
+    __syncthreads();
     if (__lane_id() == 0) {
-        if (sub) atomicAdd(&st->substeps[species], sub);
-        if (ev) atomicAdd(species == 2 ? &st->pairs : &st->emissions, (u64)ev);
-        if (cl) atomicAdd(&st->clips, (u64)cl);
-        if (cp) atomicAdd(&st->capped, (u64)cp);
-        if (nf) {
-            atomicAdd(&st->nonfinite, (u64)nf);
+        for (int k = 0; k < 6; ++k) red[wv][k] = v[k];
+        red[wv][7] = (u64)__double_as_longlong(mp);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 tot[6] = {0, 0, 0, 0, 0, 0}, mb = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            for (int k = 0; k < 6; ++k) tot[k] += red[w][k];
+            mb = red[w][7] > mb ? red[w][7] : mb;
+        }
+        if (tot[0]) atomicAdd(&st->substeps[species], tot[0]);
+        if (tot[1]) atomicAdd(species == 2 ? &st->pairs : &st->emissions, tot[1]);
+        if (tot[2]) atomicAdd(&st->clips, tot[2]);
+        if (tot[3]) atomicAdd(&st->capped, tot[3]);
+        if (tot[4]) {
+            atomicAdd(&st->nonfinite, tot[4]);
             atomicOr(&st->status_bits, 2ull);
         }
-        if (mp > 0.0) atomicMax(&st->max_p_bits, (u64)__double_as_longlong(mp));
+        if (heavy) {
+            if (tot[5]) atomicAdd(&st->heavy_particles, tot[5]);
+            if (tot[0]) atomicAdd(&st->heavy_substeps, tot[0]);
+        }
+        if (mb) atomicMax(&st->max_p_bits, mb);
     }
+}
+
+// Children of one wave staged in LDS and written out with one atomic per flush.
+template <class R>
+struct ChildBuf {
+    double x[64], y[64], z[64];
+    R px[64], py[64], pz[64], w[64];
+    uint64_t id[64], parent[64];
+    uint32_t count;
+};
+
+// Write the staged children to the species' tail.  Called by the active lanes of
+// a wave (any subset); they share the writes.
+template <class R>
+__device__ __forceinline__ void flush_children(ChildBuf<R> &cb, const SpeciesDev &dst) {
+    __syncwarp();
+    const uint32_t n = cb.count;
+    if (n == 0) return;
+    const u64 exec = __ballot(1);
+    const int leader = __ffsll((long long)exec) - 1;
+    const uint32_t nact = (uint32_t)__popcll(exec);
+    const uint32_t me = (uint32_t)__popcll(exec & lanemask_lt());
+    u64 base = 0;
+    if (__lane_id() == leader) base = atomicAdd(dst.n, (u64)n);
+    base = __shfl(base, leader);
+    for (uint32_t e = me; e < n; e += nact) {
+        const u64 slot = base + e;
+        if (slot < dst.cap) {
+            dst.x[slot] = cb.x[e];
+            dst.y[slot] = cb.y[e];
+            dst.z[slot] = cb.z[e];
+            ((R *)dst.ux)[slot] = cb.px[e];
+            ((R *)dst.uy)[slot] = cb.py[e];
+            ((R *)dst.uz)[slot] = cb.pz[e];
+            ((R *)dst.w)[slot] = cb.w[e];
+            dst.id[slot] = cb.id[e];
+            if (dst.parent) dst.parent[slot] = cb.parent[e];
+        }
+    }
+    __syncwarp();
+    cb.count = 0;
+    __syncwarp();
 }
 
 // Random pair (x, y) of sub-step k.  Float path: one Philox block serves two
@@ -118,47 +189,69 @@ __device__ __forceinline__ double chi_sub(double ux, double uy, double uz, doubl
     return chi_def(g, ux, uy, uz, ex, ey, ez, bx, by, bz);
 }
 
-// ---------------------------------------------------------------------------
-// Algorithm 1 for one electron (species 0, q = -1) or positron (species 1, q = +1).
-// ---------------------------------------------------------------------------
 template <class R>
-__device__ __forceinline__ void lepton_one(const StepArgs &a, int s, u64 i, const SynTable<R> &tab,
-                                           Tally<R> &tl) {
+struct Lepton {
+    R ux, uy, uz, ex, ey, ez, bx, by, bz;
+};
+
+template <class R>
+__device__ __forceinline__ Lepton<R> load_lepton(const StepArgs &a, int s, u64 i) {
     const SpeciesDev &sp = a.sp[s];
     const FieldDev &fl = a.fl[s];
-    const SpeciesDev &ph = a.sp[2];
-    R ux = ((const R *)sp.ux)[i], uy = ((const R *)sp.uy)[i], uz = ((const R *)sp.uz)[i];
     const u64 f = i * fl.stride;
-    const R ex = ((const R *)fl.ex)[f], ey = ((const R *)fl.ey)[f], ez = ((const R *)fl.ez)[f];
-    const R bx = ((const R *)fl.bx)[f], by = ((const R *)fl.by)[f], bz = ((const R *)fl.bz)[f];
-    if (!(finite3(ux, uy, uz) && finite3(ex, ey, ez) && finite3(bx, by, bz))) {
+    Lepton<R> p;
+    p.ux = ((const R *)sp.ux)[i];
+    p.uy = ((const R *)sp.uy)[i];
+    p.uz = ((const R *)sp.uz)[i];
+    p.ex = ((const R *)fl.ex)[f];
+    p.ey = ((const R *)fl.ey)[f];
+    p.ez = ((const R *)fl.ez)[f];
+    p.bx = ((const R *)fl.bx)[f];
+    p.by = ((const R *)fl.by)[f];
+    p.bz = ((const R *)fl.bz)[f];
+    return p;
+}
+
+// Algorithm 1, line 1: the sub-step count from the bound at the step start
+// (double).  0 for non-finite input (the particle is left alone).
+template <class R>
+__device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<R> &p, Tally<R> &tl) {
+    if (!(finite3(p.ux, p.uy, p.uz) && finite3(p.ex, p.ey, p.ez) && finite3(p.bx, p.by, p.bz))) {
         tl.nonfinite++;
-        if (sp.events) sp.events[i] = 0;
-        return;
+        return 0;
     }
-    const uint64_t pid = sp.id[i];
-    const R w = ((const R *)sp.w)[i];
-    // Algorithm 1, line 1: sub-step from the bound at the step start (double).
-    const double gd = sqrt(1.0 + (double)ux * ux + (double)uy * uy + (double)uz * uz);
-    const double chi0 = chi_def(gd, ux, uy, uz, ex, ey, ez, bx, by, bz);
+    const double gd = sqrt(1.0 + (double)p.ux * p.ux + (double)p.uy * p.uy + (double)p.uz * p.uz);
+    const double chi0 = chi_def(gd, p.ux, p.uy, p.uz, p.ex, p.ey, p.ez, p.bx, p.by, p.bz);
     bool capped;
     const uint32_t N = nsub(bound_emission(chi0, gd, a.dt), a.p_max, a.max_sub, &capped);
     tl.capped += capped;
+    return N;
+}
+
+// Algorithm 1, lines 2-7, for one electron (s = 0, q = -1) or positron (s = 1,
+// q = +1) with N >= 1 sub-steps.  s is uniform across the wave.
+template <class R>
+__device__ __forceinline__ void lepton_run(const StepArgs &a, int s, u64 i, uint32_t N, Lepton<R> p,
+                                           const SynTable<R> &tab, ChildBuf<R> &cb, Tally<R> &tl) {
+    const SpeciesDev &sp = a.sp[s];
+    const SpeciesDev &ph = a.sp[2];
+    const uint64_t pid = sp.id[i];
     const double st = a.dt / (double)N;
     const R hq = (R)((s == 0 ? -0.5 : 0.5) * st);
-    const R hex = hq * ex, hey = hq * ey, hez = hq * ez;
-    const R e2 = ex * ex + ey * ey + ez * ez;
+    const R hex = hq * p.ex, hey = hq * p.ey, hez = hq * p.ez;
+    const R e2 = p.ex * p.ex + p.ey * p.ey + p.ez * p.ez;
     const R str = (R)st;
-    // c b = kcb * chi / gamma with c = sqrt(3) alpha st / (pi gamma), b = 3 chi / 2
+    // c b = kcb chi / gamma, with c = sqrt(3) alpha st / (pi gamma) and b = 3 chi / 2
     const R kcb = (R)(1.5 * kSqrt3 * kAlpha / kPi * st);
     const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
     const uint32_t klo = (uint32_t)a.seed, khi = (uint32_t)(a.seed >> 32);
+    R ux = p.ux, uy = p.uy, uz = p.uz;
     R dx = 0, dy = 0, dz = 0;
     uint32_t nev = 0;
     Draw<R> draw;
     for (uint32_t k = 0; k < N; ++k) {
         // line 3: Boris push and move
-        boris<R>(ux, uy, uz, hex, hey, hez, hq, bx, by, bz);
+        boris<R>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
         const R u2 = ux * ux + uy * uy + uz * uz;
         const R g = sqrt_(R(1) + u2);
         const R ig = rcp(g);
@@ -167,7 +260,7 @@ __device__ __forceinline__ void lepton_one(const StepArgs &a, int s, u64 i, cons
         dy += uy * vs;
         dz += uz * vs;
         // line 4
-        const R chi = chi_sub(ux, uy, uz, g, ex, ey, ez, bx, by, bz, e2);
+        const R chi = chi_sub(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
         // line 5
         R x, y;
         draw.get(k, idlo, idhi, a.step, klo, khi, x, y);
@@ -183,30 +276,28 @@ __device__ __forceinline__ void lepton_one(const StepArgs &a, int s, u64 i, cons
         tl.max_p = fmax(tl.max_p, pm);
         tl.clips += pm > R(1);
         const bool acc = y < pm;
-        // line 7: append the photon (one atomic per wave)
+        // line 7: stage the photon in the wave's LDS buffer, recoil on the parent
         const u64 m = __ballot(acc);
         if (m) {
-            const int leader = __ffsll((long long)m) - 1;
-            u64 base = 0;
-            if (__lane_id() == leader) base = atomicAdd(ph.n, (u64)__popcll(m));
-            base = __shfl(base, leader);
+            const uint32_t c = (uint32_t)__popcll(m);
+            __syncwarp();
+            if (cb.count + c > 64) flush_children(cb, ph);
+            const uint32_t n0 = cb.count;
             if (acc) {
-                const u64 slot = base + (u64)__popcll(m & lanemask_lt());
+                const uint32_t e = n0 + (uint32_t)__popcll(m & lanemask_lt());
                 const R umag = sqrt_(u2);
                 const R inv = umag > R(0) ? rcp(umag) : R(0);
                 const R eph = x3 * g * inv;
-                if (slot < ph.cap) {
-                    ph.x[slot] = sp.x[i] + (double)dx;
-                    ph.y[slot] = sp.y[i] + (double)dy;
-                    ph.z[slot] = sp.z[i] + (double)dz;
-                    ((R *)ph.ux)[slot] = ux * eph;
-                    ((R *)ph.uy)[slot] = uy * eph;
-                    ((R *)ph.uz)[slot] = uz * eph;
-                    ((R *)ph.w)[slot] = w;
-                    ph.id[slot] = child_id(a.seed, pid, a.step, k, 0);
-                    if (ph.parent) ph.parent[slot] = pid;
-                }
-                // recoil: gamma' = (1 - delta) gamma along the same direction
+                cb.x[e] = sp.x[i] + (double)dx;
+                cb.y[e] = sp.y[i] + (double)dy;
+                cb.z[e] = sp.z[i] + (double)dz;
+                cb.px[e] = ux * eph;
+                cb.py[e] = uy * eph;
+                cb.pz[e] = uz * eph;
+                cb.w[e] = ((const R *)sp.w)[i];
+                cb.id[e] = child_id(a.seed, pid, a.step, k, 0);
+                cb.parent[e] = pid;
+                // gamma' = (1 - delta) gamma, same direction
                 const R g1 = omx3 * g;
                 const R u1 = sqrt_(fmax(g1 * g1 - R(1), R(0)));
                 const R sc = u1 * inv;
@@ -215,6 +306,9 @@ __device__ __forceinline__ void lepton_one(const StepArgs &a, int s, u64 i, cons
                 uz *= sc;
                 nev++;
             }
+            __syncwarp();
+            cb.count = n0 + c;
+            __syncwarp();
         }
     }
     ((R *)sp.ux)[i] = ux;
@@ -233,7 +327,7 @@ __device__ __forceinline__ void lepton_one(const StepArgs &a, int s, u64 i, cons
 // ---------------------------------------------------------------------------
 template <class R>
 __device__ __forceinline__ void photon_one(const StepArgs &a, u64 i, const SynTable<R> &tab,
-                                           Tally<R> &tl, uint32_t &dead_out) {
+                                           Tally<R> &tl) {
     const SpeciesDev &sp = a.sp[2];
     const FieldDev &fl = a.fl[2];
     const SpeciesDev &el = a.sp[0];
@@ -248,8 +342,6 @@ __device__ __forceinline__ void photon_one(const StepArgs &a, u64 i, const SynTa
         if (sp.events) sp.events[i] = 0;
         return;
     }
-    const uint64_t pid = sp.id[i];
-    const R w = ((const R *)sp.w)[i];
     const double eps = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
     // the field and k are frozen, so chi_g is the same at every sub-step
     const double chi = chi_def(eps, kx, ky, kz, ex, ey, ez, bx, by, bz);
@@ -262,77 +354,93 @@ __device__ __forceinline__ void photon_one(const StepArgs &a, u64 i, const SynTa
     const double st = a.dt / (double)N;
     const R inv = eps > 0.0 ? (R)(1.0 / eps) : R(0);
     const R dirx = kx * inv, diry = ky * inv, dirz = kz * inv;
-    // P_p(x) = alpha st sqrt(3)/(2 pi) (chi/eps) (G(z) - x(1-x) F(z)),  z = 2/(3 chi x (1-x))
-    const R A = eps > 0.0 ? (R)(kAlpha * st * kSqrt3 / (2.0 * kPi) * chi / eps) : R(0);
-    const R chir = (R)chi;
-    const R epsr = (R)eps;
     const R str = (R)st;
-    const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
-    const uint32_t klo = (uint32_t)a.seed, khi = (uint32_t)(a.seed >> 32);
     R dx = 0, dy = 0, dz = 0;
     bool dead = false;
-    uint32_t used = 0;
-    Draw<R> draw;
-    for (uint32_t k = 0; k < N && !dead; ++k) {
-        used = k + 1;
-        // line 3: move at the speed of light
-        dx += dirx * str;
-        dy += diry * str;
-        dz += dirz * str;
-        // lines 5-6
-        R x, y;
-        draw.get(k, idlo, idhi, a.step, klo, khi, x, y);
-        const R xx = x * (R(1) - x);
-        const R z = R(2.0 / 3.0) * rcp(chir * xx);
-        R F, G;
-        syn_eval(z, tab, F, G);
-        const R pp = A * (G - xx * F);
-        tl.max_p = fmax(tl.max_p, pp);
-        tl.clips += pp > R(1);
-        const bool acc = y < pp;
-        // lines 7-8: electron with x eps, positron with (1-x) eps, along k
-        const u64 m = __ballot(acc);
-        if (m) {
-            const int leader = __ffsll((long long)m) - 1;
-            u64 be = 0, bp = 0;
-            if (__lane_id() == leader) {
-                be = atomicAdd(el.n, (u64)__popcll(m));
-                bp = atomicAdd(po.n, (u64)__popcll(m));
-            }
-            be = __shfl(be, leader);
-            bp = __shfl(bp, leader);
-            if (acc) {
-                const u64 r = (u64)__popcll(m & lanemask_lt());
-                const double px = sp.x[i] + (double)dx, py = sp.y[i] + (double)dy,
-                             pz = sp.z[i] + (double)dz;
-                const R ge = x * epsr, gp = (R(1) - x) * epsr;
-                const R ue = sqrt_(fmax(ge * ge - R(1), R(0)));
-                const R up = sqrt_(fmax(gp * gp - R(1), R(0)));
-                if (be + r < el.cap) {
-                    const u64 j = be + r;
-                    el.x[j] = px;
-                    el.y[j] = py;
-                    el.z[j] = pz;
-                    ((R *)el.ux)[j] = ue * dirx;
-                    ((R *)el.uy)[j] = ue * diry;
-                    ((R *)el.uz)[j] = ue * dirz;
-                    ((R *)el.w)[j] = w;
-                    el.id[j] = child_id(a.seed, pid, a.step, k, 0);
-                    if (el.parent) el.parent[j] = pid;
+    uint32_t used = N;
+    if (!(chi >= kQuietPhotonChi)) {
+        // no candidate can be accepted: the photon only moves (line 3)
+        for (uint32_t k = 0; k < N; ++k) {
+            dx += dirx * str;
+            dy += diry * str;
+            dz += dirz * str;
+        }
+    } else {
+        // P_p(x) = alpha st sqrt(3)/(2 pi) (chi/eps) (G(z) - x(1-x) F(z)),
+        // z = 2/(3 chi x (1-x))
+        const R A = (R)(kAlpha * st * kSqrt3 / (2.0 * kPi) * chi / eps);
+        const R chir = (R)chi;
+        const R epsr = (R)eps;
+        const uint64_t pid = sp.id[i];
+        const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
+        const uint32_t klo = (uint32_t)a.seed, khi = (uint32_t)(a.seed >> 32);
+        Draw<R> draw;
+        for (uint32_t k = 0; k < N && !dead; ++k) {
+            used = k + 1;
+            // line 3: move at the speed of light
+            dx += dirx * str;
+            dy += diry * str;
+            dz += dirz * str;
+            // lines 5-6
+            R x, y;
+            draw.get(k, idlo, idhi, a.step, klo, khi, x, y);
+            const R xx = x * (R(1) - x);
+            const R z = R(2.0 / 3.0) * rcp(chir * xx);
+            R F, G;
+            syn_eval(z, tab, F, G);
+            const R pp = A * (G - xx * F);
+            tl.max_p = fmax(tl.max_p, pp);
+            tl.clips += pp > R(1);
+            const bool acc = y < pp;
+            // lines 7-8: electron with x eps, positron with (1-x) eps, along k; delete
+            const u64 m = __ballot(acc);
+            if (m) {
+                const int leader = __ffsll((long long)m) - 1;
+                u64 be = 0, bp = 0, bd = 0;
+                if (__lane_id() == leader) {
+                    const u64 c = (u64)__popcll(m);
+                    be = atomicAdd(el.n, c);
+                    bp = atomicAdd(po.n, c);
+                    bd = atomicAdd(&a.st->dead, c);
                 }
-                if (bp + r < po.cap) {
-                    const u64 j = bp + r;
-                    po.x[j] = px;
-                    po.y[j] = py;
-                    po.z[j] = pz;
-                    ((R *)po.ux)[j] = up * dirx;
-                    ((R *)po.uy)[j] = up * diry;
-                    ((R *)po.uz)[j] = up * dirz;
-                    ((R *)po.w)[j] = w;
-                    po.id[j] = child_id(a.seed, pid, a.step, k, 1);
-                    if (po.parent) po.parent[j] = pid;
+                be = __shfl(be, leader);
+                bp = __shfl(bp, leader);
+                bd = __shfl(bd, leader);
+                if (acc) {
+                    const u64 r = (u64)__popcll(m & lanemask_lt());
+                    a.dead_idx[bd + r] = i;
+                    const double px = sp.x[i] + (double)dx, py = sp.y[i] + (double)dy,
+                                 pz = sp.z[i] + (double)dz;
+                    const R w = ((const R *)sp.w)[i];
+                    const R ge = x * epsr, gp = (R(1) - x) * epsr;
+                    const R ue = sqrt_(fmax(ge * ge - R(1), R(0)));
+                    const R up = sqrt_(fmax(gp * gp - R(1), R(0)));
+                    if (be + r < el.cap) {
+                        const u64 j = be + r;
+                        el.x[j] = px;
+                        el.y[j] = py;
+                        el.z[j] = pz;
+                        ((R *)el.ux)[j] = ue * dirx;
+                        ((R *)el.uy)[j] = ue * diry;
+                        ((R *)el.uz)[j] = ue * dirz;
+                        ((R *)el.w)[j] = w;
+                        el.id[j] = child_id(a.seed, pid, a.step, k, 0);
+                        if (el.parent) el.parent[j] = pid;
+                    }
+                    if (bp + r < po.cap) {
+                        const u64 j = bp + r;
+                        po.x[j] = px;
+                        po.y[j] = py;
+                        po.z[j] = pz;
+                        ((R *)po.ux)[j] = up * dirx;
+                        ((R *)po.uy)[j] = up * diry;
+                        ((R *)po.uz)[j] = up * dirz;
+                        ((R *)po.w)[j] = w;
+                        po.id[j] = child_id(a.seed, pid, a.step, k, 1);
+                        if (po.parent) po.parent[j] = pid;
+                    }
+                    dead = true;
                 }
-                dead = true;
             }
         }
     }
@@ -343,26 +451,156 @@ __device__ __forceinline__ void photon_one(const StepArgs &a, u64 i, const SynTa
     if (sp.events) sp.events[i] = dead ? 1u : 0u;
     tl.substeps += used;
     tl.events += dead;
-    dead_out += dead;
+}
+
+// Bin of a sub-step count (see kBins).
+__device__ __forceinline__ int nbin(uint32_t N, uint32_t light_max) {
+    if (N <= light_max) return 0;
+    const int b = 1 + (int)floorf(4.0f * __log2f((float)N));
+    return b < kBins - 1 ? b : kBins - 1;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+// LDS of the lepton kernels: the coefficient table and one child buffer per wave.
+template <class R>
+struct LeptonLds {
+    SynTable<R> tab;
+    ChildBuf<R> cb[kBlock / 64];
+};
+
+template <class R>
+__device__ __forceinline__ ChildBuf<R> &lepton_lds_init(LeptonLds<R> &L) {
+    ChildBuf<R> &cb = L.cb[threadIdx.x / 64];
+    if (__lane_id() == 0) cb.count = 0;
+    syn_stage(L.tab);  // ends with a block barrier
+    return cb;
 }
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_lepton(StepArgs a) {
-    __shared__ SynTable<R> tab;
-    syn_stage(tab);
-    const u64 ne = a.st->n0[0], np = a.st->n0[1], total = ne + np;
+    __shared__ LeptonLds<R> L;
+    ChildBuf<R> &cb = lepton_lds_init(L);
+    const int s = blockIdx.y;
+    const u64 n = a.st->n0[s];
     Tally<R> t;
-    u64 sub_pos = 0;  // positron share of t.substeps
-    for (u64 g = (u64)blockIdx.x * kBlock + threadIdx.x; g < total; g += (u64)gridDim.x * kBlock) {
-        const int s = g < ne ? 0 : 1;
-        const u64 before = t.substeps;
-        lepton_one<R>(a, s, s ? g - ne : g, tab, t);
-        if (s) sub_pos += t.substeps - before;
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
+        const Lepton<R> p = load_lepton<R>(a, s, i);
+        const uint32_t N = lepton_nsub(a, p, t);
+        if (N)
+            lepton_run<R>(a, s, i, N, p, L.tab, cb, t);
+        else if (a.sp[s].events)
+            a.sp[s].events[i] = 0;
     }
-    const u64 sp = wave_sum(sub_pos);
-    if (__lane_id() == 0 && sp) atomicAdd(&a.st->substeps[1], sp);
-    t.substeps -= sub_pos;
-    flush_tally(t, a.st, 0);
+    flush_children(cb, a.sp[2]);
+    flush_tally(t, a.st, s);
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_prepass(StepArgs a) {
+    __shared__ uint32_t h[kBins];
+    const int s = blockIdx.y;
+    for (int b = threadIdx.x; b < kBins; b += kBlock) h[b] = 0;
+    __syncthreads();
+    const u64 n = a.st->n0[s];
+    Tally<R> t;
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
+        const Lepton<R> p = load_lepton<R>(a, s, i);
+        const uint32_t N = lepton_nsub(a, p, t);
+        a.nsub[s][i] = N;
+        if (N)
+            atomicAdd(&h[nbin(N, a.light_max)], 1u);
+        else if (a.sp[s].events)
+            a.sp[s].events[i] = 0;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBins; b += kBlock)
+        if (h[b]) atomicAdd(&a.st->hist[s][b], h[b]);
+    // only the skipped (non-finite) and capped counts are reported here
+    t.substeps = 0;
+    flush_tally(t, a.st, s);
+}
+
+// One block: heavy bins laid out heaviest first.
+__global__ void k_scan(StepArgs a) {
+    if (threadIdx.x < 2) {
+        const int s = threadIdx.x;
+        uint32_t off = 0;
+        for (int b = kBins - 1; b >= 1; --b) {
+            a.st->offset[s][b] = off;
+            a.st->cursor[s][b] = 0;
+            off += a.st->hist[s][b];
+        }
+        a.st->heavy[s] = off;
+        a.st->queue[s] = 0;
+    }
+}
+
+// Heavy slots into their bins: block-local counts in LDS, one global atomic per
+// (block, bin), LDS ranks inside the block.
+__global__ __launch_bounds__(kBlock) void k_scatter(StepArgs a) {
+    __shared__ uint32_t cnt[kBins], base[kBins];
+    const int s = blockIdx.y;
+    const u64 n = a.st->n0[s];
+    for (u64 i0 = (u64)blockIdx.x * kBlock; i0 < n; i0 += (u64)gridDim.x * kBlock) {
+        for (int b = threadIdx.x; b < kBins; b += kBlock) cnt[b] = 0;
+        __syncthreads();
+        const u64 i = i0 + threadIdx.x;
+        int bin = 0;
+        uint32_t rank = 0;
+        if (i < n) {
+            const uint32_t N = a.nsub[s][i];
+            bin = N ? nbin(N, a.light_max) : 0;
+            if (bin) rank = atomicAdd(&cnt[bin], 1u);
+        }
+        __syncthreads();
+        for (int b = threadIdx.x; b < kBins; b += kBlock)
+            if (cnt[b]) base[b] = atomicAdd(&a.st->cursor[s][b], cnt[b]);
+        __syncthreads();
+        if (bin) a.queue[s][a.st->offset[s][bin] + base[bin] + rank] = (uint32_t)i;
+        __syncthreads();
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_light(StepArgs a) {
+    __shared__ LeptonLds<R> L;
+    ChildBuf<R> &cb = lepton_lds_init(L);
+    const int s = blockIdx.y;
+    const u64 n = a.st->n0[s];
+    Tally<R> t;
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
+        const uint32_t N = a.nsub[s][i];
+        if (N >= 1 && N <= a.light_max) lepton_run<R>(a, s, i, N, load_lepton<R>(a, s, i), L.tab, cb, t);
+    }
+    flush_children(cb, a.sp[2]);
+    flush_tally(t, a.st, s);
+}
+
+// Persistent: each wave claims chunk consecutive queue entries at a time.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_heavy(StepArgs a) {
+    __shared__ LeptonLds<R> L;
+    ChildBuf<R> &cb = lepton_lds_init(L);
+    const int s = blockIdx.y;
+    const u64 H = a.st->heavy[s];
+    const uint32_t chunk = a.chunk;
+    Tally<R> t;
+    for (;;) {
+        u64 base = 0;
+        if (__lane_id() == 0) base = atomicAdd(&a.st->queue[s], (u64)chunk);
+        base = __shfl(base, 0);
+        if (base >= H) break;
+        const u64 end = base + chunk < H ? base + chunk : H;
+        for (u64 j = base + __lane_id(); j < end; j += 64) {
+            const u64 i = a.queue[s][j];
+            lepton_run<R>(a, s, i, a.nsub[s][i], load_lepton<R>(a, s, i), L.tab, cb, t);
+            t.particles++;
+        }
+    }
+    flush_children(cb, a.sp[2]);
+    flush_tally(t, a.st, s, true);
 }
 
 template <class R>
@@ -371,22 +609,21 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
     syn_stage(tab);
     const u64 n = a.st->n0[2];
     Tally<R> t;
-    uint32_t dead = 0;
     for (u64 g = (u64)blockIdx.x * kBlock + threadIdx.x; g < n; g += (u64)gridDim.x * kBlock)
-        photon_one<R>(a, g, tab, t, dead);
+        photon_one<R>(a, g, tab, t);
     flush_tally(t, a.st, 2);
-    const uint32_t d = wave_sum(dead);
-    if (__lane_id() == 0 && d) atomicAdd(&a.st->dead, (u64)d);
 }
 
 __global__ void k_begin(StepArgs a) {
+    DevState *st = a.st;
+    for (int k = threadIdx.x; k < 2 * kBins; k += blockDim.x) st->hist[k / kBins][k % kBins] = 0;
     if (threadIdx.x == 0) {
         for (int s = 0; s < 3; ++s) {
             const u64 n = *a.sp[s].n;
-            a.st->n0[s] = n < a.sp[s].cap ? n : a.sp[s].cap;
-            if (s < 2 ? a.emission : a.pairs) a.st->particles[s] += a.st->n0[s];
+            st->n0[s] = n < a.sp[s].cap ? n : a.sp[s].cap;
+            if (s < 2 ? a.emission : a.pairs) st->particles[s] += st->n0[s];
         }
-        a.st->dead = 0;
+        st->dead = 0;
     }
 }
 
@@ -410,21 +647,28 @@ __global__ void k_end(StepArgs a) {
     }
 }
 
-// Collect holes (decayed photons) below S and survivors at or above S.
+// Holes: decayed slots below S (from the dead list).  Movers: live slots in
+// [S, ntot) (a slot there is live if it was appended this step or survived).
 __global__ __launch_bounds__(kBlock) void k_fill(StepArgs a) {
     const DevState *st = a.st;
-    if (st->dead == 0) return;
-    const u64 ntot = st->ntot, S = st->S, n0 = st->n0[2];
-    for (u64 p0 = (u64)blockIdx.x * kBlock; p0 < ntot; p0 += (u64)gridDim.x * kBlock) {
-        const u64 p = p0 + threadIdx.x;
-        const bool in = p < ntot;
-        const bool dead = in && p < n0 && a.alive[p] == 0;
-        const bool hole = in && p < S && dead;
-        const bool mover = in && p >= S && !dead;
+    const u64 D = st->dead;
+    if (D == 0) return;
+    const u64 S = st->S, n0 = st->n0[2];
+    // work items: D dead-list entries, then the D slots of [S, ntot)
+    for (u64 t0 = (u64)blockIdx.x * kBlock; t0 < 2 * D; t0 += (u64)gridDim.x * kBlock) {
+        const u64 t = t0 + threadIdx.x;
+        bool hole = false, mover = false;
+        u64 p = 0;
+        if (t < D) {
+            p = a.dead_idx[t];
+            hole = p < S;
+        } else if (t < 2 * D) {
+            p = S + (t - D);
+            mover = p >= n0 || a.alive[p] != 0;
+        }
         const u64 mh = __ballot(hole), mm = __ballot(mover);
-        const int lane = __lane_id();
         u64 bh = 0, bm = 0;
-        if (lane == 0) {
+        if (__lane_id() == 0) {
             if (mh) bh = atomicAdd(&a.st->holes, (u64)__popcll(mh));
             if (mm) bm = atomicAdd(&a.st->movers, (u64)__popcll(mm));
         }
@@ -484,42 +728,30 @@ __global__ __launch_bounds__(kBlock) void k_synchrotron(const R *__restrict__ x,
     }
 }
 
+template <class R>
+hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
+    const dim3 blk(kBlock), g1(blocks), g2(blocks, 2);
+    switch (id) {
+        case K_BEGIN: hipLaunchKernelGGL(k_begin, dim3(1), dim3(256), 0, s, a); break;
+        case K_PHOTON: hipLaunchKernelGGL(k_photon<R>, g1, blk, 0, s, a); break;
+        case K_LEPTON: hipLaunchKernelGGL(k_lepton<R>, g2, blk, 0, s, a); break;
+        case K_PREPASS: hipLaunchKernelGGL(k_prepass<R>, g2, blk, 0, s, a); break;
+        case K_SCAN: hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, a); break;
+        case K_SCATTER: hipLaunchKernelGGL(k_scatter, g2, blk, 0, s, a); break;
+        case K_LIGHT: hipLaunchKernelGGL(k_light<R>, g2, blk, 0, s, a); break;
+        case K_HEAVY: hipLaunchKernelGGL(k_heavy<R>, g2, blk, 0, s, a); break;
+        case K_END: hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, s, a); break;
+        case K_FILL: hipLaunchKernelGGL(k_fill, g1, blk, 0, s, a); break;
+        case K_MOVE: hipLaunchKernelGGL(k_move<R>, g1, blk, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_kernel(int id, const StepArgs &a, int precision, int blocks, hipStream_t s) {
-    const bool f64 = precision == 0;
-    switch (id) {
-        case K_BEGIN:
-            hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, a);
-            break;
-        case K_PHOTON:
-            if (f64)
-                hipLaunchKernelGGL(k_photon<double>, dim3(blocks), dim3(kBlock), 0, s, a);
-            else
-                hipLaunchKernelGGL(k_photon<float>, dim3(blocks), dim3(kBlock), 0, s, a);
-            break;
-        case K_LEPTON:
-            if (f64)
-                hipLaunchKernelGGL(k_lepton<double>, dim3(blocks), dim3(kBlock), 0, s, a);
-            else
-                hipLaunchKernelGGL(k_lepton<float>, dim3(blocks), dim3(kBlock), 0, s, a);
-            break;
-        case K_END:
-            hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, s, a);
-            break;
-        case K_FILL:
-            hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kBlock), 0, s, a);
-            break;
-        case K_MOVE:
-            if (f64)
-                hipLaunchKernelGGL(k_move<double>, dim3(blocks), dim3(kBlock), 0, s, a);
-            else
-                hipLaunchKernelGGL(k_move<float>, dim3(blocks), dim3(kBlock), 0, s, a);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return precision == 0 ? launch_t<double>(id, a, blocks, s) : launch_t<float>(id, a, blocks, s);
 }
 
 hipError_t launch_synchrotron(const void *x, void *F, void *G, u64 n, int dtype, DevState *st,

@@ -50,9 +50,14 @@ class qed_report(C.Structure):
 
 class qed_stats(C.Structure):
     _fields_ = [("steps", C.c_uint64), ("substeps", C.c_uint64 * 3), ("particles", C.c_uint64 * 3),
-                ("emissions", C.c_uint64),
+                ("heavy_particles", C.c_uint64), ("heavy_substeps", C.c_uint64), ("emissions", C.c_uint64),
                 ("pairs", C.c_uint64), ("clips", C.c_uint64), ("capped", C.c_uint64),
                 ("max_p", C.c_double)]
+
+
+class qed_tuning(C.Structure):
+    _fields_ = [("lepton_blocks_per_cu", C.c_uint32), ("heavy_blocks_per_cu", C.c_uint32),
+                ("photon_blocks_per_cu", C.c_uint32), ("light_max", C.c_uint32), ("chunk", C.c_uint32)]
 
 
 class qed_kernel_time(C.Structure):
@@ -60,7 +65,8 @@ class qed_kernel_time(C.Structure):
 
 
 EXPORTS = ("qed_config_default", "qed_init", "qed_step", "qed_sync", "qed_synchrotron",
-           "qed_get_stats", "qed_reset_stats", "qed_profile_enable", "qed_profile_read",
+           "qed_get_stats", "qed_reset_stats", "qed_get_tuning", "qed_set_tuning",
+           "qed_profile_enable", "qed_profile_read",
            "qed_finalize", "qed_status_string")
 
 _lib = None
@@ -82,6 +88,8 @@ def load(path: str = LIB_PATH):
     L.qed_synchrotron.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int]
     L.qed_get_stats.argtypes = [C.c_void_p, C.POINTER(qed_stats)]
     L.qed_reset_stats.argtypes = [C.c_void_p]
+    L.qed_get_tuning.argtypes = [C.c_void_p, C.POINTER(qed_tuning)]
+    L.qed_set_tuning.argtypes = [C.c_void_p, C.POINTER(qed_tuning)]
     L.qed_profile_enable.argtypes = [C.c_void_p, C.c_int]
     L.qed_profile_read.argtypes = [C.c_void_p, C.POINTER(qed_kernel_time), C.c_int, C.POINTER(C.c_int)]
     L.qed_finalize.argtypes = [C.c_void_p]
@@ -147,6 +155,16 @@ def qed_get_stats(ctx):
 
 def qed_reset_stats(ctx):
     _check(load().qed_reset_stats(ctx), "qed_reset_stats")
+
+
+def qed_get_tuning(ctx):
+    t = qed_tuning()
+    _check(load().qed_get_tuning(ctx, C.byref(t)), "qed_get_tuning")
+    return t
+
+
+def qed_set_tuning(ctx, t):
+    return load().qed_set_tuning(ctx, C.byref(t))
 
 
 def qed_profile_enable(ctx, on):
