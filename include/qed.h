@@ -169,7 +169,8 @@ typedef struct qed_tuning {
     uint32_t heavy_blocks_per_cu;  /* persistent heavy-queue kernel, blocks per CU (>= 1) */
     uint32_t photon_blocks_per_cu; /* photon kernel, blocks per CU (>= 1) */
     uint32_t light_max;            /* binned scheduler: particles with at most this many
-                                      sub-steps run in buffer order (>= 1) */
+                                      sub-steps run in tiles sorted by sub-step count; the
+                                      rest go through the global heavy queue (>= 1) */
     uint32_t chunk;                /* binned scheduler: queue entries a wave claims at once
                                       (a multiple of 64, >= 64) */
 } qed_tuning;

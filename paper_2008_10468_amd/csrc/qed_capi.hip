@@ -199,7 +199,7 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     c->tune.lepton_blocks_per_cu = 8;
     c->tune.heavy_blocks_per_cu = 4;
     c->tune.photon_blocks_per_cu = 8;
-    c->tune.light_max = 2;
+    c->tune.light_max = 48;
     c->tune.chunk = 256;
     if (hipMalloc(&c->st, sizeof(qed::DevState)) != hipSuccess ||
         hipMemset(c->st, 0, sizeof(qed::DevState)) != hipSuccess) {

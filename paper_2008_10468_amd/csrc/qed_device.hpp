@@ -79,9 +79,21 @@ __device__ __forceinline__ double chi_def(double en, double px, double py, doubl
 // (Lagrange's identity), which has no cancellation in a pure E field.  Only the
 // cross term can cancel (crossed fields with u along E x B); then the value is
 // recomputed in double from the definition.
+template <int FK = 0>
 __device__ __forceinline__ float chi_lepton_f32(float ux, float uy, float uz, float gamma, float ex,
                                                 float ey, float ez, float bx, float by, float bz,
                                                 float e2) {
+    // FK = 1 (B = 0): |E|^2 + |u x E|^2;  FK = 2 (E = 0): |u x B|^2
+    if constexpr (FK == 1) {
+        const float cex = uy * ez - uz * ey, cey = uz * ex - ux * ez, cez = ux * ey - uy * ex;
+        const float s = e2 + (cex * cex + cey * cey + cez * cez);
+        return s > 0.0f ? __builtin_amdgcn_sqrtf(s) : 0.0f;
+    }
+    if constexpr (FK == 2) {
+        const float cbx = uy * bz - uz * by, cby = uz * bx - ux * bz, cbz = ux * by - uy * bx;
+        const float s = cbx * cbx + cby * cby + cbz * cbz;
+        return s > 0.0f ? __builtin_amdgcn_sqrtf(s) : 0.0f;
+    }
     const float cex = uy * ez - uz * ey, cey = uz * ex - ux * ez, cez = ux * ey - uy * ex;
     const float cbx = uy * bz - uz * by, cby = uz * bx - ux * bz, cbz = ux * by - uy * bx;
     const float t = e2 + (cex * cex + cey * cey + cez * cez) + (cbx * cbx + cby * cby + cbz * cbz);
@@ -91,7 +103,7 @@ __device__ __forceinline__ float chi_lepton_f32(float ux, float uy, float uz, fl
         return (float)chi_def(gd, ux, uy, uz, ex, ey, ez, bx, by, bz);
     }
     const float s = t + xt;
-    return s > 0.0f ? sqrtf(s) : 0.0f;
+    return s > 0.0f ? __builtin_amdgcn_sqrtf(s) : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -204,10 +216,20 @@ __device__ __forceinline__ double rsqrt_(double v) { return 1.0 / sqrt(v); }
 // Boris pusher, du/dt = q (E + u x B / gamma), frozen fields.  hq = q dt / 2 and
 // hex, hey, hez = hq E are precomputed per particle.
 // ---------------------------------------------------------------------------
-template <class R>
+// FK selects a specialisation that gives the same result as the general form for
+// the field it is used with: 0 general, 1 pure electric field (B = 0: the rotation
+// is the identity and u <- (u + hE) + hE), 2 pure magnetic field (E = 0: the
+// half kicks vanish exactly).
+template <class R, int FK = 0>
 __device__ __forceinline__ void boris(R &ux, R &uy, R &uz, R hex, R hey, R hez, R hq, R bx, R by,
                                       R bz) {
-    const R mx = ux + hex, my = uy + hey, mz = uz + hez;
+    if constexpr (FK == 1) {
+        ux = (ux + hex) + hex;
+        uy = (uy + hey) + hey;
+        uz = (uz + hez) + hez;
+        return;
+    }
+    const R mx = FK == 2 ? ux : ux + hex, my = FK == 2 ? uy : uy + hey, mz = FK == 2 ? uz : uz + hez;
     const R ig = rsqrt_(R(1) + mx * mx + my * my + mz * mz);
     const R f = hq * ig;
     const R tx = f * bx, ty = f * by, tz = f * bz;
@@ -216,9 +238,15 @@ __device__ __forceinline__ void boris(R &ux, R &uy, R &uz, R hex, R hey, R hez, 
     const R py = my + (mz * tx - mx * tz);
     const R pz = mz + (mx * ty - my * tx);
     const R sx = s * tx, sy = s * ty, sz = s * tz;
-    ux = mx + (py * sz - pz * sy) + hex;
-    uy = my + (pz * sx - px * sz) + hey;
-    uz = mz + (px * sy - py * sx) + hez;
+    if constexpr (FK == 2) {
+        ux = mx + (py * sz - pz * sy);
+        uy = my + (pz * sx - px * sz);
+        uz = mz + (px * sy - py * sx);
+    } else {
+        ux = mx + (py * sz - pz * sy) + hex;
+        uy = my + (pz * sx - px * sz) + hey;
+        uz = mz + (px * sy - py * sx) + hez;
+    }
 }
 
 }  // namespace qed

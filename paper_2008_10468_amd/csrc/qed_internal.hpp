@@ -68,7 +68,7 @@ struct StepArgs {
     int emission, pairs;   // which algorithms run in this step
     uint32_t light_max;    // binned scheduler: largest N handled by the light pass
     uint32_t chunk;        // binned scheduler: queue entries claimed per wave (multiple of 64)
-    uint8_t *alive;        // photon flags, one per photon slot
+    uint8_t *alive;        // photon flags, one per slot: 0 decayed, 1 alive
     u64 *dead_idx;         // slots of the photons that decayed this step
     u64 *hole_idx;         // compaction lists
     u64 *mover_idx;

@@ -179,10 +179,12 @@ struct Draw<double> {
 };
 
 // chi inside the sub-step loop.
+template <int FK>
 __device__ __forceinline__ float chi_sub(float ux, float uy, float uz, float g, float ex, float ey,
                                          float ez, float bx, float by, float bz, float e2) {
-    return chi_lepton_f32(ux, uy, uz, g, ex, ey, ez, bx, by, bz, e2);
+    return chi_lepton_f32<FK>(ux, uy, uz, g, ex, ey, ez, bx, by, bz, e2);
 }
+template <int FK>
 __device__ __forceinline__ double chi_sub(double ux, double uy, double uz, double g, double ex,
                                           double ey, double ez, double bx, double by, double bz,
                                           double) {
@@ -229,10 +231,11 @@ __device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<
 }
 
 // Algorithm 1, lines 2-7, for one electron (s = 0, q = -1) or positron (s = 1,
-// q = +1) with N >= 1 sub-steps.  s is uniform across the wave.
-template <class R>
-__device__ __forceinline__ void lepton_run(const StepArgs &a, int s, u64 i, uint32_t N, Lepton<R> p,
-                                           const SynTable<R> &tab, ChildBuf<R> &cb, Tally<R> &tl) {
+// q = +1) with N >= 1 sub-steps.  s is uniform across the wave.  FK: field kind
+// (0 general, 1 pure E, 2 pure B), see boris().
+template <class R, int FK>
+__device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uint32_t N, Lepton<R> p,
+                                            const SynTable<R> &tab, ChildBuf<R> &cb, Tally<R> &tl) {
     const SpeciesDev &sp = a.sp[s];
     const SpeciesDev &ph = a.sp[2];
     const uint64_t pid = sp.id[i];
@@ -251,16 +254,16 @@ __device__ __forceinline__ void lepton_run(const StepArgs &a, int s, u64 i, uint
     Draw<R> draw;
     for (uint32_t k = 0; k < N; ++k) {
         // line 3: Boris push and move
-        boris<R>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
+        boris<R, FK>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
         const R u2 = ux * ux + uy * uy + uz * uz;
-        const R g = sqrt_(R(1) + u2);
-        const R ig = rcp(g);
+        const R ig = rsqrt_(R(1) + u2);
+        const R g = (R(1) + u2) * ig;
         const R vs = str * ig;
         dx += ux * vs;
         dy += uy * vs;
         dz += uz * vs;
         // line 4
-        const R chi = chi_sub(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
+        const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
         // line 5
         R x, y;
         draw.get(k, idlo, idhi, a.step, klo, khi, x, y);
@@ -322,125 +325,141 @@ __device__ __forceinline__ void lepton_run(const StepArgs &a, int s, u64 i, uint
     tl.events += nev;
 }
 
-// ---------------------------------------------------------------------------
-// Algorithm 2 for one photon.
-// ---------------------------------------------------------------------------
 template <class R>
-__device__ __forceinline__ void photon_one(const StepArgs &a, u64 i, const SynTable<R> &tab,
-                                           Tally<R> &tl) {
+__device__ __forceinline__ void lepton_run(const StepArgs &a, int s, u64 i, uint32_t N, Lepton<R> p,
+                                           const SynTable<R> &tab, ChildBuf<R> &cb, Tally<R> &tl) {
+    const bool noB = p.bx == R(0) && p.by == R(0) && p.bz == R(0);
+    const bool noE = p.ex == R(0) && p.ey == R(0) && p.ez == R(0);
+    if (noB)
+        lepton_loop<R, 1>(a, s, i, N, p, tab, cb, tl);
+    else if (noE)
+        lepton_loop<R, 2>(a, s, i, N, p, tab, cb, tl);
+    else
+        lepton_loop<R, 0>(a, s, i, N, p, tab, cb, tl);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 2.
+// ---------------------------------------------------------------------------
+struct PhotonStart {
+    double eps, chi;
+    uint32_t N;
+};
+
+// Line 1 for one photon; false for non-finite input.
+template <class R>
+__device__ __forceinline__ bool photon_start(const StepArgs &a, u64 i, R &kx, R &ky, R &kz,
+                                             PhotonStart &ps, Tally<R> &tl) {
     const SpeciesDev &sp = a.sp[2];
     const FieldDev &fl = a.fl[2];
-    const SpeciesDev &el = a.sp[0];
-    const SpeciesDev &po = a.sp[1];
-    const R kx = ((const R *)sp.ux)[i], ky = ((const R *)sp.uy)[i], kz = ((const R *)sp.uz)[i];
+    kx = ((const R *)sp.ux)[i];
+    ky = ((const R *)sp.uy)[i];
+    kz = ((const R *)sp.uz)[i];
     const u64 f = i * fl.stride;
     const R ex = ((const R *)fl.ex)[f], ey = ((const R *)fl.ey)[f], ez = ((const R *)fl.ez)[f];
     const R bx = ((const R *)fl.bx)[f], by = ((const R *)fl.by)[f], bz = ((const R *)fl.bz)[f];
-    if (!(finite3(kx, ky, kz) && finite3(ex, ey, ez) && finite3(bx, by, bz))) {
-        tl.nonfinite++;
-        a.alive[i] = 1;
-        if (sp.events) sp.events[i] = 0;
-        return;
-    }
-    const double eps = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
+    if (!(finite3(kx, ky, kz) && finite3(ex, ey, ez) && finite3(bx, by, bz))) return false;
+    ps.eps = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
     // the field and k are frozen, so chi_g is the same at every sub-step
-    const double chi = chi_def(eps, kx, ky, kz, ex, ey, ez, bx, by, bz);
-    uint32_t N = 1;
-    if (eps > 0.0) {
+    ps.chi = chi_def(ps.eps, kx, ky, kz, ex, ey, ez, bx, by, bz);
+    ps.N = 1;
+    if (ps.eps > 0.0) {
         bool capped;
-        N = nsub(bound_pair(chi, eps, a.dt, a.pair_coef), a.p_max, a.max_sub, &capped);
+        ps.N = nsub(bound_pair(ps.chi, ps.eps, a.dt, a.pair_coef), a.p_max, a.max_sub, &capped);
         tl.capped += capped;
     }
+    return true;
+}
+
+// Lines 2-8 for one photon that can decay.
+template <class R>
+__device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R ky, R kz,
+                                              const PhotonStart &ps, const SynTable<R> &tab,
+                                              Tally<R> &tl) {
+    const SpeciesDev &sp = a.sp[2];
+    const SpeciesDev &el = a.sp[0];
+    const SpeciesDev &po = a.sp[1];
+    const uint32_t N = ps.N;
     const double st = a.dt / (double)N;
-    const R inv = eps > 0.0 ? (R)(1.0 / eps) : R(0);
+    const R inv = (R)(1.0 / ps.eps);
     const R dirx = kx * inv, diry = ky * inv, dirz = kz * inv;
     const R str = (R)st;
+    // P_p(x) = alpha st sqrt(3)/(2 pi) (chi/eps) (G(z) - x(1-x) F(z)),  z = 2/(3 chi x (1-x))
+    const R A = (R)(kAlpha * st * kSqrt3 / (2.0 * kPi) * ps.chi / ps.eps);
+    const R chir = (R)ps.chi;
+    const R epsr = (R)ps.eps;
+    const uint64_t pid = sp.id[i];
+    const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
+    const uint32_t klo = (uint32_t)a.seed, khi = (uint32_t)(a.seed >> 32);
     R dx = 0, dy = 0, dz = 0;
     bool dead = false;
-    uint32_t used = N;
-    if (!(chi >= kQuietPhotonChi)) {
-        // no candidate can be accepted: the photon only moves (line 3)
-        for (uint32_t k = 0; k < N; ++k) {
-            dx += dirx * str;
-            dy += diry * str;
-            dz += dirz * str;
-        }
-    } else {
-        // P_p(x) = alpha st sqrt(3)/(2 pi) (chi/eps) (G(z) - x(1-x) F(z)),
-        // z = 2/(3 chi x (1-x))
-        const R A = (R)(kAlpha * st * kSqrt3 / (2.0 * kPi) * chi / eps);
-        const R chir = (R)chi;
-        const R epsr = (R)eps;
-        const uint64_t pid = sp.id[i];
-        const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
-        const uint32_t klo = (uint32_t)a.seed, khi = (uint32_t)(a.seed >> 32);
-        Draw<R> draw;
-        for (uint32_t k = 0; k < N && !dead; ++k) {
-            used = k + 1;
-            // line 3: move at the speed of light
-            dx += dirx * str;
-            dy += diry * str;
-            dz += dirz * str;
-            // lines 5-6
-            R x, y;
-            draw.get(k, idlo, idhi, a.step, klo, khi, x, y);
-            const R xx = x * (R(1) - x);
-            const R z = R(2.0 / 3.0) * rcp(chir * xx);
-            R F, G;
-            syn_eval(z, tab, F, G);
-            const R pp = A * (G - xx * F);
-            tl.max_p = fmax(tl.max_p, pp);
-            tl.clips += pp > R(1);
-            const bool acc = y < pp;
-            // lines 7-8: electron with x eps, positron with (1-x) eps, along k; delete
-            const u64 m = __ballot(acc);
-            if (m) {
-                const int leader = __ffsll((long long)m) - 1;
-                u64 be = 0, bp = 0, bd = 0;
-                if (__lane_id() == leader) {
-                    const u64 c = (u64)__popcll(m);
-                    be = atomicAdd(el.n, c);
-                    bp = atomicAdd(po.n, c);
-                    bd = atomicAdd(&a.st->dead, c);
+    uint32_t used = 0;
+    Draw<R> draw;
+    for (uint32_t k = 0; k < N && !dead; ++k) {
+        used = k + 1;
+        // line 3: move at the speed of light
+        dx += dirx * str;
+        dy += diry * str;
+        dz += dirz * str;
+        // lines 5-6
+        R x, y;
+        draw.get(k, idlo, idhi, a.step, klo, khi, x, y);
+        const R xx = x * (R(1) - x);
+        const R z = R(2.0 / 3.0) * rcp(chir * xx);
+        R F, G;
+        syn_eval(z, tab, F, G);
+        const R pp = A * (G - xx * F);
+        tl.max_p = fmax(tl.max_p, pp);
+        tl.clips += pp > R(1);
+        const bool acc = y < pp;
+        // lines 7-8: electron with x eps, positron with (1-x) eps, along k; delete
+        const u64 m = __ballot(acc);
+        if (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            u64 be = 0, bp = 0, bd = 0;
+            if (__lane_id() == leader) {
+                const u64 c = (u64)__popcll(m);
+                be = atomicAdd(el.n, c);
+                bp = atomicAdd(po.n, c);
+                bd = atomicAdd(&a.st->dead, c);
+            }
+            be = __shfl(be, leader);
+            bp = __shfl(bp, leader);
+            bd = __shfl(bd, leader);
+            if (acc) {
+                const u64 r = (u64)__popcll(m & lanemask_lt());
+                a.dead_idx[bd + r] = i;
+                const double px = sp.x[i] + (double)dx, py = sp.y[i] + (double)dy,
+                             pz = sp.z[i] + (double)dz;
+                const R w = ((const R *)sp.w)[i];
+                const R ge = x * epsr, gp = (R(1) - x) * epsr;
+                const R ue = sqrt_(fmax(ge * ge - R(1), R(0)));
+                const R up = sqrt_(fmax(gp * gp - R(1), R(0)));
+                if (be + r < el.cap) {
+                    const u64 j = be + r;
+                    el.x[j] = px;
+                    el.y[j] = py;
+                    el.z[j] = pz;
+                    ((R *)el.ux)[j] = ue * dirx;
+                    ((R *)el.uy)[j] = ue * diry;
+                    ((R *)el.uz)[j] = ue * dirz;
+                    ((R *)el.w)[j] = w;
+                    el.id[j] = child_id(a.seed, pid, a.step, k, 0);
+                    if (el.parent) el.parent[j] = pid;
                 }
-                be = __shfl(be, leader);
-                bp = __shfl(bp, leader);
-                bd = __shfl(bd, leader);
-                if (acc) {
-                    const u64 r = (u64)__popcll(m & lanemask_lt());
-                    a.dead_idx[bd + r] = i;
-                    const double px = sp.x[i] + (double)dx, py = sp.y[i] + (double)dy,
-                                 pz = sp.z[i] + (double)dz;
-                    const R w = ((const R *)sp.w)[i];
-                    const R ge = x * epsr, gp = (R(1) - x) * epsr;
-                    const R ue = sqrt_(fmax(ge * ge - R(1), R(0)));
-                    const R up = sqrt_(fmax(gp * gp - R(1), R(0)));
-                    if (be + r < el.cap) {
-                        const u64 j = be + r;
-                        el.x[j] = px;
-                        el.y[j] = py;
-                        el.z[j] = pz;
-                        ((R *)el.ux)[j] = ue * dirx;
-                        ((R *)el.uy)[j] = ue * diry;
-                        ((R *)el.uz)[j] = ue * dirz;
-                        ((R *)el.w)[j] = w;
-                        el.id[j] = child_id(a.seed, pid, a.step, k, 0);
-                        if (el.parent) el.parent[j] = pid;
-                    }
-                    if (bp + r < po.cap) {
-                        const u64 j = bp + r;
-                        po.x[j] = px;
-                        po.y[j] = py;
-                        po.z[j] = pz;
-                        ((R *)po.ux)[j] = up * dirx;
-                        ((R *)po.uy)[j] = up * diry;
-                        ((R *)po.uz)[j] = up * dirz;
-                        ((R *)po.w)[j] = w;
-                        po.id[j] = child_id(a.seed, pid, a.step, k, 1);
-                        if (po.parent) po.parent[j] = pid;
-                    }
-                    dead = true;
+                if (bp + r < po.cap) {
+                    const u64 j = bp + r;
+                    po.x[j] = px;
+                    po.y[j] = py;
+                    po.z[j] = pz;
+                    ((R *)po.ux)[j] = up * dirx;
+                    ((R *)po.uy)[j] = up * diry;
+                    ((R *)po.uz)[j] = up * dirz;
+                    ((R *)po.w)[j] = w;
+                    po.id[j] = child_id(a.seed, pid, a.step, k, 1);
+                    if (po.parent) po.parent[j] = pid;
                 }
+                dead = true;
             }
         }
     }
@@ -463,6 +482,44 @@ __device__ __forceinline__ int nbin(uint32_t N, uint32_t light_max) {
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
+// End-of-kernel flush of all wave buffers of the block with one atomic: every
+// thread of the block must call it.
+template <class R>
+__device__ __forceinline__ void flush_children_block(ChildBuf<R> *cbs, const SpeciesDev &dst) {
+    __shared__ u64 base_sh;
+    __shared__ uint32_t pre[kBlock / 64 + 1];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t o = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            pre[w] = o;
+            o += cbs[w].count;
+        }
+        pre[kBlock / 64] = o;
+        base_sh = o ? atomicAdd(dst.n, (u64)o) : 0ull;
+    }
+    __syncthreads();
+    const uint32_t total = pre[kBlock / 64];
+    for (uint32_t e = threadIdx.x; e < total; e += kBlock) {
+        int w = 0;
+        while (w + 1 < kBlock / 64 && pre[w + 1] <= e) ++w;
+        const ChildBuf<R> &cb = cbs[w];
+        const uint32_t k = e - pre[w];
+        const u64 slot = base_sh + e;
+        if (slot < dst.cap) {
+            dst.x[slot] = cb.x[k];
+            dst.y[slot] = cb.y[k];
+            dst.z[slot] = cb.z[k];
+            ((R *)dst.ux)[slot] = cb.px[k];
+            ((R *)dst.uy)[slot] = cb.py[k];
+            ((R *)dst.uz)[slot] = cb.pz[k];
+            ((R *)dst.w)[slot] = cb.w[k];
+            dst.id[slot] = cb.id[k];
+            if (dst.parent) dst.parent[slot] = cb.parent[k];
+        }
+    }
+}
+
 // LDS of the lepton kernels: the coefficient table and one child buffer per wave.
 template <class R>
 struct LeptonLds {
@@ -493,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_lepton(StepArgs a) {
         else if (a.sp[s].events)
             a.sp[s].events[i] = 0;
     }
-    flush_children(cb, a.sp[2]);
+    flush_children_block(L.cb, a.sp[2]);
     flush_tally(t, a.st, s);
 }
 
@@ -563,18 +620,64 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepArgs a) {
     }
 }
 
+// Light pass: each wave takes tiles of kTile consecutive slots; inside a tile the
+// light particles (1 <= N <= light_max) are counting-sorted by N in the wave's
+// LDS, heaviest first, and run 64 at a time in that order, so the lanes of a
+// wave carry nearly the same N.  Waves never wait for each other, and the
+// particle data stay in the tile's address window.
+constexpr int kTile = 512;     // slots per wave tile (8 per lane)
+constexpr int kTileKeys = 64;  // N >= 63 share the heaviest key
+
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_light(StepArgs a) {
     __shared__ LeptonLds<R> L;
+    __shared__ uint32_t hist_sh[kBlock / 64][kTileKeys];
+    __shared__ uint16_t order_sh[kBlock / 64][kTile];
     ChildBuf<R> &cb = lepton_lds_init(L);
     const int s = blockIdx.y;
     const u64 n = a.st->n0[s];
+    const uint32_t lmax = a.light_max;
+    const uint32_t lane = __lane_id();
+    const int wv = threadIdx.x / 64;
+    uint32_t *hist = hist_sh[wv];
+    uint16_t *order = order_sh[wv];
+    const u64 nwaves = (u64)gridDim.x * (kBlock / 64);
     Tally<R> t;
-    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
-        const uint32_t N = a.nsub[s][i];
-        if (N >= 1 && N <= a.light_max) lepton_run<R>(a, s, i, N, load_lepton<R>(a, s, i), L.tab, cb, t);
+    for (u64 t0 = ((u64)blockIdx.x * (kBlock / 64) + wv) * kTile; t0 < n; t0 += nwaves * kTile) {
+        hist[lane] = 0;
+        __syncwarp();
+        uint32_t kr[kTile / 64];  // key << 16 | rank
+#pragma unroll
+        for (int q = 0; q < kTile / 64; ++q) {
+            const u64 i = t0 + q * 64 + lane;
+            const uint32_t N = i < n ? a.nsub[s][i] : 0u;
+            const uint32_t key = (N >= 1 && N <= lmax) ? kTileKeys - (N < kTileKeys - 1 ? N : kTileKeys - 1) : 0u;
+            kr[q] = key ? (key << 16) | atomicAdd(&hist[key], 1u) : 0u;
+        }
+        __syncwarp();
+        // exclusive prefix over keys 1..63 (key 0 is not in this pass)
+        const uint32_t h = lane >= 1 ? hist[lane] : 0u;
+        uint32_t incl = h;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o);
+            if ((int)lane >= o) incl += v;
+        }
+        const uint32_t total = __shfl(incl, 63);
+        __syncwarp();
+        hist[lane] = incl - h;  // now the offset of each key
+        __syncwarp();
+#pragma unroll
+        for (int q = 0; q < kTile / 64; ++q)
+            if (kr[q]) order[hist[kr[q] >> 16] + (kr[q] & 0xFFFFu)] = (uint16_t)(q * 64 + lane);
+        __syncwarp();
+        for (uint32_t p = lane; p < total; p += 64) {
+            const u64 i = t0 + order[p];
+            lepton_run<R>(a, s, i, a.nsub[s][i], load_lepton<R>(a, s, i), L.tab, cb, t);
+        }
+        __syncwarp();
     }
-    flush_children(cb, a.sp[2]);
+    flush_children_block(L.cb, a.sp[2]);
     flush_tally(t, a.st, s);
 }
 
@@ -587,10 +690,11 @@ __global__ __launch_bounds__(kBlock) void k_heavy(StepArgs a) {
     const u64 H = a.st->heavy[s];
     const uint32_t chunk = a.chunk;
     Tally<R> t;
+    // the first chunk of every wave is assigned statically; later ones are
+    // claimed from the queue, which starts after all static chunks
+    const u64 nwaves = (u64)gridDim.x * (kBlock / 64);
+    u64 base = ((u64)blockIdx.x * (kBlock / 64) + threadIdx.x / 64) * chunk;
     for (;;) {
-        u64 base = 0;
-        if (__lane_id() == 0) base = atomicAdd(&a.st->queue[s], (u64)chunk);
-        base = __shfl(base, 0);
         if (base >= H) break;
         const u64 end = base + chunk < H ? base + chunk : H;
         for (u64 j = base + __lane_id(); j < end; j += 64) {
@@ -598,19 +702,54 @@ __global__ __launch_bounds__(kBlock) void k_heavy(StepArgs a) {
             lepton_run<R>(a, s, i, a.nsub[s][i], load_lepton<R>(a, s, i), L.tab, cb, t);
             t.particles++;
         }
+        u64 nb = 0;
+        if (__lane_id() == 0) nb = nwaves * chunk + atomicAdd(&a.st->queue[s], (u64)chunk);
+        base = __shfl(nb, 0);
     }
-    flush_children(cb, a.sp[2]);
+    flush_children_block(L.cb, a.sp[2]);
     flush_tally(t, a.st, s, true);
 }
 
+// Algorithm 2 for every photon.  Photons that cannot decay (chi_g below
+// kQuietPhotonChi) only move; the others run the sampling loop.
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
     __shared__ SynTable<R> tab;
     syn_stage(tab);
     const u64 n = a.st->n0[2];
+    const SpeciesDev &sp = a.sp[2];
     Tally<R> t;
-    for (u64 g = (u64)blockIdx.x * kBlock + threadIdx.x; g < n; g += (u64)gridDim.x * kBlock)
-        photon_one<R>(a, g, tab, t);
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
+        R kx, ky, kz;
+        PhotonStart ps;
+        if (!photon_start<R>(a, i, kx, ky, kz, ps, t)) {
+            t.nonfinite++;
+            a.alive[i] = 1;
+            if (sp.events) sp.events[i] = 0;
+            continue;
+        }
+        if (ps.chi >= kQuietPhotonChi) {
+            photon_sample<R>(a, i, kx, ky, kz, ps, tab, t);
+            continue;
+        }
+        // no candidate can be accepted: the photon only moves (line 3)
+        const double st = a.dt / (double)ps.N;
+        const R inv = ps.eps > 0.0 ? (R)(1.0 / ps.eps) : R(0);
+        const R dirx = kx * inv, diry = ky * inv, dirz = kz * inv;
+        const R str = (R)st;
+        R dx = 0, dy = 0, dz = 0;
+        for (uint32_t k = 0; k < ps.N; ++k) {
+            dx += dirx * str;
+            dy += diry * str;
+            dz += dirz * str;
+        }
+        sp.x[i] += (double)dx;
+        sp.y[i] += (double)dy;
+        sp.z[i] += (double)dz;
+        a.alive[i] = 1;
+        if (sp.events) sp.events[i] = 0u;
+        t.substeps += ps.N;
+    }
     flush_tally(t, a.st, 2);
 }
 

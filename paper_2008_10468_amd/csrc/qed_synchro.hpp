@@ -56,14 +56,36 @@ __device__ __forceinline__ void syn_stage(SynTable<double> &t) {
     __syncthreads();
 }
 
-__device__ __forceinline__ float syn_cbrt(float z) { return cbrtf(z); }
+// Float z^(1/3) for 0 <= z <= 2^100: 2^(log2(z)/3) from the hardware log2 / exp2
+// (relative error about 1e-6), then one Newton step t <- (2 t + z / t^2) / 3,
+// which squares the error.  Inputs below 2^-90 are scaled by 2^90 (and the root
+// by 2^-30) so that the hardware log2 never sees a denormal.  z = 0 gives 0.
+__device__ __forceinline__ float syn_cbrt(float z) {
+    const bool tiny = z < 0x1p-90f;
+    const float zs = tiny ? z * 0x1p+90f : z;
+    float t = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(zs) * (1.0f / 3.0f));
+    const float r = __builtin_amdgcn_rcpf(t * t);
+    t = t > 0.0f ? fmaf(t, 2.0f / 3.0f, zs * r * (1.0f / 3.0f)) : 0.0f;
+    return tiny ? t * 0x1p-30f : t;
+}
 __device__ __forceinline__ double syn_cbrt(double z) { return cbrt(z); }
-__device__ __forceinline__ float syn_expm(float z) { return expf(-z); }
+
+// Float e^{-z} for z >= 0: z = n ln2 + r with ln2 split in a 16-bit high part
+// (n ln2_hi exact) and a low part, |r| <= ln2/2, e^{-r} = 2^(-r log2 e) from the
+// hardware exp2 (the product's rounding is now tiny), scaled by 2^-n.  The
+// argument is capped at 110 (e^-110 underflows to 0 in float).
+__device__ __forceinline__ float syn_expm(float z) {
+    const float zc = fminf(z, 110.0f);
+    const float n = rintf(zc * 1.44269504088896341f);
+    float r = fmaf(-n, 0.693145751953125f, zc);
+    r = fmaf(-n, 1.42860682030941723e-6f, r);
+    return ldexpf(__builtin_amdgcn_exp2f(-r * 1.44269504088896341f), -(int)n);
+}
 __device__ __forceinline__ double syn_expm(double z) { return exp(-z); }
 
 // F, G at z >= 0 (z = +inf gives 0).  Caller guarantees z is not NaN / negative.
 __device__ __forceinline__ void syn_eval(float z, const SynTable<float> &tab, float &F, float &G) {
-    const float t = syn_cbrt(z);
+    const float t = syn_cbrt(fminf(z, 0x1p100f));
     const float tc = fminf(t, SynTable<float>::kTmax);
     const int seg = min((int)(tc * 2.0f), SynTable<float>::kSeg - 1);
     const float s = fmaf(tc, SynTable<float>::kInvHalfWidth, -(float)(2 * seg + 1));

@@ -43,7 +43,8 @@ def _run(w, sched, tuning=None, steps=3, precision=None, fields_fn=None, per_spe
 
 
 @pytest.mark.parametrize("tuning", [None, {"light_max": 1, "chunk": 64, "heavy_blocks_per_cu": 1},
-                                    {"light_max": 6, "chunk": 1024, "lepton_blocks_per_cu": 2}])
+                                    {"light_max": 6, "chunk": 1024, "lepton_blocks_per_cu": 2,
+                                     "photon_blocks_per_cu": 1}])
 def test_binned_equals_naive_c2(tuning):
     from paper_2008_10468_amd import qed
     w = workloads.c2(n_e=20000, n_g=5000, seed=3)
@@ -108,4 +109,6 @@ def test_tuning_validation():
     t.chunk = 128
     t.light_max = 0
     assert qed.qed_set_tuning(g.ctx, t) == qed.QED_ERR_INVALID_ARG
+    t.light_max = 3
+    assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
     g.close()
