@@ -43,10 +43,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def c2_setup(torch, qed, workloads, steps_total, sched):
+def c2_setup(torch, qed, workloads, steps_total, sched, stream=None):
     w = workloads.c2()
     g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 23, 1 << 23, 1 << 25),
-                      parent=False, events=False, scheduler=sched)
+                      parent=False, events=False, scheduler=sched,
+                      stream=None if stream is None else stream.cuda_stream)
     # one frozen field per global step, resident on the device: step s reads entry s
     E = np.array([[workloads.c2_field(s)[k][0] for k in ("ex", "ey", "ez", "bx", "by", "bz")]
                   for s in range(steps_total)], np.float64)
@@ -170,6 +171,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--scheduler", choices=("naive", "binned"), default="naive")
+    ap.add_argument("--no-graph", action="store_true", help="launch steps eagerly in the timed pass")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -183,15 +185,25 @@ def main():
     torch.cuda.set_device(0)
     K, W = args.steps, args.warmup
     sched = qed.QED_SCHED_BINNED if args.scheduler == "binned" else qed.QED_SCHED_NAIVE
-    w, g, field = c2_setup(torch, qed, workloads, max(K, W), sched)
+    stream = torch.cuda.Stream()
+    w, g, field = c2_setup(torch, qed, workloads, max(K, W), sched, stream)
     log(f"bench: C2 workload, {w['electrons']['id'].size} e- + {w['photons']['id'].size} photons, "
         f"dt={w['dt']}, steps={K}, warmup={W}")
 
-    # warm-up on the workload, then restore the initial state
+    # warm-up on the workload (this also sizes the library's scratch), then restore
+    # the initial state
     g.load_state(w)
+    torch.cuda.synchronize()
     run_steps(qed, g, field, w, 0, W)
     st, rep = g.sync()
     assert st == qed.QED_OK, qed.status_string(st)
+    graph = None
+    if not args.no_graph:
+        # all K steps recorded once into one HIP graph; the timed pass replays it
+        assert qed.qed_graph_begin(g.ctx) == qed.QED_OK
+        run_steps(qed, g, field, w, 0, K)
+        st, graph = qed.qed_graph_end(g.ctx)
+        assert st == qed.QED_OK, qed.status_string(st)
 
     def timed(profile):
         g.load_state(w)
@@ -200,9 +212,12 @@ def main():
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        run_steps(qed, g, field, w, 0, K)
-        e1.record()
+        e0.record(stream)
+        if graph is not None and not profile:
+            assert qed.qed_graph_launch(g.ctx, graph) == qed.QED_OK
+        else:
+            run_steps(qed, g, field, w, 0, K)
+        e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         st, rep = g.sync()
@@ -243,12 +258,15 @@ def main():
                         "functions, f64 sub-step count and positions), buffers growing by appends",
             "steps": K, "p_max": 0.01, "dt_hbar_over_mc2": w["dt"], "seed": w["seed"],
             "scheduler": args.scheduler,
+            "launch": "eager" if graph is None else "one HIP graph of all timed steps",
         },
         "events_per_s": ev / (ms * 1e-3),
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(workloads, args.cpu_seconds)
+    if graph is not None:
+        qed.qed_graph_destroy(graph)
     g.close()
     print(json.dumps(out), flush=True)
 

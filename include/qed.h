@@ -193,6 +193,20 @@ typedef struct qed_kernel_time {
 QED_API qed_status qed_profile_enable(qed_ctx *ctx, int on);
 QED_API qed_status qed_profile_read(qed_ctx *ctx, qed_kernel_time *out, int max, int *count);
 
+/* Graph capture of whole steps.  Between qed_graph_begin and qed_graph_end the
+ * work enqueued by qed_step on the context's stream is recorded into a HIP graph
+ * instead of being run; qed_graph_launch replays it (all recorded steps, with the
+ * arguments they were recorded with: buffers, counts pointers, dt, seed, step).
+ * The context's stream must be a created stream (not the null stream), and the
+ * scratch must already fit the buffers (run one qed_step eagerly first):
+ * otherwise QED_ERR_STATE.  Counts stay on the device, so recorded steps handle
+ * any number of particles up to the recorded capacities. */
+typedef struct qed_graph qed_graph;
+QED_API qed_status qed_graph_begin(qed_ctx *ctx);
+QED_API qed_status qed_graph_end(qed_ctx *ctx, qed_graph **out);
+QED_API qed_status qed_graph_launch(qed_ctx *ctx, qed_graph *g);
+QED_API void qed_graph_destroy(qed_graph *g);
+
 /* Release the context's scratch.  NULL is allowed. */
 QED_API void qed_finalize(qed_ctx *ctx);
 

@@ -30,6 +30,12 @@ struct qed_ctx {
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> rec_id;  // kernel id of each recorded launch
     size_t rec_used;          // event pairs in use
+    bool capturing;           // between qed_graph_begin and qed_graph_end
+};
+
+struct qed_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
 };
 
 namespace {
@@ -91,6 +97,7 @@ void release(T *&p) {
 
 qed_status ensure_photon_scratch(qed_ctx *c, u64 cap) {
     if (cap <= c->photon_cap) return QED_OK;
+    if (c->capturing) return QED_ERR_STATE;
     HIP_TRY(hipStreamSynchronize(c->stream));
     release(c->alive);
     release(c->dead_idx);
@@ -107,6 +114,7 @@ qed_status ensure_photon_scratch(qed_ctx *c, u64 cap) {
 
 qed_status ensure_lepton_scratch(qed_ctx *c, int s, u64 cap) {
     if (cap <= c->lepton_cap[s]) return QED_OK;
+    if (c->capturing) return QED_ERR_STATE;
     HIP_TRY(hipStreamSynchronize(c->stream));
     release(c->nsub[s]);
     release(c->queue[s]);
@@ -123,7 +131,7 @@ bool tuning_ok(const qed_tuning &t) {
            t.light_max >= 1 && t.chunk >= 64 && t.chunk % 64 == 0 && t.chunk <= (1u << 20);
 }
 
-const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_prepass",
+const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_photon_sample", "k_lepton", "k_prepass",
                                          "k_scan",  "k_scatter", "k_light", "k_heavy",
                                          "k_end",   "k_fill",   "k_move",  "k_synchrotron"};
 
@@ -146,7 +154,7 @@ bool prof_pair(qed_ctx *c, int id, hipEvent_t *a, hipEvent_t *b) {
 
 hipError_t launch(qed_ctx *c, int id, const qed::StepArgs &a, int precision, int blocks) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->prof && prof_pair(c, id, &e0, &e1)) {
+    if (c->prof && !c->capturing && prof_pair(c, id, &e0, &e1)) {
         hipError_t r = hipEventRecord(e0, c->stream);
         if (r != hipSuccess) return r;
     }
@@ -273,6 +281,7 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
     const int prec = c->cfg.precision == QED_PREC_F64 ? 0 : 1;
     hipError_t r = launch(c, qed::K_BEGIN, a, prec, 1);
     if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON, a, prec, photon_blocks);
+    if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON_SAMPLE, a, prec, photon_blocks);
     if (r == hipSuccess && emission && !binned) r = launch(c, qed::K_LEPTON, a, prec, lepton_blocks);
     if (binned) {
         if (r == hipSuccess) r = launch(c, qed::K_PREPASS, a, prec, lepton_blocks);
@@ -289,6 +298,7 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
 
 qed_status qed_sync(qed_ctx *c, qed_report *rep) {
     if (!c) return QED_ERR_INVALID_ARG;
+    if (c->capturing) return QED_ERR_STATE;
     HIP_TRY(hipSetDevice(c->cfg.device));
     HIP_TRY(hipStreamSynchronize(c->stream));
     qed::DevState h;
@@ -334,6 +344,7 @@ qed_status qed_synchrotron(qed_ctx *c, const void *x, void *F, void *G, uint64_t
 
 qed_status qed_get_stats(qed_ctx *c, qed_stats *out) {
     if (!c || !out) return QED_ERR_INVALID_ARG;
+    if (c->capturing) return QED_ERR_STATE;
     HIP_TRY(hipSetDevice(c->cfg.device));
     HIP_TRY(hipStreamSynchronize(c->stream));
     qed::DevState h;
@@ -358,6 +369,7 @@ qed_status qed_get_stats(qed_ctx *c, qed_stats *out) {
 
 qed_status qed_reset_stats(qed_ctx *c) {
     if (!c) return QED_ERR_INVALID_ARG;
+    if (c->capturing) return QED_ERR_STATE;
     HIP_TRY(hipSetDevice(c->cfg.device));
     HIP_TRY(hipStreamSynchronize(c->stream));
     qed::DevState h;
@@ -370,6 +382,54 @@ qed_status qed_reset_stats(qed_ctx *c) {
     h.max_p_bits = 0;
     HIP_TRY(hipMemcpy(c->st, &h, sizeof(h), hipMemcpyHostToDevice));
     return QED_OK;
+}
+
+qed_status qed_graph_begin(qed_ctx *c) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    if (c->capturing || !c->stream) return QED_ERR_STATE;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    return QED_OK;
+}
+
+qed_status qed_graph_end(qed_ctx *c, qed_graph **out) {
+    if (!c || !out) return QED_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!c->capturing) return QED_ERR_STATE;
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamEndCapture(c->stream, &g));
+    hipGraphExec_t e = nullptr;
+    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return QED_ERR_HIP;
+    }
+    qed_graph *h = new (std::nothrow) qed_graph();
+    if (!h) {
+        (void)hipGraphExecDestroy(e);
+        (void)hipGraphDestroy(g);
+        return QED_ERR_HIP;
+    }
+    h->graph = g;
+    h->exec = e;
+    *out = h;
+    return QED_OK;
+}
+
+qed_status qed_graph_launch(qed_ctx *c, qed_graph *g) {
+    if (!c || !g) return QED_ERR_INVALID_ARG;
+    if (c->capturing) return QED_ERR_STATE;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    HIP_TRY(hipGraphLaunch(g->exec, c->stream));
+    return QED_OK;
+}
+
+void qed_graph_destroy(qed_graph *g) {
+    if (!g) return;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 qed_status qed_get_tuning(qed_ctx *c, qed_tuning *out) {
@@ -392,6 +452,7 @@ qed_status qed_profile_enable(qed_ctx *c, int on) {
 
 qed_status qed_profile_read(qed_ctx *c, qed_kernel_time *out, int max, int *count) {
     if (!c || !count || max < 0 || (max > 0 && !out)) return QED_ERR_INVALID_ARG;
+    if (c->capturing) return QED_ERR_STATE;
     HIP_TRY(hipSetDevice(c->cfg.device));
     HIP_TRY(hipStreamSynchronize(c->stream));
     double ms[qed::K_COUNT] = {0};

@@ -33,10 +33,34 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// For chi_g below this value the pair density of eq. (2) is below 1e-40 for every
-// candidate x (z_p >= 8/(3 chi_g) > 120), so no uniform y in (0,1) can accept it;
-// such photons only move, which gives the same result as sampling.
-constexpr double kQuietPhotonChi = 0.0222;
+// Smallest uniform y of each path: (2k+1) 2^-b with k = 0.
+template <class R>
+struct YMin;
+template <>
+struct YMin<float> {
+    static constexpr double value = 0x1p-24;
+};
+template <>
+struct YMin<double> {
+    static constexpr double value = 0x1p-53;
+};
+
+// True if no candidate of this photon can be accepted in this step.  With
+// d = x(1-x) <= 1/4 the argument of eq. (2) obeys z = 2/(3 chi d) >= z0 = 8/(3 chi);
+// P_p = A (G(z) - d F(z)) <= A G(z) with A = alpha st sqrt(3)/(2 pi) chi/eps; G
+// decreases for z > 0.42, and for z >= 1 G(z) <= sqrt(pi z/2) e^-z (1 + 7/(72 z))
+// (the K_{2/3} asymptotic series truncated after its positive first correction is
+// an upper bound).  If twice that bound is below the smallest uniform y, no y can
+// fall under P_p: the photon only moves, exactly as sampling would leave it.
+template <class R>
+__device__ __forceinline__ bool photon_quiet(double chi, double eps, double st) {
+    if (!(chi > 0.0) || !(eps > 0.0)) return true;
+    const double z0 = (8.0 / 3.0) / chi;
+    if (z0 < 1.0) return false;
+    const double A = kAlpha * st * kSqrt3 / (2.0 * kPi) * chi / eps;
+    const double ub = 2.0 * A * sqrt(0.5 * kPi * z0) * exp(-z0) * (1.0 + 7.0 / (72.0 * z0));
+    return ub < YMin<R>::value;
+}
 
 __device__ __forceinline__ u64 lanemask_lt() {
     const int l = __lane_id();
@@ -710,45 +734,156 @@ __global__ __launch_bounds__(kBlock) void k_heavy(StepArgs a) {
     flush_tally(t, a.st, s, true);
 }
 
-// Algorithm 2 for every photon.  Photons that cannot decay (chi_g below
-// kQuietPhotonChi) only move; the others run the sampling loop.
+// Algorithm 2, pass 1, for every photon: line 1, and for photons that cannot decay
+// in this step (photon_quiet) lines 2-3 as well: they only move.  The others are
+// marked alive = 2 for pass 2.  Light on registers; each lane takes kPhotonBatch
+// photons per round and issues all their loads before using any, and a uniform
+// field (stride 0) is loaded once, so the pass streams.
+constexpr int kPhotonBatch = 4;
+
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
-    __shared__ SynTable<R> tab;
-    syn_stage(tab);
     const u64 n = a.st->n0[2];
     const SpeciesDev &sp = a.sp[2];
+    const FieldDev &fl = a.fl[2];
+    const bool uni = fl.stride == 0;
+    R fu[6] = {0, 0, 0, 0, 0, 0};
+    if (uni) {
+        fu[0] = ((const R *)fl.ex)[0];
+        fu[1] = ((const R *)fl.ey)[0];
+        fu[2] = ((const R *)fl.ez)[0];
+        fu[3] = ((const R *)fl.bx)[0];
+        fu[4] = ((const R *)fl.by)[0];
+        fu[5] = ((const R *)fl.bz)[0];
+    }
     Tally<R> t;
-    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
-        R kx, ky, kz;
-        PhotonStart ps;
-        if (!photon_start<R>(a, i, kx, ky, kz, ps, t)) {
-            t.nonfinite++;
+    const u64 G = (u64)gridDim.x * kBlock;
+    for (u64 i0 = (u64)blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += G * kPhotonBatch) {
+        R k[kPhotonBatch][3], f[kPhotonBatch][6];
+        double x[kPhotonBatch][3];
+#pragma unroll
+        for (int b = 0; b < kPhotonBatch; ++b) {
+            const u64 i = i0 + b * G;
+            const bool in = i < n;
+            k[b][0] = in ? ((const R *)sp.ux)[i] : R(0);
+            k[b][1] = in ? ((const R *)sp.uy)[i] : R(0);
+            k[b][2] = in ? ((const R *)sp.uz)[i] : R(0);
+            x[b][0] = in ? sp.x[i] : 0.0;
+            x[b][1] = in ? sp.y[i] : 0.0;
+            x[b][2] = in ? sp.z[i] : 0.0;
+            const u64 fi = in ? i * fl.stride : 0;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) f[b][c] = fu[c];
+            if (!uni && in) {
+                f[b][0] = ((const R *)fl.ex)[fi];
+                f[b][1] = ((const R *)fl.ey)[fi];
+                f[b][2] = ((const R *)fl.ez)[fi];
+                f[b][3] = ((const R *)fl.bx)[fi];
+                f[b][4] = ((const R *)fl.by)[fi];
+                f[b][5] = ((const R *)fl.bz)[fi];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < kPhotonBatch; ++b) {
+            const u64 i = i0 + b * G;
+            if (i >= n) break;
+            const R kx = k[b][0], ky = k[b][1], kz = k[b][2];
+            if (!(finite3(kx, ky, kz) && finite3(f[b][0], f[b][1], f[b][2]) &&
+                  finite3(f[b][3], f[b][4], f[b][5]))) {
+                t.nonfinite++;
+                a.alive[i] = 1;
+                if (sp.events) sp.events[i] = 0;
+                continue;
+            }
+            const double eps = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
+            const double chi = chi_def(eps, kx, ky, kz, f[b][0], f[b][1], f[b][2], f[b][3], f[b][4], f[b][5]);
+            uint32_t N = 1;
+            if (eps > 0.0) {
+                bool capped;
+                N = nsub(bound_pair(chi, eps, a.dt, a.pair_coef), a.p_max, a.max_sub, &capped);
+                t.capped += capped;
+            }
+            const double st = a.dt / (double)N;
+            if (!photon_quiet<R>(chi, eps, st)) {
+                a.alive[i] = 2;
+                continue;
+            }
+            const R inv = eps > 0.0 ? (R)(1.0 / eps) : R(0);
+            const R dirx = kx * inv, diry = ky * inv, dirz = kz * inv;
+            const R str = (R)st;
+            R dx = 0, dy = 0, dz = 0;
+            for (uint32_t q = 0; q < N; ++q) {
+                dx += dirx * str;
+                dy += diry * str;
+                dz += dirz * str;
+            }
+            sp.x[i] = x[b][0] + (double)dx;
+            sp.y[i] = x[b][1] + (double)dy;
+            sp.z[i] = x[b][2] + (double)dz;
             a.alive[i] = 1;
-            if (sp.events) sp.events[i] = 0;
-            continue;
+            if (sp.events) sp.events[i] = 0u;
+            t.substeps += N;
         }
-        if (ps.chi >= kQuietPhotonChi) {
+    }
+    flush_tally(t, a.st, 2);
+}
+
+// Algorithm 2, pass 2: the sampling loop for the photons marked by pass 1,
+// compacted per block.  A block takes chunks of kSampleChunk consecutive slots;
+// each thread reads the flags of 16 slots with one 16-byte load, the marked
+// slots are prefix-summed into an LDS list, and the block runs the list with all
+// lanes busy except in the last partial round.
+constexpr int kSampleChunk = 16 * kBlock;
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_photon_sample(StepArgs a) {
+    __shared__ SynTable<R> tab;
+    __shared__ uint16_t list[kSampleChunk];
+    __shared__ uint32_t wsum[kBlock / 64];
+    syn_stage(tab);
+    const u64 n = a.st->n0[2];
+    const uint32_t lane = __lane_id();
+    const int wv = threadIdx.x / 64;
+    Tally<R> t;
+    for (u64 c0 = (u64)blockIdx.x * kSampleChunk; c0 < n; c0 += (u64)gridDim.x * kSampleChunk) {
+        const u64 s0 = c0 + 16ull * threadIdx.x;
+        uint32_t bits = 0;  // bit j: slot s0 + j is marked
+        if (s0 + 16 <= n) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(a.alive + s0);
+            const uint32_t wv4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 16; ++j) bits |= (((wv4[j >> 2] >> (8 * (j & 3))) & 0xFFu) == 2u) << j;
+        } else {
+            for (int j = 0; j < 16; ++j)
+                if (s0 + j < n && a.alive[s0 + j] == 2) bits |= 1u << j;
+        }
+        // block-wide exclusive prefix of the per-thread counts
+        const uint32_t c = __popc(bits);
+        uint32_t incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o);
+            if ((int)lane >= o) incl += v;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        uint32_t off = incl - c, total = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            if (w < wv) off += wsum[w];
+            total += wsum[w];
+        }
+        for (int j = 0; j < 16; ++j)
+            if (bits & (1u << j)) list[off++] = (uint16_t)(16 * threadIdx.x + j);
+        __syncthreads();
+        for (uint32_t p = threadIdx.x; p < total; p += kBlock) {
+            const u64 i = c0 + list[p];
+            R kx, ky, kz;
+            PhotonStart ps;
+            Tally<R> ignore;  // pass 1 counted the capped ones
+            photon_start<R>(a, i, kx, ky, kz, ps, ignore);
             photon_sample<R>(a, i, kx, ky, kz, ps, tab, t);
-            continue;
         }
-        // no candidate can be accepted: the photon only moves (line 3)
-        const double st = a.dt / (double)ps.N;
-        const R inv = ps.eps > 0.0 ? (R)(1.0 / ps.eps) : R(0);
-        const R dirx = kx * inv, diry = ky * inv, dirz = kz * inv;
-        const R str = (R)st;
-        R dx = 0, dy = 0, dz = 0;
-        for (uint32_t k = 0; k < ps.N; ++k) {
-            dx += dirx * str;
-            dy += diry * str;
-            dz += dirz * str;
-        }
-        sp.x[i] += (double)dx;
-        sp.y[i] += (double)dy;
-        sp.z[i] += (double)dz;
-        a.alive[i] = 1;
-        if (sp.events) sp.events[i] = 0u;
-        t.substeps += ps.N;
+        __syncthreads();
     }
     flush_tally(t, a.st, 2);
 }
@@ -873,6 +1008,7 @@ hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
     switch (id) {
         case K_BEGIN: hipLaunchKernelGGL(k_begin, dim3(1), dim3(256), 0, s, a); break;
         case K_PHOTON: hipLaunchKernelGGL(k_photon<R>, g1, blk, 0, s, a); break;
+        case K_PHOTON_SAMPLE: hipLaunchKernelGGL(k_photon_sample<R>, g1, blk, 0, s, a); break;
         case K_LEPTON: hipLaunchKernelGGL(k_lepton<R>, g2, blk, 0, s, a); break;
         case K_PREPASS: hipLaunchKernelGGL(k_prepass<R>, g2, blk, 0, s, a); break;
         case K_SCAN: hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, a); break;

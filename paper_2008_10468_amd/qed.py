@@ -66,7 +66,8 @@ class qed_kernel_time(C.Structure):
 
 EXPORTS = ("qed_config_default", "qed_init", "qed_step", "qed_sync", "qed_synchrotron",
            "qed_get_stats", "qed_reset_stats", "qed_get_tuning", "qed_set_tuning",
-           "qed_profile_enable", "qed_profile_read",
+           "qed_profile_enable", "qed_profile_read", "qed_graph_begin", "qed_graph_end",
+           "qed_graph_launch", "qed_graph_destroy",
            "qed_finalize", "qed_status_string")
 
 _lib = None
@@ -92,12 +93,17 @@ def load(path: str = LIB_PATH):
     L.qed_set_tuning.argtypes = [C.c_void_p, C.POINTER(qed_tuning)]
     L.qed_profile_enable.argtypes = [C.c_void_p, C.c_int]
     L.qed_profile_read.argtypes = [C.c_void_p, C.POINTER(qed_kernel_time), C.c_int, C.POINTER(C.c_int)]
+    L.qed_graph_begin.argtypes = [C.c_void_p]
+    L.qed_graph_end.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
+    L.qed_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
+    L.qed_graph_destroy.argtypes = [C.c_void_p]
+    L.qed_graph_destroy.restype = None
     L.qed_finalize.argtypes = [C.c_void_p]
     L.qed_finalize.restype = None
     L.qed_status_string.argtypes = [C.c_int]
     L.qed_status_string.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("qed_finalize", "qed_status_string"):
+        if name not in ("qed_finalize", "qed_status_string", "qed_graph_destroy"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -177,6 +183,24 @@ def qed_profile_read(ctx):
     cnt = C.c_int()
     _check(load().qed_profile_read(ctx, arr, 16, C.byref(cnt)), "qed_profile_read")
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(cnt.value)}
+
+
+def qed_graph_begin(ctx):
+    return load().qed_graph_begin(ctx)
+
+
+def qed_graph_end(ctx):
+    g = C.c_void_p()
+    st = load().qed_graph_end(ctx, C.byref(g))
+    return st, g
+
+
+def qed_graph_launch(ctx, g):
+    return load().qed_graph_launch(ctx, g)
+
+
+def qed_graph_destroy(g):
+    load().qed_graph_destroy(g)
 
 
 def qed_finalize(ctx):
