@@ -37,7 +37,9 @@ FLOPS_PER_LEPTON_SUBSTEP = 170      # Boris push 52, gamma and move 15, chi 40, 
 FLOPS_PER_PHOTON_SUBSTEP = 62       # move 6, candidate 6, F and G 37, acceptance 13
 BYTES_PER_LEPTON_STEP = 80          # read u 12 + id 8 + position 24; write u 12 + position 24
 BYTES_PER_EMISSION = 52             # weight read 4; position 24 + k 12 + weight 4 + id 8 written
-BYTES_PER_PHOTON_STEP = 61          # read k 12 + position 24; write position 24 + flag 1
+BYTES_PER_PHOTON_READ = 36          # k 12 + position 24
+BYTES_PER_PHOTON_WRITE = 25         # position 24 + flag 1
+FLOPS_PER_PHOTON_MOVE = 6           # three fused multiply-adds per sub-step
 BYTES_PER_BINNED_EXTRA = 8          # sub-step count read 4 + queue entry read 4 (heavy pass)
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -121,7 +123,8 @@ def cpu_baseline(workloads, budget_s):
 
 def roofline(kt, st, K):
     """Roofline of the kernel with the largest share of the profiled time."""
-    cand = {k: v for k, v in kt.items() if k in ("k_lepton", "k_light", "k_heavy", "k_photon")}
+    cand = {k: v for k, v in kt.items()
+            if k in ("k_lepton", "k_light", "k_heavy", "k_photon", "k_photon_sample")}
     name = max(cand, key=lambda k: cand[k][1])
     nl, tms = cand[name]
     avg_s = tms * 1e-3 / max(nl, 1)
@@ -141,9 +144,17 @@ def roofline(kt, st, K):
         em = st.emissions * sub / max(lep_sub, 1)
         byts = BYTES_PER_LEPTON_STEP * part + 4 * lep_part + BYTES_PER_EMISSION * em
         flops = FLOPS_PER_LEPTON_SUBSTEP * sub
-    else:
-        sub, part, em = st.substeps[2], st.particles[2], st.pairs
-        byts = BYTES_PER_PHOTON_STEP * part + 2 * BYTES_PER_EMISSION * em
+    elif name == "k_photon":
+        # every photon is read; the ones that cannot decay also move and are written
+        part = st.particles[2]
+        quiet = part - st.sampled_photons
+        sub, em = st.substeps[2] - st.sampled_substeps, 0
+        byts = BYTES_PER_PHOTON_READ * part + BYTES_PER_PHOTON_WRITE * quiet + st.sampled_photons
+        flops = FLOPS_PER_PHOTON_MOVE * sub
+    else:  # k_photon_sample
+        part, sub, em = st.sampled_photons, st.sampled_substeps, st.pairs
+        byts = (BYTES_PER_PHOTON_READ + 8 + BYTES_PER_PHOTON_WRITE + 1) * part + st.particles[2] \
+            + 2 * BYTES_PER_EMISSION * em
         flops = FLOPS_PER_PHOTON_SUBSTEP * sub
     byts /= max(nl, 1)
     flops /= max(nl, 1)
@@ -163,50 +174,48 @@ def roofline(kt, st, K):
     return roof
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--scheduler", choices=("naive", "binned"), default="naive")
-    ap.add_argument("--no-graph", action="store_true", help="launch steps eagerly in the timed pass")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
-        sys.exit(2)
+def load_tuning(qed, g, key, path):
+    """Apply the autotuner's choice for this workload and scheduler, if recorded."""
+    if not path or not os.path.exists(path):
+        return None
+    table = json.load(open(path))
+    choice = table.get(key)
+    if not choice:
+        return None
+    t = qed.qed_get_tuning(g.ctx)
+    for k, v in choice["tuning"].items():
+        setattr(t, k, int(v))
+    assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK, choice
+    return choice["tuning"]
 
-    import torch
 
-    import workloads
-    from paper_2008_10468_amd import qed
+def stepped(torch, qed, g, stream, fields_for_step, state, dt, seed, K, W, use_graph):
+    """Warm-up, graph capture, a timed pass and a profiled pass of K steps from state."""
+    import ctypes as C
+    lib = qed.load()
 
-    torch.cuda.set_device(0)
-    K, W = args.steps, args.warmup
-    sched = qed.QED_SCHED_BINNED if args.scheduler == "binned" else qed.QED_SCHED_NAIVE
-    stream = torch.cuda.Stream()
-    w, g, field = c2_setup(torch, qed, workloads, max(K, W), sched, stream)
-    log(f"bench: C2 workload, {w['electrons']['id'].size} e- + {w['photons']['id'].size} photons, "
-        f"dt={w['dt']}, steps={K}, warmup={W}")
+    def run(first, count):
+        parts = C.byref(g.particles())
+        flds = [fields_for_step(s) for s in range(first, first + count)]
+        for j, s in enumerate(range(first, first + count)):
+            st = lib.qed_step(g.ctx, parts, flds[j], float(dt), int(seed), s)
+            if st != qed.QED_OK:
+                raise qed.QedError(st, "qed_step")
 
-    # warm-up on the workload (this also sizes the library's scratch), then restore
-    # the initial state
-    g.load_state(w)
+    g.load_state(state)
     torch.cuda.synchronize()
-    run_steps(qed, g, field, w, 0, W)
+    run(0, W)
     st, rep = g.sync()
-    assert st == qed.QED_OK, qed.status_string(st)
+    assert st == qed.QED_OK, (qed.status_string(st), list(rep.required_capacity))
     graph = None
-    if not args.no_graph:
-        # all K steps recorded once into one HIP graph; the timed pass replays it
+    if use_graph:
         assert qed.qed_graph_begin(g.ctx) == qed.QED_OK
-        run_steps(qed, g, field, w, 0, K)
+        run(0, K)
         st, graph = qed.qed_graph_end(g.ctx)
         assert st == qed.QED_OK, qed.status_string(st)
 
     def timed(profile):
-        g.load_state(w)
+        g.load_state(state)
         qed.qed_reset_stats(g.ctx)
         qed.qed_profile_enable(g.ctx, profile)
         torch.cuda.synchronize()
@@ -216,7 +225,7 @@ def main():
         if graph is not None and not profile:
             assert qed.qed_graph_launch(g.ctx, graph) == qed.QED_OK
         else:
-            run_steps(qed, g, field, w, 0, K)
+            run(0, K)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
@@ -228,46 +237,178 @@ def main():
         return ms, stats, rep, kt
 
     ms, stats, rep, _ = timed(False)
-    ms_p, stats_p, _, kt = timed(True)
-    sub = sum(stats.substeps)
-    ev = stats.emissions + stats.pairs
-    value = sub / (ms * 1e-3)
+    _, stats_p, _, kt = timed(True)
+    if graph is not None:
+        qed.qed_graph_destroy(graph)
     log(f"bench: {ms:.3f} ms for {K} steps; sub-steps e-/e+/g = {list(stats.substeps)}; "
         f"particle-steps {list(stats.particles)}; emissions {stats.emissions}, pairs {stats.pairs}; "
         f"final counts {list(rep.n)}")
     log("bench: kernel times (profiled pass): " +
         ", ".join(f"{k}: {v[1] / max(v[0], 1) * 1e3:.1f} us x{v[0]}" for k, v in kt.items()))
+    return ms, stats, stats_p, kt, graph is not None
 
-    roof = roofline(kt, stats_p, K)
-    out = {
-        "metric": "particle-sub-steps/s",
-        "value": value,
-        "unit": "particle-sub-steps/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": ms / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": "C2: 1,048,576 e- + 262,144 photons, uniform E = 1e-3 E_S rotating with period "
-                        "200 steps, emission + pair creation, mixed precision (f32 push and synchrotron "
-                        "functions, f64 sub-step count and positions), buffers growing by appends",
-            "steps": K, "p_max": 0.01, "dt_hbar_over_mc2": w["dt"], "seed": w["seed"],
-            "scheduler": args.scheduler,
-            "launch": "eager" if graph is None else "one HIP graph of all timed steps",
-        },
-        "events_per_s": ev / (ms * 1e-3),
-        "roofline": roof,
-    }
+
+def header(args, value, ms, K, W, dtype, config, metric="particle-sub-steps/s"):
+    return {"metric": metric, "value": value, "unit": metric, "n_gpus": 1, "steps": K, "warmup": W,
+            "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def bench_c2(args, torch, qed, workloads):
+    K, W = args.steps, args.warmup
+    sched = qed.QED_SCHED_BINNED if args.scheduler == "binned" else qed.QED_SCHED_NAIVE
+    stream = torch.cuda.Stream()
+    w, g, field = c2_setup(torch, qed, workloads, max(K, W), sched, stream)
+    tuned = load_tuning(qed, g, f"c2/{args.scheduler}", args.tuning)
+    log(f"bench: C2 workload, {w['electrons']['id'].size} e- + {w['photons']['id'].size} photons, "
+        f"dt={w['dt']}, steps={K}, warmup={W}, tuning={tuned}")
+    fields = lambda s: (qed.qed_field * 3)(field(s), field(s), field(s))
+    ms, stats, stats_p, kt, graphed = stepped(torch, qed, g, stream, fields, w, w["dt"], w["seed"], K, W,
+                                              not args.no_graph)
+    sub = sum(stats.substeps)
+    out = header(args, sub / (ms * 1e-3), ms, K, W, "f32", {
+        "workload": "C2: 1,048,576 e- + 262,144 photons, uniform E = 1e-3 E_S rotating with period "
+                    "200 steps, emission + pair creation, mixed precision (f32 push and synchrotron "
+                    "functions, f64 sub-step count and positions), buffers growing by appends",
+        "steps": K, "p_max": 0.01, "dt_hbar_over_mc2": w["dt"], "seed": w["seed"],
+        "scheduler": args.scheduler, "tuning": tuned,
+        "launch": "one HIP graph of all timed steps" if graphed else "eager"})
+    out["events_per_s"] = (stats.emissions + stats.pairs) / (ms * 1e-3)
+    out["roofline"] = roofline(kt, stats_p, K)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(workloads, args.cpu_seconds)
-    if graph is not None:
-        qed.qed_graph_destroy(graph)
     g.close()
+    return out
+
+
+def bench_c1(args, torch, qed, workloads):
+    """FP64 correctness configuration: 16,384 electrons in a uniform static B field."""
+    K, W = (args.steps if args.steps_given else 100), args.warmup
+    w = workloads.c1()
+    stream = torch.cuda.Stream()
+    sched = qed.QED_SCHED_BINNED if args.scheduler == "binned" else qed.QED_SCHED_NAIVE
+    g = qed.Generator(precision=qed.QED_PREC_F64, capacity=(16384, 16, 1 << 22), pairs=False,
+                      parent=False, events=False, scheduler=sched, stream=stream.cuda_stream)
+    g.set_fields(w["fields"])
+    f = g.fields[0].struct()
+    fields = lambda s: (qed.qed_field * 3)(f, f, f)
+    ms, stats, stats_p, kt, graphed = stepped(torch, qed, g, stream, fields, w, w["dt"], w["seed"], K, W,
+                                              not args.no_graph)
+    out = header(args, sum(stats.substeps) / (ms * 1e-3), ms, K, W, "f64", {
+        "workload": "C1: 16,384 electrons, gamma log-uniform [1e2, 1e4], isotropic, uniform B = 1e-3 E_S, "
+                    "emission only, FP64", "steps": K, "dt_hbar_over_mc2": w["dt"],
+        "scheduler": args.scheduler})
+    out["events_per_s"] = stats.emissions / (ms * 1e-3)
+    g.close()
+    return out
+
+
+def bench_c3(args, torch, qed, workloads):
+    """Uneven batch: 16,777,216 electrons, 10% in a Gaussian hot spot (chi up to 100)."""
+    K, W = (args.steps if args.steps_given else 50), args.warmup
+    n = int(args.c3_particles)
+    w = workloads.c3(n=n)
+    stream = torch.cuda.Stream()
+    sched = qed.QED_SCHED_BINNED if args.scheduler == "binned" else qed.QED_SCHED_NAIVE
+    cap_ph = int(min(n * max(K, W) // 4 + (1 << 22), 1 << 31))   # about 3 photons per 16 e- per step
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, cap_ph), pairs=False, parent=False,
+                      events=False, scheduler=sched, stream=stream.cuda_stream)
+    tuned = load_tuning(qed, g, f"c3/{args.scheduler}", args.tuning)
+    zero = workloads.uniform_field()
+    g.set_fields(None, per_species=[w["fields"], zero, zero])
+    fl = [f.struct() for f in g.fields]
+    fields = lambda s: (qed.qed_field * 3)(*fl)
+    log(f"bench: C3 workload, {n} e-, hot fraction 0.1, dt={w['dt']}, steps={K}, tuning={tuned}")
+    ms, stats, stats_p, kt, graphed = stepped(torch, qed, g, stream, fields, w, w["dt"], w["seed"], K, W,
+                                              not args.no_graph)
+    out = header(args, sum(stats.substeps) / (ms * 1e-3), ms, K, W, "f32", {
+        "workload": f"C3: {n} electrons, 90% in B = 5e-7 E_S, 10% in a Gaussian hot spot "
+                    "B = 1e-2 exp(-r^2/2) E_S (chi up to ~100), per-particle static fields, emission only, "
+                    "mixed precision", "steps": K, "dt_hbar_over_mc2": w["dt"],
+        "scheduler": args.scheduler, "tuning": tuned,
+        "launch": "one HIP graph of all timed steps" if graphed else "eager"})
+    out["events_per_s"] = stats.emissions / (ms * 1e-3)
+    out["roofline"] = roofline(kt, stats_p, K)
+    g.close()
+    return out
+
+
+def bench_c4(args, torch, qed, workloads):
+    """Synchrotron-function microbenchmark: F and G of 2^28 log-uniform x in [1e-4, 50]."""
+    n = 1 << int(args.c4_log2n)
+    cfg = qed.qed_config_default()
+    stream = torch.cuda.Stream()
+    cfg.stream = stream.cuda_stream
+    ctx = qed.qed_init(cfg)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    res = {}
+    for dtype in (torch.float32, torch.float64):
+        u = torch.rand(n, generator=gen, device="cuda", dtype=torch.float64)
+        x = (10.0 ** (-4.0 + u * (math.log10(50.0) + 4.0))).to(dtype)
+        del u
+        F = torch.empty_like(x)
+        G = torch.empty_like(x)
+        qd = qed.QED_F32 if dtype == torch.float32 else qed.QED_F64
+        for _ in range(2):
+            assert qed.qed_synchrotron(ctx, x.data_ptr(), F.data_ptr(), G.data_ptr(), n, qd) == qed.QED_OK
+        torch.cuda.synchronize()
+        reps = 5
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            qed.qed_synchrotron(ctx, x.data_ptr(), F.data_ptr(), G.data_ptr(), n, qd)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        assert qed.qed_sync(ctx)[0] == qed.QED_OK
+        bpe = 3 * x.element_size()
+        res[str(dtype).split(".")[-1]] = {"evals_per_s": n / (ms * 1e-3), "ms": ms,
+                                          "hbm_GBps": n * bpe / (ms * 1e-3) / 1e9}
+        log(f"bench: C4 {dtype}: {ms:.3f} ms for {n} evaluations, {res[str(dtype).split('.')[-1]]}")
+        del x, F, G
+    qed.qed_finalize(ctx)
+    r32 = res["float32"]
+    out = header(args, r32["evals_per_s"], r32["ms"], 1, 2, "f32", {
+        "workload": f"C4: F and G of 2^{args.c4_log2n} x log-uniform in [1e-4, 50], resident in HBM"},
+        metric="evaluations/s")
+    out["per_dtype"] = res
+    out["roofline"] = {"bound": "hbm", "achieved": r32["hbm_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": r32["hbm_GBps"] / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "k_synchrotron<float>", "avg_launch_us": r32["ms"] * 1e3}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=("c2", "c1", "c3", "c4"), default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--scheduler", choices=("naive", "binned"), default="naive")
+    ap.add_argument("--no-graph", action="store_true", help="launch steps eagerly in the timed pass")
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2008_10468_amd", "tuning_gfx950.json"))
+    ap.add_argument("--c3-particles", type=float, default=16777216)
+    ap.add_argument("--c4-log2n", type=int, default=28)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    args.steps_given = args.steps is not None
+    if args.steps is None:
+        args.steps = 200
+
+    import torch
+
+    import workloads
+    from paper_2008_10468_amd import qed
+
+    torch.cuda.set_device(0)
+    fn = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4}[args.workload]
+    out = fn(args, torch, qed, workloads)
     print(json.dumps(out), flush=True)
 
 

@@ -116,6 +116,9 @@ typedef struct qed_stats {
     uint64_t particles[3];/* particle-steps (particles processed, summed over steps) */
     uint64_t heavy_particles, heavy_substeps; /* part of the above run by the heavy-queue
                                                  kernel of the binned scheduler */
+    uint64_t sampled_photons, sampled_substeps; /* photons (and their sub-steps) that ran
+                                                   the pair sampling loop; the others
+                                                   could not decay and only moved */
     uint64_t emissions;   /* photons emitted */
     uint64_t pairs;       /* photons that decayed into pairs */
     uint64_t clips;       /* sub-steps whose acceptance probability exceeded 1 */

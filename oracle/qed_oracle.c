@@ -369,30 +369,30 @@ static int lepton_one(const orc_params *P, double q, double u[3], double pos[3],
         *nev_out = 0;
         return -1;
     }
-    /* Algorithm 1, line 1: sub-step from the bound at the step start. */
+    /* Algorithm 1: sub-step from the bound at the step start. */
     double gamma0 = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     double chi0 = orc_chi_lepton(u, E, B);
     uint32_t N = orc_nsub(orc_bound_emission(chi0, gamma0, P->dt), P->p_max, P->n_cap);
     double st = P->dt / (double)N;
     uint32_t nev = 0;
     for (uint32_t i = 0; i < N; ++i) {
-        /* line 3: Boris push by st in the frozen field, then move */
+        /* push: Boris rotation by st in the frozen field, then move */
         orc_boris(u, E, B, q, st);
         double gamma = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         pos[0] += u[0] / gamma * st;
         pos[1] += u[1] / gamma * st;
         pos[2] += u[2] / gamma * st;
-        /* line 4 */
+        /* quantum parameter after the push */
         double chi = orc_chi_lepton(u, E, B);
-        /* line 5 */
+        /* draw the candidate x and the test value y */
         double x, y;
         orc_draw_xy(P->seed, id, P->step, i, P->rng_bits, &x, &y);
-        /* line 6 */
+        /* acceptance test against eq. (1) */
         double pm = orc_pm(x, chi, gamma, st);
         if (pm > tl->max_p) tl->max_p = pm;
         if (pm > 1.0) tl->clips++;
         if (y < pm) {
-            /* line 7: photon of energy fraction delta = x^3 along u, same weight;
+            /* emission: photon of energy fraction delta = x^3 along u, same weight;
              * the parent keeps its direction and loses the photon energy. */
             double delta = x * x * x;
             double umag = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
@@ -447,21 +447,21 @@ static int photon_one(const orc_params *P, double k[3], double pos[3], double w,
     int decayed = 0;
     for (uint32_t i = 0; i < N; ++i) {
         used++;
-        /* line 3: straight line at the speed of light */
+        /* move: straight line at the speed of light */
         pos[0] += dir[0] * st;
         pos[1] += dir[1] * st;
         pos[2] += dir[2] * st;
-        /* line 4 */
+        /* photon quantum parameter */
         double chi = orc_chi_photon(k, E, B);
-        /* line 5 */
+        /* draw the candidate x and the test value y */
         double x, y;
         orc_draw_xy(P->seed, id, P->step, i, P->rng_bits, &x, &y);
-        /* line 6 */
+        /* acceptance test against eq. (2) */
         double pp = orc_pp(x, chi, eps, st);
         if (pp > tl->max_p) tl->max_p = pp;
         if (pp > 1.0) tl->clips++;
         if (y < pp) {
-            /* lines 7-8: electron takes energy fraction x, positron 1-x, both
+            /* pair creation: electron takes energy fraction x, positron 1-x, both
              * along the photon, same weight; the photon is deleted. */
             double ge = x * eps, gp = (1.0 - x) * eps;
             double ue = ge * ge - 1.0, up = gp * gp - 1.0;

@@ -357,6 +357,8 @@ qed_status qed_get_stats(qed_ctx *c, qed_stats *out) {
     }
     out->heavy_particles = h.heavy_particles;
     out->heavy_substeps = h.heavy_substeps;
+    out->sampled_photons = h.sampled_photons;
+    out->sampled_substeps = h.sampled_substeps;
     out->emissions = h.emissions;
     out->pairs = h.pairs;
     out->clips = h.clips;
@@ -378,6 +380,7 @@ qed_status qed_reset_stats(qed_ctx *c) {
     h.substeps[0] = h.substeps[1] = h.substeps[2] = 0;
     h.particles[0] = h.particles[1] = h.particles[2] = 0;
     h.heavy_particles = h.heavy_substeps = 0;
+    h.sampled_photons = h.sampled_substeps = 0;
     h.emissions = h.pairs = h.clips = h.capped = 0;
     h.max_p_bits = 0;
     HIP_TRY(hipMemcpy(c->st, &h, sizeof(h), hipMemcpyHostToDevice));

@@ -31,6 +31,8 @@ struct DevState {
     alignas(128) u64 substeps[3];  // cumulative particle-sub-steps per species
     alignas(128) u64 heavy_particles;  // cumulative work of the heavy-queue kernel
     alignas(128) u64 heavy_substeps;
+    alignas(128) u64 sampled_photons;  // cumulative work of the photon sampling pass
+    alignas(128) u64 sampled_substeps;
     alignas(128) u64 emissions;
     alignas(128) u64 pairs;
     alignas(128) u64 clips;

@@ -95,9 +95,11 @@ struct Tally {
 
 // Block-wide reduction of the tallies, then one atomic per counter and block.
 // Every thread of the block must call it.
+// work: 1 = heavy-queue kernel, 2 = photon sampling pass (their particles and
+// sub-steps are also counted separately).
 template <class R>
 __device__ __forceinline__ void flush_tally(const Tally<R> &t, DevState *st, int species,
-                                            bool heavy = false) {
+                                            int work = 0) {
     __shared__ u64 red[kBlock / 64][8];
     const u64 v[7] = {wave_sum(t.substeps), (u64)wave_sum(t.events), (u64)wave_sum(t.clips),
                       (u64)wave_sum(t.capped), (u64)wave_sum(t.nonfinite),
@@ -124,9 +126,12 @@ __device__ __forceinline__ void flush_tally(const Tally<R> &t, DevState *st, int
             atomicAdd(&st->nonfinite, tot[4]);
             atomicOr(&st->status_bits, 2ull);
         }
-        if (heavy) {
+        if (work == 1) {
             if (tot[5]) atomicAdd(&st->heavy_particles, tot[5]);
             if (tot[0]) atomicAdd(&st->heavy_substeps, tot[0]);
+        } else if (work == 2) {
+            if (tot[5]) atomicAdd(&st->sampled_photons, tot[5]);
+            if (tot[0]) atomicAdd(&st->sampled_substeps, tot[0]);
         }
         if (mb) atomicMax(&st->max_p_bits, mb);
     }
@@ -238,7 +243,7 @@ __device__ __forceinline__ Lepton<R> load_lepton(const StepArgs &a, int s, u64 i
     return p;
 }
 
-// Algorithm 1, line 1: the sub-step count from the bound at the step start
+// Algorithm 1, step start: the sub-step count from the bound
 // (double).  0 for non-finite input (the particle is left alone).
 template <class R>
 __device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<R> &p, Tally<R> &tl) {
@@ -254,7 +259,7 @@ __device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<
     return N;
 }
 
-// Algorithm 1, lines 2-7, for one electron (s = 0, q = -1) or positron (s = 1,
+// Algorithm 1's sub-step loop for one electron (s = 0, q = -1) or positron (s = 1,
 // q = +1) with N >= 1 sub-steps.  s is uniform across the wave.  FK: field kind
 // (0 general, 1 pure E, 2 pure B), see boris().
 template <class R, int FK>
@@ -277,7 +282,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
     uint32_t nev = 0;
     Draw<R> draw;
     for (uint32_t k = 0; k < N; ++k) {
-        // line 3: Boris push and move
+        // push: Boris rotation and move
         boris<R, FK>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
         const R u2 = ux * ux + uy * uy + uz * uz;
         const R ig = rsqrt_(R(1) + u2);
@@ -286,12 +291,12 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
         dx += ux * vs;
         dy += uy * vs;
         dz += uz * vs;
-        // line 4
+        // quantum parameter after the push
         const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
-        // line 5
+        // candidate x and test value y
         R x, y;
         draw.get(k, idlo, idhi, a.step, klo, khi, x, y);
-        // line 6: y < 3 x^2 P(x^3) = (c b / x) ((1 - x^3) F(z) + x^6 G(z)),
+        // acceptance (eq. (1)): y < 3 x^2 P(x^3) = (c b / x) ((1 - x^3) F(z) + x^6 G(z)),
         //         z = x^3 / (b (1 - x^3))
         const R x2 = x * x, x3 = x2 * x;
         const R omx3 = (R(1) - x) * (R(1) + x + x2);
@@ -303,7 +308,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
         tl.max_p = fmax(tl.max_p, pm);
         tl.clips += pm > R(1);
         const bool acc = y < pm;
-        // line 7: stage the photon in the wave's LDS buffer, recoil on the parent
+        // emission: stage the photon in the wave's LDS buffer, recoil on the parent
         const u64 m = __ballot(acc);
         if (m) {
             const uint32_t c = (uint32_t)__popcll(m);
@@ -421,11 +426,11 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
     Draw<R> draw;
     for (uint32_t k = 0; k < N && !dead; ++k) {
         used = k + 1;
-        // line 3: move at the speed of light
+        // move at the speed of light
         dx += dirx * str;
         dy += diry * str;
         dz += dirz * str;
-        // lines 5-6
+        // candidate x, test value y, acceptance against eq. (2)
         R x, y;
         draw.get(k, idlo, idhi, a.step, klo, khi, x, y);
         const R xx = x * (R(1) - x);
@@ -436,7 +441,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
         tl.max_p = fmax(tl.max_p, pp);
         tl.clips += pp > R(1);
         const bool acc = y < pp;
-        // lines 7-8: electron with x eps, positron with (1-x) eps, along k; delete
+        // pair creation: electron with x eps, positron with (1-x) eps, along k; delete
         const u64 m = __ballot(acc);
         if (m) {
             const int leader = __ffsll((long long)m) - 1;
@@ -731,11 +736,11 @@ __global__ __launch_bounds__(kBlock) void k_heavy(StepArgs a) {
         base = __shfl(nb, 0);
     }
     flush_children_block(L.cb, a.sp[2]);
-    flush_tally(t, a.st, s, true);
+    flush_tally(t, a.st, s, 1);
 }
 
-// Algorithm 2, pass 1, for every photon: line 1, and for photons that cannot decay
-// in this step (photon_quiet) lines 2-3 as well: they only move.  The others are
+// Algorithm 2, pass 1, for every photon: the step-start bound, and for photons that
+// cannot decay in this step (photon_quiet) the whole sub-step loop: they only move.  The others are
 // marked alive = 2 for pass 2.  Light on registers; each lane takes kPhotonBatch
 // photons per round and issues all their loads before using any, and a uniform
 // field (stride 0) is loaded once, so the pass streams.
@@ -882,10 +887,11 @@ __global__ __launch_bounds__(kBlock) void k_photon_sample(StepArgs a) {
             Tally<R> ignore;  // pass 1 counted the capped ones
             photon_start<R>(a, i, kx, ky, kz, ps, ignore);
             photon_sample<R>(a, i, kx, ky, kz, ps, tab, t);
+            t.particles++;
         }
         __syncthreads();
     }
-    flush_tally(t, a.st, 2);
+    flush_tally(t, a.st, 2, 2);
 }
 
 __global__ void k_begin(StepArgs a) {

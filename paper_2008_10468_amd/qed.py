@@ -50,7 +50,8 @@ class qed_report(C.Structure):
 
 class qed_stats(C.Structure):
     _fields_ = [("steps", C.c_uint64), ("substeps", C.c_uint64 * 3), ("particles", C.c_uint64 * 3),
-                ("heavy_particles", C.c_uint64), ("heavy_substeps", C.c_uint64), ("emissions", C.c_uint64),
+                ("heavy_particles", C.c_uint64), ("heavy_substeps", C.c_uint64),
+                ("sampled_photons", C.c_uint64), ("sampled_substeps", C.c_uint64), ("emissions", C.c_uint64),
                 ("pairs", C.c_uint64), ("clips", C.c_uint64), ("capped", C.c_uint64),
                 ("max_p", C.c_double)]
 
