@@ -41,6 +41,10 @@ BYTES_PER_PHOTON_READ = 36          # k 12 + position 24
 BYTES_PER_PHOTON_WRITE = 25         # position 24 + flag 1
 FLOPS_PER_PHOTON_MOVE = 6           # three fused multiply-adds per sub-step
 BYTES_PER_BINNED_EXTRA = 8          # sub-step count read 4 + queue entry read 4 (heavy pass)
+SCHEDULERS = {"naive": lambda q: q.QED_SCHED_NAIVE, "binned": lambda q: q.QED_SCHED_BINNED,
+              "tiled": lambda q: q.QED_SCHED_TILED}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -256,7 +260,7 @@ def header(args, value, ms, K, W, dtype, config, metric="particle-sub-steps/s"):
 
 def bench_c2(args, torch, qed, workloads):
     K, W = args.steps, args.warmup
-    sched = qed.QED_SCHED_BINNED if args.scheduler == "binned" else qed.QED_SCHED_NAIVE
+    sched = SCHEDULERS[args.scheduler](qed)
     stream = torch.cuda.Stream()
     w, g, field = c2_setup(torch, qed, workloads, max(K, W), sched, stream)
     tuned = load_tuning(qed, g, f"c2/{args.scheduler}", args.tuning)
@@ -286,7 +290,7 @@ def bench_c1(args, torch, qed, workloads):
     K, W = (args.steps if args.steps_given else 100), args.warmup
     w = workloads.c1()
     stream = torch.cuda.Stream()
-    sched = qed.QED_SCHED_BINNED if args.scheduler == "binned" else qed.QED_SCHED_NAIVE
+    sched = SCHEDULERS[args.scheduler](qed)
     g = qed.Generator(precision=qed.QED_PREC_F64, capacity=(16384, 16, 1 << 22), pairs=False,
                       parent=False, events=False, scheduler=sched, stream=stream.cuda_stream)
     g.set_fields(w["fields"])
@@ -309,8 +313,8 @@ def bench_c3(args, torch, qed, workloads):
     n = int(args.c3_particles)
     w = workloads.c3(n=n)
     stream = torch.cuda.Stream()
-    sched = qed.QED_SCHED_BINNED if args.scheduler == "binned" else qed.QED_SCHED_NAIVE
-    cap_ph = int(min(n * max(K, W) // 4 + (1 << 22), 1 << 31))   # about 3 photons per 16 e- per step
+    sched = SCHEDULERS[args.scheduler](qed)
+    cap_ph = int(min(0.65 * n * max(K, W) + (1 << 23), 1 << 31))   # about 0.55 photons per e- per step
     g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, cap_ph), pairs=False, parent=False,
                       events=False, scheduler=sched, stream=stream.cuda_stream)
     tuned = load_tuning(qed, g, f"c3/{args.scheduler}", args.tuning)
@@ -380,19 +384,98 @@ def bench_c4(args, torch, qed, workloads):
     return out
 
 
+def bench_c5(args, torch, qed, workloads):
+    """Learned sampler: train the network on this GPU, then run the hot-spot workload
+    with the surrogate (optical depth + network, binned scheduler) against the plain
+    rejection generator (naive and binned)."""
+    K, W = (args.steps if args.steps_given else 20), args.warmup
+    n = int(args.c3_particles)
+    ctx = qed.qed_init(qed.qed_config_default())
+    tc = qed.qed_train_config_default()
+    t0 = time.perf_counter()
+    params, loss, err, fb = qed.qed_train_sampler(ctx, tc)
+    train_s = time.perf_counter() - t0
+    qed.qed_finalize(ctx)
+    batch = tc.blocks * 64 * tc.batch_tiles
+    log(f"bench: trained in {train_s:.2f} s ({tc.steps} steps x {batch} samples); final loss {loss[-1]:.3e}; "
+        f"bins above {tc.tolerance}: {int(fb.sum())} of {tc.nbins}; max bin error {err.max():.2e}")
+    if args.save_model:
+        np.savez(args.save_model, params=params, fallback=fb, bin_err=err, loss=loss,
+                 log10_chi_lo=tc.log10_chi_lo, log10_chi_hi=tc.log10_chi_hi)
+    w = workloads.c3(n=n)
+    zero = workloads.uniform_field()
+    cap_ph = int(min(0.65 * n * max(K, W) + (1 << 23), 1 << 31))
+    runs = {}
+    for name, sched, sampler in (("plain_naive", qed.QED_SCHED_NAIVE, qed.QED_SAMPLER_REJECTION),
+                                 ("plain_binned", qed.QED_SCHED_BINNED, qed.QED_SAMPLER_REJECTION),
+                                 ("surrogate_rejection_binned", qed.QED_SCHED_BINNED, qed.QED_SAMPLER_SURROGATE),
+                                 ("surrogate_binned", qed.QED_SCHED_BINNED, qed.QED_SAMPLER_SURROGATE)):
+        stream = torch.cuda.Stream()
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, cap_ph), pairs=False, parent=False,
+                          events=False, scheduler=sched, stream=stream.cuda_stream, sampler=sampler)
+        if name == "surrogate_binned":
+            assert qed.qed_sampler_set(g.ctx, params, fb, tc.log10_chi_lo, tc.log10_chi_hi) == qed.QED_OK
+        g.set_fields(None, per_species=[w["fields"], zero, zero])
+        fl = [f.struct() for f in g.fields]
+        fields = lambda s: (qed.qed_field * 3)(*fl)
+        log(f"bench: C5 {name}")
+        ms, stats, stats_p, kt, graphed = stepped(torch, qed, g, stream, fields, w, w["dt"], w["seed"], K, W,
+                                                  not args.no_graph)
+        runs[name] = {"substeps_per_s": sum(stats.substeps) / (ms * 1e-3), "ms_per_step": ms / K,
+                      "events_per_s": stats.emissions / (ms * 1e-3), "emissions": stats.emissions,
+                      "learned_events": stats.learned_events, "fallback_events": stats.fallback_events,
+                      "fallback_draws": stats.fallback_draws}
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    best = runs["surrogate_binned"]
+    out = header(args, best["substeps_per_s"], best["ms_per_step"] * K, K, W, "f32+bf16", {
+        "workload": f"C5: learned sampler (2-64-64-64-1, bf16 hidden layers) deployed in the hot-spot "
+                    f"workload ({n} electrons, 10% hot), surrogate + binned vs plain rejection",
+        "steps": K, "train_steps": tc.steps, "train_batch": batch})
+    out["runs"] = runs
+    out["speedup_vs_plain_naive"] = best["substeps_per_s"] / runs["plain_naive"]["substeps_per_s"]
+    out["speedup_vs_plain_binned"] = best["substeps_per_s"] / runs["plain_binned"]["substeps_per_s"]
+    out["network_gain_vs_rejection"] = best["substeps_per_s"] / runs["surrogate_rejection_binned"]["substeps_per_s"]
+    out["training"] = {"seconds": train_s, "samples": tc.steps * batch, "final_loss": float(loss[-1]),
+                       "bins": tc.nbins, "fallback_bins": int(fb.sum()), "max_bin_cdf_error": float(err.max()),
+                       "median_bin_cdf_error": float(np.median(err))}
+    return out
+
+
+def copy_probe(torch, mib):
+    """One plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counter readings
+    convert the generator kernels' readings into bytes."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return {"bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms, "GBps": 8 * n / (ms * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=("c2", "c1", "c3", "c4"), default="c2")
+    ap.add_argument("--workload", choices=("c2", "c1", "c3", "c4", "c5"), default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--scheduler", choices=("naive", "binned"), default="naive")
+    ap.add_argument("--scheduler", choices=("naive", "binned", "tiled"), default="naive")
     ap.add_argument("--no-graph", action="store_true", help="launch steps eagerly in the timed pass")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2008_10468_amd", "tuning_gfx950.json"))
     ap.add_argument("--c3-particles", type=float, default=16777216)
     ap.add_argument("--c4-log2n", type=int, default=28)
+    ap.add_argument("--save-model", default=None, help="c5: write the trained network to this .npz")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-MiB float buffer once (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -407,8 +490,10 @@ def main():
     from paper_2008_10468_amd import qed
 
     torch.cuda.set_device(0)
-    fn = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4}[args.workload]
+    fn = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload]
     out = fn(args, torch, qed, workloads)
+    if args.copy_probe:
+        out["copy_probe"] = copy_probe(torch, args.copy_probe)
     print(json.dumps(out), flush=True)
 
 

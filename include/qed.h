@@ -55,10 +55,26 @@ typedef enum qed_dtype { QED_F32 = 0, QED_F64 = 1 } qed_dtype;
  *   double (24-bit uniforms, one Philox block per two sub-steps). */
 typedef enum qed_precision { QED_PREC_F64 = 0, QED_PREC_MIXED = 1 } qed_precision;
 
+/* How a lepton decides when it emits and with which energy.
+ * QED_SAMPLER_REJECTION: Algorithm 1 as printed, one candidate (x, y) per sub-step
+ *   accepted against eq. (1).
+ * QED_SAMPLER_SURROGATE: the same sub-steps and push, but the emission time comes
+ *   from the optical depth: each sub-step subtracts W(chi, gamma) sub_t from the
+ *   particle's remaining optical depth tau (accumulated in double), with the total
+ *   rate W = int_0^1 eq. (1) dx per unit time from a fit; when tau reaches zero
+ *   the particle emits and draws tau = -ln(u').  The energy fraction comes from
+ *   the learned inverse CDF of eq. (1) set by qed_sampler_set, or, for chi outside
+ *   its range or in a bin flagged as not accurate enough, from rejection sampling
+ *   of eq. (1) at that chi.  Statistically equivalent to Algorithm 1, not
+ *   particle-by-particle identical.  QED_PREC_MIXED only. */
+typedef enum qed_sampler { QED_SAMPLER_REJECTION = 0, QED_SAMPLER_SURROGATE = 1 } qed_sampler;
+
 /* Scheduling of the per-particle work (results are identical for both). */
 typedef enum qed_scheduler {
-    QED_SCHED_NAIVE = 0, /* one lane per particle in buffer order */
-    QED_SCHED_BINNED = 1 /* sub-step-count binned persistent work queue */
+    QED_SCHED_NAIVE = 0,  /* one lane per particle in buffer order */
+    QED_SCHED_BINNED = 1, /* sub-step-count binned persistent work queue */
+    QED_SCHED_TILED = 2   /* one pass: each wave sorts tiles of 512 consecutive particles
+                             by sub-step count in LDS and runs them in that order */
 } qed_scheduler;
 
 /* One particle species, structure of arrays.  Slot i of every array belongs to
@@ -74,6 +90,10 @@ typedef struct qed_species {
     uint64_t *parent;   /* optional (NULL): id of the parent, written for new particles */
     uint32_t *events;   /* optional (NULL): events of each pre-existing particle in the
                            last step (emissions of a lepton; 1 if a photon decayed) */
+    double *tau;        /* electrons and positrons with QED_SAMPLER_SURROGATE (required
+                           there, ignored otherwise): optical depth left until the next
+                           emission; a value <= 0 or NaN makes the particle draw a fresh
+                           one.  New pairs get -1. */
 } qed_species;
 
 typedef struct qed_particles {
@@ -98,6 +118,7 @@ typedef struct qed_config {
     int scheduler;          /* qed_scheduler */
     double pair_bound_coef; /* coefficient of the pair bound f = coef c b; 0.1 */
     uint32_t max_substeps;  /* cap on sub-steps per particle and step; 1 << 24 */
+    int sampler;            /* qed_sampler; QED_SAMPLER_REJECTION */
 } qed_config;
 
 /* Errors and counts observed on the device since the previous qed_sync. */
@@ -124,6 +145,10 @@ typedef struct qed_stats {
     uint64_t clips;       /* sub-steps whose acceptance probability exceeded 1 */
     uint64_t capped;      /* particle-steps whose sub-step count hit max_substeps */
     double max_p;         /* largest acceptance probability evaluated */
+    uint64_t learned_events;  /* surrogate: energies drawn from the learned inverse CDF */
+    uint64_t fallback_events; /* surrogate: energies drawn by rejection */
+    uint64_t fallback_draws;  /* surrogate: candidates those rejections used */
+    uint64_t envelope_clips;  /* surrogate: candidates above the rejection envelope */
 } qed_stats;
 
 typedef struct qed_ctx qed_ctx;
@@ -209,6 +234,88 @@ QED_API qed_status qed_graph_begin(qed_ctx *ctx);
 QED_API qed_status qed_graph_end(qed_ctx *ctx, qed_graph **out);
 QED_API qed_status qed_graph_launch(qed_ctx *ctx, qed_graph *g);
 QED_API void qed_graph_destroy(qed_graph *g);
+
+/* Learned inverse CDF of the emitted energy (the surrogate sampler's model).
+ * Network: inputs s = 2 (log10 chi - lo) / (hi - lo) - 1 and v = 2 u - 1; three
+ * hidden layers of 64 units with activation a(t) = t / sqrt(1 + t^2); output y;
+ * the candidate x = delta^(1/3) of eq. (1) is y (b / (1 + b))^(1/3), b = 3 chi / 2,
+ * clamped to (0, 1).  Layer 1 (2 -> 64) and the output layer (64 -> 1) run in
+ * float; the two 64 x 64 layers take bfloat16 weights and activations with float
+ * accumulation (matrix cores).  params holds QED_MLP_NPARAMS floats in the order
+ * W1[64][2], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[64], b4 (W[out][in]).
+ * fallback[j] != 0 sends chi bin j (nbins bins uniform in log10 chi over [lo, hi))
+ * to rejection sampling.  All pointers are HOST pointers; the model is copied. */
+#define QED_MLP_HIDDEN 64
+#define QED_MLP_NPARAMS 8577
+#define QED_MLP_MAX_BINS 256
+typedef struct qed_sampler_model {
+    const float *params;
+    const uint8_t *fallback;
+    int32_t nbins;          /* 1 .. QED_MLP_MAX_BINS */
+    int32_t pad;
+    double log10_chi_lo, log10_chi_hi;
+} qed_sampler_model;
+
+/* Install (m != NULL) or remove (m == NULL: rejection for every chi) the model.
+ * Stream-ordered with the context's later steps. */
+QED_API qed_status qed_sampler_set(qed_ctx *ctx, const qed_sampler_model *m);
+
+/* Energy-fraction candidates x = delta^(1/3) for n (chi, u) pairs (float DEVICE
+ * arrays) as the surrogate sampler draws them with the installed model: the
+ * network where it is used, else NaN (the bins that fall back to rejection). */
+QED_API qed_status qed_sampler_infer(qed_ctx *ctx, const float *chi, const float *u, float *x,
+                                     uint64_t n);
+
+/* Total emission rate of the surrogate sampler: for n float values chi (DEVICE),
+ * writes chi q(chi) (DEVICE) such that the probability of an emission in a
+ * sub-step of length s is alpha s chi q(chi) / gamma, i.e. eq. (1) integrated
+ * over the candidate x in [0, 1] (from the fit the generator uses). */
+QED_API qed_status qed_emission_rate(qed_ctx *ctx, const float *chi, float *chi_q, uint64_t n);
+
+/* The normalised CDF of eq. (1) over the candidate x, as the trainer tabulates it
+ * (double, from the double fits of F and G, trapezoid rule): nchi (>= 2) values
+ * of chi log-uniform over [10^lo, 10^hi], each at the nx + 1 points
+ * x = 1 - (1 - k/nx)^2, k = 0..nx (nx a multiple of 256).  cdf_out (HOST, nchi
+ * (nx + 1) doubles) gets the CDF rows, total_out (HOST, nchi doubles, may be NULL)
+ * the integral of eq. (1) over x divided by c b.  Synchronous. */
+QED_API qed_status qed_emission_cdf(qed_ctx *ctx, double log10_chi_lo, double log10_chi_hi, uint32_t nchi,
+                                    uint32_t nx, double *cdf_out, double *total_out);
+
+/* Training of the sampler's network on this GPU.  Samples: log10 chi uniform over
+ * [lo, hi], u uniform, target x = CDF_chi^{-1}(u) from the table above; loss:
+ * the squared error of the network output y weighted by the squared density
+ * dCDF/dy at the target (so it approximates the squared CDF error); Adam with a
+ * cosine-decayed step size; the batch is blocks x 4 waves x batch_tiles x 16
+ * samples.  After training, every chi bin is checked on a grid of 1024 u values
+ * at per_bin values of chi: the largest |CDF_chi(x(chi, u)) - u| of the packed
+ * network, and bins above tolerance are flagged to fall back to rejection. */
+typedef struct qed_train_config {
+    double log10_chi_lo, log10_chi_hi; /* chi range of the network; -3, 2 */
+    uint32_t table_chi, table_x;       /* CDF table; 1025 x 8192 */
+    uint32_t steps;                    /* optimizer steps; 2000 */
+    uint32_t blocks, batch_tiles;      /* batch = blocks * 64 * batch_tiles; 256, 4 */
+    float lr, lr_final;                /* 3e-3 -> 3e-5 */
+    uint64_t seed;                     /* data and initial weights; 1 */
+    int32_t nbins, per_bin;            /* validation; 50, 5 */
+    double tolerance;                  /* CDF error above which a bin falls back; 1e-3 */
+} qed_train_config;
+
+QED_API qed_status qed_train_config_default(qed_train_config *cfg);
+
+/* Synchronous.  init_params (HOST, QED_MLP_NPARAMS floats) may be NULL for a
+ * seeded initialisation.  Outputs (HOST): params_out (QED_MLP_NPARAMS), and,
+ * where not NULL, loss_out (steps values), bin_err_out and fallback_out (nbins
+ * values each). */
+QED_API qed_status qed_train_sampler(qed_ctx *ctx, const qed_train_config *cfg, const float *init_params,
+                                     float *params_out, float *loss_out, float *bin_err_out,
+                                     uint8_t *fallback_out);
+
+/* Loss and gradient of the training loss for given parameters and samples, from
+ * the same kernels as training (for checks).  samples: HOST, n rows of
+ * (s, v, y_target, weight), n a positive multiple of 64.  loss = (1/n) sum w (y -
+ * y_target)^2.  grad_out: HOST, QED_MLP_NPARAMS.  Synchronous. */
+QED_API qed_status qed_mlp_gradient(qed_ctx *ctx, const float *params, const float *samples, uint64_t n,
+                                    float *loss_out, float *grad_out);
 
 /* Release the context's scratch.  NULL is allowed. */
 QED_API void qed_finalize(qed_ctx *ctx);

@@ -157,7 +157,7 @@ def _workload(name, torch, workloads, sched, stream, steps):
     if name == "c3":
         w = workloads.c3()
         n = w["electrons"]["id"].size
-        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, n * steps // 4 + (1 << 22)),
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, int(0.65 * n * steps) + (1 << 23)),
                           pairs=False, parent=False, events=False, scheduler=sched,
                           stream=stream.cuda_stream)
         zero = workloads.uniform_field()
@@ -170,7 +170,7 @@ def _workload(name, torch, workloads, sched, stream, steps):
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Tune launch shapes of the QED generator on this GPU")
     ap.add_argument("--workload", choices=("c2", "c3"), action="append")
-    ap.add_argument("--scheduler", choices=("naive", "binned"), action="append")
+    ap.add_argument("--scheduler", choices=("naive", "binned", "tiled"), action="append")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--out", required=True)
@@ -184,8 +184,8 @@ def main(argv=None):
     table = json.load(open(args.out)) if os.path.exists(args.out) else {}
     table["device"] = torch.cuda.get_device_properties(0).gcnArchName
     for wl in args.workload or ["c2"]:
-        for sn in args.scheduler or ["naive", "binned"]:
-            sched = qed.QED_SCHED_BINNED if sn == "binned" else qed.QED_SCHED_NAIVE
+        for sn in args.scheduler or ["naive", "binned", "tiled"]:
+            sched = {"naive": qed.QED_SCHED_NAIVE, "binned": qed.QED_SCHED_BINNED, "tiled": qed.QED_SCHED_TILED}[sn]
             stream = torch.cuda.Stream()
             g, w, fields = _workload(wl, torch, workloads, sched, stream, args.steps)
             keys = BINNED_KEYS if sn == "binned" else NAIVE_KEYS

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -31,6 +32,8 @@ struct qed_ctx {
     std::vector<int> rec_id;  // kernel id of each recorded launch
     size_t rec_used;          // event pairs in use
     bool capturing;           // between qed_graph_begin and qed_graph_end
+    qed::MlpModel *model;     // surrogate sampler's network (device)
+    bool have_model;
 };
 
 struct qed_graph {
@@ -67,6 +70,7 @@ qed::SpeciesDev to_dev(const qed_species &s) {
     d.id = s.id;
     d.parent = s.parent;
     d.events = s.events;
+    d.tau = s.tau;
     return d;
 }
 
@@ -133,7 +137,7 @@ bool tuning_ok(const qed_tuning &t) {
 
 const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_photon_sample", "k_lepton", "k_prepass",
                                          "k_scan",  "k_scatter", "k_light", "k_heavy",
-                                         "k_end",   "k_fill",   "k_move",  "k_synchrotron"};
+                                         "k_end",   "k_fill",   "k_move",  "k_synchrotron", "k_tiled"};
 
 // Event pair for one profiled launch (grown on demand, reused after a read).
 bool prof_pair(qed_ctx *c, int id, hipEvent_t *a, hipEvent_t *b) {
@@ -165,6 +169,65 @@ hipError_t launch(qed_ctx *c, int id, const qed::StepArgs &a, int precision, int
 
 }  // namespace
 
+namespace {
+
+// Device buffers of one table / training run, released on every exit path.
+struct DevBufs {
+    std::vector<void *> p;
+    template <class T>
+    bool alloc(T **out, size_t bytes) {
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) return false;
+        p.push_back(q);
+        *out = static_cast<T *>(q);
+        return true;
+    }
+    ~DevBufs() {
+        for (void *q : p) (void)hipFree(q);
+    }
+};
+
+bool table_args_ok(double lo, double hi, uint32_t nchi, uint32_t nx) {
+    return isfinite(lo) && isfinite(hi) && hi > lo && nchi >= 2 && nchi <= 65536 && nx >= 256 && nx % 256 == 0 &&
+           nx <= (1u << 20) && (u64)nchi * (nx + 1) <= (1ull << 31);
+}
+
+qed_status build_table(qed_ctx *c, DevBufs &B, double lo, double hi, uint32_t nchi, uint32_t nx,
+                       qed::CdfTableDev &t) {
+    t.nchi = (int)nchi;
+    t.nx = (int)nx;
+    t.lo10 = lo;
+    t.hi10 = hi;
+    if (!B.alloc(&t.cdf, (size_t)nchi * (nx + 1) * sizeof(double)) || !B.alloc(&t.total, nchi * sizeof(double)))
+        return QED_ERR_HIP;
+    if (qed::launch_cdf_table(t, c->stream) != hipSuccess) return QED_ERR_HIP;
+    return QED_OK;
+}
+
+// Seeded initial weights: uniform in +-sqrt(6 / (fan_in + fan_out)), zero biases.
+void init_params(float *p, uint64_t seed) {
+    uint64_t x = seed * 0x9E3779B97F4A7C15ull + 0xD1B54A32D192ED03ull;
+    auto next = [&x]() {  // splitmix64
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * 0x1p-53;
+    };
+    for (int k = 0; k < QED_MLP_NPARAMS; ++k) p[k] = 0.0f;
+    auto fill = [&](int off, int n, int fin, int fout) {
+        const double a = sqrt(6.0 / (fin + fout));
+        for (int k = 0; k < n; ++k) p[off + k] = (float)((2.0 * next() - 1.0) * a);
+    };
+    fill(qed::kOffW1, 128, 2, 64);
+    fill(qed::kOffW2, 4096, 64, 64);
+    fill(qed::kOffW3, 4096, 64, 64);
+    fill(qed::kOffW4, 64, 64, 1);
+}
+
+}  // namespace
+
 extern "C" {
 
 qed_status qed_config_default(qed_config *cfg) {
@@ -179,6 +242,7 @@ qed_status qed_config_default(qed_config *cfg) {
     cfg->scheduler = QED_SCHED_NAIVE;
     cfg->pair_bound_coef = 0.1;
     cfg->max_substeps = 1u << 24;
+    cfg->sampler = QED_SAMPLER_REJECTION;
     return QED_OK;
 }
 
@@ -189,7 +253,10 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     if (!(cfg->p_max > 0.0 && cfg->p_max <= 1.0)) return QED_ERR_INVALID_ARG;
     if (!(cfg->pair_bound_coef > 0.0) || !isfinite(cfg->pair_bound_coef)) return QED_ERR_INVALID_ARG;
     if (cfg->max_substeps < 1) return QED_ERR_INVALID_ARG;
-    if (cfg->scheduler != QED_SCHED_NAIVE && cfg->scheduler != QED_SCHED_BINNED) return QED_ERR_INVALID_ARG;
+    if (cfg->scheduler != QED_SCHED_NAIVE && cfg->scheduler != QED_SCHED_BINNED && cfg->scheduler != QED_SCHED_TILED)
+        return QED_ERR_INVALID_ARG;
+    if (cfg->sampler != QED_SAMPLER_REJECTION && cfg->sampler != QED_SAMPLER_SURROGATE) return QED_ERR_INVALID_ARG;
+    if (cfg->sampler == QED_SAMPLER_SURROGATE && cfg->precision != QED_PREC_MIXED) return QED_ERR_INVALID_ARG;
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (cfg->device < 0 || cfg->device >= ndev) return QED_ERR_INVALID_ARG;
@@ -210,8 +277,10 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     c->tune.light_max = 48;
     c->tune.chunk = 256;
     if (hipMalloc(&c->st, sizeof(qed::DevState)) != hipSuccess ||
-        hipMemset(c->st, 0, sizeof(qed::DevState)) != hipSuccess) {
+        hipMemset(c->st, 0, sizeof(qed::DevState)) != hipSuccess ||
+        hipMalloc(&c->model, sizeof(qed::MlpModel)) != hipSuccess) {
         if (c->st) (void)hipFree(c->st);
+        if (c->model) (void)hipFree(c->model);
         delete c;
         return QED_ERR_HIP;
     }
@@ -232,6 +301,8 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
         if (!species_ok(*sp[s])) return QED_ERR_INVALID_ARG;
     }
     if (emission && (!field_ok(fields[0]) || !field_ok(fields[1]))) return QED_ERR_INVALID_ARG;
+    const bool surrogate = c->cfg.sampler == QED_SAMPLER_SURROGATE;
+    if (surrogate && emission && (!sp[0]->tau || !sp[1]->tau)) return QED_ERR_INVALID_ARG;
     if (pairs && !field_ok(fields[2])) return QED_ERR_INVALID_ARG;
     const bool binned = c->cfg.scheduler == QED_SCHED_BINNED && emission;
     if (binned && (sp[0]->capacity > 0xFFFFFFFFull || sp[1]->capacity > 0xFFFFFFFFull))
@@ -273,6 +344,8 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
         a.nsub[s] = c->nsub[s];
         a.queue[s] = c->queue[s];
     }
+    a.sampler = surrogate ? 1 : 0;
+    a.model = c->have_model ? c->model : nullptr;
     const u64 lep_cap = sp[0]->capacity > sp[1]->capacity ? sp[0]->capacity : sp[1]->capacity;
     const int lepton_blocks = grid_for(lep_cap, c->num_cu * (int)c->tune.lepton_blocks_per_cu);
     const int heavy_blocks = c->num_cu * (int)c->tune.heavy_blocks_per_cu;
@@ -282,7 +355,9 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
     hipError_t r = launch(c, qed::K_BEGIN, a, prec, 1);
     if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON, a, prec, photon_blocks);
     if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON_SAMPLE, a, prec, photon_blocks);
-    if (r == hipSuccess && emission && !binned) r = launch(c, qed::K_LEPTON, a, prec, lepton_blocks);
+    const bool tiled = c->cfg.scheduler == QED_SCHED_TILED;
+    if (r == hipSuccess && emission && !binned)
+        r = launch(c, tiled ? qed::K_TILED : qed::K_LEPTON, a, prec, lepton_blocks);
     if (binned) {
         if (r == hipSuccess) r = launch(c, qed::K_PREPASS, a, prec, lepton_blocks);
         if (r == hipSuccess) r = launch(c, qed::K_SCAN, a, prec, 1);
@@ -363,6 +438,10 @@ qed_status qed_get_stats(qed_ctx *c, qed_stats *out) {
     out->pairs = h.pairs;
     out->clips = h.clips;
     out->capped = h.capped;
+    out->learned_events = h.learned_events;
+    out->fallback_events = h.fallback_events;
+    out->fallback_draws = h.fallback_draws;
+    out->envelope_clips = h.envelope_clips;
     double mp;
     memcpy(&mp, &h.max_p_bits, sizeof(mp));
     out->max_p = mp;
@@ -382,6 +461,7 @@ qed_status qed_reset_stats(qed_ctx *c) {
     h.heavy_particles = h.heavy_substeps = 0;
     h.sampled_photons = h.sampled_substeps = 0;
     h.emissions = h.pairs = h.clips = h.capped = 0;
+    h.learned_events = h.fallback_events = h.fallback_draws = h.envelope_clips = 0;
     h.max_p_bits = 0;
     HIP_TRY(hipMemcpy(c->st, &h, sizeof(h), hipMemcpyHostToDevice));
     return QED_OK;
@@ -479,6 +559,231 @@ qed_status qed_profile_read(qed_ctx *c, qed_kernel_time *out, int max, int *coun
     return QED_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Surrogate sampler: model installation, evaluation, training.
+// ---------------------------------------------------------------------------
+qed_status qed_sampler_set(qed_ctx *c, const qed_sampler_model *m) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    if (c->capturing) return QED_ERR_STATE;
+    if (!m) {
+        HIP_TRY(hipSetDevice(c->cfg.device));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        c->have_model = false;
+        return QED_OK;
+    }
+    if (!m->params || m->nbins < 1 || m->nbins > QED_MLP_MAX_BINS || !m->fallback) return QED_ERR_INVALID_ARG;
+    if (!(m->log10_chi_hi > m->log10_chi_lo) || !isfinite(m->log10_chi_lo) || !isfinite(m->log10_chi_hi))
+        return QED_ERR_INVALID_ARG;
+    for (int k = 0; k < QED_MLP_NPARAMS; ++k)
+        if (!isfinite(m->params[k])) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    float *dp = nullptr;
+    HIP_TRY(hipMalloc(&dp, QED_MLP_NPARAMS * sizeof(float)));
+    qed_status st = QED_OK;
+    if (hipMemcpy(dp, m->params, QED_MLP_NPARAMS * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        qed::launch_mlp_pack(dp, c->model, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        st = QED_ERR_HIP;
+    (void)hipFree(dp);
+    if (st != QED_OK) return st;
+    // the range, bins and fallback flags
+    struct {
+        float lo, inv_span;
+        int nbins;
+    } head = {(float)m->log10_chi_lo, (float)(1.0 / (m->log10_chi_hi - m->log10_chi_lo)), m->nbins};
+    uint8_t fb[QED_MLP_MAX_BINS];
+    memset(fb, 1, sizeof(fb));
+    for (int k = 0; k < m->nbins; ++k) fb[k] = m->fallback[k] ? 1 : 0;
+    char *base = reinterpret_cast<char *>(c->model);
+    HIP_TRY(hipMemcpy(base + offsetof(qed::MlpModel, lo), &head, sizeof(head), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + offsetof(qed::MlpModel, fallback), fb, sizeof(fb), hipMemcpyHostToDevice));
+    c->have_model = true;
+    return QED_OK;
+}
+
+qed_status qed_sampler_infer(qed_ctx *c, const float *chi, const float *u, float *x, uint64_t n) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    if (n == 0) return QED_OK;
+    if (!chi || !u || !x) return QED_ERR_INVALID_ARG;
+    if (!c->have_model) return QED_ERR_STATE;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    if (qed::launch_mlp_infer(c->model, chi, u, x, n, grid_for(n, c->num_cu * 8), c->stream) != hipSuccess)
+        return QED_ERR_HIP;
+    return QED_OK;
+}
+
+qed_status qed_emission_rate(qed_ctx *c, const float *chi, float *chi_q, uint64_t n) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    if (n == 0) return QED_OK;
+    if (!chi || !chi_q) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    if (qed::launch_rate(chi, chi_q, n, grid_for(n, c->num_cu * 8), c->stream) != hipSuccess) return QED_ERR_HIP;
+    return QED_OK;
+}
+
+
+qed_status qed_emission_cdf(qed_ctx *c, double lo, double hi, uint32_t nchi, uint32_t nx, double *cdf_out,
+                            double *total_out) {
+    if (!c || !cdf_out || !table_args_ok(lo, hi, nchi, nx)) return QED_ERR_INVALID_ARG;
+    if (c->capturing) return QED_ERR_STATE;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    DevBufs B;
+    qed::CdfTableDev t;
+    qed_status st = build_table(c, B, lo, hi, nchi, nx, t);
+    if (st != QED_OK) return st;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(cdf_out, t.cdf, (size_t)nchi * (nx + 1) * sizeof(double), hipMemcpyDeviceToHost));
+    if (total_out) HIP_TRY(hipMemcpy(total_out, t.total, nchi * sizeof(double), hipMemcpyDeviceToHost));
+    return QED_OK;
+}
+
+qed_status qed_train_config_default(qed_train_config *cfg) {
+    if (!cfg) return QED_ERR_INVALID_ARG;
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->log10_chi_lo = -3.0;
+    cfg->log10_chi_hi = 2.0;
+    cfg->table_chi = 1025;
+    cfg->table_x = 8192;
+    cfg->steps = 2000;
+    cfg->blocks = 256;
+    cfg->batch_tiles = 4;
+    cfg->lr = 3e-3f;
+    cfg->lr_final = 3e-5f;
+    cfg->seed = 1;
+    cfg->nbins = 50;
+    cfg->per_bin = 5;
+    cfg->tolerance = 1e-3;
+    return QED_OK;
+}
+
+qed_status qed_train_sampler(qed_ctx *c, const qed_train_config *cfg, const float *init, float *params_out,
+                             float *loss_out, float *bin_err_out, uint8_t *fallback_out) {
+    if (!c || !cfg || !params_out) return QED_ERR_INVALID_ARG;
+    if (c->capturing) return QED_ERR_STATE;
+    if (!table_args_ok(cfg->log10_chi_lo, cfg->log10_chi_hi, cfg->table_chi, cfg->table_x)) return QED_ERR_INVALID_ARG;
+    if (cfg->steps < 1 || cfg->blocks < 1 || cfg->blocks > 65536 || cfg->batch_tiles < 1 || cfg->batch_tiles > 1024)
+        return QED_ERR_INVALID_ARG;
+    if (cfg->nbins < 1 || cfg->nbins > QED_MLP_MAX_BINS || cfg->per_bin < 2 || cfg->per_bin > 64)
+        return QED_ERR_INVALID_ARG;
+    if (!(cfg->lr > 0.0f) || !(cfg->lr_final > 0.0f) || !(cfg->tolerance > 0.0)) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    DevBufs B;
+    qed::CdfTableDev t;
+    qed_status st = build_table(c, B, cfg->log10_chi_lo, cfg->log10_chi_hi, cfg->table_chi, cfg->table_x, t);
+    if (st != QED_OK) return st;
+    const u64 batch = (u64)cfg->blocks * 64 * cfg->batch_tiles;
+    float *params, *m, *v, *partials, *loss, *bin_err;
+    qed::Sample *data;
+    qed::MlpModel *model;
+    if (!B.alloc(&params, QED_MLP_NPARAMS * sizeof(float)) || !B.alloc(&m, QED_MLP_NPARAMS * sizeof(float)) ||
+        !B.alloc(&v, QED_MLP_NPARAMS * sizeof(float)) ||
+        !B.alloc(&partials, (size_t)cfg->blocks * (QED_MLP_NPARAMS + 1) * sizeof(float)) ||
+        !B.alloc(&loss, cfg->steps * sizeof(float)) || !B.alloc(&bin_err, cfg->nbins * sizeof(float)) ||
+        !B.alloc(&data, batch * sizeof(qed::Sample)) || !B.alloc(&model, sizeof(qed::MlpModel)))
+        return QED_ERR_HIP;
+    std::vector<float> h(QED_MLP_NPARAMS);
+    if (init)
+        memcpy(h.data(), init, h.size() * sizeof(float));
+    else
+        init_params(h.data(), cfg->seed);
+    HIP_TRY(hipMemcpy(params, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemsetAsync(m, 0, QED_MLP_NPARAMS * sizeof(float), c->stream));
+    HIP_TRY(hipMemsetAsync(v, 0, QED_MLP_NPARAMS * sizeof(float), c->stream));
+    HIP_TRY(hipMemsetAsync(bin_err, 0, cfg->nbins * sizeof(float), c->stream));
+    const double beta1 = 0.9, beta2 = 0.999;
+    const int data_blocks = grid_for(batch, c->num_cu * 8);
+    for (uint32_t k = 0; k < cfg->steps; ++k) {
+        if (qed::launch_mlp_data(t, data, batch, cfg->seed, k, cfg->log10_chi_lo, cfg->log10_chi_hi, data_blocks,
+                                 c->stream) != hipSuccess)
+            return QED_ERR_HIP;
+        qed::TrainArgs ta;
+        ta.params = params;
+        ta.batch = data;
+        ta.partials = partials;
+        ta.tiles = cfg->batch_tiles;
+        ta.inv_batch = (float)(1.0 / (double)batch);
+        if (qed::launch_mlp_train(ta, (int)cfg->blocks, c->stream) != hipSuccess) return QED_ERR_HIP;
+        qed::ReduceArgs ra;
+        memset(&ra, 0, sizeof(ra));
+        ra.partials = partials;
+        ra.blocks = (int)cfg->blocks;
+        ra.params = params;
+        ra.m = m;
+        ra.v = v;
+        ra.loss_out = loss + k;
+        const double frac = cfg->steps > 1 ? (double)k / (double)(cfg->steps - 1) : 1.0;
+        ra.lr = (float)(cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) * (1.0 + cos(M_PI * frac)));
+        ra.beta1 = (float)beta1;
+        ra.beta2 = (float)beta2;
+        ra.eps = 1e-8f;
+        ra.c1 = (float)(1.0 / (1.0 - pow(beta1, k + 1.0)));
+        ra.c2 = (float)(1.0 / (1.0 - pow(beta2, k + 1.0)));
+        if (qed::launch_mlp_reduce(ra, c->stream) != hipSuccess) return QED_ERR_HIP;
+    }
+    // validation of the packed network on the table
+    if (qed::launch_mlp_pack(params, model, c->stream) != hipSuccess) return QED_ERR_HIP;
+    struct {
+        float lo, inv_span;
+        int nbins;
+    } head = {(float)cfg->log10_chi_lo, (float)(1.0 / (cfg->log10_chi_hi - cfg->log10_chi_lo)), cfg->nbins};
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(reinterpret_cast<char *>(model) + offsetof(qed::MlpModel, lo), &head, sizeof(head),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(reinterpret_cast<char *>(model) + offsetof(qed::MlpModel, fallback), 0, QED_MLP_MAX_BINS));
+    if (qed::launch_mlp_validate(model, t, cfg->nbins, cfg->per_bin, bin_err, c->stream) != hipSuccess)
+        return QED_ERR_HIP;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(params_out, params, QED_MLP_NPARAMS * sizeof(float), hipMemcpyDeviceToHost));
+    if (loss_out) HIP_TRY(hipMemcpy(loss_out, loss, cfg->steps * sizeof(float), hipMemcpyDeviceToHost));
+    std::vector<float> be(cfg->nbins);
+    HIP_TRY(hipMemcpy(be.data(), bin_err, cfg->nbins * sizeof(float), hipMemcpyDeviceToHost));
+    for (int k = 0; k < cfg->nbins; ++k) {
+        if (bin_err_out) bin_err_out[k] = be[k];
+        if (fallback_out) fallback_out[k] = !(be[k] <= cfg->tolerance);
+    }
+    return QED_OK;
+}
+
+qed_status qed_mlp_gradient(qed_ctx *c, const float *params, const float *samples, uint64_t n, float *loss_out,
+                            float *grad_out) {
+    if (!c || !params || !samples || !grad_out || n == 0 || n % 64 != 0 || n > (1ull << 26))
+        return QED_ERR_INVALID_ARG;
+    if (c->capturing) return QED_ERR_STATE;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    DevBufs B;
+    const int blocks = (int)(n / 64);
+    float *dp, *partials, *grad, *loss;
+    qed::Sample *data;
+    if (!B.alloc(&dp, QED_MLP_NPARAMS * sizeof(float)) ||
+        !B.alloc(&partials, (size_t)blocks * (QED_MLP_NPARAMS + 1) * sizeof(float)) ||
+        !B.alloc(&grad, QED_MLP_NPARAMS * sizeof(float)) || !B.alloc(&loss, sizeof(float)) ||
+        !B.alloc(&data, n * sizeof(qed::Sample)))
+        return QED_ERR_HIP;
+    HIP_TRY(hipMemcpy(dp, params, QED_MLP_NPARAMS * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(data, samples, n * sizeof(qed::Sample), hipMemcpyHostToDevice));
+    qed::TrainArgs ta;
+    ta.params = dp;
+    ta.batch = data;
+    ta.partials = partials;
+    ta.tiles = 1;
+    ta.inv_batch = (float)(1.0 / (double)n);
+    if (qed::launch_mlp_train(ta, blocks, c->stream) != hipSuccess) return QED_ERR_HIP;
+    qed::ReduceArgs ra;
+    memset(&ra, 0, sizeof(ra));
+    ra.partials = partials;
+    ra.blocks = blocks;
+    ra.grad_out = grad;
+    ra.loss_out = loss;
+    if (qed::launch_mlp_reduce(ra, c->stream) != hipSuccess) return QED_ERR_HIP;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(grad_out, grad, QED_MLP_NPARAMS * sizeof(float), hipMemcpyDeviceToHost));
+    if (loss_out) HIP_TRY(hipMemcpy(loss_out, loss, sizeof(float), hipMemcpyDeviceToHost));
+    return QED_OK;
+}
+
 void qed_finalize(qed_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->cfg.device);
@@ -493,6 +798,7 @@ void qed_finalize(qed_ctx *c) {
         release(c->queue[s]);
     }
     release(c->st);
+    release(c->model);
     delete c;
 }
 

@@ -3,7 +3,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "qed_mlp.hpp"
 
 namespace qed {
 
@@ -38,6 +41,10 @@ struct DevState {
     alignas(128) u64 clips;
     alignas(128) u64 capped;
     alignas(128) u64 nonfinite;
+    alignas(128) u64 learned_events;   // surrogate sampler
+    alignas(128) u64 fallback_events;
+    alignas(128) u64 fallback_draws;
+    alignas(128) u64 envelope_clips;
     alignas(128) u64 max_p_bits;   // largest acceptance probability (bits of a non-negative double)
     alignas(128) u64 status_bits;  // bit 0: capacity exceeded, bit 1: non-finite input
     u64 required[3];  // largest count requested per species (capacity errors)
@@ -53,6 +60,7 @@ struct SpeciesDev {
     void *ux, *uy, *uz, *w;
     uint64_t *id, *parent;
     uint32_t *events;
+    double *tau;
 };
 
 struct FieldDev {
@@ -76,6 +84,8 @@ struct StepArgs {
     u64 *mover_idx;
     uint32_t *nsub[2];     // binned scheduler: sub-step count per lepton slot (0: skipped)
     uint32_t *queue[2];    // binned scheduler: heavy lepton slots sorted by bin, heaviest first
+    int sampler;           // 0 rejection, 1 surrogate
+    const MlpModel *model; // surrogate: installed network (nullptr: rejection for every chi)
 };
 
 // Kernels, in launch order, and the standalone synchrotron kernel.
@@ -93,12 +103,59 @@ enum KernelId {
     K_FILL,
     K_MOVE,
     K_SYNCHROTRON,
+    K_TILED,    // tile-sorted scheduler: the whole lepton pass
     K_COUNT
 };
 
 // Enqueue one kernel of a step (precision: 0 = F64, 1 = MIXED).  blocks is the
 // grid size in x; lepton kernels add y = 2 (one row per lepton species).
 hipError_t launch_kernel(int id, const StepArgs &a, int precision, int blocks, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Training of the surrogate sampler's network.
+// ---------------------------------------------------------------------------
+// CDF of the emitted energy over x in [0, 1] on a grid of chi: row c (chi =
+// 10^(lo10 + c (hi10 - lo10) / (nchi - 1))) holds nx + 1 values at
+// x = 1 - (1 - k/nx)^2; total[c] is the integral of eq. (1) over c b.
+struct CdfTableDev {
+    double *cdf;
+    double *total;
+    int nchi, nx;
+    double lo10, hi10;
+};
+
+struct Sample {
+    float s, v, y, w;  // network inputs, target output, loss weight
+};
+
+struct TrainArgs {
+    const float *params;   // float parameters (kMlpParams)
+    const Sample *batch;   // blocks * 4 waves * tiles * 16 samples
+    float *partials;       // [blocks][kMlpParams + 1]: gradient sums and the loss
+    uint32_t tiles;        // 16-sample tiles per wave
+    float inv_batch;       // 1 / batch size
+};
+
+struct ReduceArgs {
+    const float *partials;
+    int blocks;
+    float *params, *m, *v;  // Adam state (unused when grad_out is set)
+    float *grad_out;        // non-null: write the summed gradient, no update
+    float *loss_out;        // optional: the summed loss
+    float lr, beta1, beta2, eps, c1, c2;  // c1 = 1/(1-beta1^t), c2 = 1/(1-beta2^t)
+};
+
+hipError_t launch_rate(const float *chi, float *out, u64 n, int blocks, hipStream_t s);
+hipError_t launch_cdf_table(const CdfTableDev &t, hipStream_t s);
+hipError_t launch_mlp_data(const CdfTableDev &t, Sample *out, u64 n, uint64_t seed, uint32_t step,
+                           double lo10, double hi10, int blocks, hipStream_t s);
+hipError_t launch_mlp_train(const TrainArgs &ta, int blocks, hipStream_t s);
+hipError_t launch_mlp_reduce(const ReduceArgs &ra, hipStream_t s);
+hipError_t launch_mlp_pack(const float *params, MlpModel *out, hipStream_t s);
+hipError_t launch_mlp_validate(const MlpModel *model, const CdfTableDev &t, int nbins, int per_bin,
+                               float *bin_err, hipStream_t s);
+hipError_t launch_mlp_infer(const MlpModel *model, const float *chi, const float *u, float *x, u64 n,
+                            int blocks, hipStream_t s);
 
 // Enqueue the elementwise synchrotron kernel (dtype: 0 = float, 1 = double).
 hipError_t launch_synchrotron(const void *x, void *F, void *G, u64 n, int dtype, DevState *st,

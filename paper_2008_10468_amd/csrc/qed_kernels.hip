@@ -23,8 +23,12 @@
 // Random numbers are keyed by (seed, id, step, sub-step), so every schedule gives
 // the same per-particle result.  The sub-step count of a particle comes from the
 // bounds f(b) of Sec. 3.1.1, evaluated in double at the step start.
+#include <type_traits>
+
 #include "qed_device.hpp"
 #include "qed_internal.hpp"
+#include "qed_mlp.hpp"
+#include "qed_rate.hpp"
 #include "qed_synchro.hpp"
 
 namespace qed {
@@ -90,6 +94,7 @@ template <class R>
 struct Tally {
     u64 substeps = 0;
     uint32_t events = 0, clips = 0, capped = 0, nonfinite = 0, particles = 0;
+    uint32_t learned = 0, fallback = 0, fb_draws = 0, env_clips = 0;  // surrogate sampler
     R max_p = 0;
 };
 
@@ -100,24 +105,31 @@ struct Tally {
 template <class R>
 __device__ __forceinline__ void flush_tally(const Tally<R> &t, DevState *st, int species,
                                             int work = 0) {
-    __shared__ u64 red[kBlock / 64][8];
-    const u64 v[7] = {wave_sum(t.substeps), (u64)wave_sum(t.events), (u64)wave_sum(t.clips),
-                      (u64)wave_sum(t.capped), (u64)wave_sum(t.nonfinite),
-                      (u64)wave_sum(t.particles), 0};
+    constexpr int kN = 10;
+    __shared__ u64 red[kBlock / 64][kN + 1];
+    const u64 v[kN] = {wave_sum(t.substeps), (u64)wave_sum(t.events), (u64)wave_sum(t.clips),
+                       (u64)wave_sum(t.capped), (u64)wave_sum(t.nonfinite),
+                       (u64)wave_sum(t.particles), (u64)wave_sum(t.learned),
+                       (u64)wave_sum(t.fallback), (u64)wave_sum(t.fb_draws),
+                       (u64)wave_sum(t.env_clips)};
     const double mp = wave_max((double)t.max_p);
     const int wv = threadIdx.x / 64;
     __syncthreads();
     if (__lane_id() == 0) {
-        for (int k = 0; k < 6; ++k) red[wv][k] = v[k];
-        red[wv][7] = (u64)__double_as_longlong(mp);
+        for (int k = 0; k < kN; ++k) red[wv][k] = v[k];
+        red[wv][kN] = (u64)__double_as_longlong(mp);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        u64 tot[6] = {0, 0, 0, 0, 0, 0}, mb = 0;
+        u64 tot[kN] = {}, mb = 0;
         for (int w = 0; w < kBlock / 64; ++w) {
-            for (int k = 0; k < 6; ++k) tot[k] += red[w][k];
-            mb = red[w][7] > mb ? red[w][7] : mb;
+            for (int k = 0; k < kN; ++k) tot[k] += red[w][k];
+            mb = red[w][kN] > mb ? red[w][kN] : mb;
         }
+        if (tot[6]) atomicAdd(&st->learned_events, tot[6]);
+        if (tot[7]) atomicAdd(&st->fallback_events, tot[7]);
+        if (tot[8]) atomicAdd(&st->fallback_draws, tot[8]);
+        if (tot[9]) atomicAdd(&st->envelope_clips, tot[9]);
         if (tot[0]) atomicAdd(&st->substeps[species], tot[0]);
         if (tot[1]) atomicAdd(species == 2 ? &st->pairs : &st->emissions, tot[1]);
         if (tot[2]) atomicAdd(&st->clips, tot[2]);
@@ -259,6 +271,48 @@ __device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<
     return N;
 }
 
+// Photon emission of the accepting lanes (acc; m = their ballot): the photon of
+// energy fraction delta = x3 along u is staged in the wave's LDS buffer with the
+// parent's position and weight, and the parent recoils to gamma' = (1 - delta)
+// gamma in the same direction.  Called by every lane of the wave that is still in
+// the sub-step loop.
+template <class R>
+__device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesDev &sp, u64 i, uint64_t pid,
+                                               uint32_t k, bool acc, u64 m, R x3, R omx3, R g, R u2, R dx,
+                                               R dy, R dz, R &ux, R &uy, R &uz, ChildBuf<R> &cb,
+                                               uint32_t &nev) {
+    const uint32_t c = (uint32_t)__popcll(m);
+    __syncwarp();
+    if (cb.count + c > 64) flush_children(cb, a.sp[2]);
+    const uint32_t n0 = cb.count;
+    if (acc) {
+        const uint32_t e = n0 + (uint32_t)__popcll(m & lanemask_lt());
+        const R umag = sqrt_(u2);
+        const R inv = umag > R(0) ? rcp(umag) : R(0);
+        const R eph = x3 * g * inv;
+        cb.x[e] = sp.x[i] + (double)dx;
+        cb.y[e] = sp.y[i] + (double)dy;
+        cb.z[e] = sp.z[i] + (double)dz;
+        cb.px[e] = ux * eph;
+        cb.py[e] = uy * eph;
+        cb.pz[e] = uz * eph;
+        cb.w[e] = ((const R *)sp.w)[i];
+        cb.id[e] = child_id(a.seed, pid, a.step, k, 0);
+        cb.parent[e] = pid;
+        // gamma' = (1 - delta) gamma, same direction
+        const R g1 = omx3 * g;
+        const R u1 = sqrt_(fmax(g1 * g1 - R(1), R(0)));
+        const R sc = u1 * inv;
+        ux *= sc;
+        uy *= sc;
+        uz *= sc;
+        nev++;
+    }
+    __syncwarp();
+    cb.count = n0 + c;
+    __syncwarp();
+}
+
 // Algorithm 1's sub-step loop for one electron (s = 0, q = -1) or positron (s = 1,
 // q = +1) with N >= 1 sub-steps.  s is uniform across the wave.  FK: field kind
 // (0 general, 1 pure E, 2 pure B), see boris().
@@ -266,7 +320,6 @@ template <class R, int FK>
 __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uint32_t N, Lepton<R> p,
                                             const SynTable<R> &tab, ChildBuf<R> &cb, Tally<R> &tl) {
     const SpeciesDev &sp = a.sp[s];
-    const SpeciesDev &ph = a.sp[2];
     const uint64_t pid = sp.id[i];
     const double st = a.dt / (double)N;
     const R hq = (R)((s == 0 ? -0.5 : 0.5) * st);
@@ -310,38 +363,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
         const bool acc = y < pm;
         // emission: stage the photon in the wave's LDS buffer, recoil on the parent
         const u64 m = __ballot(acc);
-        if (m) {
-            const uint32_t c = (uint32_t)__popcll(m);
-            __syncwarp();
-            if (cb.count + c > 64) flush_children(cb, ph);
-            const uint32_t n0 = cb.count;
-            if (acc) {
-                const uint32_t e = n0 + (uint32_t)__popcll(m & lanemask_lt());
-                const R umag = sqrt_(u2);
-                const R inv = umag > R(0) ? rcp(umag) : R(0);
-                const R eph = x3 * g * inv;
-                cb.x[e] = sp.x[i] + (double)dx;
-                cb.y[e] = sp.y[i] + (double)dy;
-                cb.z[e] = sp.z[i] + (double)dz;
-                cb.px[e] = ux * eph;
-                cb.py[e] = uy * eph;
-                cb.pz[e] = uz * eph;
-                cb.w[e] = ((const R *)sp.w)[i];
-                cb.id[e] = child_id(a.seed, pid, a.step, k, 0);
-                cb.parent[e] = pid;
-                // gamma' = (1 - delta) gamma, same direction
-                const R g1 = omx3 * g;
-                const R u1 = sqrt_(fmax(g1 * g1 - R(1), R(0)));
-                const R sc = u1 * inv;
-                ux *= sc;
-                uy *= sc;
-                uz *= sc;
-                nev++;
-            }
-            __syncwarp();
-            cb.count = n0 + c;
-            __syncwarp();
-        }
+        if (m) stage_emission<R>(a, sp, i, pid, k, acc, m, x3, omx3, g, u2, dx, dy, dz, ux, uy, uz, cb, nev);
     }
     ((R *)sp.ux)[i] = ux;
     ((R *)sp.uy)[i] = uy;
@@ -366,6 +388,186 @@ __device__ __forceinline__ void lepton_run(const StepArgs &a, int s, u64 i, uint
     else
         lepton_loop<R, 0>(a, s, i, N, p, tab, cb, tl);
 }
+
+// ---------------------------------------------------------------------------
+// Surrogate sampler (mixed precision): the sub-steps and push of Algorithm 1,
+// with the emission time from the optical depth and the energy from the learned
+// inverse CDF (or rejection sampling of eq. (1) at the current chi).
+// ---------------------------------------------------------------------------
+// Key tag of the surrogate's random stream: the draws of particle id in step
+// `step` are Philox blocks (id_lo, id_hi, step, j) under the seed key xor'ed
+// with this tag, j counting the particle's draws within the step.
+constexpr uint32_t kSurrTagLo = 0x2545F491u, kSurrTagHi = 0x9E3779B9u;
+constexpr uint32_t kMaxRejections = 1u << 12;
+
+struct SurrLds {
+    RateTable rate;
+    MlpLds mlp;
+    MlpWave ws[kBlock / 64];
+    int have_model;
+};
+
+__device__ __forceinline__ void surr_stage(const StepArgs &a, SurrLds &S) {
+    if (a.model) mlp_stage(a.model, S.mlp);
+    if (threadIdx.x == 0) S.have_model = a.model != nullptr;
+    rate_stage(S.rate);  // ends with a barrier
+}
+
+// x = delta^(1/3) from eq. (1) at fixed chi by rejection against the envelope.
+__device__ __forceinline__ float surr_reject(float chi, const SurrLds &S, const SynTable<float> &tab,
+                                             uint32_t idlo, uint32_t idhi, uint32_t step, uint32_t klo,
+                                             uint32_t khi, uint32_t &j, Tally<float> &tl) {
+    const float b = 1.5f * chi;
+    const float env = rate_envelope(chi, S.rate);
+    u32x4 w = {0u, 0u, 0u, 0u};
+    float x = 0.5f;
+    for (uint32_t it = 0; it < kMaxRejections; ++it) {
+        if ((it & 1u) == 0u) w = philox10(idlo, idhi, step, j++, klo, khi);
+        const bool odd = (it & 1u) != 0u;
+        x = u24(odd ? w.z : w.x);
+        const float y = u24(odd ? w.w : w.y);
+        const float x2 = x * x, x3 = x2 * x;
+        const float omx3 = (1.0f - x) * (1.0f + x + x2);
+        float F, G;
+        syn_eval(x3 * rcp(b * omx3), tab, F, G);
+        const float d = (omx3 * F + x3 * x3 * G) * rcp(x);
+        tl.fb_draws++;
+        tl.env_clips += d > env;
+        if (y * env < d) break;
+    }
+    return x;
+}
+
+// N: this lane's sub-steps (0 for a lane without a particle); Nw: the largest N
+// of the wave.  Every lane of the wave runs Nw iterations so that the network
+// passes see all 64 lanes.
+template <int FK>
+__device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i, uint32_t N, uint32_t Nw,
+                                                 const Lepton<float> &p, const SynTable<float> &tab, SurrLds &S,
+                                                 ChildBuf<float> &cb, Tally<float> &tl) {
+    using R = float;
+    const SpeciesDev &sp = a.sp[s];
+    const bool has = N > 0;
+    const uint64_t pid = has ? sp.id[i] : 0ull;
+    const double st = has ? a.dt / (double)N : 0.0;
+    const R hq = (R)((s == 0 ? -0.5 : 0.5) * st);
+    const R hex = hq * p.ex, hey = hq * p.ey, hez = hq * p.ez;
+    const R e2 = p.ex * p.ex + p.ey * p.ey + p.ez * p.ez;
+    const R str = (R)st;
+    // W sub_t = alpha sub_t chi q(chi) / gamma
+    const R wk = (R)(kAlpha * st);
+    const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
+    const uint32_t klo = (uint32_t)a.seed ^ kSurrTagLo, khi = (uint32_t)(a.seed >> 32) ^ kSurrTagHi;
+    MlpWave &ws = S.ws[threadIdx.x / 64];
+    uint32_t j = 0;
+    double tau = has ? sp.tau[i] : 1.0;
+    if (has && !(tau > 0.0)) {
+        const u32x4 w = philox10(idlo, idhi, a.step, j++, klo, khi);
+        tau = -log(u53(w.x, w.y));
+    }
+    R ux = p.ux, uy = p.uy, uz = p.uz;
+    R dx = 0, dy = 0, dz = 0;
+    uint32_t nev = 0;
+    for (uint32_t k = 0; k < Nw; ++k) {
+        const bool live = k < N;
+        R chi = 0, g = 1, u2 = 0;
+        if (live) {
+            boris<R, FK>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
+            u2 = ux * ux + uy * uy + uz * uz;
+            const R ig = rsqrt_(R(1) + u2);
+            g = (R(1) + u2) * ig;
+            const R vs = str * ig;
+            dx += ux * vs;
+            dy += uy * vs;
+            dz += uz * vs;
+            chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
+            tau -= (double)(wk * rate_chi_q(chi, S.rate) * ig);
+        }
+        const bool fire = live && tau <= 0.0;
+        const u64 m = __ballot(fire);
+        if (m) {
+            R u = 0.5f, sin = 0.0f;
+            double tnew = 1.0;
+            bool use_net = false;
+            if (fire) {
+                const u32x4 w = philox10(idlo, idhi, a.step, j++, klo, khi);
+                u = u24(w.x);
+                tnew = -log(u53(w.z, w.w));
+                if (S.have_model) {
+                    bool in_range;
+                    int bin;
+                    sin = mlp_input_s(S.mlp, chi, in_range, bin);
+                    use_net = in_range && !S.mlp.fallback[bin];
+                }
+            }
+            R yv = 0.0f;
+            if (__ballot(use_net)) yv = mlp_infer_wave(S.mlp, ws, use_net, sin, 2.0f * u - 1.0f);
+            R x3 = 0, omx3 = 1;
+            if (fire) {
+                R x;
+                if (use_net) {
+                    x = mlp_x_of_y(yv, chi);
+                    tl.learned++;
+                } else {
+                    x = surr_reject(chi, S, tab, idlo, idhi, a.step, klo, khi, j, tl);
+                    tl.fallback++;
+                }
+                const R x2 = x * x;
+                x3 = x2 * x;
+                omx3 = (R(1) - x) * (R(1) + x + x2);
+                tau = tnew;
+            }
+            stage_emission<R>(a, sp, i, pid, k, fire, m, x3, omx3, g, u2, dx, dy, dz, ux, uy, uz, cb, nev);
+        }
+    }
+    if (has) {
+        ((R *)sp.ux)[i] = ux;
+        ((R *)sp.uy)[i] = uy;
+        ((R *)sp.uz)[i] = uz;
+        sp.x[i] += (double)dx;
+        sp.y[i] += (double)dy;
+        sp.z[i] += (double)dz;
+        sp.tau[i] = tau;
+        if (sp.events) sp.events[i] = nev;
+        tl.substeps += N;
+        tl.events += nev;
+    }
+}
+
+// One particle per lane, all lanes of the wave (has = false: no particle).
+template <class R, bool SURR>
+struct LeptonRunner;
+
+template <class R>
+struct LeptonRunner<R, false> {
+    template <class L>
+    __device__ static void run(const StepArgs &a, int s, u64 i, uint32_t N, const Lepton<R> &p, L &lds,
+                               ChildBuf<R> &cb, Tally<R> &t) {
+        if (N) lepton_run<R>(a, s, i, N, p, lds.tab, cb, t);
+    }
+};
+
+template <>
+struct LeptonRunner<float, true> {
+    template <class L>
+    __device__ static void run(const StepArgs &a, int s, u64 i, uint32_t n, const Lepton<float> &p, L &lds,
+                               ChildBuf<float> &cb, Tally<float> &t) {
+        uint32_t nw = n;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) nw = max(nw, (uint32_t)__shfl_xor((int)nw, o));
+        if (nw == 0) return;
+        // one field kind for the whole wave (the general form is valid for all)
+        const bool noB = p.bx == 0.0f && p.by == 0.0f && p.bz == 0.0f;
+        const bool noE = p.ex == 0.0f && p.ey == 0.0f && p.ez == 0.0f;
+        const u64 live = __ballot(n != 0);
+        if ((__ballot(n != 0 && noB) == live))
+            lepton_loop_surr<1>(a, s, i, n, nw, p, lds.tab, lds.surr, cb, t);
+        else if ((__ballot(n != 0 && noE) == live))
+            lepton_loop_surr<2>(a, s, i, n, nw, p, lds.tab, lds.surr, cb, t);
+        else
+            lepton_loop_surr<0>(a, s, i, n, nw, p, lds.tab, lds.surr, cb, t);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Algorithm 2.
@@ -475,6 +677,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
                     ((R *)el.w)[j] = w;
                     el.id[j] = child_id(a.seed, pid, a.step, k, 0);
                     if (el.parent) el.parent[j] = pid;
+                    if (el.tau) el.tau[j] = -1.0;
                 }
                 if (bp + r < po.cap) {
                     const u64 j = bp + r;
@@ -487,6 +690,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
                     ((R *)po.w)[j] = w;
                     po.id[j] = child_id(a.seed, pid, a.step, k, 1);
                     if (po.parent) po.parent[j] = pid;
+                    if (po.tau) po.tau[j] = -1.0;
                 }
                 dead = true;
             }
@@ -549,35 +753,57 @@ __device__ __forceinline__ void flush_children_block(ChildBuf<R> *cbs, const Spe
     }
 }
 
-// LDS of the lepton kernels: the coefficient table and one child buffer per wave.
-template <class R>
+// LDS of the lepton kernels: the coefficient table and one child buffer per wave,
+// plus the rate table and the network for the surrogate sampler.
+template <class R, bool SURR>
 struct LeptonLds {
     SynTable<R> tab;
     ChildBuf<R> cb[kBlock / 64];
 };
 
-template <class R>
-__device__ __forceinline__ ChildBuf<R> &lepton_lds_init(LeptonLds<R> &L) {
+template <>
+struct LeptonLds<float, true> {
+    SynTable<float> tab;
+    ChildBuf<float> cb[kBlock / 64];
+    SurrLds surr;
+};
+
+template <class R, bool SURR>
+__device__ __forceinline__ ChildBuf<R> &lepton_lds_init(const StepArgs &a, LeptonLds<R, SURR> &L) {
     ChildBuf<R> &cb = L.cb[threadIdx.x / 64];
     if (__lane_id() == 0) cb.count = 0;
+    if constexpr (SURR) surr_stage(a, L.surr);
     syn_stage(L.tab);  // ends with a block barrier
     return cb;
 }
 
+// The particle of this lane (N = 0 and a zero record when there is none).
 template <class R>
+__device__ __forceinline__ uint32_t lepton_fetch(const StepArgs &a, int s, u64 i, bool has, Lepton<R> &p,
+                                                 Tally<R> &t) {
+    if (!has) {
+        p = Lepton<R>{0, 0, 0, 0, 0, 0, 0, 0, 0};
+        return 0;
+    }
+    p = load_lepton<R>(a, s, i);
+    return lepton_nsub(a, p, t);
+}
+
+// Naive scheduler: one lane per particle in buffer order; the loop runs with
+// whole waves (lanes past the end carry no particle).
+template <class R, bool SURR>
 __global__ __launch_bounds__(kBlock) void k_lepton(StepArgs a) {
-    __shared__ LeptonLds<R> L;
-    ChildBuf<R> &cb = lepton_lds_init(L);
+    __shared__ LeptonLds<R, SURR> L;
+    ChildBuf<R> &cb = lepton_lds_init<R, SURR>(a, L);
     const int s = blockIdx.y;
     const u64 n = a.st->n0[s];
     Tally<R> t;
-    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
-        const Lepton<R> p = load_lepton<R>(a, s, i);
-        const uint32_t N = lepton_nsub(a, p, t);
-        if (N)
-            lepton_run<R>(a, s, i, N, p, L.tab, cb, t);
-        else if (a.sp[s].events)
-            a.sp[s].events[i] = 0;
+    for (u64 i0 = (u64)blockIdx.x * kBlock + (threadIdx.x & ~63u); i0 < n; i0 += (u64)gridDim.x * kBlock) {
+        const u64 i = i0 + __lane_id();
+        Lepton<R> p;
+        const uint32_t N = lepton_fetch(a, s, i, i < n, p, t);
+        if (i < n && N == 0 && a.sp[s].events) a.sp[s].events[i] = 0;
+        LeptonRunner<R, SURR>::run(a, s, i, N, p, L, cb, t);
     }
     flush_children_block(L.cb, a.sp[2]);
     flush_tally(t, a.st, s);
@@ -657,12 +883,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepArgs a) {
 constexpr int kTile = 512;     // slots per wave tile (8 per lane)
 constexpr int kTileKeys = 64;  // N >= 63 share the heaviest key
 
-template <class R>
+template <class R, bool SURR>
 __global__ __launch_bounds__(kBlock) void k_light(StepArgs a) {
-    __shared__ LeptonLds<R> L;
+    __shared__ LeptonLds<R, SURR> L;
     __shared__ uint32_t hist_sh[kBlock / 64][kTileKeys];
     __shared__ uint16_t order_sh[kBlock / 64][kTile];
-    ChildBuf<R> &cb = lepton_lds_init(L);
+    ChildBuf<R> &cb = lepton_lds_init<R, SURR>(a, L);
     const int s = blockIdx.y;
     const u64 n = a.st->n0[s];
     const uint32_t lmax = a.light_max;
@@ -700,9 +926,79 @@ __global__ __launch_bounds__(kBlock) void k_light(StepArgs a) {
         for (int q = 0; q < kTile / 64; ++q)
             if (kr[q]) order[hist[kr[q] >> 16] + (kr[q] & 0xFFFFu)] = (uint16_t)(q * 64 + lane);
         __syncwarp();
-        for (uint32_t p = lane; p < total; p += 64) {
-            const u64 i = t0 + order[p];
-            lepton_run<R>(a, s, i, a.nsub[s][i], load_lepton<R>(a, s, i), L.tab, cb, t);
+        for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+            const uint32_t p = p0 + lane;
+            const bool has = p < total;
+            const u64 i = has ? t0 + order[p] : 0;
+            const uint32_t N = has ? a.nsub[s][i] : 0u;
+            const Lepton<R> q = has ? load_lepton<R>(a, s, i) : Lepton<R>{0, 0, 0, 0, 0, 0, 0, 0, 0};
+            LeptonRunner<R, SURR>::run(a, s, i, N, q, L, cb, t);
+        }
+        __syncwarp();
+    }
+    flush_children_block(L.cb, a.sp[2]);
+    flush_tally(t, a.st, s);
+}
+
+// Tile-sorted scheduler (one pass, no pre-pass): each wave takes tiles of kTile
+// consecutive slots, computes every particle's sub-step count, counting-sorts the
+// tile by it in LDS (heaviest first) and runs the tile 64 particles at a time in
+// that order, so the lanes of a wave carry nearly the same N.  The particle
+// records are read twice, the second time from the cache.
+template <class R, bool SURR>
+__global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
+    __shared__ LeptonLds<R, SURR> L;
+    __shared__ uint32_t hist_sh[kBlock / 64][kTileKeys];
+    __shared__ uint16_t order_sh[kBlock / 64][kTile];
+    __shared__ uint32_t nsub_sh[kBlock / 64][kTile];
+    ChildBuf<R> &cb = lepton_lds_init<R, SURR>(a, L);
+    const int s = blockIdx.y;
+    const u64 n = a.st->n0[s];
+    const uint32_t lane = __lane_id();
+    const int wv = threadIdx.x / 64;
+    uint32_t *hist = hist_sh[wv];
+    uint16_t *order = order_sh[wv];
+    uint32_t *nsub = nsub_sh[wv];
+    const u64 nwaves = (u64)gridDim.x * (kBlock / 64);
+    Tally<R> t;
+    for (u64 t0 = ((u64)blockIdx.x * (kBlock / 64) + wv) * kTile; t0 < n; t0 += nwaves * kTile) {
+        hist[lane] = 0;
+        __syncwarp();
+        uint32_t kr[kTile / 64];  // key << 16 | rank
+#pragma unroll
+        for (int q = 0; q < kTile / 64; ++q) {
+            const u64 i = t0 + q * 64 + lane;
+            Lepton<R> p;
+            const uint32_t N = lepton_fetch(a, s, i, i < n, p, t);
+            if (i < n && N == 0 && a.sp[s].events) a.sp[s].events[i] = 0;
+            nsub[q * 64 + lane] = N;
+            const uint32_t key = N ? kTileKeys - (N < kTileKeys - 1 ? N : kTileKeys - 1) : 0u;
+            kr[q] = key ? (key << 16) | atomicAdd(&hist[key], 1u) : 0u;
+        }
+        __syncwarp();
+        const uint32_t h = lane >= 1 ? hist[lane] : 0u;
+        uint32_t incl = h;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o);
+            if ((int)lane >= o) incl += v;
+        }
+        const uint32_t total = __shfl(incl, 63);
+        __syncwarp();
+        hist[lane] = incl - h;
+        __syncwarp();
+#pragma unroll
+        for (int q = 0; q < kTile / 64; ++q)
+            if (kr[q]) order[hist[kr[q] >> 16] + (kr[q] & 0xFFFFu)] = (uint16_t)(q * 64 + lane);
+        __syncwarp();
+        for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+            const uint32_t p = p0 + lane;
+            const bool has = p < total;
+            const uint32_t idx = has ? order[p] : 0u;
+            const u64 i = t0 + idx;
+            const uint32_t N = has ? nsub[idx] : 0u;
+            const Lepton<R> q = has ? load_lepton<R>(a, s, i) : Lepton<R>{0, 0, 0, 0, 0, 0, 0, 0, 0};
+            LeptonRunner<R, SURR>::run(a, s, i, N, q, L, cb, t);
         }
         __syncwarp();
     }
@@ -711,10 +1007,10 @@ __global__ __launch_bounds__(kBlock) void k_light(StepArgs a) {
 }
 
 // Persistent: each wave claims chunk consecutive queue entries at a time.
-template <class R>
+template <class R, bool SURR>
 __global__ __launch_bounds__(kBlock) void k_heavy(StepArgs a) {
-    __shared__ LeptonLds<R> L;
-    ChildBuf<R> &cb = lepton_lds_init(L);
+    __shared__ LeptonLds<R, SURR> L;
+    ChildBuf<R> &cb = lepton_lds_init<R, SURR>(a, L);
     const int s = blockIdx.y;
     const u64 H = a.st->heavy[s];
     const uint32_t chunk = a.chunk;
@@ -726,10 +1022,14 @@ __global__ __launch_bounds__(kBlock) void k_heavy(StepArgs a) {
     for (;;) {
         if (base >= H) break;
         const u64 end = base + chunk < H ? base + chunk : H;
-        for (u64 j = base + __lane_id(); j < end; j += 64) {
-            const u64 i = a.queue[s][j];
-            lepton_run<R>(a, s, i, a.nsub[s][i], load_lepton<R>(a, s, i), L.tab, cb, t);
-            t.particles++;
+        for (u64 j0 = base; j0 < end; j0 += 64) {
+            const u64 j = j0 + __lane_id();
+            const bool has = j < end;
+            const u64 i = has ? a.queue[s][j] : 0;
+            const uint32_t N = has ? a.nsub[s][i] : 0u;
+            const Lepton<R> q = has ? load_lepton<R>(a, s, i) : Lepton<R>{0, 0, 0, 0, 0, 0, 0, 0, 0};
+            LeptonRunner<R, SURR>::run(a, s, i, N, q, L, cb, t);
+            t.particles += has;
         }
         u64 nb = 0;
         if (__lane_id() == 0) nb = nwaves * chunk + atomicAdd(&a.st->queue[s], (u64)chunk);
@@ -1008,6 +1308,14 @@ __global__ __launch_bounds__(kBlock) void k_synchrotron(const R *__restrict__ x,
     }
 }
 
+// Elementwise chi q(chi) of the rate fit.
+__global__ __launch_bounds__(kBlock) void k_rate(const float *__restrict__ chi, float *__restrict__ out, u64 n) {
+    __shared__ RateTable t;
+    rate_stage(t);
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock)
+        out[i] = rate_chi_q(chi[i], t);
+}
+
 template <class R>
 hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
     const dim3 blk(kBlock), g1(blocks), g2(blocks, 2);
@@ -1015,12 +1323,41 @@ hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
         case K_BEGIN: hipLaunchKernelGGL(k_begin, dim3(1), dim3(256), 0, s, a); break;
         case K_PHOTON: hipLaunchKernelGGL(k_photon<R>, g1, blk, 0, s, a); break;
         case K_PHOTON_SAMPLE: hipLaunchKernelGGL(k_photon_sample<R>, g1, blk, 0, s, a); break;
-        case K_LEPTON: hipLaunchKernelGGL(k_lepton<R>, g2, blk, 0, s, a); break;
+        case K_LEPTON:
+            if constexpr (std::is_same<R, float>::value)
+                if (a.sampler) {
+                    hipLaunchKernelGGL((k_lepton<float, true>), g2, blk, 0, s, a);
+                    break;
+                }
+            hipLaunchKernelGGL((k_lepton<R, false>), g2, blk, 0, s, a);
+            break;
         case K_PREPASS: hipLaunchKernelGGL(k_prepass<R>, g2, blk, 0, s, a); break;
         case K_SCAN: hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, a); break;
         case K_SCATTER: hipLaunchKernelGGL(k_scatter, g2, blk, 0, s, a); break;
-        case K_LIGHT: hipLaunchKernelGGL(k_light<R>, g2, blk, 0, s, a); break;
-        case K_HEAVY: hipLaunchKernelGGL(k_heavy<R>, g2, blk, 0, s, a); break;
+        case K_LIGHT:
+            if constexpr (std::is_same<R, float>::value)
+                if (a.sampler) {
+                    hipLaunchKernelGGL((k_light<float, true>), g2, blk, 0, s, a);
+                    break;
+                }
+            hipLaunchKernelGGL((k_light<R, false>), g2, blk, 0, s, a);
+            break;
+        case K_HEAVY:
+            if constexpr (std::is_same<R, float>::value)
+                if (a.sampler) {
+                    hipLaunchKernelGGL((k_heavy<float, true>), g2, blk, 0, s, a);
+                    break;
+                }
+            hipLaunchKernelGGL((k_heavy<R, false>), g2, blk, 0, s, a);
+            break;
+        case K_TILED:
+            if constexpr (std::is_same<R, float>::value)
+                if (a.sampler) {
+                    hipLaunchKernelGGL((k_tiled<float, true>), g2, blk, 0, s, a);
+                    break;
+                }
+            hipLaunchKernelGGL((k_tiled<R, false>), g2, blk, 0, s, a);
+            break;
         case K_END: hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, s, a); break;
         case K_FILL: hipLaunchKernelGGL(k_fill, g1, blk, 0, s, a); break;
         case K_MOVE: hipLaunchKernelGGL(k_move<R>, g1, blk, 0, s, a); break;
@@ -1032,7 +1369,13 @@ hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_kernel(int id, const StepArgs &a, int precision, int blocks, hipStream_t s) {
+    if (a.sampler && precision == 0) return hipErrorInvalidValue;  // surrogate: mixed precision only
     return precision == 0 ? launch_t<double>(id, a, blocks, s) : launch_t<float>(id, a, blocks, s);
+}
+
+hipError_t launch_rate(const float *chi, float *out, u64 n, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_rate, dim3(blocks), dim3(kBlock), 0, s, chi, out, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_synchrotron(const void *x, void *F, void *G, u64 n, int dtype, DevState *st,

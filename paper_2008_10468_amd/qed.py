@@ -15,7 +15,10 @@ LIB_PATH = os.path.join(_HERE, "libqed.so")
 QED_OK, QED_ERR_INVALID_ARG, QED_ERR_CAPACITY, QED_ERR_NONFINITE, QED_ERR_HIP, QED_ERR_STATE = 0, -1, -2, -3, -4, -5
 QED_F32, QED_F64 = 0, 1
 QED_PREC_F64, QED_PREC_MIXED = 0, 1
-QED_SCHED_NAIVE, QED_SCHED_BINNED = 0, 1
+QED_SCHED_NAIVE, QED_SCHED_BINNED, QED_SCHED_TILED = 0, 1, 2
+QED_SAMPLER_REJECTION, QED_SAMPLER_SURROGATE = 0, 1
+QED_MLP_NPARAMS = 8577
+QED_MLP_MAX_BINS = 256
 
 SPECIES = ("electrons", "positrons", "photons")
 
@@ -25,7 +28,7 @@ class qed_species(C.Structure):
                 ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("ux", C.c_void_p), ("uy", C.c_void_p), ("uz", C.c_void_p),
                 ("w", C.c_void_p), ("id", C.c_void_p), ("parent", C.c_void_p),
-                ("events", C.c_void_p)]
+                ("events", C.c_void_p), ("tau", C.c_void_p)]
 
 
 class qed_particles(C.Structure):
@@ -40,7 +43,7 @@ class qed_config(C.Structure):
     _fields_ = [("device", C.c_int), ("stream", C.c_void_p), ("precision", C.c_int),
                 ("p_max", C.c_double), ("emission", C.c_int), ("pairs", C.c_int),
                 ("scheduler", C.c_int), ("pair_bound_coef", C.c_double),
-                ("max_substeps", C.c_uint32)]
+                ("max_substeps", C.c_uint32), ("sampler", C.c_int)]
 
 
 class qed_report(C.Structure):
@@ -53,12 +56,25 @@ class qed_stats(C.Structure):
                 ("heavy_particles", C.c_uint64), ("heavy_substeps", C.c_uint64),
                 ("sampled_photons", C.c_uint64), ("sampled_substeps", C.c_uint64), ("emissions", C.c_uint64),
                 ("pairs", C.c_uint64), ("clips", C.c_uint64), ("capped", C.c_uint64),
-                ("max_p", C.c_double)]
+                ("max_p", C.c_double), ("learned_events", C.c_uint64), ("fallback_events", C.c_uint64),
+                ("fallback_draws", C.c_uint64), ("envelope_clips", C.c_uint64)]
 
 
 class qed_tuning(C.Structure):
     _fields_ = [("lepton_blocks_per_cu", C.c_uint32), ("heavy_blocks_per_cu", C.c_uint32),
                 ("photon_blocks_per_cu", C.c_uint32), ("light_max", C.c_uint32), ("chunk", C.c_uint32)]
+
+
+class qed_sampler_model(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("fallback", C.c_void_p), ("nbins", C.c_int32), ("pad", C.c_int32),
+                ("log10_chi_lo", C.c_double), ("log10_chi_hi", C.c_double)]
+
+
+class qed_train_config(C.Structure):
+    _fields_ = [("log10_chi_lo", C.c_double), ("log10_chi_hi", C.c_double),
+                ("table_chi", C.c_uint32), ("table_x", C.c_uint32), ("steps", C.c_uint32),
+                ("blocks", C.c_uint32), ("batch_tiles", C.c_uint32), ("lr", C.c_float), ("lr_final", C.c_float),
+                ("seed", C.c_uint64), ("nbins", C.c_int32), ("per_bin", C.c_int32), ("tolerance", C.c_double)]
 
 
 class qed_kernel_time(C.Structure):
@@ -69,6 +85,8 @@ EXPORTS = ("qed_config_default", "qed_init", "qed_step", "qed_sync", "qed_synchr
            "qed_get_stats", "qed_reset_stats", "qed_get_tuning", "qed_set_tuning",
            "qed_profile_enable", "qed_profile_read", "qed_graph_begin", "qed_graph_end",
            "qed_graph_launch", "qed_graph_destroy",
+           "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
+           "qed_train_config_default", "qed_train_sampler", "qed_mlp_gradient",
            "qed_finalize", "qed_status_string")
 
 _lib = None
@@ -99,6 +117,15 @@ def load(path: str = LIB_PATH):
     L.qed_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
     L.qed_graph_destroy.argtypes = [C.c_void_p]
     L.qed_graph_destroy.restype = None
+    L.qed_sampler_set.argtypes = [C.c_void_p, C.POINTER(qed_sampler_model)]
+    L.qed_sampler_infer.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
+    L.qed_emission_rate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
+    L.qed_emission_cdf.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_uint32, C.c_uint32, C.c_void_p,
+                                   C.c_void_p]
+    L.qed_train_config_default.argtypes = [C.POINTER(qed_train_config)]
+    L.qed_train_sampler.argtypes = [C.c_void_p, C.POINTER(qed_train_config), C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]
+    L.qed_mlp_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p]
     L.qed_finalize.argtypes = [C.c_void_p]
     L.qed_finalize.restype = None
     L.qed_status_string.argtypes = [C.c_int]
@@ -208,6 +235,67 @@ def qed_finalize(ctx):
     load().qed_finalize(ctx)
 
 
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def qed_sampler_set(ctx, params=None, fallback=None, log10_chi_lo=-3.0, log10_chi_hi=2.0):
+    """Install a model (numpy float32 params, uint8 fallback flags per bin) or remove it (None)."""
+    if params is None:
+        return load().qed_sampler_set(ctx, None)
+    p = np.ascontiguousarray(params, np.float32)
+    fb = np.ascontiguousarray(fallback, np.uint8)
+    m = qed_sampler_model(params=_ptr(p).value, fallback=_ptr(fb).value, nbins=int(fb.size), pad=0,
+                          log10_chi_lo=float(log10_chi_lo), log10_chi_hi=float(log10_chi_hi))
+    return load().qed_sampler_set(ctx, C.byref(m))
+
+
+def qed_sampler_infer(ctx, chi, u, x, n):
+    return load().qed_sampler_infer(ctx, chi, u, x, int(n))
+
+
+def qed_emission_rate(ctx, chi, out, n):
+    return load().qed_emission_rate(ctx, chi, out, int(n))
+
+
+def qed_emission_cdf(ctx, lo, hi, nchi, nx):
+    """(cdf [nchi, nx + 1], total [nchi]) as numpy float64."""
+    cdf = np.zeros((nchi, nx + 1), np.float64)
+    tot = np.zeros(nchi, np.float64)
+    _check(load().qed_emission_cdf(ctx, float(lo), float(hi), int(nchi), int(nx), _ptr(cdf), _ptr(tot)),
+           "qed_emission_cdf")
+    return cdf, tot
+
+
+def qed_train_config_default():
+    cfg = qed_train_config()
+    _check(load().qed_train_config_default(C.byref(cfg)), "qed_train_config_default")
+    return cfg
+
+
+def qed_train_sampler(ctx, cfg, init=None):
+    """Train on the GPU; returns (params, loss per step, CDF error per bin, fallback flags)."""
+    params = np.zeros(QED_MLP_NPARAMS, np.float32)
+    loss = np.zeros(cfg.steps, np.float32)
+    err = np.zeros(cfg.nbins, np.float32)
+    fb = np.zeros(cfg.nbins, np.uint8)
+    ini = None if init is None else np.ascontiguousarray(init, np.float32)
+    _check(load().qed_train_sampler(ctx, C.byref(cfg), None if ini is None else _ptr(ini), _ptr(params),
+                                    _ptr(loss), _ptr(err), _ptr(fb)), "qed_train_sampler")
+    return params, loss, err, fb
+
+
+def qed_mlp_gradient(ctx, params, samples):
+    """(loss, gradient) of the training loss from the GPU kernels."""
+    p = np.ascontiguousarray(params, np.float32)
+    smp = np.ascontiguousarray(samples, np.float32)
+    n = smp.shape[0]
+    grad = np.zeros(QED_MLP_NPARAMS, np.float32)
+    loss = np.zeros(1, np.float32)
+    _check(load().qed_mlp_gradient(ctx, _ptr(p), _ptr(smp), int(n), _ptr(loss), _ptr(grad)), "qed_mlp_gradient")
+    return float(loss[0]), grad
+
+
 # ---------------------------------------------------------------- torch helpers
 
 def _torch():
@@ -218,7 +306,7 @@ def _torch():
 class SpeciesBuffers:
     """Device SoA buffers of one species (torch tensors) with a fixed capacity."""
 
-    def __init__(self, capacity, real, device="cuda", parent=True, events=True):
+    def __init__(self, capacity, real, device="cuda", parent=True, events=True, tau=False):
         torch = _torch()
         self.capacity = int(capacity)
         self.real = real
@@ -234,6 +322,7 @@ class SpeciesBuffers:
         self.id = torch.zeros(cap, dtype=torch.int64, device=device)
         self.parent = torch.zeros(cap, dtype=torch.int64, device=device) if parent else None
         self.events = torch.zeros(cap, dtype=torch.int32, device=device) if events else None
+        self.tau = torch.full((cap,), -1.0, dtype=torch.float64, device=device) if tau else None
 
     def struct(self):
         s = qed_species()
@@ -243,6 +332,7 @@ class SpeciesBuffers:
             setattr(s, k, getattr(self, k).data_ptr())
         s.parent = self.parent.data_ptr() if self.parent is not None else None
         s.events = self.events.data_ptr() if self.events is not None else None
+        s.tau = self.tau.data_ptr() if self.tau is not None else None
         return s
 
     def upload(self, host):
@@ -256,6 +346,10 @@ class SpeciesBuffers:
         for k in ("ux", "uy", "uz", "w"):
             getattr(self, k)[:n].copy_(torch.from_numpy(np.ascontiguousarray(host[k], np.float64)).to(self.real))
         self.id[:n].copy_(torch.from_numpy(np.ascontiguousarray(host["id"]).view(np.int64)))
+        if self.tau is not None:
+            self.tau.fill_(-1.0)
+            if "tau" in host:
+                self.tau[:n].copy_(torch.from_numpy(np.ascontiguousarray(host["tau"], np.float64)))
         self.n.fill_(n)
 
     def count(self):
@@ -267,6 +361,8 @@ class SpeciesBuffers:
         out["id"] = self.id[:n].cpu().numpy().view(np.uint64)
         if self.parent is not None:
             out["parent"] = self.parent[:n].cpu().numpy().view(np.uint64)
+        if self.tau is not None:
+            out["tau"] = self.tau[:n].cpu().numpy()
         return out
 
     def events_host(self, n):
@@ -305,7 +401,8 @@ class Generator:
 
     def __init__(self, precision=QED_PREC_MIXED, capacity=(1 << 20, 1 << 20, 1 << 20), emission=True,
                  pairs=True, p_max=0.01, scheduler=QED_SCHED_NAIVE, pair_bound_coef=0.1,
-                 max_substeps=1 << 24, device=0, stream=None, parent=True, events=True):
+                 max_substeps=1 << 24, device=0, stream=None, parent=True, events=True,
+                 sampler=QED_SAMPLER_REJECTION):
         torch = _torch()
         self.real = torch.float64 if precision == QED_PREC_F64 else torch.float32
         self.precision = precision
@@ -319,9 +416,12 @@ class Generator:
         cfg.scheduler = scheduler
         cfg.pair_bound_coef = pair_bound_coef
         cfg.max_substeps = max_substeps
+        cfg.sampler = sampler
         self.cfg = cfg
         self.ctx = qed_init(cfg)
-        self.sp = [SpeciesBuffers(c, self.real, parent=parent, events=events) for c in capacity]
+        surr = sampler == QED_SAMPLER_SURROGATE
+        self.sp = [SpeciesBuffers(c, self.real, parent=parent, events=events, tau=surr and k < 2)
+                   for k, c in enumerate(capacity)]
         self.fields = [None, None, None]
 
     def load_state(self, state):
