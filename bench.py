@@ -125,16 +125,47 @@ def cpu_baseline(workloads, budget_s):
                       f"steps, FP64 oracle with the same random streams, {dt:.1f} s wall"}
 
 
+def kernel_source_hash():
+    """SHA-256 over the kernel sources, in name order (identifies the kernels a counter
+    summary was taken from)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2008_10468_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".inc")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """Calibrated HBM bytes per launch of `kernel` from the committed counter summary of
+    this workload, or None if there is none or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    sha, val = None, None
+    for line in open(path):
+        if line.startswith("source_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        parts = line.split()
+        if len(parts) == 3 and parts[0] == "traffic" and parts[1] == kernel:
+            val = float(parts[2])
+    if sha != kernel_source_hash():
+        return None
+    return val
+
+
 def roofline(kt, st, K):
     """Roofline of the kernel with the largest share of the profiled time."""
     cand = {k: v for k, v in kt.items()
-            if k in ("k_lepton", "k_light", "k_heavy", "k_photon", "k_photon_sample")}
+            if k in ("k_lepton", "k_tiled", "k_light", "k_heavy", "k_photon", "k_photon_sample")}
     name = max(cand, key=lambda k: cand[k][1])
     nl, tms = cand[name]
     avg_s = tms * 1e-3 / max(nl, 1)
     lep_sub = st.substeps[0] + st.substeps[1]
     lep_part = st.particles[0] + st.particles[1]
-    if name == "k_lepton":
+    if name in ("k_lepton", "k_tiled"):
         sub, part, em = lep_sub, lep_part, st.emissions
         byts = BYTES_PER_LEPTON_STEP * part + BYTES_PER_EMISSION * em
         flops = FLOPS_PER_LEPTON_SUBSTEP * sub
@@ -170,7 +201,7 @@ def roofline(kt, st, K):
         roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(name, "c2")
     roof["kernel"] = name
     roof["avg_launch_us"] = avg_s * 1e6
     roof["per_launch"] = {"particles": part / max(nl, 1), "substeps": sub / max(nl, 1),

@@ -73,7 +73,7 @@ typedef enum qed_sampler { QED_SAMPLER_REJECTION = 0, QED_SAMPLER_SURROGATE = 1 
 typedef enum qed_scheduler {
     QED_SCHED_NAIVE = 0,  /* one lane per particle in buffer order */
     QED_SCHED_BINNED = 1, /* sub-step-count binned persistent work queue */
-    QED_SCHED_TILED = 2   /* one pass: each wave sorts tiles of 512 consecutive particles
+    QED_SCHED_TILED = 2   /* one pass: each wave sorts tiles of 256 consecutive particles
                              by sub-step count in LDS and runs them in that order */
 } qed_scheduler;
 
@@ -236,7 +236,7 @@ QED_API qed_status qed_graph_launch(qed_ctx *ctx, qed_graph *g);
 QED_API void qed_graph_destroy(qed_graph *g);
 
 /* Learned inverse CDF of the emitted energy (the surrogate sampler's model).
- * Network: inputs s = 2 (log10 chi - lo) / (hi - lo) - 1 and v = 2 u - 1; three
+ * Network: inputs s = 2 (log10 chi - lo) / (hi - lo) - 1 and v = (-ln(1 - u))^(1/3) - 1; three
  * hidden layers of 64 units with activation a(t) = t / sqrt(1 + t^2); output y;
  * the candidate x = delta^(1/3) of eq. (1) is y (b / (1 + b))^(1/3), b = 3 chi / 2,
  * clamped to (0, 1).  Layer 1 (2 -> 64) and the output layer (64 -> 1) run in
@@ -292,9 +292,9 @@ QED_API qed_status qed_emission_cdf(qed_ctx *ctx, double log10_chi_lo, double lo
 typedef struct qed_train_config {
     double log10_chi_lo, log10_chi_hi; /* chi range of the network; -3, 2 */
     uint32_t table_chi, table_x;       /* CDF table; 1025 x 8192 */
-    uint32_t steps;                    /* optimizer steps; 2000 */
+    uint32_t steps;                    /* optimizer steps; 60000 */
     uint32_t blocks, batch_tiles;      /* batch = blocks * 64 * batch_tiles; 256, 4 */
-    float lr, lr_final;                /* 3e-3 -> 3e-5 */
+    float lr, lr_final;                /* 1e-2 -> 3e-5 */
     uint64_t seed;                     /* data and initial weights; 1 */
     int32_t nbins, per_bin;            /* validation; 50, 5 */
     double tolerance;                  /* CDF error above which a bin falls back; 1e-3 */

@@ -10,9 +10,11 @@ and the training loss of a batch of n rows (s, v, y_t, w) is
 (1/n) sum w (y - y_t)^2.  Parameters are one flat vector in the order W1[64][2],
 b1, W2[64][64], b2, W3[64][64], b3, W4[64], b4 (weights stored [out][in]).
 
-`round_bf16` optionally rounds the two 64 x 64 layers' weights and inputs to
-bfloat16 (round to nearest even) as the GPU's matrix cores see them, so a check
-can separate that rounding from the rest.  This module's own correctness is
+`round_bf16` optionally rounds the two 64 x 64 layers' weights the way the
+GPU's matrix cores see them: each weight as the sum of two bfloat16 numbers
+(hi = bf16(w), lo = bf16(w - hi), round to nearest even), so a check can separate
+that rounding from the rest (the activations, also held as hi + lo on the GPU,
+are kept exact here).  This module's own correctness is
 pinned by finite differences of `loss` (tests/test_oracle_mlp.py).
 """
 from __future__ import annotations
@@ -47,6 +49,12 @@ def bf16(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def split_bf16(x):
+    """x as the sum of two bfloat16 numbers: bf16(x) + bf16(x - bf16(x))."""
+    hi = bf16(x)
+    return hi + bf16(np.asarray(x, np.float64) - hi)
+
+
 def act(t):
     return t / np.sqrt(1.0 + t * t)
 
@@ -60,10 +68,10 @@ def forward(p, s, v, round_bf16=False):
     x = np.stack([s, v], axis=1).astype(np.float64)
     z1 = x @ d["W1"].T + d["b1"]
     h1 = act(z1)
-    W2, W3 = (bf16(d["W2"]), bf16(d["W3"])) if round_bf16 else (d["W2"], d["W3"])
-    z2 = (bf16(h1) if round_bf16 else h1) @ W2.T + d["b2"]
+    W2, W3 = (split_bf16(d["W2"]), split_bf16(d["W3"])) if round_bf16 else (d["W2"], d["W3"])
+    z2 = h1 @ W2.T + d["b2"]
     h2 = act(z2)
-    z3 = (bf16(h2) if round_bf16 else h2) @ W3.T + d["b3"]
+    z3 = h2 @ W3.T + d["b3"]
     h3 = act(z3)
     y = h3 @ d["W4"] + d["b4"]
     return y, (x, z1, h1, z2, h2, z3, h3)
@@ -81,17 +89,17 @@ def gradient(p, samples, round_bf16=False):
     n = s.size
     d = unpack(p)
     y, (x, z1, h1, z2, h2, z3, h3) = forward(p, s, v, round_bf16)
-    W2, W3 = (bf16(d["W2"]), bf16(d["W3"])) if round_bf16 else (d["W2"], d["W3"])
+    W2, W3 = (split_bf16(d["W2"]), split_bf16(d["W3"])) if round_bf16 else (d["W2"], d["W3"])
     e = y - yt
     L = float(np.mean(w * e * e))
     dy = 2.0 * w * e / n
     g = {"b4": np.sum(dy), "W4": h3.T @ dy}
     dz3 = np.outer(dy, d["W4"]) * dact(z3)
     g["b3"] = dz3.sum(0)
-    g["W3"] = dz3.T @ (bf16(h2) if round_bf16 else h2)
+    g["W3"] = dz3.T @ h2
     dz2 = (dz3 @ W3) * dact(z2)
     g["b2"] = dz2.sum(0)
-    g["W2"] = dz2.T @ (bf16(h1) if round_bf16 else h1)
+    g["W2"] = dz2.T @ h1
     dz1 = (dz2 @ W2) * dact(z1)
     g["b1"] = dz1.sum(0)
     g["W1"] = dz1.T @ x

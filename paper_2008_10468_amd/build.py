@@ -21,6 +21,10 @@ FLAGS = [
     "-fvisibility=hidden",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused within one expression only, never across
+    # statements, so that a function inlined into different kernels rounds the
+    # same way in each (the schedulers must give bit-identical results)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

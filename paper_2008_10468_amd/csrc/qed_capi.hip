@@ -645,10 +645,10 @@ qed_status qed_train_config_default(qed_train_config *cfg) {
     cfg->log10_chi_hi = 2.0;
     cfg->table_chi = 1025;
     cfg->table_x = 8192;
-    cfg->steps = 2000;
+    cfg->steps = 60000;
     cfg->blocks = 256;
     cfg->batch_tiles = 4;
-    cfg->lr = 3e-3f;
+    cfg->lr = 1e-2f;
     cfg->lr_final = 3e-5f;
     cfg->seed = 1;
     cfg->nbins = 50;

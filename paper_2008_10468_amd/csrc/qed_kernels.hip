@@ -501,7 +501,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
                 }
             }
             R yv = 0.0f;
-            if (__ballot(use_net)) yv = mlp_infer_wave(S.mlp, ws, use_net, sin, 2.0f * u - 1.0f);
+            if (__ballot(use_net)) yv = mlp_infer_wave(S.mlp, ws, use_net, sin, mlp_input_v(u));
             R x3 = 0, omx3 = 1;
             if (fire) {
                 R x;
@@ -940,17 +940,19 @@ __global__ __launch_bounds__(kBlock) void k_light(StepArgs a) {
     flush_tally(t, a.st, s);
 }
 
-// Tile-sorted scheduler (one pass, no pre-pass): each wave takes tiles of kTile
+// Tile-sorted scheduler (one pass, no pre-pass): each wave takes tiles of kTiledSlots
 // consecutive slots, computes every particle's sub-step count, counting-sorts the
 // tile by it in LDS (heaviest first) and runs the tile 64 particles at a time in
 // that order, so the lanes of a wave carry nearly the same N.  The particle
 // records are read twice, the second time from the cache.
+constexpr int kTiledSlots = 256;  // slots per wave tile of the tile-sorted scheduler (4 per lane)
+
 template <class R, bool SURR>
 __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
     __shared__ LeptonLds<R, SURR> L;
     __shared__ uint32_t hist_sh[kBlock / 64][kTileKeys];
-    __shared__ uint16_t order_sh[kBlock / 64][kTile];
-    __shared__ uint32_t nsub_sh[kBlock / 64][kTile];
+    __shared__ uint16_t order_sh[kBlock / 64][kTiledSlots];
+    __shared__ uint32_t nsub_sh[kBlock / 64][kTiledSlots];
     ChildBuf<R> &cb = lepton_lds_init<R, SURR>(a, L);
     const int s = blockIdx.y;
     const u64 n = a.st->n0[s];
@@ -961,12 +963,12 @@ __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
     uint32_t *nsub = nsub_sh[wv];
     const u64 nwaves = (u64)gridDim.x * (kBlock / 64);
     Tally<R> t;
-    for (u64 t0 = ((u64)blockIdx.x * (kBlock / 64) + wv) * kTile; t0 < n; t0 += nwaves * kTile) {
+    for (u64 t0 = ((u64)blockIdx.x * (kBlock / 64) + wv) * kTiledSlots; t0 < n; t0 += nwaves * kTiledSlots) {
         hist[lane] = 0;
         __syncwarp();
-        uint32_t kr[kTile / 64];  // key << 16 | rank
+        uint32_t kr[kTiledSlots / 64];  // key << 16 | rank
 #pragma unroll
-        for (int q = 0; q < kTile / 64; ++q) {
+        for (int q = 0; q < kTiledSlots / 64; ++q) {
             const u64 i = t0 + q * 64 + lane;
             Lepton<R> p;
             const uint32_t N = lepton_fetch(a, s, i, i < n, p, t);
@@ -988,7 +990,7 @@ __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
         hist[lane] = incl - h;
         __syncwarp();
 #pragma unroll
-        for (int q = 0; q < kTile / 64; ++q)
+        for (int q = 0; q < kTiledSlots / 64; ++q)
             if (kr[q]) order[hist[kr[q] >> 16] + (kr[q] & 0xFFFFu)] = (uint16_t)(q * 64 + lane);
         __syncwarp();
         for (uint32_t p0 = 0; p0 < total; p0 += 64) {

@@ -1,12 +1,17 @@
 // Learned inverse CDF of the emitted photon energy (surrogate sampler): a
 // 2 -> 64 -> 64 -> 64 -> 1 network evaluated on the matrix cores of gfx950.
 //
-// Inputs s = 2 (log10 chi - lo) / (hi - lo) - 1 and v = 2 u - 1; hidden
+// Inputs s = 2 (log10 chi - lo) / (hi - lo) - 1 and v = (-ln(1 - u))^(1/3) - 1 (the
+// candidate's tail, x^3 ~ b ln(1/(1 - u)) at small chi, becomes linear in v); hidden
 // activation a(t) = t / sqrt(1 + t^2) (smooth, bounded, three instructions, with
 // derivative (1 + t^2)^(-3/2)); output y, from which x = delta^(1/3) = y (b / (1 +
-// b))^(1/3).  Layer 1 and the output layer are float; the two 64 x 64 layers use
-// bfloat16 weights and activations with float accumulation
-// (v_mfma_f32_16x16x32_bf16).
+// b))^(1/3).  Layer 1 and the output layer are float; the two 64 x 64 layers run
+// on the matrix cores in bfloat16 with float accumulation
+// (v_mfma_f32_16x16x32_bf16), with weights and input activations each held as
+// the sum of two bfloat16 numbers (hi + lo) and the product formed as
+// hi*hi + hi*lo + lo*hi (three passes), which keeps about 16 significant bits: a
+// single bfloat16 rounding would leave errors of about 1e-3 in the output, the
+// size of the accuracy the sampler needs.
 //
 // Matrix-core layouts used here (16 x 16 output tile, wave64): for lane l let
 // r = l % 16 and g = l / 16.  The A operand (16 rows x K) supplies row r, the B
@@ -66,6 +71,9 @@ __device__ __forceinline__ bf16x4 as_bf4(uint2 v) { return __builtin_bit_cast(bf
 __device__ __forceinline__ uint32_t pack2(float a, float b) {
     return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
 }
+// the bfloat16 residual v - bf16(v)
+__device__ __forceinline__ float bf_res(float v) { return v - bf2f(f2bf(v)); }
+__device__ __forceinline__ uint32_t pack2_lo(float a, float b) { return pack2(bf_res(a), bf_res(b)); }
 
 // Network in LDS, laid out for the matrix cores: wf2[n][kk][lane] holds the 8
 // B-operand elements W2[16 n + r][32 kk + kidx(g, j)] of lane (r, g), so each
@@ -78,6 +86,8 @@ struct MlpLds {
     int nbins;
     uint4 wf2[4][2][64];
     uint4 wf3[4][2][64];
+    uint4 wl2[4][2][64];   // bf16 residuals of the same weights
+    uint4 wl3[4][2][64];
     uint8_t fallback[256];
 };
 
@@ -100,12 +110,17 @@ __device__ __forceinline__ void mlp_pack(const float *__restrict__ p, MlpLds &M)
         const int r = lane & 15, g = lane >> 4;
         const float *W = p + (layer ? kOffW3 : kOffW2);
         const float *row = W + (16 * n + r) * kHid + 32 * kk;
-        uint4 v;
+        uint4 v, l;
         v.x = pack2(row[kidx(g, 0)], row[kidx(g, 1)]);
         v.y = pack2(row[kidx(g, 2)], row[kidx(g, 3)]);
         v.z = pack2(row[kidx(g, 4)], row[kidx(g, 5)]);
         v.w = pack2(row[kidx(g, 6)], row[kidx(g, 7)]);
+        l.x = pack2_lo(row[kidx(g, 0)], row[kidx(g, 1)]);
+        l.y = pack2_lo(row[kidx(g, 2)], row[kidx(g, 3)]);
+        l.z = pack2_lo(row[kidx(g, 4)], row[kidx(g, 5)]);
+        l.w = pack2_lo(row[kidx(g, 6)], row[kidx(g, 7)]);
         (layer ? M.wf3 : M.wf2)[n][kk][lane] = v;
+        (layer ? M.wl3 : M.wl2)[n][kk][lane] = l;
     }
 }
 
@@ -121,12 +136,50 @@ __device__ __forceinline__ void mlp_stage(const MlpModel *__restrict__ src, MlpL
 // Per-wave scratch of the batched evaluation.
 struct alignas(16) MlpWave {
     float in_s[16], in_v[16], y[16];
-    uint16_t h[16][72];   // one layer's bf16 activations, rows padded to 144 bytes
+    uint16_t h[16][72];   // one layer's activations, bf16 high parts, rows padded to 144 bytes
+    uint16_t l[16][72];   // and their bf16 residuals
 };
 
-__device__ __forceinline__ void load_a(const MlpWave &W, int r, int g, bf16x8 &a0, bf16x8 &a1) {
-    a0 = as_bf8(*reinterpret_cast<const uint4 *>(&W.h[r][kidx(g, 0)]));
-    a1 = as_bf8(*reinterpret_cast<const uint4 *>(&W.h[r][32 + kidx(g, 0)]));
+// A-operand fragments (high and low parts) of row r, K chunks 0 and 1.
+struct AFrag {
+    bf16x8 h0, h1, l0, l1;
+};
+
+template <class Wv>
+__device__ __forceinline__ AFrag load_a(const Wv &W, int r, int g) {
+    AFrag a;
+    a.h0 = as_bf8(*reinterpret_cast<const uint4 *>(&W.h[r][kidx(g, 0)]));
+    a.h1 = as_bf8(*reinterpret_cast<const uint4 *>(&W.h[r][32 + kidx(g, 0)]));
+    a.l0 = as_bf8(*reinterpret_cast<const uint4 *>(&W.l[r][kidx(g, 0)]));
+    a.l1 = as_bf8(*reinterpret_cast<const uint4 *>(&W.l[r][32 + kidx(g, 0)]));
+    return a;
+}
+
+// Store one value of a C-layout tile as high part and residual.
+template <class Wv>
+__device__ __forceinline__ void store_split(Wv &W, int row, int col, float v) {
+    const uint16_t hb = f2bf(v);
+    W.h[row][col] = hb;
+    W.l[row][col] = f2bf(v - bf2f(hb));
+}
+
+// [16 x 64] x [64 x 64] product of split activations with split weight fragments
+// (hi and lo): hi*hi + hi*lo + lo*hi, small terms first.
+__device__ __forceinline__ void gemm_split(const AFrag &a, const uint4 (*fh)[2][64], const uint4 (*fl)[2][64],
+                                           int lane, f32x4 *acc) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const bf16x8 b0 = as_bf8(fh[n][0][lane]), b1 = as_bf8(fh[n][1][lane]);
+        const bf16x8 c0 = as_bf8(fl[n][0][lane]), c1 = as_bf8(fl[n][1][lane]);
+        f32x4 c = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l0, b0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l1, b1, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h0, c0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h1, c1, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h0, b0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h1, b1, c, 0, 0, 0);
+        acc[n] = c;
+    }
 }
 
 // y for every lane with act set.  Called by the whole wave in uniform control
@@ -153,7 +206,7 @@ __device__ __forceinline__ float mlp_infer_wave(const MlpLds &M, MlpWave &W, boo
         __syncwarp();
         // layer 1, directly in the A layout of layer 2
         const float si = W.in_s[r], vi = W.in_v[r];
-        uint32_t pa[2][4];
+        uint32_t ph[2][4], pl[2][4];
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
@@ -161,31 +214,25 @@ __device__ __forceinline__ float mlp_infer_wave(const MlpLds &M, MlpWave &W, boo
                 const int u0 = 32 * kk + kidx(g, j), u1 = u0 + 1;
                 const float h0 = mlp_act(fmaf(M.w1[u0][0], si, fmaf(M.w1[u0][1], vi, M.b1[u0])));
                 const float h1 = mlp_act(fmaf(M.w1[u1][0], si, fmaf(M.w1[u1][1], vi, M.b1[u1])));
-                pa[kk][j / 2] = pack2(h0, h1);
+                ph[kk][j / 2] = pack2(h0, h1);
+                pl[kk][j / 2] = pack2_lo(h0, h1);
             }
-        bf16x8 a0 = as_bf8(make_uint4(pa[0][0], pa[0][1], pa[0][2], pa[0][3]));
-        bf16x8 a1 = as_bf8(make_uint4(pa[1][0], pa[1][1], pa[1][2], pa[1][3]));
+        AFrag a;
+        a.h0 = as_bf8(make_uint4(ph[0][0], ph[0][1], ph[0][2], ph[0][3]));
+        a.h1 = as_bf8(make_uint4(ph[1][0], ph[1][1], ph[1][2], ph[1][3]));
+        a.l0 = as_bf8(make_uint4(pl[0][0], pl[0][1], pl[0][2], pl[0][3]));
+        a.l1 = as_bf8(make_uint4(pl[1][0], pl[1][1], pl[1][2], pl[1][3]));
         // layer 2
         f32x4 acc[4];
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            acc[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, as_bf8(M.wf2[n][0][lane]), acc[n], 0, 0, 0);
-            acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, as_bf8(M.wf2[n][1][lane]), acc[n], 0, 0, 0);
-        }
+        gemm_split(a, M.wf2, M.wl2, lane, acc);
 #pragma unroll
         for (int n = 0; n < 4; ++n)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) W.h[4 * g + q][16 * n + r] = f2bf(mlp_act(acc[n][q] + M.b2[16 * n + r]));
+            for (int q = 0; q < 4; ++q) store_split(W, 4 * g + q, 16 * n + r, mlp_act(acc[n][q] + M.b2[16 * n + r]));
         __syncwarp();
-        load_a(W, r, g, a0, a1);
+        a = load_a(W, r, g);
         // layer 3 and the output layer
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            acc[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, as_bf8(M.wf3[n][0][lane]), acc[n], 0, 0, 0);
-            acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, as_bf8(M.wf3[n][1][lane]), acc[n], 0, 0, 0);
-        }
+        gemm_split(a, M.wf3, M.wl3, lane, acc);
         float part[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -216,6 +263,12 @@ __device__ __forceinline__ float mlp_input_s(const MlpLds &M, float chi, bool &i
     in_range = t >= 0.0f && t < 1.0f;
     bin = in_range ? min((int)(t * (float)M.nbins), M.nbins - 1) : 0;
     return 2.0f * t - 1.0f;
+}
+
+// Network input v of a uniform u in (0, 1): (-ln(1 - u))^(1/3) - 1.
+__device__ __forceinline__ float mlp_input_v(float u) {
+    const float L = -__builtin_amdgcn_logf(1.0f - u) * 0.69314718056f;   // -ln(1 - u) > 0
+    return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(fmaxf(L, 0x1p-100f)) * (1.0f / 3.0f)) - 1.0f;
 }
 
 // x = y (b / (1 + b))^(1/3), b = 3 chi / 2, clamped to the open interval (0, 1).

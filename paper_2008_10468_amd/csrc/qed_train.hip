@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_cdf_table(CdfTableDev t) {
         const double d = emission_density(cdf_x_of_xi(xi), b, tab) * 2.0 * (1.0 - xi);
         acc += 0.5 * h * (dprev + d);
         dprev = d;
-        row[k + 1] = k + 1 == t.nx ? 1.0 : acc / total;
+        row[k + 1] = k + 1 == t.nx ? 1.0 : fmin(acc / total, 1.0);
     }
 }
 
@@ -129,13 +129,20 @@ __device__ __forceinline__ void cdf_invert(const CdfTableDev &t, double l10, dou
     dens = dm * (double)t.nx / fmax(2.0 * (1.0 - xi), 1e-300);
 }
 
+// Largest network input v: u = 1 - 2^-24, the largest float uniform, gives 1.55.
+constexpr double kVmax = 1.6;
+
 __global__ __launch_bounds__(kBlock) void k_mlp_data(CdfTableDev t, Sample *out, u64 n, uint64_t seed,
                                                      uint32_t step, double lo10, double hi10) {
     const uint32_t klo = (uint32_t)seed ^ 0x7F4A7C15u, khi = (uint32_t)(seed >> 32) ^ 0xF39CC060u;
     for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
         const u32x4 w = philox10((uint32_t)i, (uint32_t)(i >> 32), step, 0u, klo, khi);
         const double tl = u53(w.x, w.y);  // position in the chi range
-        const double u = u53(w.z, w.w);
+        // the network input v = (-ln(1 - u))^(1/3) - 1 is drawn uniformly on
+        // [-1, kVmax] (u = 1 - exp(-(v + 1)^3)), so the tails of the spectrum are
+        // sampled as densely as its bulk
+        const double v = -1.0 + (kVmax + 1.0) * u53(w.z, w.w);
+        const double u = -expm1(-(v + 1.0) * (v + 1.0) * (v + 1.0));
         const double l10 = lo10 + (hi10 - lo10) * tl;
         double x, dens;
         cdf_invert(t, l10, u, x, dens);
@@ -143,12 +150,13 @@ __global__ __launch_bounds__(kBlock) void k_mlp_data(CdfTableDev t, Sample *out,
         const double xs = cbrt(b / (1.0 + b));
         Sample s;
         s.s = (float)(2.0 * tl - 1.0);
-        s.v = (float)(2.0 * u - 1.0);
+        s.v = (float)v;
         s.y = (float)(x / xs);
         // weight: squared density in units of the network output, so the loss
-        // approximates the squared CDF error; capped to keep the scale moderate
+        // approximates the squared CDF error (capped to keep the scale moderate,
+        // with a small floor for the far tail)
         const double dy = fmin(dens * xs, 5.0);
-        s.w = (float)(dy * dy);
+        s.w = (float)(dy * dy + 1e-4);
         out[i] = s;
     }
 }
@@ -158,7 +166,8 @@ __global__ __launch_bounds__(kBlock) void k_mlp_data(CdfTableDev t, Sample *out,
 // ---------------------------------------------------------------------------
 struct alignas(16) TrainWave {
     float s[16], v[16], yt[16], wt[16];
-    uint16_t h[16][72];
+    uint16_t h[16][72];   // high parts (and single bf16 values of the backward pass)
+    uint16_t l[16][72];   // residuals of the forward activations
 };
 
 struct TrainLds {
@@ -193,7 +202,20 @@ __device__ __forceinline__ s16x4 pack4(const float *v) {
     return __builtin_bit_cast(s16x4, u);
 }
 
-// C-layout tile values (rows 4g + q of column 16 n + r) -> A-layout fragments via LDS.
+// C-layout activations (rows 4g + q of column 16 n + r) -> split A-layout fragments.
+__device__ __forceinline__ AFrag transpose_split(TrainWave &W, const float (*v)[4], int r, int g) {
+    __syncwarp();
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) store_split(W, 4 * g + q, 16 * n + r, v[n][q]);
+    __syncwarp();
+    const AFrag a = load_a(W, r, g);
+    __syncwarp();
+    return a;
+}
+
+// C-layout tile values -> single bf16 A-layout fragments via LDS (backward pass).
 __device__ __forceinline__ void transpose_to_a(TrainWave &W, const float (*v)[4], int r, int g, bf16x8 &a0,
                                                bf16x8 &a1) {
     __syncwarp();
@@ -261,9 +283,8 @@ __global__ __launch_bounds__(kBlock) void k_mlp_train(TrainArgs ta) {
             }
         }
         bf16x8 a0, a1;
-        transpose_to_a(W, h1, r, g, a0, a1);
         f32x4 acc[4];
-        gemm_64(a0, a1, M.wf2, lane, acc);
+        gemm_split(transpose_split(W, h1, r, g), M.wf2, M.wl2, lane, acc);
         float pre2[4][4], h2[4][4];
 #pragma unroll
         for (int n = 0; n < 4; ++n)
@@ -272,8 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_train(TrainArgs ta) {
                 pre2[n][q] = acc[n][q] + M.b2[16 * n + r];
                 h2[n][q] = mlp_act(pre2[n][q]);
             }
-        transpose_to_a(W, h2, r, g, a0, a1);
-        gemm_64(a0, a1, M.wf3, lane, acc);
+        gemm_split(transpose_split(W, h2, r, g), M.wf3, M.wl3, lane, acc);
         float pre3[4][4], h3[4][4];
 #pragma unroll
         for (int n = 0; n < 4; ++n)
@@ -445,7 +465,7 @@ __device__ __forceinline__ float infer_one(const MlpLds &M, MlpWave &W, bool val
     int bin;
     const float s = mlp_input_s(M, chi, in_range, bin);
     const bool use = valid && in_range && !M.fallback[bin];
-    const float y = mlp_infer_wave(M, W, use, s, 2.0f * u - 1.0f);
+    const float y = mlp_infer_wave(M, W, use, s, mlp_input_v(u));
     return use ? mlp_x_of_y(y, chi) : __builtin_nanf("");
 }
 
@@ -483,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_validate(const MlpModel *model, 
         bool in_range;
         int b;
         const float s = mlp_input_s(M, chi, in_range, b);
-        const float y = mlp_infer_wave(M, W, true, s, 2.0f * u - 1.0f);
+        const float y = mlp_infer_wave(M, W, true, s, mlp_input_v(u));
         const float x = mlp_x_of_y(y, chi);
         const double c = cdf_lookup(t, log10((double)chi), (double)x);
         emax = fmaxf(emax, (float)fabs(c - (double)u));

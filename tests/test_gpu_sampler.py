@@ -55,7 +55,7 @@ def test_cdf_table_matches_oracle():
     cdf, tot = qed.qed_emission_cdf(ctx, -3.0, 2.0, nchi, nx)
     xi = np.arange(nx + 1) / nx
     xg = 1.0 - (1.0 - xi) ** 2
-    assert np.all(np.diff(cdf, axis=1) >= 0) and np.all(cdf[:, 0] == 0) and np.all(cdf[:, -1] == 1)
+    assert np.all(np.diff(cdf, axis=1) >= -1e-14) and np.all(cdf[:, 0] == 0) and np.all(cdf[:, -1] == 1)
     for c in range(0, nchi, 2):
         chi = 10.0 ** (-3.0 + 0.5 * c)
         b = 1.5 * chi
@@ -99,15 +99,11 @@ def test_mlp_gradient_matches_reference():
 
 @pytest.fixture(scope="module")
 def trained():
-    """A short training run on the GPU (the full run is the benchmark's)."""
+    """A shorter training run on the GPU (the default run is the benchmark's)."""
     from paper_2008_10468_amd import qed
     ctx = qed.qed_init(qed.qed_config_default())
     cfg = qed.qed_train_config_default()
-    cfg.steps = 800
-    cfg.blocks = 128
-    cfg.batch_tiles = 4
-    cfg.table_chi = 513
-    cfg.table_x = 4096
+    cfg.steps = 40000
     params, loss, err, fb = qed.qed_train_sampler(ctx, cfg)
     qed.qed_finalize(ctx)
     return cfg, params, loss, err, fb
@@ -118,8 +114,9 @@ def test_training_reduces_loss(trained):
     assert np.all(np.isfinite(loss)) and np.all(np.isfinite(params))
     assert loss[-50:].mean() < 0.05 * loss[:5].mean(), (loss[:5], loss[-50:].mean())
     assert np.all(np.isfinite(err)) and err.max() < 0.5
-    # most of the range is learnt to the tolerance already in this short run
-    assert np.mean(err <= cfg.tolerance) >= 0.5, err
+    # nearly all of the range is learnt to the tolerance already in this shorter run
+    assert np.mean(err <= cfg.tolerance) >= 0.8, err
+    assert err.max() <= 3 * cfg.tolerance, err
 
 
 def test_trained_network_against_oracle_cdf(trained):
