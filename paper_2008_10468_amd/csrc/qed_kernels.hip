@@ -438,11 +438,18 @@ __device__ __forceinline__ float surr_reject(float chi, const SurrLds &S, const 
     return x;
 }
 
-// N: this lane's sub-steps (0 for a lane without a particle); Nw: the largest N
-// of the wave.  Every lane of the wave runs Nw iterations so that the network
-// passes see all 64 lanes.
+// Emissions are resolved in batches: a lane whose optical depth runs out draws its
+// random numbers and waits (it does not advance) while the other lanes go on;
+// once kResolveBatch lanes wait, or no lane can advance, the wave evaluates the
+// network for all waiting lanes together (rows of matrix-core passes), stages the
+// photons, applies the recoils and releases the lanes.  A lane's own sequence of
+// operations and draws does not depend on when its emission is resolved, so the
+// result is the same for any batching and any scheduler.  N: this lane's
+// sub-steps (0 for a lane without a particle).  All 64 lanes of the wave call it.
+constexpr int kResolveBatch = 16;
+
 template <int FK>
-__device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i, uint32_t N, uint32_t Nw,
+__device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i, uint32_t N,
                                                  const Lepton<float> &p, const SynTable<float> &tab, SurrLds &S,
                                                  ChildBuf<float> &cb, Tally<float> &tl) {
     using R = float;
@@ -468,57 +475,66 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
     R ux = p.ux, uy = p.uy, uz = p.uz;
     R dx = 0, dy = 0, dz = 0;
     uint32_t nev = 0;
-    for (uint32_t k = 0; k < Nw; ++k) {
-        const bool live = k < N;
-        R chi = 0, g = 1, u2 = 0;
-        if (live) {
+    uint32_t k = 0;     // next sub-step of this lane
+    bool pend = false;  // an emission waits for its energy
+    uint32_t pk = 0;    // its sub-step
+    R pchi = 0, pg = 1, pu2 = 0, pu = 0.5f;
+    double ptau = 1.0;  // the optical depth drawn for after it
+    for (;;) {
+        if (k < N && !pend) {
             boris<R, FK>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
-            u2 = ux * ux + uy * uy + uz * uz;
+            const R u2 = ux * ux + uy * uy + uz * uz;
             const R ig = rsqrt_(R(1) + u2);
-            g = (R(1) + u2) * ig;
+            const R g = (R(1) + u2) * ig;
             const R vs = str * ig;
             dx += ux * vs;
             dy += uy * vs;
             dz += uz * vs;
-            chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
+            const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
             tau -= (double)(wk * rate_chi_q(chi, S.rate) * ig);
-        }
-        const bool fire = live && tau <= 0.0;
-        const u64 m = __ballot(fire);
-        if (m) {
-            R u = 0.5f, sin = 0.0f;
-            double tnew = 1.0;
-            bool use_net = false;
-            if (fire) {
+            if (tau <= 0.0) {
                 const u32x4 w = philox10(idlo, idhi, a.step, j++, klo, khi);
-                u = u24(w.x);
-                tnew = -log(u53(w.z, w.w));
-                if (S.have_model) {
-                    bool in_range;
-                    int bin;
-                    sin = mlp_input_s(S.mlp, chi, in_range, bin);
-                    use_net = in_range && !S.mlp.fallback[bin];
-                }
+                pend = true;
+                pk = k;
+                pchi = chi;
+                pg = g;
+                pu2 = u2;
+                pu = u24(w.x);
+                ptau = -log(u53(w.z, w.w));
             }
-            R yv = 0.0f;
-            if (__ballot(use_net)) yv = mlp_infer_wave(S.mlp, ws, use_net, sin, mlp_input_v(u));
-            R x3 = 0, omx3 = 1;
-            if (fire) {
-                R x;
-                if (use_net) {
-                    x = mlp_x_of_y(yv, chi);
-                    tl.learned++;
-                } else {
-                    x = surr_reject(chi, S, tab, idlo, idhi, a.step, klo, khi, j, tl);
-                    tl.fallback++;
-                }
-                const R x2 = x * x;
-                x3 = x2 * x;
-                omx3 = (R(1) - x) * (R(1) + x + x2);
-                tau = tnew;
-            }
-            stage_emission<R>(a, sp, i, pid, k, fire, m, x3, omx3, g, u2, dx, dy, dz, ux, uy, uz, cb, nev);
+            ++k;
         }
+        const u64 mp = __ballot(pend);
+        const u64 mr = __ballot(k < N && !pend);
+        if (mp == 0 && mr == 0) break;
+        if (mp == 0 || (__popcll(mp) < kResolveBatch && mr != 0)) continue;
+        bool use_net = false;
+        R sin = 0.0f;
+        if (pend && S.have_model) {
+            bool in_range;
+            int bin;
+            sin = mlp_input_s(S.mlp, pchi, in_range, bin);
+            use_net = in_range && !S.mlp.fallback[bin];
+        }
+        R yv = 0.0f;
+        if (__ballot(use_net)) yv = mlp_infer_wave(S.mlp, ws, use_net, sin, mlp_input_v(pu));
+        R x3 = 0, omx3 = 1;
+        if (pend) {
+            R x;
+            if (use_net) {
+                x = mlp_x_of_y(yv, pchi);
+                tl.learned++;
+            } else {
+                x = surr_reject(pchi, S, tab, idlo, idhi, a.step, klo, khi, j, tl);
+                tl.fallback++;
+            }
+            const R x2 = x * x;
+            x3 = x2 * x;
+            omx3 = (R(1) - x) * (R(1) + x + x2);
+            tau = ptau;
+        }
+        stage_emission<R>(a, sp, i, pid, pk, pend, mp, x3, omx3, pg, pu2, dx, dy, dz, ux, uy, uz, cb, nev);
+        pend = false;
     }
     if (has) {
         ((R *)sp.ux)[i] = ux;
@@ -552,20 +568,17 @@ struct LeptonRunner<float, true> {
     template <class L>
     __device__ static void run(const StepArgs &a, int s, u64 i, uint32_t n, const Lepton<float> &p, L &lds,
                                ChildBuf<float> &cb, Tally<float> &t) {
-        uint32_t nw = n;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) nw = max(nw, (uint32_t)__shfl_xor((int)nw, o));
-        if (nw == 0) return;
+        if (__ballot(n != 0) == 0) return;
         // one field kind for the whole wave (the general form is valid for all)
         const bool noB = p.bx == 0.0f && p.by == 0.0f && p.bz == 0.0f;
         const bool noE = p.ex == 0.0f && p.ey == 0.0f && p.ez == 0.0f;
         const u64 live = __ballot(n != 0);
         if ((__ballot(n != 0 && noB) == live))
-            lepton_loop_surr<1>(a, s, i, n, nw, p, lds.tab, lds.surr, cb, t);
+            lepton_loop_surr<1>(a, s, i, n, p, lds.tab, lds.surr, cb, t);
         else if ((__ballot(n != 0 && noE) == live))
-            lepton_loop_surr<2>(a, s, i, n, nw, p, lds.tab, lds.surr, cb, t);
+            lepton_loop_surr<2>(a, s, i, n, p, lds.tab, lds.surr, cb, t);
         else
-            lepton_loop_surr<0>(a, s, i, n, nw, p, lds.tab, lds.surr, cb, t);
+            lepton_loop_surr<0>(a, s, i, n, p, lds.tab, lds.surr, cb, t);
     }
 };
 
@@ -1010,7 +1023,7 @@ __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
 
 // Persistent: each wave claims chunk consecutive queue entries at a time.
 template <class R, bool SURR>
-__global__ __launch_bounds__(kBlock) void k_heavy(StepArgs a) {
+__global__ __launch_bounds__(kBlock, 3) void k_heavy(StepArgs a) {
     __shared__ LeptonLds<R, SURR> L;
     ChildBuf<R> &cb = lepton_lds_init<R, SURR>(a, L);
     const int s = blockIdx.y;

@@ -16,8 +16,9 @@
 // Matrix-core layouts used here (16 x 16 output tile, wave64): for lane l let
 // r = l % 16 and g = l / 16.  The A operand (16 rows x K) supplies row r, the B
 // operand (K x 16 columns) column r, and lane l holds the result rows 4g .. 4g+3
-// of column r.  Each lane's 8 (or 4) K-elements are K indices kidx(g, j); any
-// fixed assignment works as long as A and B use the same one.
+// of column r.  Which K indices a lane's 8 (or 4) elements stand for is a free
+// choice as long as A and B make the same one: inference uses unit_of (below),
+// training kidx.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,23 +36,15 @@ constexpr int kMlpParams = 8577;
 constexpr int kOffW1 = 0, kOffB1 = 128, kOffW2 = 192, kOffB2 = 4288, kOffW3 = 4352, kOffB3 = 8448,
               kOffW4 = 8512, kOffB4 = 8576;
 
-// K index of element j of lane group g in a 32-wide K chunk.
+// K index of element j of lane group g in a 32-wide K chunk (training layout).
 __device__ __forceinline__ int kidx(int g, int j) { return 8 * g + j; }
 
-// float -> bfloat16 bits, round to nearest even (NaN kept quiet).
-__host__ __device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u;
-    __builtin_memcpy(&u, &f, 4);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__host__ __device__ __forceinline__ float bf2f(uint16_t h) {
-    const uint32_t u = (uint32_t)h << 16;
-    float f;
-    __builtin_memcpy(&f, &u, 4);
-    return f;
-}
+// Hidden unit behind element j of lane group g in K chunk kk of the inference
+// layout.  A product's result tile leaves lane (r, g) holding units 16 n + 4 g + q
+// (n, q = 0..3) of batch row r; taking chunk kk = units of n = 2 kk and 2 kk + 1
+// makes that exactly the lane's B-operand fragment for the next layer, so the
+// activations never leave the registers between layers.
+__device__ __forceinline__ int unit_of(int kk, int g, int j) { return 16 * (2 * kk + (j >> 2)) + 4 * g + (j & 3); }
 
 __device__ __forceinline__ float mlp_act(float t) { return t * __builtin_amdgcn_rsqf(fmaf(t, t, 1.0f)); }
 // a'(t) = (1 + t^2)^(-3/2)
@@ -68,16 +61,20 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 
 __device__ __forceinline__ bf16x8 as_bf8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 __device__ __forceinline__ bf16x4 as_bf4(uint2 v) { return __builtin_bit_cast(bf16x4, v); }
+// Two floats to packed bfloat16 (round to nearest even; one v_cvt_pk_bf16_f32).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pack2(float a, float b) {
-    return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
+    const bf16x2 v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
 }
+__device__ __forceinline__ uint16_t bf_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 // the bfloat16 residual v - bf16(v)
-__device__ __forceinline__ float bf_res(float v) { return v - bf2f(f2bf(v)); }
+__device__ __forceinline__ float bf_res(float v) { return v - (float)(__bf16)v; }
 __device__ __forceinline__ uint32_t pack2_lo(float a, float b) { return pack2(bf_res(a), bf_res(b)); }
 
-// Network in LDS, laid out for the matrix cores: wf2[n][kk][lane] holds the 8
-// B-operand elements W2[16 n + r][32 kk + kidx(g, j)] of lane (r, g), so each
-// K chunk of each output tile is one 16-byte load per lane.
+// Network in LDS, laid out for the matrix cores with the weights as the A
+// operand: wf2[n][kk][lane] holds the 8 elements W2[16 n + r][unit_of(kk, g, j)]
+// of lane (r, g) (high parts; wl2 the residuals), one 16-byte load per pass.
 struct MlpLds {
     float w1[kHid][2];
     float b1[kHid], b2[kHid], b3[kHid], w4[kHid];
@@ -94,7 +91,7 @@ struct MlpLds {
 // Device copy of an installed model (same layout; staged into LDS per block).
 typedef MlpLds MlpModel;
 
-// Build the fragment layout from float parameters (one block; every thread calls).
+// Build the inference layout from float parameters (one block; every thread calls).
 __device__ __forceinline__ void mlp_pack(const float *__restrict__ p, MlpLds &M) {
     for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
         M.w1[i][0] = p[kOffW1 + 2 * i];
@@ -108,17 +105,13 @@ __device__ __forceinline__ void mlp_pack(const float *__restrict__ p, MlpLds &M)
     for (int e = threadIdx.x; e < 2 * 4 * 2 * 64; e += blockDim.x) {
         const int lane = e & 63, kk = (e >> 6) & 1, n = (e >> 7) & 3, layer = e >> 9;
         const int r = lane & 15, g = lane >> 4;
-        const float *W = p + (layer ? kOffW3 : kOffW2);
-        const float *row = W + (16 * n + r) * kHid + 32 * kk;
-        uint4 v, l;
-        v.x = pack2(row[kidx(g, 0)], row[kidx(g, 1)]);
-        v.y = pack2(row[kidx(g, 2)], row[kidx(g, 3)]);
-        v.z = pack2(row[kidx(g, 4)], row[kidx(g, 5)]);
-        v.w = pack2(row[kidx(g, 6)], row[kidx(g, 7)]);
-        l.x = pack2_lo(row[kidx(g, 0)], row[kidx(g, 1)]);
-        l.y = pack2_lo(row[kidx(g, 2)], row[kidx(g, 3)]);
-        l.z = pack2_lo(row[kidx(g, 4)], row[kidx(g, 5)]);
-        l.w = pack2_lo(row[kidx(g, 6)], row[kidx(g, 7)]);
+        const float *row = p + (layer ? kOffW3 : kOffW2) + (16 * n + r) * kHid;
+        float w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w[j] = row[unit_of(kk, g, j)];
+        const uint4 v = make_uint4(pack2(w[0], w[1]), pack2(w[2], w[3]), pack2(w[4], w[5]), pack2(w[6], w[7]));
+        const uint4 l = make_uint4(pack2_lo(w[0], w[1]), pack2_lo(w[2], w[3]), pack2_lo(w[4], w[5]),
+                                   pack2_lo(w[6], w[7]));
         (layer ? M.wf3 : M.wf2)[n][kk][lane] = v;
         (layer ? M.wl3 : M.wl2)[n][kk][lane] = l;
     }
@@ -133,59 +126,60 @@ __device__ __forceinline__ void mlp_stage(const MlpModel *__restrict__ src, MlpL
     __syncthreads();
 }
 
-// Per-wave scratch of the batched evaluation.
-struct alignas(16) MlpWave {
+// Per-wave scratch of the batched evaluation: the rows' inputs and outputs.
+struct MlpWave {
     float in_s[16], in_v[16], y[16];
-    uint16_t h[16][72];   // one layer's activations, bf16 high parts, rows padded to 144 bytes
-    uint16_t l[16][72];   // and their bf16 residuals
 };
 
-// A-operand fragments (high and low parts) of row r, K chunks 0 and 1.
-struct AFrag {
-    bf16x8 h0, h1, l0, l1;
+// Activations of one batch row as B-operand fragments (high parts and residuals).
+struct BFrag {
+    uint32_t h[2][4], l[2][4];
 };
 
-template <class Wv>
-__device__ __forceinline__ AFrag load_a(const Wv &W, int r, int g) {
-    AFrag a;
-    a.h0 = as_bf8(*reinterpret_cast<const uint4 *>(&W.h[r][kidx(g, 0)]));
-    a.h1 = as_bf8(*reinterpret_cast<const uint4 *>(&W.h[r][32 + kidx(g, 0)]));
-    a.l0 = as_bf8(*reinterpret_cast<const uint4 *>(&W.l[r][kidx(g, 0)]));
-    a.l1 = as_bf8(*reinterpret_cast<const uint4 *>(&W.l[r][32 + kidx(g, 0)]));
-    return a;
-}
-
-// Store one value of a C-layout tile as high part and residual.
-template <class Wv>
-__device__ __forceinline__ void store_split(Wv &W, int row, int col, float v) {
-    const uint16_t hb = f2bf(v);
-    W.h[row][col] = hb;
-    W.l[row][col] = f2bf(v - bf2f(hb));
-}
-
-// [16 x 64] x [64 x 64] product of split activations with split weight fragments
-// (hi and lo): hi*hi + hi*lo + lo*hi, small terms first.
-__device__ __forceinline__ void gemm_split(const AFrag &a, const uint4 (*fh)[2][64], const uint4 (*fl)[2][64],
-                                           int lane, f32x4 *acc) {
+// z = W x for the batch: acc[n][q] = sum_k W[16 n + 4 g + q][k] x[row r][k],
+// as hi*hi + hi*lo + lo*hi, small terms first.
+__device__ __forceinline__ void mlp_layer(const BFrag &x, const uint4 (*wh)[2][64], const uint4 (*wl)[2][64],
+                                          int lane, f32x4 *acc) {
+    const bf16x8 xh0 = as_bf8(make_uint4(x.h[0][0], x.h[0][1], x.h[0][2], x.h[0][3]));
+    const bf16x8 xh1 = as_bf8(make_uint4(x.h[1][0], x.h[1][1], x.h[1][2], x.h[1][3]));
+    const bf16x8 xl0 = as_bf8(make_uint4(x.l[0][0], x.l[0][1], x.l[0][2], x.l[0][3]));
+    const bf16x8 xl1 = as_bf8(make_uint4(x.l[1][0], x.l[1][1], x.l[1][2], x.l[1][3]));
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        const bf16x8 b0 = as_bf8(fh[n][0][lane]), b1 = as_bf8(fh[n][1][lane]);
-        const bf16x8 c0 = as_bf8(fl[n][0][lane]), c1 = as_bf8(fl[n][1][lane]);
+        const bf16x8 a0 = as_bf8(wh[n][0][lane]), a1 = as_bf8(wh[n][1][lane]);
+        const bf16x8 c0 = as_bf8(wl[n][0][lane]), c1 = as_bf8(wl[n][1][lane]);
         f32x4 c = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l0, b0, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l1, b1, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h0, c0, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h1, c1, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h0, b0, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h1, b1, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, xl0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, xl1, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c0, xh0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c1, xh1, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, xh0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, xh1, c, 0, 0, 0);
         acc[n] = c;
     }
 }
 
+// a(z + b) of a layer's result, written as the next layer's B fragments.
+__device__ __forceinline__ BFrag mlp_activate(const f32x4 *acc, const float *bias, int g) {
+    BFrag x;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        float h[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h[q] = mlp_act(acc[n][q] + bias[16 * n + 4 * g + q]);
+        // units 16 n + 4 g + q sit in chunk n / 2, slots 4 (n % 2) + q
+        x.h[n >> 1][2 * (n & 1)] = pack2(h[0], h[1]);
+        x.h[n >> 1][2 * (n & 1) + 1] = pack2(h[2], h[3]);
+        x.l[n >> 1][2 * (n & 1)] = pack2_lo(h[0], h[1]);
+        x.l[n >> 1][2 * (n & 1) + 1] = pack2_lo(h[2], h[3]);
+    }
+    return x;
+}
+
 // y for every lane with act set.  Called by the whole wave in uniform control
 // flow (all 64 lanes active); lanes without act get 0.  The active lanes are
-// taken 16 at a time as the rows of one matrix-core pass; each row's result is
-// independent of the other rows.
+// taken 16 at a time as the columns (batch rows) of one matrix-core pass; each
+// row's result is independent of the other rows.
 __device__ __forceinline__ float mlp_infer_wave(const MlpLds &M, MlpWave &W, bool act, float s, float v) {
     const int lane = __lane_id(), r = lane & 15, g = lane >> 4;
     float out = 0.0f;
@@ -204,50 +198,35 @@ __device__ __forceinline__ float mlp_infer_wave(const MlpLds &M, MlpWave &W, boo
             W.in_v[rank] = v;
         }
         __syncwarp();
-        // layer 1, directly in the A layout of layer 2
+        // layer 1 (float), straight into the B layout of layer 2
         const float si = W.in_s[r], vi = W.in_v[r];
-        uint32_t ph[2][4], pl[2][4];
+        BFrag x;
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
             for (int j = 0; j < 8; j += 2) {
-                const int u0 = 32 * kk + kidx(g, j), u1 = u0 + 1;
+                const int u0 = unit_of(kk, g, j), u1 = unit_of(kk, g, j + 1);
                 const float h0 = mlp_act(fmaf(M.w1[u0][0], si, fmaf(M.w1[u0][1], vi, M.b1[u0])));
                 const float h1 = mlp_act(fmaf(M.w1[u1][0], si, fmaf(M.w1[u1][1], vi, M.b1[u1])));
-                ph[kk][j / 2] = pack2(h0, h1);
-                pl[kk][j / 2] = pack2_lo(h0, h1);
+                x.h[kk][j / 2] = pack2(h0, h1);
+                x.l[kk][j / 2] = pack2_lo(h0, h1);
             }
-        AFrag a;
-        a.h0 = as_bf8(make_uint4(ph[0][0], ph[0][1], ph[0][2], ph[0][3]));
-        a.h1 = as_bf8(make_uint4(ph[1][0], ph[1][1], ph[1][2], ph[1][3]));
-        a.l0 = as_bf8(make_uint4(pl[0][0], pl[0][1], pl[0][2], pl[0][3]));
-        a.l1 = as_bf8(make_uint4(pl[1][0], pl[1][1], pl[1][2], pl[1][3]));
-        // layer 2
         f32x4 acc[4];
-        gemm_split(a, M.wf2, M.wl2, lane, acc);
+        mlp_layer(x, M.wf2, M.wl2, lane, acc);
+        x = mlp_activate(acc, M.b2, g);
+        mlp_layer(x, M.wf3, M.wl3, lane, acc);
+        // output layer: this lane's 16 units, then the sum over the four lane groups
+        float part = 0.0f;
 #pragma unroll
         for (int n = 0; n < 4; ++n)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) store_split(W, 4 * g + q, 16 * n + r, mlp_act(acc[n][q] + M.b2[16 * n + r]));
-        __syncwarp();
-        a = load_a(W, r, g);
-        // layer 3 and the output layer
-        gemm_split(a, M.wf3, M.wl3, lane, acc);
-        float part[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            float sacc = 0.0f;
-#pragma unroll
-            for (int n = 0; n < 4; ++n) sacc = fmaf(M.w4[16 * n + r], mlp_act(acc[n][q] + M.b3[16 * n + r]), sacc);
-            part[q] = sacc;
-        }
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) part[q] += __shfl_xor(part[q], o);
-        if (r == 0)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) W.y[4 * g + q] = part[q] + M.b4;
+            for (int q = 0; q < 4; ++q) {
+                const int u = 16 * n + 4 * g + q;
+                part = fmaf(M.w4[u], mlp_act(acc[n][q] + M.b3[u]), part);
+            }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (g == 0) W.y[r] = part + M.b4;
         __syncwarp();
         if (mine) out = W.y[rank];
         m &= ~__ballot(mine);

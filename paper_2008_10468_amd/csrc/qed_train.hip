@@ -170,28 +170,74 @@ struct alignas(16) TrainWave {
     uint16_t l[16][72];   // residuals of the forward activations
 };
 
+struct TrainParams {
+    float w1[kHid][2];
+    float b1[kHid], b2[kHid], b3[kHid], w4[kHid];
+    float b4;
+};
+
+// Training layout (activations as the A operand, weights as B): tf2[n][kk][lane]
+// holds W2[16 n + r][32 kk + kidx(g, j)] (high parts; tl2 the residuals), and
+// wt2 the transposed weights W2[32 kk + kidx(g, j)][16 n + r] for dZ W.
 struct TrainLds {
-    MlpLds M;
-    uint4 wt2[4][2][64];  // W2 transposed fragments: element j = W2[32 kk + kidx(g, j)][16 n + r]
-    uint4 wt3[4][2][64];
+    TrainParams P;
+    uint4 tf2[4][2][64], tf3[4][2][64];
+    uint4 tl2[4][2][64], tl3[4][2][64];
+    uint4 wt2[4][2][64], wt3[4][2][64];
     TrainWave ws[kBlock / 64];
     float red[kMlpParams + 1];
 };
 
-__device__ __forceinline__ void pack_transposed(const float *__restrict__ p, TrainLds &L) {
+__device__ __forceinline__ void pack_train(const float *__restrict__ p, TrainLds &L) {
+    for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
+        L.P.w1[i][0] = p[kOffW1 + 2 * i];
+        L.P.w1[i][1] = p[kOffW1 + 2 * i + 1];
+        L.P.b1[i] = p[kOffB1 + i];
+        L.P.b2[i] = p[kOffB2 + i];
+        L.P.b3[i] = p[kOffB3 + i];
+        L.P.w4[i] = p[kOffW4 + i];
+    }
+    if (threadIdx.x == 0) L.P.b4 = p[kOffB4];
     for (int e = threadIdx.x; e < 2 * 4 * 2 * 64; e += blockDim.x) {
         const int lane = e & 63, kk = (e >> 6) & 1, n = (e >> 7) & 3, layer = e >> 9;
         const int r = lane & 15, g = lane >> 4;
         const float *W = p + (layer ? kOffW3 : kOffW2);
-        float v[8];
+        float f[8], t[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = W[(32 * kk + kidx(g, j)) * kHid + 16 * n + r];
-        uint4 q;
-        q.x = pack2(v[0], v[1]);
-        q.y = pack2(v[2], v[3]);
-        q.z = pack2(v[4], v[5]);
-        q.w = pack2(v[6], v[7]);
-        (layer ? L.wt3 : L.wt2)[n][kk][lane] = q;
+        for (int j = 0; j < 8; ++j) {
+            f[j] = W[(16 * n + r) * kHid + 32 * kk + kidx(g, j)];
+            t[j] = W[(32 * kk + kidx(g, j)) * kHid + 16 * n + r];
+        }
+        (layer ? L.tf3 : L.tf2)[n][kk][lane] =
+            make_uint4(pack2(f[0], f[1]), pack2(f[2], f[3]), pack2(f[4], f[5]), pack2(f[6], f[7]));
+        (layer ? L.tl3 : L.tl2)[n][kk][lane] =
+            make_uint4(pack2_lo(f[0], f[1]), pack2_lo(f[2], f[3]), pack2_lo(f[4], f[5]), pack2_lo(f[6], f[7]));
+        (layer ? L.wt3 : L.wt2)[n][kk][lane] =
+            make_uint4(pack2(t[0], t[1]), pack2(t[2], t[3]), pack2(t[4], t[5]), pack2(t[6], t[7]));
+    }
+}
+
+// A-operand fragments (high and low parts) of row r, K chunks 0 and 1.
+struct AFrag {
+    bf16x8 h0, h1, l0, l1;
+};
+
+// [16 x 64] x [64 x 64] product of split activations (A) with split weights (B):
+// hi*hi + hi*lo + lo*hi, small terms first.
+__device__ __forceinline__ void gemm_split(const AFrag &a, const uint4 (*fh)[2][64], const uint4 (*fl)[2][64],
+                                           int lane, f32x4 *acc) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const bf16x8 b0 = as_bf8(fh[n][0][lane]), b1 = as_bf8(fh[n][1][lane]);
+        const bf16x8 c0 = as_bf8(fl[n][0][lane]), c1 = as_bf8(fl[n][1][lane]);
+        f32x4 c = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l0, b0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l1, b1, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h0, c0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h1, c1, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h0, b0, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h1, b1, c, 0, 0, 0);
+        acc[n] = c;
     }
 }
 
@@ -208,9 +254,17 @@ __device__ __forceinline__ AFrag transpose_split(TrainWave &W, const float (*v)[
 #pragma unroll
     for (int n = 0; n < 4; ++n)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) store_split(W, 4 * g + q, 16 * n + r, v[n][q]);
+        for (int q = 0; q < 4; ++q) {
+            const __bf16 hb = (__bf16)v[n][q];
+            W.h[4 * g + q][16 * n + r] = __builtin_bit_cast(uint16_t, hb);
+            W.l[4 * g + q][16 * n + r] = bf_bits(v[n][q] - (float)hb);
+        }
     __syncwarp();
-    const AFrag a = load_a(W, r, g);
+    AFrag a;
+    a.h0 = as_bf8(*reinterpret_cast<const uint4 *>(&W.h[r][kidx(g, 0)]));
+    a.h1 = as_bf8(*reinterpret_cast<const uint4 *>(&W.h[r][32 + kidx(g, 0)]));
+    a.l0 = as_bf8(*reinterpret_cast<const uint4 *>(&W.l[r][kidx(g, 0)]));
+    a.l1 = as_bf8(*reinterpret_cast<const uint4 *>(&W.l[r][32 + kidx(g, 0)]));
     __syncwarp();
     return a;
 }
@@ -222,7 +276,7 @@ __device__ __forceinline__ void transpose_to_a(TrainWave &W, const float (*v)[4]
 #pragma unroll
     for (int n = 0; n < 4; ++n)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) W.h[4 * g + q][16 * n + r] = f2bf(v[n][q]);
+        for (int q = 0; q < 4; ++q) W.h[4 * g + q][16 * n + r] = bf_bits(v[n][q]);
     __syncwarp();
     a0 = as_bf8(*reinterpret_cast<const uint4 *>(&W.h[r][kidx(g, 0)]));
     a1 = as_bf8(*reinterpret_cast<const uint4 *>(&W.h[r][32 + kidx(g, 0)]));
@@ -242,10 +296,9 @@ __device__ __forceinline__ void gemm_64(bf16x8 a0, bf16x8 a1, const uint4 (*frag
 __global__ __launch_bounds__(kBlock) void k_mlp_train(TrainArgs ta) {
     __shared__ TrainLds L;
     for (int i = threadIdx.x; i <= kMlpParams; i += kBlock) L.red[i] = 0.0f;
-    mlp_pack(ta.params, L.M);
-    pack_transposed(ta.params, L);
+    pack_train(ta.params, L);
     __syncthreads();
-    const MlpLds &M = L.M;
+    const TrainParams &M = L.P;
     const int lane = __lane_id(), r = lane & 15, g = lane >> 4, wv = threadIdx.x / 64;
     TrainWave &W = L.ws[wv];
     f32x4 gw2[16], gw3[16];
@@ -284,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_train(TrainArgs ta) {
         }
         bf16x8 a0, a1;
         f32x4 acc[4];
-        gemm_split(transpose_split(W, h1, r, g), M.wf2, M.wl2, lane, acc);
+        gemm_split(transpose_split(W, h1, r, g), L.tf2, L.tl2, lane, acc);
         float pre2[4][4], h2[4][4];
 #pragma unroll
         for (int n = 0; n < 4; ++n)
@@ -293,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_train(TrainArgs ta) {
                 pre2[n][q] = acc[n][q] + M.b2[16 * n + r];
                 h2[n][q] = mlp_act(pre2[n][q]);
             }
-        gemm_split(transpose_split(W, h2, r, g), M.wf3, M.wl3, lane, acc);
+        gemm_split(transpose_split(W, h2, r, g), L.tf3, L.tl3, lane, acc);
         float pre3[4][4], h3[4][4];
 #pragma unroll
         for (int n = 0; n < 4; ++n)
