@@ -41,6 +41,7 @@ BYTES_PER_PHOTON_READ = 36          # k 12 + position 24
 BYTES_PER_PHOTON_WRITE = 25         # position 24 + flag 1
 FLOPS_PER_PHOTON_MOVE = 6           # three fused multiply-adds per sub-step
 BYTES_PER_BINNED_EXTRA = 8          # sub-step count read 4 + queue entry read 4 (heavy pass)
+BYTES_PER_PAIR = 104                # two lepton records (position 24, u 12, weight 4, id 8) + dead-list entry 8
 SCHEDULERS = {"naive": lambda q: q.QED_SCHED_NAIVE, "binned": lambda q: q.QED_SCHED_BINNED,
               "tiled": lambda q: q.QED_SCHED_TILED}
 
@@ -159,7 +160,7 @@ def measured_traffic(kernel, workload):
 def roofline(kt, st, K):
     """Roofline of the kernel with the largest share of the profiled time."""
     cand = {k: v for k, v in kt.items()
-            if k in ("k_lepton", "k_tiled", "k_light", "k_heavy", "k_photon", "k_photon_sample")}
+            if k in ("k_lepton", "k_tiled", "k_light", "k_heavy", "k_photon")}
     name = max(cand, key=lambda k: cand[k][1])
     nl, tms = cand[name]
     avg_s = tms * 1e-3 / max(nl, 1)
@@ -179,18 +180,12 @@ def roofline(kt, st, K):
         em = st.emissions * sub / max(lep_sub, 1)
         byts = BYTES_PER_LEPTON_STEP * part + 4 * lep_part + BYTES_PER_EMISSION * em
         flops = FLOPS_PER_LEPTON_SUBSTEP * sub
-    elif name == "k_photon":
-        # every photon is read; the ones that cannot decay also move and are written
-        part = st.particles[2]
-        quiet = part - st.sampled_photons
-        sub, em = st.substeps[2] - st.sampled_substeps, 0
-        byts = BYTES_PER_PHOTON_READ * part + BYTES_PER_PHOTON_WRITE * quiet + st.sampled_photons
-        flops = FLOPS_PER_PHOTON_MOVE * sub
-    else:  # k_photon_sample
-        part, sub, em = st.sampled_photons, st.sampled_substeps, st.pairs
-        byts = (BYTES_PER_PHOTON_READ + 8 + BYTES_PER_PHOTON_WRITE + 1) * part + st.particles[2] \
-            + 2 * BYTES_PER_EMISSION * em
-        flops = FLOPS_PER_PHOTON_SUBSTEP * sub
+    else:  # k_photon: every photon is read and written back (position, flag); the ones
+        # that can decay also run the sampling loop (their second read of the record
+        # hits the cache); each pair writes two lepton records and a dead-list entry
+        part, sub, em = st.particles[2], st.substeps[2], st.pairs
+        byts = (BYTES_PER_PHOTON_READ + BYTES_PER_PHOTON_WRITE) * part + BYTES_PER_PAIR * em
+        flops = FLOPS_PER_PHOTON_MOVE * (sub - st.sampled_substeps) + FLOPS_PER_PHOTON_SUBSTEP * st.sampled_substeps
     byts /= max(nl, 1)
     flops /= max(nl, 1)
     t_mem = byts / (HBM_PEAK_GBS * 1e9)
@@ -276,7 +271,8 @@ def stepped(torch, qed, g, stream, fields_for_step, state, dt, seed, K, W, use_g
     if graph is not None:
         qed.qed_graph_destroy(graph)
     log(f"bench: {ms:.3f} ms for {K} steps; sub-steps e-/e+/g = {list(stats.substeps)}; "
-        f"particle-steps {list(stats.particles)}; emissions {stats.emissions}, pairs {stats.pairs}; "
+        f"particle-steps {list(stats.particles)}; sampled photons {stats.sampled_photons}; "
+        f"emissions {stats.emissions}, pairs {stats.pairs}; "
         f"final counts {list(rep.n)}")
     log("bench: kernel times (profiled pass): " +
         ", ".join(f"{k}: {v[1] / max(v[0], 1) * 1e3:.1f} us x{v[0]}" for k, v in kt.items()))

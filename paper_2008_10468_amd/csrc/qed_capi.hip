@@ -135,7 +135,7 @@ bool tuning_ok(const qed_tuning &t) {
            t.light_max >= 1 && t.chunk >= 64 && t.chunk % 64 == 0 && t.chunk <= (1u << 20);
 }
 
-const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_photon_sample", "k_lepton", "k_prepass",
+const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_prepass",
                                          "k_scan",  "k_scatter", "k_light", "k_heavy",
                                          "k_end",   "k_fill",   "k_move",  "k_synchrotron", "k_tiled"};
 
@@ -354,7 +354,6 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
     const int prec = c->cfg.precision == QED_PREC_F64 ? 0 : 1;
     hipError_t r = launch(c, qed::K_BEGIN, a, prec, 1);
     if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON, a, prec, photon_blocks);
-    if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON_SAMPLE, a, prec, photon_blocks);
     const bool tiled = c->cfg.scheduler == QED_SCHED_TILED;
     if (r == hipSuccess && emission && !binned)
         r = launch(c, tiled ? qed::K_TILED : qed::K_LEPTON, a, prec, lepton_blocks);

@@ -78,7 +78,7 @@ struct StepArgs {
     int emission, pairs;   // which algorithms run in this step
     uint32_t light_max;    // binned scheduler: largest N handled by the light pass
     uint32_t chunk;        // binned scheduler: queue entries claimed per wave (multiple of 64)
-    uint8_t *alive;        // photon flags, one per slot: 0 decayed, 1 alive, 2 to be sampled
+    uint8_t *alive;        // photon flags, one per slot: 0 decayed, 1 alive
     u64 *dead_idx;         // slots of the photons that decayed this step
     u64 *hole_idx;         // compaction lists
     u64 *mover_idx;
@@ -91,8 +91,7 @@ struct StepArgs {
 // Kernels, in launch order, and the standalone synchrotron kernel.
 enum KernelId {
     K_BEGIN = 0,
-    K_PHOTON,         // all photons; finishes those that cannot decay
-    K_PHOTON_SAMPLE,  // sampling loop of the photons that can
+    K_PHOTON,   // Algorithm 2 for all photons
     K_LEPTON,   // naive scheduler: one lane per lepton
     K_PREPASS,  // binned scheduler: sub-step counts and histogram
     K_SCAN,

@@ -4,7 +4,8 @@
 //   k_begin    snapshot the live counts (particles appended later in the step wait
 //              for the next step) and clear the per-step counters;
 //   k_photon   Algorithm 2 for every photon: straight-line sub-steps, pair creation
-//              with density eq. (2); pairs are appended to the e-/e+ buffers, the
+//              with density eq. (2) (photons that provably cannot decay in the step
+//              skip the sampling); pairs are appended to the e-/e+ buffers, the
 //              photon is flagged dead and its slot is put on the dead list;
 //   Algorithm 1 for every electron and positron (Boris sub-steps, emission with
 //   density eq. (1), recoil, photons appended), scheduled one of two ways:
@@ -590,32 +591,7 @@ struct PhotonStart {
     uint32_t N;
 };
 
-// Line 1 for one photon; false for non-finite input.
-template <class R>
-__device__ __forceinline__ bool photon_start(const StepArgs &a, u64 i, R &kx, R &ky, R &kz,
-                                             PhotonStart &ps, Tally<R> &tl) {
-    const SpeciesDev &sp = a.sp[2];
-    const FieldDev &fl = a.fl[2];
-    kx = ((const R *)sp.ux)[i];
-    ky = ((const R *)sp.uy)[i];
-    kz = ((const R *)sp.uz)[i];
-    const u64 f = i * fl.stride;
-    const R ex = ((const R *)fl.ex)[f], ey = ((const R *)fl.ey)[f], ez = ((const R *)fl.ez)[f];
-    const R bx = ((const R *)fl.bx)[f], by = ((const R *)fl.by)[f], bz = ((const R *)fl.bz)[f];
-    if (!(finite3(kx, ky, kz) && finite3(ex, ey, ez) && finite3(bx, by, bz))) return false;
-    ps.eps = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
-    // the field and k are frozen, so chi_g is the same at every sub-step
-    ps.chi = chi_def(ps.eps, kx, ky, kz, ex, ey, ez, bx, by, bz);
-    ps.N = 1;
-    if (ps.eps > 0.0) {
-        bool capped;
-        ps.N = nsub(bound_pair(ps.chi, ps.eps, a.dt, a.pair_coef), a.p_max, a.max_sub, &capped);
-        tl.capped += capped;
-    }
-    return true;
-}
-
-// Lines 2-8 for one photon that can decay.
+// Algorithm 2's sub-step loop for one photon that can decay.
 template <class R>
 __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R ky, R kz,
                                               const PhotonStart &ps, const SynTable<R> &tab,
@@ -1054,19 +1030,43 @@ __global__ __launch_bounds__(kBlock, 3) void k_heavy(StepArgs a) {
     flush_tally(t, a.st, s, 1);
 }
 
-// Algorithm 2, pass 1, for every photon: the step-start bound, and for photons that
-// cannot decay in this step (photon_quiet) the whole sub-step loop: they only move.  The others are
-// marked alive = 2 for pass 2.  Light on registers; each lane takes kPhotonBatch
-// photons per round and issues all their loads before using any, and a uniform
-// field (stride 0) is loaded once, so the pass streams.
-constexpr int kPhotonBatch = 4;
+// The sampling loop of one photon that can decay, from its queued step-start
+// values (its momentum is read again, from the cache).
+template <class R>
+__device__ __forceinline__ void photon_sample_one(const StepArgs &a, u64 i, const PhotonStart &ps,
+                                                  const SynTable<R> &tab, Tally<R> &ts) {
+    const SpeciesDev &sp = a.sp[2];
+    const R kx = ((const R *)sp.ux)[i], ky = ((const R *)sp.uy)[i], kz = ((const R *)sp.uz)[i];
+    photon_sample<R>(a, i, kx, ky, kz, ps, tab, ts);
+    ts.particles++;
+}
+
+// Algorithm 2 for every photon, in one pass.  Each lane loads kPhotonBatch
+// photons per round (all loads issued before use; a uniform field, stride 0, is
+// loaded once) and computes the step-start bound.  Photons that cannot decay in
+// this step (photon_quiet) run their sub-step loop in closed form: they only
+// move.  The others go to a wave-local queue, which is drained 64 photons at a
+// time, so the sampling loops run with all lanes busy; their records were read by
+// this wave shortly before, so the second read hits the cache.
+constexpr int kPhotonBatch = 2;
+constexpr int kPhotonQueue = 64 * (kPhotonBatch + 1);
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
+    __shared__ SynTable<R> tab;
+    __shared__ u64 queue_sh[kBlock / 64][kPhotonQueue];
+    __shared__ double qchi_sh[kBlock / 64][kPhotonQueue], qeps_sh[kBlock / 64][kPhotonQueue];
+    __shared__ uint32_t qn_sh[kBlock / 64][kPhotonQueue];
+    syn_stage(tab);
     const u64 n = a.st->n0[2];
     const SpeciesDev &sp = a.sp[2];
     const FieldDev &fl = a.fl[2];
     const bool uni = fl.stride == 0;
+    const uint32_t lane = __lane_id();
+    u64 *queue = queue_sh[threadIdx.x / 64];
+    double *qchi = qchi_sh[threadIdx.x / 64], *qeps = qeps_sh[threadIdx.x / 64];
+    uint32_t *qn = qn_sh[threadIdx.x / 64];
+    uint32_t queued = 0;  // wave-uniform
     R fu[6] = {0, 0, 0, 0, 0, 0};
     if (uni) {
         fu[0] = ((const R *)fl.ex)[0];
@@ -1076,9 +1076,11 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
         fu[4] = ((const R *)fl.by)[0];
         fu[5] = ((const R *)fl.bz)[0];
     }
-    Tally<R> t;
+    Tally<R> t, ts;  // all photons; the sampled ones
     const u64 G = (u64)gridDim.x * kBlock;
-    for (u64 i0 = (u64)blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += G * kPhotonBatch) {
+    // wave-uniform loop: photon b of this lane is slot wbase + lane + b G
+    for (u64 wbase = (u64)blockIdx.x * kBlock + (threadIdx.x & ~63u); wbase < n; wbase += G * kPhotonBatch) {
+        const u64 i0 = wbase + lane;
         R k[kPhotonBatch][3], f[kPhotonBatch][6];
         double x[kPhotonBatch][3];
 #pragma unroll
@@ -1103,6 +1105,8 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
                 f[b][5] = ((const R *)fl.bz)[fi];
             }
         }
+        uint32_t need = 0;  // bit b: photon b can decay
+        PhotonStart pst[kPhotonBatch];
 #pragma unroll
         for (int b = 0; b < kPhotonBatch; ++b) {
             const u64 i = i0 + b * G;
@@ -1125,7 +1129,10 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
             }
             const double st = a.dt / (double)N;
             if (!photon_quiet<R>(chi, eps, st)) {
-                a.alive[i] = 2;
+                need |= 1u << b;
+                pst[b].eps = eps;
+                pst[b].chi = chi;
+                pst[b].N = N;
                 continue;
             }
             const R inv = eps > 0.0 ? (R)(1.0 / eps) : R(0);
@@ -1144,69 +1151,35 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
             if (sp.events) sp.events[i] = 0u;
             t.substeps += N;
         }
+        // queue the photons that can decay; sample 64 at a time
+#pragma unroll
+        for (int b = 0; b < kPhotonBatch; ++b) {
+            const bool nb = (need >> b) & 1u;
+            const u64 m = __ballot(nb);
+            if (nb) {
+                const uint32_t q = queued + (uint32_t)__popcll(m & lanemask_lt());
+                queue[q] = i0 + b * G;
+                qchi[q] = pst[b].chi;
+                qeps[q] = pst[b].eps;
+                qn[q] = pst[b].N;
+            }
+            queued += (uint32_t)__popcll(m);
+        }
+        __syncwarp();
+        while (queued >= 64) {
+            queued -= 64;
+            const uint32_t q = queued + lane;
+            const PhotonStart ps = {qeps[q], qchi[q], qn[q]};
+            photon_sample_one<R>(a, queue[q], ps, tab, ts);
+            __syncwarp();
+        }
+    }
+    if (lane < queued) {
+        const PhotonStart ps = {qeps[lane], qchi[lane], qn[lane]};
+        photon_sample_one<R>(a, queue[lane], ps, tab, ts);
     }
     flush_tally(t, a.st, 2);
-}
-
-// Algorithm 2, pass 2: the sampling loop for the photons marked by pass 1,
-// compacted per block.  A block takes chunks of kSampleChunk consecutive slots;
-// each thread reads the flags of 16 slots with one 16-byte load, the marked
-// slots are prefix-summed into an LDS list, and the block runs the list with all
-// lanes busy except in the last partial round.
-constexpr int kSampleChunk = 16 * kBlock;
-
-template <class R>
-__global__ __launch_bounds__(kBlock) void k_photon_sample(StepArgs a) {
-    __shared__ SynTable<R> tab;
-    __shared__ uint16_t list[kSampleChunk];
-    __shared__ uint32_t wsum[kBlock / 64];
-    syn_stage(tab);
-    const u64 n = a.st->n0[2];
-    const uint32_t lane = __lane_id();
-    const int wv = threadIdx.x / 64;
-    Tally<R> t;
-    for (u64 c0 = (u64)blockIdx.x * kSampleChunk; c0 < n; c0 += (u64)gridDim.x * kSampleChunk) {
-        const u64 s0 = c0 + 16ull * threadIdx.x;
-        uint32_t bits = 0;  // bit j: slot s0 + j is marked
-        if (s0 + 16 <= n) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(a.alive + s0);
-            const uint32_t wv4[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int j = 0; j < 16; ++j) bits |= (((wv4[j >> 2] >> (8 * (j & 3))) & 0xFFu) == 2u) << j;
-        } else {
-            for (int j = 0; j < 16; ++j)
-                if (s0 + j < n && a.alive[s0 + j] == 2) bits |= 1u << j;
-        }
-        // block-wide exclusive prefix of the per-thread counts
-        const uint32_t c = __popc(bits);
-        uint32_t incl = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t v = __shfl_up(incl, o);
-            if ((int)lane >= o) incl += v;
-        }
-        if (lane == 63) wsum[wv] = incl;
-        __syncthreads();
-        uint32_t off = incl - c, total = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
-            if (w < wv) off += wsum[w];
-            total += wsum[w];
-        }
-        for (int j = 0; j < 16; ++j)
-            if (bits & (1u << j)) list[off++] = (uint16_t)(16 * threadIdx.x + j);
-        __syncthreads();
-        for (uint32_t p = threadIdx.x; p < total; p += kBlock) {
-            const u64 i = c0 + list[p];
-            R kx, ky, kz;
-            PhotonStart ps;
-            Tally<R> ignore;  // pass 1 counted the capped ones
-            photon_start<R>(a, i, kx, ky, kz, ps, ignore);
-            photon_sample<R>(a, i, kx, ky, kz, ps, tab, t);
-            t.particles++;
-        }
-        __syncthreads();
-    }
-    flush_tally(t, a.st, 2, 2);
+    flush_tally(ts, a.st, 2, 2);
 }
 
 __global__ void k_begin(StepArgs a) {
@@ -1337,7 +1310,6 @@ hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
     switch (id) {
         case K_BEGIN: hipLaunchKernelGGL(k_begin, dim3(1), dim3(256), 0, s, a); break;
         case K_PHOTON: hipLaunchKernelGGL(k_photon<R>, g1, blk, 0, s, a); break;
-        case K_PHOTON_SAMPLE: hipLaunchKernelGGL(k_photon_sample<R>, g1, blk, 0, s, a); break;
         case K_LEPTON:
             if constexpr (std::is_same<R, float>::value)
                 if (a.sampler) {
