@@ -51,7 +51,7 @@ class Children(C.Structure):
     _fields_ = [("cap", C.c_int64), ("n", C.c_int64)] + \
         [(f, C.POINTER(C.c_double)) for f in ("x", "y", "z", "px", "py", "pz", "w")] + \
         [("id", C.POINTER(C.c_uint64)), ("parent", C.POINTER(C.c_uint64)),
-         ("sub", C.POINTER(C.c_uint32)), ("kind", C.POINTER(C.c_int32))]
+         ("sub", C.POINTER(C.c_uint32)), ("kind", C.POINTER(C.c_int32)), ("tb", C.POINTER(C.c_double))]
 
 
 class Tally(C.Structure):
@@ -110,11 +110,11 @@ def lib():
             L.orc_pair_prob.restype = C.c_double
             fld = C.POINTER(_D)
             L.orc_lepton_batch.argtypes = [C.POINTER(Params), C.c_double, C.c_int64,
-                                           _D, _D, _D, _D, _D, _D, _D, _U64, fld, C.c_int64,
+                                           _D, _D, _D, _D, _D, _D, _D, _U64, _D, fld, C.c_int64,
                                            _U32, _U32, C.POINTER(Children), C.POINTER(Tally)]
             L.orc_lepton_batch.restype = C.c_int64
             L.orc_photon_batch.argtypes = [C.POINTER(Params), C.c_int64,
-                                           _D, _D, _D, _D, _D, _D, _D, _U64, fld, C.c_int64,
+                                           _D, _D, _D, _D, _D, _D, _D, _U64, _D, fld, C.c_int64,
                                            _U8, _U32, _U32, C.POINTER(Children), C.POINTER(Tally)]
             L.orc_photon_batch.restype = C.c_int64
             _lib = L
@@ -250,6 +250,7 @@ def _children(cap):
     arrs["parent"] = np.zeros(cap, np.uint64)
     arrs["sub"] = np.zeros(cap, np.uint32)
     arrs["kind"] = np.zeros(cap, np.int32)
+    arrs["tb"] = np.zeros(cap, np.float64)
     c = Children()
     c.cap = cap
     c.n = 0
@@ -259,6 +260,7 @@ def _children(cap):
     c.parent = _p(arrs["parent"], C.c_uint64)
     c.sub = _p(arrs["sub"], C.c_uint32)
     c.kind = _p(arrs["kind"], C.c_int32)
+    c.tb = _p(arrs["tb"], C.c_double)
     return c, arrs
 
 
@@ -297,17 +299,24 @@ def _run_chunks(n, fn, threads):
 
 def _merge(results):
     out = {}
-    for key in ("x", "y", "z", "px", "py", "pz", "w", "id", "parent", "sub", "kind"):
+    for key in ("x", "y", "z", "px", "py", "pz", "w", "id", "parent", "sub", "kind", "tb"):
         parts = [r[key] for r in results]
         out[key] = np.concatenate(parts) if parts else np.zeros(0)
     return out
 
 
+def _t0_ptr(t0, a):
+    return None if t0 is None else C.cast(t0.ctypes.data + 8 * a, _D)
+
+
 def lepton_step(state, fields, q, dt, seed, step, p_max=0.01, rng_bits=53, n_cap=1 << 24,
-                threads=None):
+                threads=None, t0=None):
     """Algorithm 1 on arrays.  ``state`` has float64 arrays ux,uy,uz,x,y,z,w and uint64 id;
-    they are updated in place.  Returns (children dict, per-particle nsub, per-particle
-    event counts, tally dict)."""
+    they are updated in place.  ``t0`` (optional float64 array): each particle's start
+    time within the step (it runs over dt - t0).  Returns (children dict, per-particle
+    nsub, per-particle event counts, tally dict); children carry their birth time tb."""
+    if t0 is not None:
+        t0 = np.ascontiguousarray(t0, np.float64)
     n = state["id"].size
     for k in ("ux", "uy", "uz", "x", "y", "z", "w"):
         assert state[k].dtype == np.float64 and state[k].flags.c_contiguous
@@ -329,7 +338,7 @@ def lepton_step(state, fields, q, dt, seed, step, p_max=0.01, rng_bits=53, n_cap
                 return C.cast(state[k].ctypes.data + off * a, C.POINTER(dt_))
             bad = lib().orc_lepton_batch(
                 C.byref(P), q, m, ptr("ux"), ptr("uy"), ptr("uz"), ptr("x"), ptr("y"), ptr("z"),
-                ptr("w"), ptr("id", C.c_uint64), fp, stride,
+                ptr("w"), ptr("id", C.c_uint64), _t0_ptr(t0, a), fp, stride,
                 C.cast(nsub_a.ctypes.data + 4 * a, _U32), C.cast(nev_a.ctypes.data + 4 * a, _U32),
                 C.byref(ch), C.byref(tl))
             if ch.n <= cap:
@@ -351,10 +360,12 @@ def lepton_step(state, fields, q, dt, seed, step, p_max=0.01, rng_bits=53, n_cap
 
 
 def photon_step(state, fields, dt, seed, step, p_max=0.01, rng_bits=53, pair_coef=0.1,
-                n_cap=1 << 24, threads=None):
+                n_cap=1 << 24, threads=None, t0=None):
     """Algorithm 2 on arrays (state: photon momentum k in ux,uy,uz, and x,y,z,w float64,
-    id uint64; updated in place).
+    id uint64; updated in place; t0 as for lepton_step).
     Returns (children dict [kind 1 = e-, 2 = e+], alive mask, nsub, events, tally)."""
+    if t0 is not None:
+        t0 = np.ascontiguousarray(t0, np.float64)
     n = state["id"].size
     fl, stride = _fields(fields, n)
     alive = np.ones(n, np.uint8)
@@ -373,7 +384,7 @@ def photon_step(state, fields, dt, seed, step, p_max=0.01, rng_bits=53, pair_coe
             return C.cast(state[k].ctypes.data + off * a, C.POINTER(dt_))
         bad = lib().orc_photon_batch(
             C.byref(P), m, ptr("ux"), ptr("uy"), ptr("uz"), ptr("x"), ptr("y"), ptr("z"),
-            ptr("w"), ptr("id", C.c_uint64), fp, stride,
+            ptr("w"), ptr("id", C.c_uint64), _t0_ptr(t0, a), fp, stride,
             C.cast(alive.ctypes.data + a, _U8),
             C.cast(nsub_a.ctypes.data + 4 * a, _U32), C.cast(nev_a.ctypes.data + 4 * a, _U32),
             C.byref(ch), C.byref(tl))
@@ -389,3 +400,55 @@ def photon_step(state, fields, dt, seed, step, p_max=0.01, rng_bits=53, pair_coe
                  max_p=max([r["tally"][3] for r in results], default=0.0),
                  nonfinite=sum(r["tally"][4] for r in results))
     return _merge(results), alive, nsub_a, nev_a, tally
+
+
+# ---------------------------------------------------------------- cascades
+
+def _append(dst, ch, sel):
+    for k, ck in zip(("x", "y", "z", "ux", "uy", "uz", "w", "id"), ("x", "y", "z", "px", "py", "pz", "w", "id")):
+        dst[k] = np.concatenate([dst[k], ch[ck][sel]])
+
+
+def cascade_step(electrons, positrons, photons, fields, dt, seed, step, generations, p_max=0.01,
+                 rng_bits=53, pair_coef=0.1, n_cap=1 << 24, threads=None):
+    """One global step with in-step cascades (the generator's follow-up passes): the
+    particles present at the step start run over the whole step (Algorithms 2 then 1);
+    then, for each of ``generations`` passes, the particles created in the previous
+    pass run over the rest of the step, dt - (their birth time), in the same field (a
+    dict of uniform values).  Children of the last pass are kept but not moved.
+    The species dicts are replaced by the new populations (photons that decayed are
+    removed).  Returns (electrons, positrons, photons, per-pass tallies)."""
+    sp = {"e": {k: v.copy() for k, v in electrons.items()}, "p": {k: v.copy() for k, v in positrons.items()},
+          "g": {k: v.copy() for k, v in photons.items()}}
+    lo = {k: 0 for k in sp}
+    hi = {k: sp[k]["id"].size for k in sp}
+    t0 = {k: np.zeros(hi[k]) for k in sp}   # start time of every particle in the step
+    alive_all = np.ones(hi["g"], np.uint8)
+    tallies = []
+    for gen in range(generations + 1):
+        sub = {k: {kk: np.ascontiguousarray(v[lo[k]:hi[k]]) for kk, v in sp[k].items()} for k in sp}
+        tz = {k: (None if gen == 0 else np.ascontiguousarray(t0[k][lo[k]:hi[k]])) for k in sp}
+        chg, alive, _, _, tg = photon_step(sub["g"], fields, dt, seed, step, p_max=p_max, rng_bits=rng_bits,
+                                           pair_coef=pair_coef, n_cap=n_cap, threads=threads, t0=tz["g"])
+        che, _, _, te = lepton_step(sub["e"], fields, -1.0, dt, seed, step, p_max=p_max, rng_bits=rng_bits,
+                                    n_cap=n_cap, threads=threads, t0=tz["e"])
+        chp, _, _, tp = lepton_step(sub["p"], fields, 1.0, dt, seed, step, p_max=p_max, rng_bits=rng_bits,
+                                    n_cap=n_cap, threads=threads, t0=tz["p"])
+        for k in sp:
+            for kk in sp[k]:
+                sp[k][kk][lo[k]:hi[k]] = sub[k][kk]
+        alive_all[lo["g"]:hi["g"]] = alive
+        tallies.append((tg, te, tp))
+        # children: pairs to the leptons, photons to the photons, with their birth times
+        for k, ch, sel in (("e", chg, chg["kind"] == 1), ("p", chg, chg["kind"] == 2)):
+            _append(sp[k], ch, sel)
+            t0[k] = np.concatenate([t0[k], ch["tb"][sel]])
+        for ch in (che, chp):
+            _append(sp["g"], ch, slice(None))
+            t0["g"] = np.concatenate([t0["g"], ch["tb"]])
+        alive_all = np.concatenate([alive_all, np.ones(sp["g"]["id"].size - alive_all.size, np.uint8)])
+        for k in sp:
+            lo[k], hi[k] = hi[k], sp[k]["id"].size
+    keep = alive_all.astype(bool)
+    sp["g"] = {k: v[keep] for k, v in sp["g"].items()}
+    return sp["e"], sp["p"], sp["g"], tallies

@@ -327,6 +327,7 @@ typedef struct {
     uint64_t *id, *parent;
     uint32_t *sub;  /* sub-step index of the event */
     int32_t *kind;  /* 0 photon, 1 electron, 2 positron */
+    double *tb;     /* birth time within the step (end of the event's sub-step) */
 } orc_children;
 
 typedef struct {
@@ -335,10 +336,11 @@ typedef struct {
 } orc_tally;
 
 static void push_child(orc_children *c, const double pos[3], const double p[3], double w,
-                       uint64_t id, uint64_t parent, uint32_t sub, int kind)
+                       uint64_t id, uint64_t parent, uint32_t sub, int kind, double tb)
 {
     int64_t j = c->n++;
     if (j >= c->cap) return;
+    c->tb[j] = tb;
     c->x[j] = pos[0];
     c->y[j] = pos[1];
     c->z[j] = pos[2];
@@ -359,10 +361,13 @@ static int all_finite(const double *v, int n)
     return 1;
 }
 
-/* Returns 0, or -1 if the particle had non-finite input and was left alone. */
-static int lepton_one(const orc_params *P, double q, double u[3], double pos[3], double w, uint64_t id,
-                      const double E[3], const double B[3], uint32_t *nsub_out, uint32_t *nev_out,
-                      orc_children *ch, orc_tally *tl)
+/* Returns 0, or -1 if the particle had non-finite input and was left alone.
+ * t0: the time within the step at which the particle starts (0 for particles
+ * present at the step start; the birth time of a child in a cascade pass); it
+ * runs Algorithm 1 over the remaining time dt - t0. */
+static int lepton_one(const orc_params *P, double t0, double q, double u[3], double pos[3], double w,
+                      uint64_t id, const double E[3], const double B[3], uint32_t *nsub_out,
+                      uint32_t *nev_out, orc_children *ch, orc_tally *tl)
 {
     if (!all_finite(u, 3) || !all_finite(E, 3) || !all_finite(B, 3)) {
         *nsub_out = 0;
@@ -372,8 +377,9 @@ static int lepton_one(const orc_params *P, double q, double u[3], double pos[3],
     /* Algorithm 1: sub-step from the bound at the step start. */
     double gamma0 = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     double chi0 = orc_chi_lepton(u, E, B);
-    uint32_t N = orc_nsub(orc_bound_emission(chi0, gamma0, P->dt), P->p_max, P->n_cap);
-    double st = P->dt / (double)N;
+    double dt = P->dt - t0;
+    uint32_t N = orc_nsub(orc_bound_emission(chi0, gamma0, dt), P->p_max, P->n_cap);
+    double st = dt / (double)N;
     uint32_t nev = 0;
     for (uint32_t i = 0; i < N; ++i) {
         /* push: Boris rotation by st in the frozen field, then move */
@@ -404,7 +410,8 @@ static int lepton_one(const orc_params *P, double q, double u[3], double pos[3],
             }
             double eph = delta * gamma;
             double k[3] = {eph * dir[0], eph * dir[1], eph * dir[2]};
-            push_child(ch, pos, k, w, orc_child_id(P->seed, id, P->step, i, 0), id, i, 0);
+            push_child(ch, pos, k, w, orc_child_id(P->seed, id, P->step, i, 0), id, i, 0,
+                       t0 + (double)(i + 1) * st);
             double g1 = (1.0 - delta) * gamma;
             double u1 = g1 * g1 - 1.0;
             u1 = u1 > 0.0 ? sqrt(u1) : 0.0;
@@ -423,7 +430,7 @@ static int lepton_one(const orc_params *P, double q, double u[3], double pos[3],
 
 /* Algorithm 2 for one photon.  Returns 1 if it decayed, 0 if it survived,
  * -1 for non-finite input (left alone, alive). */
-static int photon_one(const orc_params *P, double k[3], double pos[3], double w, uint64_t id,
+static int photon_one(const orc_params *P, double t0, double k[3], double pos[3], double w, uint64_t id,
                       const double E[3], const double B[3], uint32_t *nsub_out, uint32_t *nev_out,
                       orc_children *ch, orc_tally *tl)
 {
@@ -434,9 +441,10 @@ static int photon_one(const orc_params *P, double k[3], double pos[3], double w,
     }
     double eps = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
     double chi0 = orc_chi_photon(k, E, B);
+    double dt = P->dt - t0;
     uint32_t N = 1;
-    if (eps > 0.0) N = orc_nsub(orc_bound_pair(chi0, eps, P->dt, P->pair_coef), P->p_max, P->n_cap);
-    double st = P->dt / (double)N;
+    if (eps > 0.0) N = orc_nsub(orc_bound_pair(chi0, eps, dt, P->pair_coef), P->p_max, P->n_cap);
+    double st = dt / (double)N;
     double dir[3] = {0.0, 0.0, 0.0};
     if (eps > 0.0) {
         dir[0] = k[0] / eps;
@@ -469,8 +477,9 @@ static int photon_one(const orc_params *P, double k[3], double pos[3], double w,
             up = up > 0.0 ? sqrt(up) : 0.0;
             double pe[3] = {ue * dir[0], ue * dir[1], ue * dir[2]};
             double pq[3] = {up * dir[0], up * dir[1], up * dir[2]};
-            push_child(ch, pos, pe, w, orc_child_id(P->seed, id, P->step, i, 0), id, i, 1);
-            push_child(ch, pos, pq, w, orc_child_id(P->seed, id, P->step, i, 1), id, i, 2);
+            double tb = t0 + (double)(i + 1) * st;
+            push_child(ch, pos, pe, w, orc_child_id(P->seed, id, P->step, i, 0), id, i, 1, tb);
+            push_child(ch, pos, pq, w, orc_child_id(P->seed, id, P->step, i, 1), id, i, 2, tb);
             decayed = 1;
             break;
         }
@@ -483,12 +492,13 @@ static int photon_one(const orc_params *P, double k[3], double pos[3], double w,
 }
 
 /* Batch drivers.  Fields are six arrays (Ex,Ey,Ez,Bx,By,Bz) read at index
- * i*fstride (fstride 0: one field for all).  Children are appended in particle
+ * i*fstride (fstride 0: one field for all).  t0 (may be NULL: all zero) gives each
+ * particle's start time within the step.  Children are appended in particle
  * order, then sub-step order.  Return value: number of non-finite particles. */
 int64_t orc_lepton_batch(const orc_params *P, double q, int64_t n, double *ux, double *uy, double *uz,
                          double *x, double *y, double *z, const double *w, const uint64_t *id,
-                         const double *const fld[6], int64_t fstride, uint32_t *nsub, uint32_t *nev,
-                         orc_children *ch, orc_tally *tl)
+                         const double *t0, const double *const fld[6], int64_t fstride, uint32_t *nsub,
+                         uint32_t *nev, orc_children *ch, orc_tally *tl)
 {
     int64_t bad = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -497,7 +507,7 @@ int64_t orc_lepton_batch(const orc_params *P, double q, int64_t n, double *ux, d
         double B[3] = {fld[3][f], fld[4][f], fld[5][f]};
         double u[3] = {ux[i], uy[i], uz[i]};
         double pos[3] = {x[i], y[i], z[i]};
-        if (lepton_one(P, q, u, pos, w[i], id[i], E, B, &nsub[i], &nev[i], ch, tl) < 0) {
+        if (lepton_one(P, t0 ? t0[i] : 0.0, q, u, pos, w[i], id[i], E, B, &nsub[i], &nev[i], ch, tl) < 0) {
             bad++;
             continue;
         }
@@ -512,7 +522,7 @@ int64_t orc_lepton_batch(const orc_params *P, double q, int64_t n, double *ux, d
 }
 
 int64_t orc_photon_batch(const orc_params *P, int64_t n, double *kx, double *ky, double *kz, double *x,
-                         double *y, double *z, const double *w, const uint64_t *id,
+                         double *y, double *z, const double *w, const uint64_t *id, const double *t0,
                          const double *const fld[6], int64_t fstride, uint8_t *alive, uint32_t *nsub,
                          uint32_t *nev, orc_children *ch, orc_tally *tl)
 {
@@ -523,7 +533,7 @@ int64_t orc_photon_batch(const orc_params *P, int64_t n, double *kx, double *ky,
         double B[3] = {fld[3][f], fld[4][f], fld[5][f]};
         double k[3] = {kx[i], ky[i], kz[i]};
         double pos[3] = {x[i], y[i], z[i]};
-        int r = photon_one(P, k, pos, w[i], id[i], E, B, &nsub[i], &nev[i], ch, tl);
+        int r = photon_one(P, t0 ? t0[i] : 0.0, k, pos, w[i], id[i], E, B, &nsub[i], &nev[i], ch, tl);
         if (r < 0) {
             bad++;
             alive[i] = 1;
