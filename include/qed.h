@@ -94,6 +94,13 @@ typedef struct qed_species {
                            there, ignored otherwise): optical depth left until the next
                            emission; a value <= 0 or NaN makes the particle draw a fresh
                            one.  New pairs get -1. */
+    double *birth;      /* with cascade_generations > 0 (required there, ignored
+                           otherwise): written for every particle appended in a step,
+                           the time within the step (0 .. dt) at which it was created,
+                           and kept with the particle when the photon buffer is
+                           compacted; read for the particles of each cascade pass.
+                           Slots of particles present at the step start are neither
+                           read nor written. */
 } qed_species;
 
 typedef struct qed_particles {
@@ -119,6 +126,16 @@ typedef struct qed_config {
     double pair_bound_coef; /* coefficient of the pair bound f = coef c b; 0.1 */
     uint32_t max_substeps;  /* cap on sub-steps per particle and step; 1 << 24 */
     int sampler;            /* qed_sampler; QED_SAMPLER_REJECTION */
+    uint32_t cascade_generations; /* in-step cascades (Sec. 2.2: the sub-stepping lets
+                           a cascade of events develop inside one time step): after the
+                           main pass, this many passes in which the particles created by
+                           the previous pass run Algorithms 1 and 2 over the rest of the
+                           step, from their birth time to dt.  0 (default): new particles
+                           first act in the next step.  > 0 needs QED_SAMPLER_REJECTION,
+                           the birth array of every species and stride-0 fields (one
+                           field for every particle: the library has no field for a new
+                           slot); the cascade passes use the one-lane-per-particle
+                           kernels whatever the scheduler.  At most 64. */
 } qed_config;
 
 /* Errors and counts observed on the device since the previous qed_sync. */
@@ -163,7 +180,8 @@ QED_API qed_status qed_init(qed_ctx **ctx, const qed_config *cfg);
 /* One global step of length dt (> 0) for all species (Algorithms 1 and 2,
  * Sec. 2.2 and 3.1).  fields[0..2] are the fields seen by electrons, positrons
  * and photons.  Particles created in this step (photons from emission, pairs)
- * are appended after the live particles and first act in the next step.
+ * are appended after the live particles and first act in the next step, or,
+ * with cascade_generations > 0, in the cascade passes of this step.
  * Photons that decay are removed; the order of the photon buffer may change.
  * The random stream of a particle is keyed by (seed, id, step, sub-step), so
  * results do not depend on buffer order or scheduling.  Asynchronous: errors

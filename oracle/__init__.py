@@ -417,7 +417,9 @@ def cascade_step(electrons, positrons, photons, fields, dt, seed, step, generati
     pass run over the rest of the step, dt - (their birth time), in the same field (a
     dict of uniform values).  Children of the last pass are kept but not moved.
     The species dicts are replaced by the new populations (photons that decayed are
-    removed).  Returns (electrons, positrons, photons, per-pass tallies)."""
+    removed), each with a "birth" array: the time within the step at which the
+    particle was created (0 for those present at the start).  Returns (electrons,
+    positrons, photons, per-pass tallies)."""
     sp = {"e": {k: v.copy() for k, v in electrons.items()}, "p": {k: v.copy() for k, v in positrons.items()},
           "g": {k: v.copy() for k, v in photons.items()}}
     lo = {k: 0 for k in sp}
@@ -449,6 +451,8 @@ def cascade_step(electrons, positrons, photons, fields, dt, seed, step, generati
         alive_all = np.concatenate([alive_all, np.ones(sp["g"]["id"].size - alive_all.size, np.uint8)])
         for k in sp:
             lo[k], hi[k] = hi[k], sp[k]["id"].size
+    for k in sp:
+        sp[k]["birth"] = t0[k]
     keep = alive_all.astype(bool)
     sp["g"] = {k: v[keep] for k, v in sp["g"].items()}
     return sp["e"], sp["p"], sp["g"], tallies

@@ -71,6 +71,7 @@ qed::SpeciesDev to_dev(const qed_species &s) {
     d.parent = s.parent;
     d.events = s.events;
     d.tau = s.tau;
+    d.birth = nullptr;  // set by qed_step when cascades run
     return d;
 }
 
@@ -137,7 +138,8 @@ bool tuning_ok(const qed_tuning &t) {
 
 const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_prepass",
                                          "k_scan",  "k_scatter", "k_light", "k_heavy",
-                                         "k_end",   "k_fill",   "k_move",  "k_synchrotron", "k_tiled"};
+                                         "k_end",   "k_fill",   "k_move",  "k_synchrotron", "k_tiled",
+                                         "k_gen"};
 
 // Event pair for one profiled launch (grown on demand, reused after a read).
 bool prof_pair(qed_ctx *c, int id, hipEvent_t *a, hipEvent_t *b) {
@@ -257,6 +259,8 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
         return QED_ERR_INVALID_ARG;
     if (cfg->sampler != QED_SAMPLER_REJECTION && cfg->sampler != QED_SAMPLER_SURROGATE) return QED_ERR_INVALID_ARG;
     if (cfg->sampler == QED_SAMPLER_SURROGATE && cfg->precision != QED_PREC_MIXED) return QED_ERR_INVALID_ARG;
+    if (cfg->cascade_generations > 64) return QED_ERR_INVALID_ARG;
+    if (cfg->cascade_generations > 0 && cfg->sampler != QED_SAMPLER_REJECTION) return QED_ERR_INVALID_ARG;
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (cfg->device < 0 || cfg->device >= ndev) return QED_ERR_INVALID_ARG;
@@ -304,6 +308,13 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
     const bool surrogate = c->cfg.sampler == QED_SAMPLER_SURROGATE;
     if (surrogate && emission && (!sp[0]->tau || !sp[1]->tau)) return QED_ERR_INVALID_ARG;
     if (pairs && !field_ok(fields[2])) return QED_ERR_INVALID_ARG;
+    const uint32_t gens = c->cfg.cascade_generations;
+    if (gens > 0) {
+        for (int s = 0; s < 3; ++s)
+            if (need[s] && !sp[s]->birth) return QED_ERR_INVALID_ARG;
+        for (int s = 0; s < 3; ++s)
+            if ((s < 2 ? emission : pairs) && fields[s].stride != 0) return QED_ERR_INVALID_ARG;
+    }
     const bool binned = c->cfg.scheduler == QED_SCHED_BINNED && emission;
     if (binned && (sp[0]->capacity > 0xFFFFFFFFull || sp[1]->capacity > 0xFFFFFFFFull))
         return QED_ERR_INVALID_ARG;
@@ -322,6 +333,7 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
     memset(&a, 0, sizeof(a));
     for (int s = 0; s < 3; ++s) {
         a.sp[s] = to_dev(*sp[s]);
+        if (gens > 0) a.sp[s].birth = sp[s]->birth;
         a.fl[s] = to_dev(fields[s]);
         c->last_n[s] = a.sp[s].n;
     }
@@ -364,6 +376,14 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
         if (r == hipSuccess) r = launch(c, qed::K_LIGHT, a, prec, lepton_blocks);
         if (r == hipSuccess) r = launch(c, qed::K_HEAVY, a, prec, heavy_blocks);
     }
+    // cascade passes: the particles of the previous pass, from their birth time
+    for (uint32_t g = 1; g <= gens && r == hipSuccess; ++g) {
+        a.gen = g;
+        r = launch(c, qed::K_GEN, a, prec, 1);
+        if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON, a, prec, photon_blocks);
+        if (r == hipSuccess && emission) r = launch(c, qed::K_LEPTON, a, prec, lepton_blocks);
+    }
+    a.gen = 0;
     if (r == hipSuccess) r = launch(c, qed::K_END, a, prec, 1);
     if (r == hipSuccess && pairs) r = launch(c, qed::K_FILL, a, prec, aux_blocks);
     if (r == hipSuccess && pairs) r = launch(c, qed::K_MOVE, a, prec, aux_blocks);

@@ -48,6 +48,8 @@ struct DevState {
     alignas(128) u64 max_p_bits;   // largest acceptance probability (bits of a non-negative double)
     alignas(128) u64 status_bits;  // bit 0: capacity exceeded, bit 1: non-finite input
     u64 required[3];  // largest count requested per species (capacity errors)
+    u64 lo[3], hi[3]; // slots of the current pass: [0, n0) in the main pass; the
+                      // particles appended by the previous pass in a cascade pass
     uint32_t hist[2][kBins];    // per-bin counts of the current step
     uint32_t offset[2][kBins];  // start of each heavy bin in the work queue
     uint32_t cursor[2][kBins];  // fill position inside each bin
@@ -61,6 +63,7 @@ struct SpeciesDev {
     uint64_t *id, *parent;
     uint32_t *events;
     double *tau;
+    double *birth;  // cascades: time within the step at which each new particle was born
 };
 
 struct FieldDev {
@@ -86,6 +89,8 @@ struct StepArgs {
     uint32_t *queue[2];    // binned scheduler: heavy lepton slots sorted by bin, heaviest first
     int sampler;           // 0 rejection, 1 surrogate
     const MlpModel *model; // surrogate: installed network (nullptr: rejection for every chi)
+    uint32_t gen;          // 0: main pass; g >= 1: cascade pass g over DevState's lo..hi,
+                           // each particle starting at its birth time
 };
 
 // Kernels, in launch order, and the standalone synchrotron kernel.
@@ -103,6 +108,7 @@ enum KernelId {
     K_MOVE,
     K_SYNCHROTRON,
     K_TILED,    // tile-sorted scheduler: the whole lepton pass
+    K_GEN,      // cascades: advance the pass ranges to the particles of the previous pass
     K_COUNT
 };
 

@@ -156,6 +156,7 @@ struct ChildBuf {
     double x[64], y[64], z[64];
     R px[64], py[64], pz[64], w[64];
     uint64_t id[64], parent[64];
+    double tb[64];  // birth time within the step
     uint32_t count;
 };
 
@@ -185,6 +186,7 @@ __device__ __forceinline__ void flush_children(ChildBuf<R> &cb, const SpeciesDev
             ((R *)dst.w)[slot] = cb.w[e];
             dst.id[slot] = cb.id[e];
             if (dst.parent) dst.parent[slot] = cb.parent[e];
+            if (dst.birth) dst.birth[slot] = cb.tb[e];
         }
     }
     __syncwarp();
@@ -256,10 +258,11 @@ __device__ __forceinline__ Lepton<R> load_lepton(const StepArgs &a, int s, u64 i
     return p;
 }
 
-// Algorithm 1, step start: the sub-step count from the bound
-// (double).  0 for non-finite input (the particle is left alone).
+// Algorithm 1, step start: the sub-step count from the bound over the interval
+// dt (double).  0 for non-finite input (the particle is left alone).
 template <class R>
-__device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<R> &p, Tally<R> &tl) {
+__device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<R> &p, Tally<R> &tl,
+                                                double dt) {
     if (!(finite3(p.ux, p.uy, p.uz) && finite3(p.ex, p.ey, p.ez) && finite3(p.bx, p.by, p.bz))) {
         tl.nonfinite++;
         return 0;
@@ -267,7 +270,7 @@ __device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<
     const double gd = sqrt(1.0 + (double)p.ux * p.ux + (double)p.uy * p.uy + (double)p.uz * p.uz);
     const double chi0 = chi_def(gd, p.ux, p.uy, p.uz, p.ex, p.ey, p.ez, p.bx, p.by, p.bz);
     bool capped;
-    const uint32_t N = nsub(bound_emission(chi0, gd, a.dt), a.p_max, a.max_sub, &capped);
+    const uint32_t N = nsub(bound_emission(chi0, gd, dt), a.p_max, a.max_sub, &capped);
     tl.capped += capped;
     return N;
 }
@@ -281,7 +284,7 @@ template <class R>
 __device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesDev &sp, u64 i, uint64_t pid,
                                                uint32_t k, bool acc, u64 m, R x3, R omx3, R g, R u2, R dx,
                                                R dy, R dz, R &ux, R &uy, R &uz, ChildBuf<R> &cb,
-                                               uint32_t &nev) {
+                                               uint32_t &nev, double t0, double st) {
     const uint32_t c = (uint32_t)__popcll(m);
     __syncwarp();
     if (cb.count + c > 64) flush_children(cb, a.sp[2]);
@@ -300,6 +303,7 @@ __device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesD
         cb.w[e] = ((const R *)sp.w)[i];
         cb.id[e] = child_id(a.seed, pid, a.step, k, 0);
         cb.parent[e] = pid;
+        cb.tb[e] = t0 + (double)(k + 1) * st;
         // gamma' = (1 - delta) gamma, same direction
         const R g1 = omx3 * g;
         const R u1 = sqrt_(fmax(g1 * g1 - R(1), R(0)));
@@ -319,10 +323,10 @@ __device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesD
 // (0 general, 1 pure E, 2 pure B), see boris().
 template <class R, int FK>
 __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uint32_t N, Lepton<R> p,
-                                            const SynTable<R> &tab, ChildBuf<R> &cb, Tally<R> &tl) {
+                                            const SynTable<R> &tab, ChildBuf<R> &cb, Tally<R> &tl, double t0) {
     const SpeciesDev &sp = a.sp[s];
     const uint64_t pid = sp.id[i];
-    const double st = a.dt / (double)N;
+    const double st = (a.dt - t0) / (double)N;
     const R hq = (R)((s == 0 ? -0.5 : 0.5) * st);
     const R hex = hq * p.ex, hey = hq * p.ey, hez = hq * p.ez;
     const R e2 = p.ex * p.ex + p.ey * p.ey + p.ez * p.ez;
@@ -364,7 +368,8 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
         const bool acc = y < pm;
         // emission: stage the photon in the wave's LDS buffer, recoil on the parent
         const u64 m = __ballot(acc);
-        if (m) stage_emission<R>(a, sp, i, pid, k, acc, m, x3, omx3, g, u2, dx, dy, dz, ux, uy, uz, cb, nev);
+        if (m)
+            stage_emission<R>(a, sp, i, pid, k, acc, m, x3, omx3, g, u2, dx, dy, dz, ux, uy, uz, cb, nev, t0, st);
     }
     ((R *)sp.ux)[i] = ux;
     ((R *)sp.uy)[i] = uy;
@@ -379,15 +384,15 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
 
 template <class R>
 __device__ __forceinline__ void lepton_run(const StepArgs &a, int s, u64 i, uint32_t N, Lepton<R> p,
-                                           const SynTable<R> &tab, ChildBuf<R> &cb, Tally<R> &tl) {
+                                           const SynTable<R> &tab, ChildBuf<R> &cb, Tally<R> &tl, double t0) {
     const bool noB = p.bx == R(0) && p.by == R(0) && p.bz == R(0);
     const bool noE = p.ex == R(0) && p.ey == R(0) && p.ez == R(0);
     if (noB)
-        lepton_loop<R, 1>(a, s, i, N, p, tab, cb, tl);
+        lepton_loop<R, 1>(a, s, i, N, p, tab, cb, tl, t0);
     else if (noE)
-        lepton_loop<R, 2>(a, s, i, N, p, tab, cb, tl);
+        lepton_loop<R, 2>(a, s, i, N, p, tab, cb, tl, t0);
     else
-        lepton_loop<R, 0>(a, s, i, N, p, tab, cb, tl);
+        lepton_loop<R, 0>(a, s, i, N, p, tab, cb, tl, t0);
 }
 
 // ---------------------------------------------------------------------------
@@ -534,7 +539,8 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
             omx3 = (R(1) - x) * (R(1) + x + x2);
             tau = ptau;
         }
-        stage_emission<R>(a, sp, i, pid, pk, pend, mp, x3, omx3, pg, pu2, dx, dy, dz, ux, uy, uz, cb, nev);
+        stage_emission<R>(a, sp, i, pid, pk, pend, mp, x3, omx3, pg, pu2, dx, dy, dz, ux, uy, uz, cb, nev, 0.0,
+                          st);
         pend = false;
     }
     if (has) {
@@ -559,8 +565,8 @@ template <class R>
 struct LeptonRunner<R, false> {
     template <class L>
     __device__ static void run(const StepArgs &a, int s, u64 i, uint32_t N, const Lepton<R> &p, L &lds,
-                               ChildBuf<R> &cb, Tally<R> &t) {
-        if (N) lepton_run<R>(a, s, i, N, p, lds.tab, cb, t);
+                               ChildBuf<R> &cb, Tally<R> &t, double t0 = 0.0) {
+        if (N) lepton_run<R>(a, s, i, N, p, lds.tab, cb, t, t0);
     }
 };
 
@@ -568,7 +574,7 @@ template <>
 struct LeptonRunner<float, true> {
     template <class L>
     __device__ static void run(const StepArgs &a, int s, u64 i, uint32_t n, const Lepton<float> &p, L &lds,
-                               ChildBuf<float> &cb, Tally<float> &t) {
+                               ChildBuf<float> &cb, Tally<float> &t, double = 0.0) {
         if (__ballot(n != 0) == 0) return;
         // one field kind for the whole wave (the general form is valid for all)
         const bool noB = p.bx == 0.0f && p.by == 0.0f && p.bz == 0.0f;
@@ -588,6 +594,7 @@ struct LeptonRunner<float, true> {
 // ---------------------------------------------------------------------------
 struct PhotonStart {
     double eps, chi;
+    double t0;  // start time within the step (birth time in a cascade pass, else 0)
     uint32_t N;
 };
 
@@ -600,7 +607,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
     const SpeciesDev &el = a.sp[0];
     const SpeciesDev &po = a.sp[1];
     const uint32_t N = ps.N;
-    const double st = a.dt / (double)N;
+    const double st = (a.dt - ps.t0) / (double)N;
     const R inv = (R)(1.0 / ps.eps);
     const R dirx = kx * inv, diry = ky * inv, dirz = kz * inv;
     const R str = (R)st;
@@ -652,6 +659,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
                 const double px = sp.x[i] + (double)dx, py = sp.y[i] + (double)dy,
                              pz = sp.z[i] + (double)dz;
                 const R w = ((const R *)sp.w)[i];
+                const double tb = ps.t0 + (double)(k + 1) * st;
                 const R ge = x * epsr, gp = (R(1) - x) * epsr;
                 const R ue = sqrt_(fmax(ge * ge - R(1), R(0)));
                 const R up = sqrt_(fmax(gp * gp - R(1), R(0)));
@@ -667,6 +675,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
                     el.id[j] = child_id(a.seed, pid, a.step, k, 0);
                     if (el.parent) el.parent[j] = pid;
                     if (el.tau) el.tau[j] = -1.0;
+                    if (el.birth) el.birth[j] = tb;
                 }
                 if (bp + r < po.cap) {
                     const u64 j = bp + r;
@@ -680,6 +689,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
                     po.id[j] = child_id(a.seed, pid, a.step, k, 1);
                     if (po.parent) po.parent[j] = pid;
                     if (po.tau) po.tau[j] = -1.0;
+                    if (po.birth) po.birth[j] = tb;
                 }
                 dead = true;
             }
@@ -738,6 +748,7 @@ __device__ __forceinline__ void flush_children_block(ChildBuf<R> *cbs, const Spe
             ((R *)dst.w)[slot] = cb.w[k];
             dst.id[slot] = cb.id[k];
             if (dst.parent) dst.parent[slot] = cb.parent[k];
+            if (dst.birth) dst.birth[slot] = cb.tb[k];
         }
     }
 }
@@ -769,30 +780,34 @@ __device__ __forceinline__ ChildBuf<R> &lepton_lds_init(const StepArgs &a, Lepto
 // The particle of this lane (N = 0 and a zero record when there is none).
 template <class R>
 __device__ __forceinline__ uint32_t lepton_fetch(const StepArgs &a, int s, u64 i, bool has, Lepton<R> &p,
-                                                 Tally<R> &t) {
+                                                 Tally<R> &t, double dt) {
     if (!has) {
         p = Lepton<R>{0, 0, 0, 0, 0, 0, 0, 0, 0};
         return 0;
     }
     p = load_lepton<R>(a, s, i);
-    return lepton_nsub(a, p, t);
+    return lepton_nsub(a, p, t, dt);
 }
 
 // Naive scheduler: one lane per particle in buffer order; the loop runs with
-// whole waves (lanes past the end carry no particle).
+// whole waves (lanes past the end carry no particle).  The pass covers the slots
+// lo..hi of the device state; in a cascade pass (gen >= 1) each particle runs
+// over the rest of the step from its birth time.
 template <class R, bool SURR>
 __global__ __launch_bounds__(kBlock) void k_lepton(StepArgs a) {
     __shared__ LeptonLds<R, SURR> L;
     ChildBuf<R> &cb = lepton_lds_init<R, SURR>(a, L);
     const int s = blockIdx.y;
-    const u64 n = a.st->n0[s];
+    const u64 lo = a.st->lo[s], hi = a.st->hi[s];
     Tally<R> t;
-    for (u64 i0 = (u64)blockIdx.x * kBlock + (threadIdx.x & ~63u); i0 < n; i0 += (u64)gridDim.x * kBlock) {
+    for (u64 i0 = lo + (u64)blockIdx.x * kBlock + (threadIdx.x & ~63u); i0 < hi; i0 += (u64)gridDim.x * kBlock) {
         const u64 i = i0 + __lane_id();
+        const bool has = i < hi;
+        const double t0 = a.gen && has ? a.sp[s].birth[i] : 0.0;
         Lepton<R> p;
-        const uint32_t N = lepton_fetch(a, s, i, i < n, p, t);
-        if (i < n && N == 0 && a.sp[s].events) a.sp[s].events[i] = 0;
-        LeptonRunner<R, SURR>::run(a, s, i, N, p, L, cb, t);
+        const uint32_t N = lepton_fetch(a, s, i, has, p, t, a.dt - t0);
+        if (has && N == 0 && a.sp[s].events) a.sp[s].events[i] = 0;
+        LeptonRunner<R, SURR>::run(a, s, i, N, p, L, cb, t, t0);
     }
     flush_children_block(L.cb, a.sp[2]);
     flush_tally(t, a.st, s);
@@ -808,7 +823,7 @@ __global__ __launch_bounds__(kBlock) void k_prepass(StepArgs a) {
     Tally<R> t;
     for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
         const Lepton<R> p = load_lepton<R>(a, s, i);
-        const uint32_t N = lepton_nsub(a, p, t);
+        const uint32_t N = lepton_nsub(a, p, t, a.dt);
         a.nsub[s][i] = N;
         if (N)
             atomicAdd(&h[nbin(N, a.light_max)], 1u);
@@ -960,7 +975,7 @@ __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
         for (int q = 0; q < kTiledSlots / 64; ++q) {
             const u64 i = t0 + q * 64 + lane;
             Lepton<R> p;
-            const uint32_t N = lepton_fetch(a, s, i, i < n, p, t);
+            const uint32_t N = lepton_fetch(a, s, i, i < n, p, t, a.dt);
             if (i < n && N == 0 && a.sp[s].events) a.sp[s].events[i] = 0;
             nsub[q * 64 + lane] = N;
             const uint32_t key = N ? kTileKeys - (N < kTileKeys - 1 ? N : kTileKeys - 1) : 0u;
@@ -1047,7 +1062,9 @@ __device__ __forceinline__ void photon_sample_one(const StepArgs &a, u64 i, cons
 // this step (photon_quiet) run their sub-step loop in closed form: they only
 // move.  The others go to a wave-local queue, which is drained 64 photons at a
 // time, so the sampling loops run with all lanes busy; their records were read by
-// this wave shortly before, so the second read hits the cache.
+// this wave shortly before, so the second read hits the cache.  The pass covers
+// the slots lo..hi of the device state; in a cascade pass (gen >= 1) each photon
+// runs over the rest of the step from its birth time.
 constexpr int kPhotonBatch = 2;
 constexpr int kPhotonQueue = 64 * (kPhotonBatch + 1);
 
@@ -1056,15 +1073,16 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
     __shared__ SynTable<R> tab;
     __shared__ u64 queue_sh[kBlock / 64][kPhotonQueue];
     __shared__ double qchi_sh[kBlock / 64][kPhotonQueue], qeps_sh[kBlock / 64][kPhotonQueue];
+    __shared__ double qt0_sh[kBlock / 64][kPhotonQueue];
     __shared__ uint32_t qn_sh[kBlock / 64][kPhotonQueue];
     syn_stage(tab);
-    const u64 n = a.st->n0[2];
+    const u64 lo = a.st->lo[2], n = a.st->hi[2];
     const SpeciesDev &sp = a.sp[2];
     const FieldDev &fl = a.fl[2];
     const bool uni = fl.stride == 0;
     const uint32_t lane = __lane_id();
     u64 *queue = queue_sh[threadIdx.x / 64];
-    double *qchi = qchi_sh[threadIdx.x / 64], *qeps = qeps_sh[threadIdx.x / 64];
+    double *qchi = qchi_sh[threadIdx.x / 64], *qeps = qeps_sh[threadIdx.x / 64], *qt0 = qt0_sh[threadIdx.x / 64];
     uint32_t *qn = qn_sh[threadIdx.x / 64];
     uint32_t queued = 0;  // wave-uniform
     R fu[6] = {0, 0, 0, 0, 0, 0};
@@ -1079,7 +1097,7 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
     Tally<R> t, ts;  // all photons; the sampled ones
     const u64 G = (u64)gridDim.x * kBlock;
     // wave-uniform loop: photon b of this lane is slot wbase + lane + b G
-    for (u64 wbase = (u64)blockIdx.x * kBlock + (threadIdx.x & ~63u); wbase < n; wbase += G * kPhotonBatch) {
+    for (u64 wbase = lo + (u64)blockIdx.x * kBlock + (threadIdx.x & ~63u); wbase < n; wbase += G * kPhotonBatch) {
         const u64 i0 = wbase + lane;
         R k[kPhotonBatch][3], f[kPhotonBatch][6];
         double x[kPhotonBatch][3];
@@ -1121,17 +1139,20 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
             }
             const double eps = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
             const double chi = chi_def(eps, kx, ky, kz, f[b][0], f[b][1], f[b][2], f[b][3], f[b][4], f[b][5]);
+            const double t0 = a.gen ? sp.birth[i] : 0.0;
+            const double dti = a.dt - t0;
             uint32_t N = 1;
             if (eps > 0.0) {
                 bool capped;
-                N = nsub(bound_pair(chi, eps, a.dt, a.pair_coef), a.p_max, a.max_sub, &capped);
+                N = nsub(bound_pair(chi, eps, dti, a.pair_coef), a.p_max, a.max_sub, &capped);
                 t.capped += capped;
             }
-            const double st = a.dt / (double)N;
+            const double st = dti / (double)N;
             if (!photon_quiet<R>(chi, eps, st)) {
                 need |= 1u << b;
                 pst[b].eps = eps;
                 pst[b].chi = chi;
+                pst[b].t0 = t0;
                 pst[b].N = N;
                 continue;
             }
@@ -1161,6 +1182,7 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
                 queue[q] = i0 + b * G;
                 qchi[q] = pst[b].chi;
                 qeps[q] = pst[b].eps;
+                qt0[q] = pst[b].t0;
                 qn[q] = pst[b].N;
             }
             queued += (uint32_t)__popcll(m);
@@ -1169,13 +1191,13 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
         while (queued >= 64) {
             queued -= 64;
             const uint32_t q = queued + lane;
-            const PhotonStart ps = {qeps[q], qchi[q], qn[q]};
+            const PhotonStart ps = {qeps[q], qchi[q], qt0[q], qn[q]};
             photon_sample_one<R>(a, queue[q], ps, tab, ts);
             __syncwarp();
         }
     }
     if (lane < queued) {
-        const PhotonStart ps = {qeps[lane], qchi[lane], qn[lane]};
+        const PhotonStart ps = {qeps[lane], qchi[lane], qt0[lane], qn[lane]};
         photon_sample_one<R>(a, queue[lane], ps, tab, ts);
     }
     flush_tally(t, a.st, 2);
@@ -1189,9 +1211,25 @@ __global__ void k_begin(StepArgs a) {
         for (int s = 0; s < 3; ++s) {
             const u64 n = *a.sp[s].n;
             st->n0[s] = n < a.sp[s].cap ? n : a.sp[s].cap;
+            st->lo[s] = 0;
+            st->hi[s] = st->n0[s];
             if (s < 2 ? a.emission : a.pairs) st->particles[s] += st->n0[s];
         }
         st->dead = 0;
+    }
+}
+
+// Cascade pass: the next pass covers the particles appended since the previous
+// pass's range was fixed (clamped to capacity; an overflow is reported by k_end).
+__global__ void k_gen(StepArgs a) {
+    if (threadIdx.x == 0) {
+        DevState *st = a.st;
+        for (int s = 0; s < 3; ++s) {
+            const u64 n = *a.sp[s].n;
+            st->lo[s] = st->hi[s];
+            st->hi[s] = n < a.sp[s].cap ? n : a.sp[s].cap;
+            if (s < 2 ? a.emission : a.pairs) st->particles[s] += st->hi[s] - st->lo[s];
+        }
     }
 }
 
@@ -1216,12 +1254,13 @@ __global__ void k_end(StepArgs a) {
 }
 
 // Holes: decayed slots below S (from the dead list).  Movers: live slots in
-// [S, ntot) (a slot there is live if it was appended this step or survived).
+// [S, ntot) (a slot there is live if it survived the last pass that covered it,
+// or if it was appended after that pass's range was fixed).
 __global__ __launch_bounds__(kBlock) void k_fill(StepArgs a) {
     const DevState *st = a.st;
     const u64 D = st->dead;
     if (D == 0) return;
-    const u64 S = st->S, n0 = st->n0[2];
+    const u64 S = st->S, done = st->hi[2];  // slots below done carry an alive flag
     // work items: D dead-list entries, then the D slots of [S, ntot)
     for (u64 t0 = (u64)blockIdx.x * kBlock; t0 < 2 * D; t0 += (u64)gridDim.x * kBlock) {
         const u64 t = t0 + threadIdx.x;
@@ -1232,7 +1271,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(StepArgs a) {
             hole = p < S;
         } else if (t < 2 * D) {
             p = S + (t - D);
-            mover = p >= n0 || a.alive[p] != 0;
+            mover = p >= done || a.alive[p] != 0;
         }
         const u64 mh = __ballot(hole), mm = __ballot(mover);
         u64 bh = 0, bm = 0;
@@ -1264,6 +1303,7 @@ __global__ __launch_bounds__(kBlock) void k_move(StepArgs a) {
         ((R *)sp.w)[d] = ((const R *)sp.w)[s];
         sp.id[d] = sp.id[s];
         if (sp.parent) sp.parent[d] = sp.parent[s];
+        if (sp.birth) sp.birth[d] = sp.birth[s];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *sp.n = st->S;
 }
@@ -1346,6 +1386,7 @@ hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
             hipLaunchKernelGGL((k_tiled<R, false>), g2, blk, 0, s, a);
             break;
         case K_END: hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, s, a); break;
+        case K_GEN: hipLaunchKernelGGL(k_gen, dim3(1), dim3(64), 0, s, a); break;
         case K_FILL: hipLaunchKernelGGL(k_fill, g1, blk, 0, s, a); break;
         case K_MOVE: hipLaunchKernelGGL(k_move<R>, g1, blk, 0, s, a); break;
         default: return hipErrorInvalidValue;

@@ -28,7 +28,7 @@ class qed_species(C.Structure):
                 ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("ux", C.c_void_p), ("uy", C.c_void_p), ("uz", C.c_void_p),
                 ("w", C.c_void_p), ("id", C.c_void_p), ("parent", C.c_void_p),
-                ("events", C.c_void_p), ("tau", C.c_void_p)]
+                ("events", C.c_void_p), ("tau", C.c_void_p), ("birth", C.c_void_p)]
 
 
 class qed_particles(C.Structure):
@@ -43,7 +43,7 @@ class qed_config(C.Structure):
     _fields_ = [("device", C.c_int), ("stream", C.c_void_p), ("precision", C.c_int),
                 ("p_max", C.c_double), ("emission", C.c_int), ("pairs", C.c_int),
                 ("scheduler", C.c_int), ("pair_bound_coef", C.c_double),
-                ("max_substeps", C.c_uint32), ("sampler", C.c_int)]
+                ("max_substeps", C.c_uint32), ("sampler", C.c_int), ("cascade_generations", C.c_uint32)]
 
 
 class qed_report(C.Structure):
@@ -306,7 +306,7 @@ def _torch():
 class SpeciesBuffers:
     """Device SoA buffers of one species (torch tensors) with a fixed capacity."""
 
-    def __init__(self, capacity, real, device="cuda", parent=True, events=True, tau=False):
+    def __init__(self, capacity, real, device="cuda", parent=True, events=True, tau=False, birth=False):
         torch = _torch()
         self.capacity = int(capacity)
         self.real = real
@@ -323,6 +323,7 @@ class SpeciesBuffers:
         self.parent = torch.zeros(cap, dtype=torch.int64, device=device) if parent else None
         self.events = torch.zeros(cap, dtype=torch.int32, device=device) if events else None
         self.tau = torch.full((cap,), -1.0, dtype=torch.float64, device=device) if tau else None
+        self.birth = torch.zeros(cap, dtype=torch.float64, device=device) if birth else None
 
     def struct(self):
         s = qed_species()
@@ -333,6 +334,7 @@ class SpeciesBuffers:
         s.parent = self.parent.data_ptr() if self.parent is not None else None
         s.events = self.events.data_ptr() if self.events is not None else None
         s.tau = self.tau.data_ptr() if self.tau is not None else None
+        s.birth = self.birth.data_ptr() if self.birth is not None else None
         return s
 
     def upload(self, host):
@@ -363,6 +365,8 @@ class SpeciesBuffers:
             out["parent"] = self.parent[:n].cpu().numpy().view(np.uint64)
         if self.tau is not None:
             out["tau"] = self.tau[:n].cpu().numpy()
+        if self.birth is not None:
+            out["birth"] = self.birth[:n].cpu().numpy()
         return out
 
     def events_host(self, n):
@@ -402,7 +406,7 @@ class Generator:
     def __init__(self, precision=QED_PREC_MIXED, capacity=(1 << 20, 1 << 20, 1 << 20), emission=True,
                  pairs=True, p_max=0.01, scheduler=QED_SCHED_NAIVE, pair_bound_coef=0.1,
                  max_substeps=1 << 24, device=0, stream=None, parent=True, events=True,
-                 sampler=QED_SAMPLER_REJECTION):
+                 sampler=QED_SAMPLER_REJECTION, cascade_generations=0):
         torch = _torch()
         self.real = torch.float64 if precision == QED_PREC_F64 else torch.float32
         self.precision = precision
@@ -417,10 +421,12 @@ class Generator:
         cfg.pair_bound_coef = pair_bound_coef
         cfg.max_substeps = max_substeps
         cfg.sampler = sampler
+        cfg.cascade_generations = cascade_generations
         self.cfg = cfg
         self.ctx = qed_init(cfg)
         surr = sampler == QED_SAMPLER_SURROGATE
-        self.sp = [SpeciesBuffers(c, self.real, parent=parent, events=events, tau=surr and k < 2)
+        self.sp = [SpeciesBuffers(c, self.real, parent=parent, events=events, tau=surr and k < 2,
+                                  birth=cascade_generations > 0)
                    for k, c in enumerate(capacity)]
         self.fields = [None, None, None]
 

@@ -63,6 +63,8 @@ def test_children_run_the_rest_of_the_step():
         moved = np.array([gg["x"][jj] - che["x"][j], gg["y"][jj] - che["y"][j], gg["z"][jj] - che["z"][j]])
         expect = d[:, j] * (dt - che["tb"][j])
         assert np.allclose(moved, expect, rtol=1e-10, atol=1e-9 * dt)
+        assert gg["birth"][jj] == che["tb"][j]
+    assert np.all(ee["birth"] == 0.0)
     # the follow-up pass ran exactly these photons
     assert tallies[1][0]["substeps"] >= che["id"].size
 

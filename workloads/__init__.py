@@ -16,6 +16,10 @@ the regime a QED-PIC push stage sees (Sec. 2.2 and 3.1 of the paper):
           hot spot B = 1e-2 exp(-r^2/2) z with r ~ N(0, I_3) in units of the spot
           size; fields are per particle and static.
 * ``c4``  log-uniform x in [1e-4, 50] for the synchrotron-function microbenchmark.
+* ``shower``  in-step cascades: electrons, positrons and photons in equal numbers,
+          gamma (photon energy) log-uniform in [1e4, 10^5.5], isotropic, uniform
+          static B = 2e-3 along z, dt = 3e5: particles created early in the step
+          create further particles within it, five to six generations deep.
 
 All species arrays are float64 numpy arrays (``x, y, z, ux, uy, uz, w``) plus
 uint64 ``id``; photon momenta are stored in ``ux, uy, uz`` as k = hbar k/(m c).
@@ -32,6 +36,8 @@ import numpy as np
 DT_C1 = 8.37e4         # mean emission probability per step about 0.5
 DT_C2 = 10358.420305623711   # (0.8 um laser period) / 200
 DT_C3 = 2.0696e5       # hot-spot particles need at most 1000 sub-steps
+DT_SHOWER = 3.0e5      # five to six generations of events inside one step
+B_SHOWER = 2.0e-3
 E0_C2 = 1.0e-3
 B_C1 = 1.0e-3
 P_MAX = 0.01
@@ -76,6 +82,22 @@ def c1(n=16384, seed=1):
     return {"electrons": e, "positrons": _empty(), "photons": _empty(),
             "fields": uniform_field(bz=B_C1), "dt": DT_C1, "steps": 100, "seed": 1,
             "p_max": P_MAX}
+
+
+def shower(n=4096, seed=6):
+    """In-step cascades: n electrons, n positrons and n photons seeding a shower."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for k, name in enumerate(("electrons", "positrons", "photons")):
+        s = _species(n, k * n, rng)
+        energy = 10.0 ** rng.uniform(4.0, 5.5, n)
+        u = energy if name == "photons" else np.sqrt(energy * energy - 1.0)
+        dx, dy, dz = _isotropic(rng, n)
+        s["ux"], s["uy"], s["uz"] = u * dx, u * dy, u * dz
+        out[name] = s
+    out.update({"fields": uniform_field(bz=B_SHOWER), "dt": DT_SHOWER, "steps": 4, "seed": 1,
+                "p_max": P_MAX})
+    return out
 
 
 def _joint_chi_energy(rng, n, e0):
