@@ -136,6 +136,14 @@ typedef struct qed_config {
                            field for every particle: the library has no field for a new
                            slot); the cascade passes use the one-lane-per-particle
                            kernels whatever the scheduler.  At most 64. */
+    double surrogate_p_max; /* QED_SAMPLER_SURROGATE: target of the lepton sub-step bound
+                           (as p_max, which pair creation keeps), in (0, 1]; 0.1.  The
+                           optical depth gives the emission law at any sub-step length;
+                           the sub-steps resolve the change of chi along the path.  The
+                           emissions of a sub-step happen at its end: each draws the next
+                           optical depth, the rest of the sub-step's integrated rate counts
+                           against it, and while it is still crossed the particle emits
+                           again, so no emission is lost or deferred. */
 } qed_config;
 
 /* Errors and counts observed on the device since the previous qed_sync. */

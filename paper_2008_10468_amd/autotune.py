@@ -36,6 +36,7 @@ SPACE = {
     "chunk": (64, 128, 256, 512, 1024, 4096),
 }
 NAIVE_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu")
+MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "sampler_gfx950.npz")
 BINNED_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu", "heavy_blocks_per_cu", "light_max", "chunk")
 
 
@@ -164,12 +165,29 @@ def _workload(name, torch, workloads, sched, stream, steps):
         g.set_fields(None, per_species=[w["fields"], zero, zero])
         fl = [f.struct() for f in g.fields]
         return g, w, lambda s: (qed.qed_field * 3)(*fl)
+    if name == "c5":
+        # the hot-spot workload on the surrogate path, with the network shipped for gfx950
+        import numpy as np
+        w = workloads.c3()
+        n = w["electrons"]["id"].size
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, int(0.65 * n * steps) + (1 << 23)),
+                          pairs=False, parent=False, events=False, scheduler=sched,
+                          stream=stream.cuda_stream, sampler=qed.QED_SAMPLER_SURROGATE)
+        m = np.load(MODEL)
+        st = qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
+                                 float(m["log10_chi_hi"]))
+        if st != qed.QED_OK:
+            raise qed.QedError(st, "qed_sampler_set")
+        zero = workloads.uniform_field()
+        g.set_fields(None, per_species=[w["fields"], zero, zero])
+        fl = [f.struct() for f in g.fields]
+        return g, w, lambda s: (qed.qed_field * 3)(*fl)
     raise ValueError(name)
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Tune launch shapes of the QED generator on this GPU")
-    ap.add_argument("--workload", choices=("c2", "c3"), action="append")
+    ap.add_argument("--workload", choices=("c2", "c3", "c5"), action="append")
     ap.add_argument("--scheduler", choices=("naive", "binned", "tiled"), action="append")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--passes", type=int, default=2)

@@ -245,6 +245,8 @@ qed_status qed_config_default(qed_config *cfg) {
     cfg->pair_bound_coef = 0.1;
     cfg->max_substeps = 1u << 24;
     cfg->sampler = QED_SAMPLER_REJECTION;
+    cfg->cascade_generations = 0;
+    cfg->surrogate_p_max = 0.1;
     return QED_OK;
 }
 
@@ -260,6 +262,8 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     if (cfg->sampler != QED_SAMPLER_REJECTION && cfg->sampler != QED_SAMPLER_SURROGATE) return QED_ERR_INVALID_ARG;
     if (cfg->sampler == QED_SAMPLER_SURROGATE && cfg->precision != QED_PREC_MIXED) return QED_ERR_INVALID_ARG;
     if (cfg->cascade_generations > 64) return QED_ERR_INVALID_ARG;
+    if (cfg->sampler == QED_SAMPLER_SURROGATE && !(cfg->surrogate_p_max > 0.0 && cfg->surrogate_p_max <= 1.0))
+        return QED_ERR_INVALID_ARG;
     if (cfg->cascade_generations > 0 && cfg->sampler != QED_SAMPLER_REJECTION) return QED_ERR_INVALID_ARG;
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
@@ -340,6 +344,7 @@ qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], dou
     a.st = c->st;
     a.dt = dt;
     a.p_max = c->cfg.p_max;
+    a.p_max_lep = surrogate ? c->cfg.surrogate_p_max : c->cfg.p_max;
     a.pair_coef = c->cfg.pair_bound_coef;
     a.seed = seed;
     a.step = step;

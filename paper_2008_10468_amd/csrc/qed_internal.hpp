@@ -76,6 +76,7 @@ struct StepArgs {
     FieldDev fl[3];
     DevState *st;
     double dt, p_max, pair_coef;
+    double p_max_lep;      // sub-step bound target of the leptons (p_max, or the surrogate's)
     uint64_t seed;
     uint32_t step, max_sub;
     int emission, pairs;   // which algorithms run in this step

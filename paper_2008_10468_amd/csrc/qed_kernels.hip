@@ -151,19 +151,20 @@ __device__ __forceinline__ void flush_tally(const Tally<R> &t, DevState *st, int
 }
 
 // Children of one wave staged in LDS and written out with one atomic per flush.
-template <class R>
+// TB: with birth times (the surrogate path, which runs no cascades, saves the LDS).
+template <class R, bool TB = true>
 struct ChildBuf {
     double x[64], y[64], z[64];
     R px[64], py[64], pz[64], w[64];
     uint64_t id[64], parent[64];
-    double tb[64];  // birth time within the step
+    double tb[TB ? 64 : 1];  // birth time within the step
     uint32_t count;
 };
 
 // Write the staged children to the species' tail.  Called by the active lanes of
 // a wave (any subset); they share the writes.
-template <class R>
-__device__ __forceinline__ void flush_children(ChildBuf<R> &cb, const SpeciesDev &dst) {
+template <class R, bool TB>
+__device__ __forceinline__ void flush_children(ChildBuf<R, TB> &cb, const SpeciesDev &dst) {
     __syncwarp();
     const uint32_t n = cb.count;
     if (n == 0) return;
@@ -186,7 +187,8 @@ __device__ __forceinline__ void flush_children(ChildBuf<R> &cb, const SpeciesDev
             ((R *)dst.w)[slot] = cb.w[e];
             dst.id[slot] = cb.id[e];
             if (dst.parent) dst.parent[slot] = cb.parent[e];
-            if (dst.birth) dst.birth[slot] = cb.tb[e];
+            if constexpr (TB)
+                if (dst.birth) dst.birth[slot] = cb.tb[e];
         }
     }
     __syncwarp();
@@ -270,7 +272,7 @@ __device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<
     const double gd = sqrt(1.0 + (double)p.ux * p.ux + (double)p.uy * p.uy + (double)p.uz * p.uz);
     const double chi0 = chi_def(gd, p.ux, p.uy, p.uz, p.ex, p.ey, p.ez, p.bx, p.by, p.bz);
     bool capped;
-    const uint32_t N = nsub(bound_emission(chi0, gd, dt), a.p_max, a.max_sub, &capped);
+    const uint32_t N = nsub(bound_emission(chi0, gd, dt), a.p_max_lep, a.max_sub, &capped);
     tl.capped += capped;
     return N;
 }
@@ -279,11 +281,14 @@ __device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<
 // energy fraction delta = x3 along u is staged in the wave's LDS buffer with the
 // parent's position and weight, and the parent recoils to gamma' = (1 - delta)
 // gamma in the same direction.  Called by every lane of the wave that is still in
-// the sub-step loop.
-template <class R>
+// the sub-step loop.  k: the sub-step (birth time t0 + (k + 1) st); ctr: the
+// counter of the photon's id (the sub-step in Algorithm 1, the emission's index in
+// the step for the surrogate, which can emit more than once in a sub-step).
+template <class R, bool TB>
 __device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesDev &sp, u64 i, uint64_t pid,
-                                               uint32_t k, bool acc, u64 m, R x3, R omx3, R g, R u2, R dx,
-                                               R dy, R dz, R &ux, R &uy, R &uz, ChildBuf<R> &cb,
+                                               uint32_t ctr, uint32_t k, bool acc, u64 m, R x3, R omx3, R g,
+                                               R u2, R dx,
+                                               R dy, R dz, R &ux, R &uy, R &uz, ChildBuf<R, TB> &cb,
                                                uint32_t &nev, double t0, double st) {
     const uint32_t c = (uint32_t)__popcll(m);
     __syncwarp();
@@ -301,9 +306,9 @@ __device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesD
         cb.py[e] = uy * eph;
         cb.pz[e] = uz * eph;
         cb.w[e] = ((const R *)sp.w)[i];
-        cb.id[e] = child_id(a.seed, pid, a.step, k, 0);
+        cb.id[e] = child_id(a.seed, pid, a.step, ctr, 0);
         cb.parent[e] = pid;
-        cb.tb[e] = t0 + (double)(k + 1) * st;
+        if constexpr (TB) cb.tb[e] = t0 + (double)(k + 1) * st;
         // gamma' = (1 - delta) gamma, same direction
         const R g1 = omx3 * g;
         const R u1 = sqrt_(fmax(g1 * g1 - R(1), R(0)));
@@ -369,7 +374,8 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
         // emission: stage the photon in the wave's LDS buffer, recoil on the parent
         const u64 m = __ballot(acc);
         if (m)
-            stage_emission<R>(a, sp, i, pid, k, acc, m, x3, omx3, g, u2, dx, dy, dz, ux, uy, uz, cb, nev, t0, st);
+            stage_emission<R>(a, sp, i, pid, k, k, acc, m, x3, omx3, g, u2, dx, dy, dz, ux, uy, uz, cb, nev, t0,
+                              st);
     }
     ((R *)sp.ux)[i] = ux;
     ((R *)sp.uy)[i] = uy;
@@ -457,7 +463,7 @@ constexpr int kResolveBatch = 16;
 template <int FK>
 __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i, uint32_t N,
                                                  const Lepton<float> &p, const SynTable<float> &tab, SurrLds &S,
-                                                 ChildBuf<float> &cb, Tally<float> &tl) {
+                                                 ChildBuf<float, false> &cb, Tally<float> &tl) {
     using R = float;
     const SpeciesDev &sp = a.sp[s];
     const bool has = N > 0;
@@ -484,8 +490,11 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
     uint32_t k = 0;     // next sub-step of this lane
     bool pend = false;  // an emission waits for its energy
     uint32_t pk = 0;    // its sub-step
-    R pchi = 0, pg = 1, pu2 = 0, pu = 0.5f;
-    double ptau = 1.0;  // the optical depth drawn for after it
+    // A pending lane keeps its momentum at the crossing, so chi, gamma and the rate
+    // there are recomputed when the emission is resolved instead of held.
+    R pu = 0.5f;         // the uniform of the emitted energy
+    double pover = 0.0;  // the optical depth's overshoot (<= 0) in the sub-step that crossed
+    double ptau = 1.0;   // the optical depth drawn for after the emission
     for (;;) {
         if (k < N && !pend) {
             boris<R, FK>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
@@ -497,15 +506,14 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
             dy += uy * vs;
             dz += uz * vs;
             const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
-            tau -= (double)(wk * rate_chi_q(chi, S.rate) * ig);
+            const R rw = rate_chi_q(chi, S.rate) * ig;
+            tau -= (double)(wk * rw);
             if (tau <= 0.0) {
                 const u32x4 w = philox10(idlo, idhi, a.step, j++, klo, khi);
                 pend = true;
                 pk = k;
-                pchi = chi;
-                pg = g;
-                pu2 = u2;
                 pu = u24(w.x);
+                pover = tau;
                 ptau = -log(u53(w.z, w.w));
             }
             ++k;
@@ -514,12 +522,21 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
         const u64 mr = __ballot(k < N && !pend);
         if (mp == 0 && mr == 0) break;
         if (mp == 0 || (__popcll(mp) < kResolveBatch && mr != 0)) continue;
+        // the pending lanes' state at the crossing
+        R cu2 = 0, cg = 1, cchi = 0, crw = 1;
+        if (pend) {
+            cu2 = ux * ux + uy * uy + uz * uz;
+            const R ig = rsqrt_(R(1) + cu2);
+            cg = (R(1) + cu2) * ig;
+            cchi = chi_sub<FK>(ux, uy, uz, cg, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
+            crw = rate_chi_q(cchi, S.rate) * ig;
+        }
         bool use_net = false;
         R sin = 0.0f;
         if (pend && S.have_model) {
             bool in_range;
             int bin;
-            sin = mlp_input_s(S.mlp, pchi, in_range, bin);
+            sin = mlp_input_s(S.mlp, cchi, in_range, bin);
             use_net = in_range && !S.mlp.fallback[bin];
         }
         R yv = 0.0f;
@@ -528,20 +545,38 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
         if (pend) {
             R x;
             if (use_net) {
-                x = mlp_x_of_y(yv, pchi);
+                x = mlp_x_of_y(yv, cchi);
                 tl.learned++;
             } else {
-                x = surr_reject(pchi, S, tab, idlo, idhi, a.step, klo, khi, j, tl);
+                x = surr_reject(cchi, S, tab, idlo, idhi, a.step, klo, khi, j, tl);
                 tl.fallback++;
             }
             const R x2 = x * x;
             x3 = x2 * x;
             omx3 = (R(1) - x) * (R(1) + x + x2);
-            tau = ptau;
         }
-        stage_emission<R>(a, sp, i, pid, pk, pend, mp, x3, omx3, pg, pu2, dx, dy, dz, ux, uy, uz, cb, nev, 0.0,
-                          st);
-        pend = false;
+        stage_emission<R>(a, sp, i, pid, nev, pk, pend, mp, x3, omx3, cg, cu2, dx, dy, dz, ux, uy, uz, cb, nev,
+                          0.0, st);
+        // The part of the sub-step after the crossing (the overshoot, at the rate before
+        // the emission) counts against the new optical depth at the rate after the
+        // recoil.  If that crosses it again, the particle emits again before moving on.
+        bool again = false;
+        if (pend) {
+            const R u2 = ux * ux + uy * uy + uz * uz;
+            const R ig = rsqrt_(R(1) + u2);
+            const R g = (R(1) + u2) * ig;
+            const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
+            const R rw = rate_chi_q(chi, S.rate) * ig;
+            tau = ptau + pover * (double)(rw / crw);
+            if (tau <= 0.0) {
+                const u32x4 w = philox10(idlo, idhi, a.step, j++, klo, khi);
+                pu = u24(w.x);
+                pover = tau;
+                ptau = -log(u53(w.z, w.w));
+                again = true;
+            }
+        }
+        pend = again;
     }
     if (has) {
         ((R *)sp.ux)[i] = ux;
@@ -574,7 +609,7 @@ template <>
 struct LeptonRunner<float, true> {
     template <class L>
     __device__ static void run(const StepArgs &a, int s, u64 i, uint32_t n, const Lepton<float> &p, L &lds,
-                               ChildBuf<float> &cb, Tally<float> &t, double = 0.0) {
+                               ChildBuf<float, false> &cb, Tally<float> &t, double = 0.0) {
         if (__ballot(n != 0) == 0) return;
         // one field kind for the whole wave (the general form is valid for all)
         const bool noB = p.bx == 0.0f && p.by == 0.0f && p.bz == 0.0f;
@@ -716,8 +751,8 @@ __device__ __forceinline__ int nbin(uint32_t N, uint32_t light_max) {
 // ---------------------------------------------------------------------------
 // End-of-kernel flush of all wave buffers of the block with one atomic: every
 // thread of the block must call it.
-template <class R>
-__device__ __forceinline__ void flush_children_block(ChildBuf<R> *cbs, const SpeciesDev &dst) {
+template <class R, bool TB>
+__device__ __forceinline__ void flush_children_block(ChildBuf<R, TB> *cbs, const SpeciesDev &dst) {
     __shared__ u64 base_sh;
     __shared__ uint32_t pre[kBlock / 64 + 1];
     __syncthreads();
@@ -735,7 +770,7 @@ __device__ __forceinline__ void flush_children_block(ChildBuf<R> *cbs, const Spe
     for (uint32_t e = threadIdx.x; e < total; e += kBlock) {
         int w = 0;
         while (w + 1 < kBlock / 64 && pre[w + 1] <= e) ++w;
-        const ChildBuf<R> &cb = cbs[w];
+        const ChildBuf<R, TB> &cb = cbs[w];
         const uint32_t k = e - pre[w];
         const u64 slot = base_sh + e;
         if (slot < dst.cap) {
@@ -748,7 +783,8 @@ __device__ __forceinline__ void flush_children_block(ChildBuf<R> *cbs, const Spe
             ((R *)dst.w)[slot] = cb.w[k];
             dst.id[slot] = cb.id[k];
             if (dst.parent) dst.parent[slot] = cb.parent[k];
-            if (dst.birth) dst.birth[slot] = cb.tb[k];
+            if constexpr (TB)
+                if (dst.birth) dst.birth[slot] = cb.tb[k];
         }
     }
 }
@@ -764,13 +800,13 @@ struct LeptonLds {
 template <>
 struct LeptonLds<float, true> {
     SynTable<float> tab;
-    ChildBuf<float> cb[kBlock / 64];
+    ChildBuf<float, false> cb[kBlock / 64];
     SurrLds surr;
 };
 
 template <class R, bool SURR>
-__device__ __forceinline__ ChildBuf<R> &lepton_lds_init(const StepArgs &a, LeptonLds<R, SURR> &L) {
-    ChildBuf<R> &cb = L.cb[threadIdx.x / 64];
+__device__ __forceinline__ auto &lepton_lds_init(const StepArgs &a, LeptonLds<R, SURR> &L) {
+    auto &cb = L.cb[threadIdx.x / 64];
     if (__lane_id() == 0) cb.count = 0;
     if constexpr (SURR) surr_stage(a, L.surr);
     syn_stage(L.tab);  // ends with a block barrier
@@ -796,7 +832,7 @@ __device__ __forceinline__ uint32_t lepton_fetch(const StepArgs &a, int s, u64 i
 template <class R, bool SURR>
 __global__ __launch_bounds__(kBlock) void k_lepton(StepArgs a) {
     __shared__ LeptonLds<R, SURR> L;
-    ChildBuf<R> &cb = lepton_lds_init<R, SURR>(a, L);
+    auto &cb = lepton_lds_init<R, SURR>(a, L);
     const int s = blockIdx.y;
     const u64 lo = a.st->lo[s], hi = a.st->hi[s];
     Tally<R> t;
@@ -853,29 +889,34 @@ __global__ void k_scan(StepArgs a) {
     }
 }
 
-// Heavy slots into their bins: block-local counts in LDS, one global atomic per
-// (block, bin), LDS ranks inside the block.
+// Heavy slots into their bins.  Each block takes one contiguous range of slots:
+// it counts the range's heavy particles per bin in LDS, reserves its segment of
+// every bin with one global atomic per (block, bin), and then places them, with
+// LDS ranks inside the segment (a second read of the range's counts).
 __global__ __launch_bounds__(kBlock) void k_scatter(StepArgs a) {
     __shared__ uint32_t cnt[kBins], base[kBins];
     const int s = blockIdx.y;
     const u64 n = a.st->n0[s];
-    for (u64 i0 = (u64)blockIdx.x * kBlock; i0 < n; i0 += (u64)gridDim.x * kBlock) {
-        for (int b = threadIdx.x; b < kBins; b += kBlock) cnt[b] = 0;
-        __syncthreads();
-        const u64 i = i0 + threadIdx.x;
-        int bin = 0;
-        uint32_t rank = 0;
-        if (i < n) {
-            const uint32_t N = a.nsub[s][i];
-            bin = N ? nbin(N, a.light_max) : 0;
-            if (bin) rank = atomicAdd(&cnt[bin], 1u);
-        }
-        __syncthreads();
-        for (int b = threadIdx.x; b < kBins; b += kBlock)
-            if (cnt[b]) base[b] = atomicAdd(&a.st->cursor[s][b], cnt[b]);
-        __syncthreads();
-        if (bin) a.queue[s][a.st->offset[s][bin] + base[bin] + rank] = (uint32_t)i;
-        __syncthreads();
+    const u64 per = ((n + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+    const u64 lo = (u64)blockIdx.x * per;
+    const u64 hi = lo + per < n ? lo + per : n;
+    for (int b = threadIdx.x; b < kBins; b += kBlock) cnt[b] = 0;
+    __syncthreads();
+    for (u64 i = lo + threadIdx.x; i < hi; i += kBlock) {
+        const uint32_t N = a.nsub[s][i];
+        const int bin = N ? nbin(N, a.light_max) : 0;
+        if (bin) atomicAdd(&cnt[bin], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBins; b += kBlock) {
+        base[b] = cnt[b] ? atomicAdd(&a.st->cursor[s][b], cnt[b]) + a.st->offset[s][b] : 0u;
+        cnt[b] = 0;
+    }
+    __syncthreads();
+    for (u64 i = lo + threadIdx.x; i < hi; i += kBlock) {
+        const uint32_t N = a.nsub[s][i];
+        const int bin = N ? nbin(N, a.light_max) : 0;
+        if (bin) a.queue[s][base[bin] + atomicAdd(&cnt[bin], 1u)] = (uint32_t)i;
     }
 }
 
@@ -892,7 +933,7 @@ __global__ __launch_bounds__(kBlock) void k_light(StepArgs a) {
     __shared__ LeptonLds<R, SURR> L;
     __shared__ uint32_t hist_sh[kBlock / 64][kTileKeys];
     __shared__ uint16_t order_sh[kBlock / 64][kTile];
-    ChildBuf<R> &cb = lepton_lds_init<R, SURR>(a, L);
+    auto &cb = lepton_lds_init<R, SURR>(a, L);
     const int s = blockIdx.y;
     const u64 n = a.st->n0[s];
     const uint32_t lmax = a.light_max;
@@ -957,7 +998,7 @@ __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
     __shared__ uint32_t hist_sh[kBlock / 64][kTileKeys];
     __shared__ uint16_t order_sh[kBlock / 64][kTiledSlots];
     __shared__ uint32_t nsub_sh[kBlock / 64][kTiledSlots];
-    ChildBuf<R> &cb = lepton_lds_init<R, SURR>(a, L);
+    auto &cb = lepton_lds_init<R, SURR>(a, L);
     const int s = blockIdx.y;
     const u64 n = a.st->n0[s];
     const uint32_t lane = __lane_id();
@@ -1016,7 +1057,7 @@ __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
 template <class R, bool SURR>
 __global__ __launch_bounds__(kBlock, 3) void k_heavy(StepArgs a) {
     __shared__ LeptonLds<R, SURR> L;
-    ChildBuf<R> &cb = lepton_lds_init<R, SURR>(a, L);
+    auto &cb = lepton_lds_init<R, SURR>(a, L);
     const int s = blockIdx.y;
     const u64 H = a.st->heavy[s];
     const uint32_t chunk = a.chunk;

@@ -43,7 +43,8 @@ class qed_config(C.Structure):
     _fields_ = [("device", C.c_int), ("stream", C.c_void_p), ("precision", C.c_int),
                 ("p_max", C.c_double), ("emission", C.c_int), ("pairs", C.c_int),
                 ("scheduler", C.c_int), ("pair_bound_coef", C.c_double),
-                ("max_substeps", C.c_uint32), ("sampler", C.c_int), ("cascade_generations", C.c_uint32)]
+                ("max_substeps", C.c_uint32), ("sampler", C.c_int), ("cascade_generations", C.c_uint32),
+                ("surrogate_p_max", C.c_double)]
 
 
 class qed_report(C.Structure):
@@ -406,7 +407,7 @@ class Generator:
     def __init__(self, precision=QED_PREC_MIXED, capacity=(1 << 20, 1 << 20, 1 << 20), emission=True,
                  pairs=True, p_max=0.01, scheduler=QED_SCHED_NAIVE, pair_bound_coef=0.1,
                  max_substeps=1 << 24, device=0, stream=None, parent=True, events=True,
-                 sampler=QED_SAMPLER_REJECTION, cascade_generations=0):
+                 sampler=QED_SAMPLER_REJECTION, cascade_generations=0, surrogate_p_max=0.1):
         torch = _torch()
         self.real = torch.float64 if precision == QED_PREC_F64 else torch.float32
         self.precision = precision
@@ -422,6 +423,7 @@ class Generator:
         cfg.max_substeps = max_substeps
         cfg.sampler = sampler
         cfg.cascade_generations = cascade_generations
+        cfg.surrogate_p_max = surrogate_p_max
         self.cfg = cfg
         self.ctx = qed_init(cfg)
         surr = sampler == QED_SAMPLER_SURROGATE
