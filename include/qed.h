@@ -199,6 +199,15 @@ QED_API qed_status qed_init(qed_ctx **ctx, const qed_config *cfg);
 QED_API qed_status qed_step(qed_ctx *ctx, qed_particles *p, const qed_field fields[3], double dt,
                             uint64_t seed, uint32_t step);
 
+/* qed_step with a device-side step counter (the random streams are keyed by the
+ * step number, Sec. 2.2's per-particle draws): step is a DEVICE pointer to one
+ * uint32; the step reads its number there when it runs and adds one at its end.
+ * A graph that records one such call (qed_graph_*) and is replayed K times thus
+ * runs steps s, s+1, ..., s+K-1, as K eager qed_step calls would.  The caller
+ * owns the counter; NULL: QED_ERR_INVALID_ARG.  Otherwise as qed_step. */
+QED_API qed_status qed_step_counted(qed_ctx *ctx, qed_particles *p, const qed_field fields[3], double dt,
+                                    uint64_t seed, uint32_t *step);
+
 /* Wait for the context's stream; fill *rep (may be NULL) and return its status.
  * Clears the sticky device status. */
 QED_API qed_status qed_sync(qed_ctx *ctx, qed_report *rep);

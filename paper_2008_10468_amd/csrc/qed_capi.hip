@@ -230,6 +230,110 @@ void init_params(float *p, uint64_t seed) {
 
 }  // namespace
 
+namespace {
+
+qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], double dt, uint64_t seed,
+                     uint32_t step, uint32_t *step_dev) {
+    if (!c || !p || !fields) return QED_ERR_INVALID_ARG;
+    if (!(dt > 0.0) || !isfinite(dt)) return QED_ERR_INVALID_ARG;
+    const bool emission = c->cfg.emission != 0, pairs = c->cfg.pairs != 0;
+    const qed_species *sp[3] = {&p->electrons, &p->positrons, &p->photons};
+    // every species that can be read or appended to must be complete
+    const bool need[3] = {emission || pairs, emission || pairs, emission || pairs};
+    for (int s = 0; s < 3; ++s) {
+        if (!need[s]) continue;
+        if (!species_ok(*sp[s])) return QED_ERR_INVALID_ARG;
+    }
+    if (emission && (!field_ok(fields[0]) || !field_ok(fields[1]))) return QED_ERR_INVALID_ARG;
+    const bool surrogate = c->cfg.sampler == QED_SAMPLER_SURROGATE;
+    if (surrogate && emission && (!sp[0]->tau || !sp[1]->tau)) return QED_ERR_INVALID_ARG;
+    if (pairs && !field_ok(fields[2])) return QED_ERR_INVALID_ARG;
+    const uint32_t gens = c->cfg.cascade_generations;
+    if (gens > 0) {
+        for (int s = 0; s < 3; ++s)
+            if (need[s] && !sp[s]->birth) return QED_ERR_INVALID_ARG;
+        for (int s = 0; s < 3; ++s)
+            if ((s < 2 ? emission : pairs) && fields[s].stride != 0) return QED_ERR_INVALID_ARG;
+    }
+    const bool binned = c->cfg.scheduler == QED_SCHED_BINNED && emission;
+    if (binned && (sp[0]->capacity > 0xFFFFFFFFull || sp[1]->capacity > 0xFFFFFFFFull))
+        return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    if (pairs) {
+        qed_status r = ensure_photon_scratch(c, sp[2]->capacity > 0 ? sp[2]->capacity : 1);
+        if (r != QED_OK) return r;
+    }
+    if (binned) {
+        for (int s = 0; s < 2; ++s) {
+            qed_status r = ensure_lepton_scratch(c, s, sp[s]->capacity > 0 ? sp[s]->capacity : 1);
+            if (r != QED_OK) return r;
+        }
+    }
+    qed::StepArgs a;
+    memset(&a, 0, sizeof(a));
+    for (int s = 0; s < 3; ++s) {
+        a.sp[s] = to_dev(*sp[s]);
+        if (gens > 0) a.sp[s].birth = sp[s]->birth;
+        a.fl[s] = to_dev(fields[s]);
+        c->last_n[s] = a.sp[s].n;
+    }
+    a.st = c->st;
+    a.dt = dt;
+    a.p_max = c->cfg.p_max;
+    a.p_max_lep = surrogate ? c->cfg.surrogate_p_max : c->cfg.p_max;
+    a.pair_coef = c->cfg.pair_bound_coef;
+    a.seed = seed;
+    a.step = step;
+    a.step_dev = step_dev;
+    a.max_sub = c->cfg.max_substeps;
+    a.emission = emission;
+    a.pairs = pairs;
+    a.light_max = c->tune.light_max;
+    a.chunk = c->tune.chunk;
+    a.alive = c->alive;
+    a.dead_idx = c->dead_idx;
+    a.hole_idx = c->hole_idx;
+    a.mover_idx = c->mover_idx;
+    for (int s = 0; s < 2; ++s) {
+        a.nsub[s] = c->nsub[s];
+        a.queue[s] = c->queue[s];
+    }
+    a.sampler = surrogate ? 1 : 0;
+    a.model = c->have_model ? c->model : nullptr;
+    const u64 lep_cap = sp[0]->capacity > sp[1]->capacity ? sp[0]->capacity : sp[1]->capacity;
+    const int lepton_blocks = grid_for(lep_cap, c->num_cu * (int)c->tune.lepton_blocks_per_cu);
+    const int heavy_blocks = c->num_cu * (int)c->tune.heavy_blocks_per_cu;
+    const int photon_blocks = grid_for(sp[2]->capacity, c->num_cu * (int)c->tune.photon_blocks_per_cu);
+    const int aux_blocks = grid_for(sp[2]->capacity, c->num_cu * 4);
+    const int prec = c->cfg.precision == QED_PREC_F64 ? 0 : 1;
+    hipError_t r = launch(c, qed::K_BEGIN, a, prec, 1);
+    if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON, a, prec, photon_blocks);
+    const bool tiled = c->cfg.scheduler == QED_SCHED_TILED;
+    if (r == hipSuccess && emission && !binned)
+        r = launch(c, tiled ? qed::K_TILED : qed::K_LEPTON, a, prec, lepton_blocks);
+    if (binned) {
+        if (r == hipSuccess) r = launch(c, qed::K_PREPASS, a, prec, lepton_blocks);
+        if (r == hipSuccess) r = launch(c, qed::K_SCAN, a, prec, 1);
+        if (r == hipSuccess) r = launch(c, qed::K_SCATTER, a, prec, lepton_blocks);
+        if (r == hipSuccess) r = launch(c, qed::K_LIGHT, a, prec, lepton_blocks);
+        if (r == hipSuccess) r = launch(c, qed::K_HEAVY, a, prec, heavy_blocks);
+    }
+    // cascade passes: the particles of the previous pass, from their birth time
+    for (uint32_t g = 1; g <= gens && r == hipSuccess; ++g) {
+        a.gen = g;
+        r = launch(c, qed::K_GEN, a, prec, 1);
+        if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON, a, prec, photon_blocks);
+        if (r == hipSuccess && emission) r = launch(c, qed::K_LEPTON, a, prec, lepton_blocks);
+    }
+    a.gen = 0;
+    if (r == hipSuccess) r = launch(c, qed::K_END, a, prec, 1);
+    if (r == hipSuccess && pairs) r = launch(c, qed::K_FILL, a, prec, aux_blocks);
+    if (r == hipSuccess && pairs) r = launch(c, qed::K_MOVE, a, prec, aux_blocks);
+    return r == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
+}  // namespace
+
 extern "C" {
 
 qed_status qed_config_default(qed_config *cfg) {
@@ -298,101 +402,13 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
 
 qed_status qed_step(qed_ctx *c, qed_particles *p, const qed_field fields[3], double dt, uint64_t seed,
                     uint32_t step) {
-    if (!c || !p || !fields) return QED_ERR_INVALID_ARG;
-    if (!(dt > 0.0) || !isfinite(dt)) return QED_ERR_INVALID_ARG;
-    const bool emission = c->cfg.emission != 0, pairs = c->cfg.pairs != 0;
-    const qed_species *sp[3] = {&p->electrons, &p->positrons, &p->photons};
-    // every species that can be read or appended to must be complete
-    const bool need[3] = {emission || pairs, emission || pairs, emission || pairs};
-    for (int s = 0; s < 3; ++s) {
-        if (!need[s]) continue;
-        if (!species_ok(*sp[s])) return QED_ERR_INVALID_ARG;
-    }
-    if (emission && (!field_ok(fields[0]) || !field_ok(fields[1]))) return QED_ERR_INVALID_ARG;
-    const bool surrogate = c->cfg.sampler == QED_SAMPLER_SURROGATE;
-    if (surrogate && emission && (!sp[0]->tau || !sp[1]->tau)) return QED_ERR_INVALID_ARG;
-    if (pairs && !field_ok(fields[2])) return QED_ERR_INVALID_ARG;
-    const uint32_t gens = c->cfg.cascade_generations;
-    if (gens > 0) {
-        for (int s = 0; s < 3; ++s)
-            if (need[s] && !sp[s]->birth) return QED_ERR_INVALID_ARG;
-        for (int s = 0; s < 3; ++s)
-            if ((s < 2 ? emission : pairs) && fields[s].stride != 0) return QED_ERR_INVALID_ARG;
-    }
-    const bool binned = c->cfg.scheduler == QED_SCHED_BINNED && emission;
-    if (binned && (sp[0]->capacity > 0xFFFFFFFFull || sp[1]->capacity > 0xFFFFFFFFull))
-        return QED_ERR_INVALID_ARG;
-    HIP_TRY(hipSetDevice(c->cfg.device));
-    if (pairs) {
-        qed_status r = ensure_photon_scratch(c, sp[2]->capacity > 0 ? sp[2]->capacity : 1);
-        if (r != QED_OK) return r;
-    }
-    if (binned) {
-        for (int s = 0; s < 2; ++s) {
-            qed_status r = ensure_lepton_scratch(c, s, sp[s]->capacity > 0 ? sp[s]->capacity : 1);
-            if (r != QED_OK) return r;
-        }
-    }
-    qed::StepArgs a;
-    memset(&a, 0, sizeof(a));
-    for (int s = 0; s < 3; ++s) {
-        a.sp[s] = to_dev(*sp[s]);
-        if (gens > 0) a.sp[s].birth = sp[s]->birth;
-        a.fl[s] = to_dev(fields[s]);
-        c->last_n[s] = a.sp[s].n;
-    }
-    a.st = c->st;
-    a.dt = dt;
-    a.p_max = c->cfg.p_max;
-    a.p_max_lep = surrogate ? c->cfg.surrogate_p_max : c->cfg.p_max;
-    a.pair_coef = c->cfg.pair_bound_coef;
-    a.seed = seed;
-    a.step = step;
-    a.max_sub = c->cfg.max_substeps;
-    a.emission = emission;
-    a.pairs = pairs;
-    a.light_max = c->tune.light_max;
-    a.chunk = c->tune.chunk;
-    a.alive = c->alive;
-    a.dead_idx = c->dead_idx;
-    a.hole_idx = c->hole_idx;
-    a.mover_idx = c->mover_idx;
-    for (int s = 0; s < 2; ++s) {
-        a.nsub[s] = c->nsub[s];
-        a.queue[s] = c->queue[s];
-    }
-    a.sampler = surrogate ? 1 : 0;
-    a.model = c->have_model ? c->model : nullptr;
-    const u64 lep_cap = sp[0]->capacity > sp[1]->capacity ? sp[0]->capacity : sp[1]->capacity;
-    const int lepton_blocks = grid_for(lep_cap, c->num_cu * (int)c->tune.lepton_blocks_per_cu);
-    const int heavy_blocks = c->num_cu * (int)c->tune.heavy_blocks_per_cu;
-    const int photon_blocks = grid_for(sp[2]->capacity, c->num_cu * (int)c->tune.photon_blocks_per_cu);
-    const int aux_blocks = grid_for(sp[2]->capacity, c->num_cu * 4);
-    const int prec = c->cfg.precision == QED_PREC_F64 ? 0 : 1;
-    hipError_t r = launch(c, qed::K_BEGIN, a, prec, 1);
-    if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON, a, prec, photon_blocks);
-    const bool tiled = c->cfg.scheduler == QED_SCHED_TILED;
-    if (r == hipSuccess && emission && !binned)
-        r = launch(c, tiled ? qed::K_TILED : qed::K_LEPTON, a, prec, lepton_blocks);
-    if (binned) {
-        if (r == hipSuccess) r = launch(c, qed::K_PREPASS, a, prec, lepton_blocks);
-        if (r == hipSuccess) r = launch(c, qed::K_SCAN, a, prec, 1);
-        if (r == hipSuccess) r = launch(c, qed::K_SCATTER, a, prec, lepton_blocks);
-        if (r == hipSuccess) r = launch(c, qed::K_LIGHT, a, prec, lepton_blocks);
-        if (r == hipSuccess) r = launch(c, qed::K_HEAVY, a, prec, heavy_blocks);
-    }
-    // cascade passes: the particles of the previous pass, from their birth time
-    for (uint32_t g = 1; g <= gens && r == hipSuccess; ++g) {
-        a.gen = g;
-        r = launch(c, qed::K_GEN, a, prec, 1);
-        if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON, a, prec, photon_blocks);
-        if (r == hipSuccess && emission) r = launch(c, qed::K_LEPTON, a, prec, lepton_blocks);
-    }
-    a.gen = 0;
-    if (r == hipSuccess) r = launch(c, qed::K_END, a, prec, 1);
-    if (r == hipSuccess && pairs) r = launch(c, qed::K_FILL, a, prec, aux_blocks);
-    if (r == hipSuccess && pairs) r = launch(c, qed::K_MOVE, a, prec, aux_blocks);
-    return r == hipSuccess ? QED_OK : QED_ERR_HIP;
+    return step_impl(c, p, fields, dt, seed, step, nullptr);
+}
+
+qed_status qed_step_counted(qed_ctx *c, qed_particles *p, const qed_field fields[3], double dt, uint64_t seed,
+                            uint32_t *step) {
+    if (!step) return QED_ERR_INVALID_ARG;
+    return step_impl(c, p, fields, dt, seed, 0, step);
 }
 
 qed_status qed_sync(qed_ctx *c, qed_report *rep) {

@@ -92,7 +92,11 @@ struct StepArgs {
     const MlpModel *model; // surrogate: installed network (nullptr: rejection for every chi)
     uint32_t gen;          // 0: main pass; g >= 1: cascade pass g over DevState's lo..hi,
                            // each particle starting at its birth time
+    uint32_t *step_dev;    // non-null: the step number is *step_dev (k_end increments it)
 };
+
+// The step number of the random streams and child ids.
+__device__ __forceinline__ uint32_t step_of(const StepArgs &a) { return a.step_dev ? *a.step_dev : a.step; }
 
 // Kernels, in launch order, and the standalone synchrotron kernel.
 enum KernelId {

@@ -289,7 +289,7 @@ __device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesD
                                                uint32_t ctr, uint32_t k, bool acc, u64 m, R x3, R omx3, R g,
                                                R u2, R dx,
                                                R dy, R dz, R &ux, R &uy, R &uz, ChildBuf<R, TB> &cb,
-                                               uint32_t &nev, double t0, double st) {
+                                               uint32_t &nev, double t0, double st, uint32_t step) {
     const uint32_t c = (uint32_t)__popcll(m);
     __syncwarp();
     if (cb.count + c > 64) flush_children(cb, a.sp[2]);
@@ -306,7 +306,7 @@ __device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesD
         cb.py[e] = uy * eph;
         cb.pz[e] = uz * eph;
         cb.w[e] = ((const R *)sp.w)[i];
-        cb.id[e] = child_id(a.seed, pid, a.step, ctr, 0);
+        cb.id[e] = child_id(a.seed, pid, step, ctr, 0);
         cb.parent[e] = pid;
         if constexpr (TB) cb.tb[e] = t0 + (double)(k + 1) * st;
         // gamma' = (1 - delta) gamma, same direction
@@ -340,6 +340,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
     const R kcb = (R)(1.5 * kSqrt3 * kAlpha / kPi * st);
     const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
     const uint32_t klo = (uint32_t)a.seed, khi = (uint32_t)(a.seed >> 32);
+    const uint32_t step = step_of(a);
     R ux = p.ux, uy = p.uy, uz = p.uz;
     R dx = 0, dy = 0, dz = 0;
     uint32_t nev = 0;
@@ -358,7 +359,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
         const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
         // candidate x and test value y
         R x, y;
-        draw.get(k, idlo, idhi, a.step, klo, khi, x, y);
+        draw.get(k, idlo, idhi, step, klo, khi, x, y);
         // acceptance (eq. (1)): y < 3 x^2 P(x^3) = (c b / x) ((1 - x^3) F(z) + x^6 G(z)),
         //         z = x^3 / (b (1 - x^3))
         const R x2 = x * x, x3 = x2 * x;
@@ -375,7 +376,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
         const u64 m = __ballot(acc);
         if (m)
             stage_emission<R>(a, sp, i, pid, k, k, acc, m, x3, omx3, g, u2, dx, dy, dz, ux, uy, uz, cb, nev, t0,
-                              st);
+                              st, step);
     }
     ((R *)sp.ux)[i] = ux;
     ((R *)sp.uy)[i] = uy;
@@ -477,11 +478,12 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
     const R wk = (R)(kAlpha * st);
     const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
     const uint32_t klo = (uint32_t)a.seed ^ kSurrTagLo, khi = (uint32_t)(a.seed >> 32) ^ kSurrTagHi;
+    const uint32_t step = step_of(a);
     MlpWave &ws = S.ws[threadIdx.x / 64];
     uint32_t j = 0;
     double tau = has ? sp.tau[i] : 1.0;
     if (has && !(tau > 0.0)) {
-        const u32x4 w = philox10(idlo, idhi, a.step, j++, klo, khi);
+        const u32x4 w = philox10(idlo, idhi, step, j++, klo, khi);
         tau = -log(u53(w.x, w.y));
     }
     R ux = p.ux, uy = p.uy, uz = p.uz;
@@ -509,7 +511,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
             const R rw = rate_chi_q(chi, S.rate) * ig;
             tau -= (double)(wk * rw);
             if (tau <= 0.0) {
-                const u32x4 w = philox10(idlo, idhi, a.step, j++, klo, khi);
+                const u32x4 w = philox10(idlo, idhi, step, j++, klo, khi);
                 pend = true;
                 pk = k;
                 pu = u24(w.x);
@@ -548,7 +550,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
                 x = mlp_x_of_y(yv, cchi);
                 tl.learned++;
             } else {
-                x = surr_reject(cchi, S, tab, idlo, idhi, a.step, klo, khi, j, tl);
+                x = surr_reject(cchi, S, tab, idlo, idhi, step, klo, khi, j, tl);
                 tl.fallback++;
             }
             const R x2 = x * x;
@@ -556,7 +558,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
             omx3 = (R(1) - x) * (R(1) + x + x2);
         }
         stage_emission<R>(a, sp, i, pid, nev, pk, pend, mp, x3, omx3, cg, cu2, dx, dy, dz, ux, uy, uz, cb, nev,
-                          0.0, st);
+                          0.0, st, step);
         // The part of the sub-step after the crossing (the overshoot, at the rate before
         // the emission) counts against the new optical depth at the rate after the
         // recoil.  If that crosses it again, the particle emits again before moving on.
@@ -569,7 +571,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
             const R rw = rate_chi_q(chi, S.rate) * ig;
             tau = ptau + pover * (double)(rw / crw);
             if (tau <= 0.0) {
-                const u32x4 w = philox10(idlo, idhi, a.step, j++, klo, khi);
+                const u32x4 w = philox10(idlo, idhi, step, j++, klo, khi);
                 pu = u24(w.x);
                 pover = tau;
                 ptau = -log(u53(w.z, w.w));
@@ -653,6 +655,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
     const uint64_t pid = sp.id[i];
     const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
     const uint32_t klo = (uint32_t)a.seed, khi = (uint32_t)(a.seed >> 32);
+    const uint32_t step = step_of(a);
     R dx = 0, dy = 0, dz = 0;
     bool dead = false;
     uint32_t used = 0;
@@ -665,7 +668,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
         dz += dirz * str;
         // candidate x, test value y, acceptance against eq. (2)
         R x, y;
-        draw.get(k, idlo, idhi, a.step, klo, khi, x, y);
+        draw.get(k, idlo, idhi, step, klo, khi, x, y);
         const R xx = x * (R(1) - x);
         const R z = R(2.0 / 3.0) * rcp(chir * xx);
         R F, G;
@@ -707,7 +710,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
                     ((R *)el.uy)[j] = ue * diry;
                     ((R *)el.uz)[j] = ue * dirz;
                     ((R *)el.w)[j] = w;
-                    el.id[j] = child_id(a.seed, pid, a.step, k, 0);
+                    el.id[j] = child_id(a.seed, pid, step, k, 0);
                     if (el.parent) el.parent[j] = pid;
                     if (el.tau) el.tau[j] = -1.0;
                     if (el.birth) el.birth[j] = tb;
@@ -721,7 +724,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
                     ((R *)po.uy)[j] = up * diry;
                     ((R *)po.uz)[j] = up * dirz;
                     ((R *)po.w)[j] = w;
-                    po.id[j] = child_id(a.seed, pid, a.step, k, 1);
+                    po.id[j] = child_id(a.seed, pid, step, k, 1);
                     if (po.parent) po.parent[j] = pid;
                     if (po.tau) po.tau[j] = -1.0;
                     if (po.birth) po.birth[j] = tb;
@@ -1291,6 +1294,7 @@ __global__ void k_end(StepArgs a) {
         st->holes = 0;
         st->movers = 0;
         st->steps += 1;
+        if (a.step_dev) *a.step_dev += 1u;
     }
 }
 

@@ -86,7 +86,7 @@ EXPORTS = ("qed_config_default", "qed_init", "qed_step", "qed_sync", "qed_synchr
            "qed_get_stats", "qed_reset_stats", "qed_get_tuning", "qed_set_tuning",
            "qed_profile_enable", "qed_profile_read", "qed_graph_begin", "qed_graph_end",
            "qed_graph_launch", "qed_graph_destroy",
-           "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
+           "qed_step_counted", "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
            "qed_train_config_default", "qed_train_sampler", "qed_mlp_gradient",
            "qed_finalize", "qed_status_string")
 
@@ -105,6 +105,8 @@ def load(path: str = LIB_PATH):
     L.qed_init.argtypes = [C.POINTER(C.c_void_p), C.POINTER(qed_config)]
     L.qed_step.argtypes = [C.c_void_p, C.POINTER(qed_particles), C.POINTER(qed_field), C.c_double,
                            C.c_uint64, C.c_uint32]
+    L.qed_step_counted.argtypes = [C.c_void_p, C.POINTER(qed_particles), C.POINTER(qed_field), C.c_double,
+                                   C.c_uint64, C.c_void_p]
     L.qed_sync.argtypes = [C.c_void_p, C.POINTER(qed_report)]
     L.qed_synchrotron.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int]
     L.qed_get_stats.argtypes = [C.c_void_p, C.POINTER(qed_stats)]
@@ -170,6 +172,12 @@ def qed_init(cfg):
 def qed_step(ctx, particles, fields, dt, seed, step):
     arr = (qed_field * 3)(*fields)
     return load().qed_step(ctx, C.byref(particles), arr, float(dt), int(seed), int(step))
+
+
+def qed_step_counted(ctx, particles, fields, dt, seed, step_ptr):
+    """step_ptr: device address of a uint32 step counter."""
+    arr = (qed_field * 3)(*fields)
+    return load().qed_step_counted(ctx, C.byref(particles), arr, float(dt), int(seed), step_ptr)
 
 
 def qed_sync(ctx):
