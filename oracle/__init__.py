@@ -106,6 +106,8 @@ def lib():
             L.orc_emission_energy.restype = C.c_double
             L.orc_emission_cdf.argtypes = [C.c_double] * 2
             L.orc_emission_cdf.restype = C.c_double
+            L.orc_pair_cdf.argtypes = [C.c_double] * 2
+            L.orc_pair_cdf.restype = C.c_double
             L.orc_pair_prob.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int]
             L.orc_pair_prob.restype = C.c_double
             fld = C.POINTER(_D)
@@ -237,6 +239,11 @@ def emission_cdf(chi, delta):
 
 def pair_prob(chi_g, eps_g, dt, clip=False):
     return lib().orc_pair_prob(chi_g, eps_g, dt, int(clip))
+
+
+def pair_cdf(chi_g, x):
+    """Normalised CDF of the electron's energy fraction x in pair creation (eq. (2))."""
+    return lib().orc_pair_cdf(chi_g, x)
 
 
 # ---------------------------------------------------------------- batch steps

@@ -661,6 +661,17 @@ double orc_pair_prob(double chi_g, double eps_g, double dt, int clip)
     return integrate01(clip ? f_pp_clip : f_pp, par, 0.0, 1.0, 1e-13);
 }
 
+/* Normalised energy-split CDF of pair creation (eq. (2)): the probability that the
+ * electron takes an energy fraction below x, int_0^x P_p / int_0^1 P_p. */
+double orc_pair_cdf(double chi_g, double x)
+{
+    double par[3] = {chi_g, 1.0, 1.0};
+    if (x <= 0.0) return 0.0;
+    if (x >= 1.0) return 1.0;
+    double tot = integrate01(f_pp, par, 0.0, 1.0, 1e-13);
+    return integrate01(f_pp, par, 0.0, x, 1e-13) / tot;
+}
+
 /* Vectorised helpers for the Python side. */
 void orc_synchrotron_vec(int64_t n, const double *x, double *F, double *G)
 {

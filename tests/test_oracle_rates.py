@@ -94,6 +94,33 @@ def test_pair_total_small_chi(orc):
         prev = err
 
 
+@pytest.mark.parametrize("chi_g", [0.7, 8.0])
+def test_pair_cdf_against_baier_katkov_quadrature(orc, chi_g):
+    """The energy-split CDF of pair creation equals the normalised integral of the
+    Baier-Katkov spectrum, by SciPy quadrature of Bessel functions (no oracle code)."""
+    def bk(d):
+        xi = 2.0 / (3.0 * chi_g * d * (1 - d))
+        return (d * d + (1 - d) ** 2) / (d * (1 - d)) * special.kv(2.0 / 3.0, xi) + int_K(1.0 / 3.0, xi)
+    tot = 2 * integrate.quad(bk, 1e-12, 0.5, epsrel=1e-11, limit=200)[0]
+    for x in (0.05, 0.2, 0.41, 0.5):
+        ref = integrate.quad(bk, 1e-12, x, epsrel=1e-11, limit=200)[0] / tot
+        assert abs(orc.pair_cdf(chi_g, x) - ref) < 1e-9, (x, orc.pair_cdf(chi_g, x), ref)
+
+
+def test_pair_cdf_symmetric_and_gaussian_at_small_chi(orc):
+    """The split is symmetric, C(x) + C(1 - x) = 1; at small chi_g it is Gaussian around 1/2
+    with variance 3 chi_g / 64 (Laplace's method on e^{-z}, z = 2/(3 chi_g x (1 - x)))."""
+    for chi in (0.3, 3.0, 40.0):
+        for x in (0.03, 0.25, 0.45):
+            assert abs(orc.pair_cdf(chi, x) + orc.pair_cdf(chi, 1 - x) - 1) < 1e-12
+        assert abs(orc.pair_cdf(chi, 0.5) - 0.5) < 1e-12
+    chi = 0.004
+    sig = math.sqrt(3 * chi / 64)
+    for k in (0.5, 1.0, 2.0):
+        phi = 0.5 * (1 + math.erf(k / math.sqrt(2)))
+        assert abs(orc.pair_cdf(chi, 0.5 + k * sig) - phi) < 0.02, (k, orc.pair_cdf(chi, 0.5 + k * sig), phi)
+
+
 def test_emission_bound_is_upper_bound(orc):
     """f(b) of Sec. 3.1.1 exceeds the exact per-step probability for b in [1e-4, 1e3]."""
     gamma, dt = 1e4, 1.0
