@@ -90,10 +90,12 @@ typedef struct qed_species {
     uint64_t *parent;   /* optional (NULL): id of the parent, written for new particles */
     uint32_t *events;   /* optional (NULL): events of each pre-existing particle in the
                            last step (emissions of a lepton; 1 if a photon decayed) */
-    double *tau;        /* electrons and positrons with QED_SAMPLER_SURROGATE (required
-                           there, ignored otherwise): optical depth left until the next
-                           emission; a value <= 0 or NaN makes the particle draw a fresh
-                           one.  New pairs get -1. */
+    double *tau;        /* optical depth left until the next event: electrons and
+                           positrons with sampler QED_SAMPLER_SURROGATE, photons with
+                           pair_sampler QED_SAMPLER_SURROGATE (required there, ignored
+                           otherwise); a value <= 0 or NaN makes the particle draw a
+                           fresh one.  Particles the library creates get -1, and the
+                           value moves with a photon when the buffer is compacted. */
     double *birth;      /* with cascade_generations > 0 (required there, ignored
                            otherwise): written for every particle appended in a step,
                            the time within the step (0 .. dt) at which it was created,
@@ -144,6 +146,15 @@ typedef struct qed_config {
                            optical depth, the rest of the sub-step's integrated rate counts
                            against it, and while it is still crossed the particle emits
                            again, so no emission is lost or deferred. */
+    int pair_sampler;       /* qed_sampler for pair creation; QED_SAMPLER_REJECTION:
+                           Algorithm 2 with sub-steps.  QED_SAMPLER_SURROGATE (mixed
+                           precision, no cascades; photons need tau): in the frozen field
+                           of a step a photon's chi and energy are constant, so with the
+                           total rate W = alpha (chi / eps) T(chi) (eq. (2) integrated over
+                           the energy split, a fit) it decays at t = tau / W if that falls
+                           inside the step, else tau -= W dt; no sub-steps.  The split is
+                           drawn from eq. (2) at that chi by rejection.  Photons then run
+                           one pass with no sub-step loop. */
 } qed_config;
 
 /* Errors and counts observed on the device since the previous qed_sync. */
@@ -174,6 +185,10 @@ typedef struct qed_stats {
     uint64_t fallback_events; /* surrogate: energies drawn by rejection */
     uint64_t fallback_draws;  /* surrogate: candidates those rejections used */
     uint64_t envelope_clips;  /* surrogate: candidates above the rejection envelope */
+    uint64_t pair_learned;    /* photon optical-depth path: energy splits from the network, */
+    uint64_t pair_fallback;   /* by rejection, */
+    uint64_t pair_fallback_draws;  /* the candidates those rejections used */
+    uint64_t pair_envelope_clips;  /* and the candidates above the envelope */
 } qed_stats;
 
 typedef struct qed_ctx qed_ctx;
@@ -306,6 +321,13 @@ QED_API qed_status qed_sampler_infer(qed_ctx *ctx, const float *chi, const float
  * sub-step of length s is alpha s chi q(chi) / gamma, i.e. eq. (1) integrated
  * over the candidate x in [0, 1] (from the fit the generator uses). */
 QED_API qed_status qed_emission_rate(qed_ctx *ctx, const float *chi, float *chi_q, uint64_t n);
+
+/* Total pair-creation rate of the photon optical-depth path: for n float values
+ * chi (DEVICE), writes T(chi) (DEVICE) such that a photon of energy eps decays in a
+ * time s with probability alpha s (chi / eps) T(chi) for small s, i.e. eq. (2)
+ * integrated over the energy split (from the fit the generator uses; 0 below
+ * chi ~ 0.03, where the value underflows). */
+QED_API qed_status qed_pair_rate(qed_ctx *ctx, const float *chi, float *T, uint64_t n);
 
 /* The normalised CDF of eq. (1) over the candidate x, as the trainer tabulates it
  * (double, from the double fits of F and G, trapezoid rule): nchi (>= 2) values

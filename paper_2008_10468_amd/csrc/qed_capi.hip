@@ -139,7 +139,7 @@ bool tuning_ok(const qed_tuning &t) {
 const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_prepass",
                                          "k_scan",  "k_scatter", "k_light", "k_heavy",
                                          "k_end",   "k_fill",   "k_move",  "k_synchrotron", "k_tiled",
-                                         "k_gen"};
+                                         "k_gen", "k_photon_surr"};
 
 // Event pair for one profiled launch (grown on demand, reused after a read).
 bool prof_pair(qed_ctx *c, int id, hipEvent_t *a, hipEvent_t *b) {
@@ -248,6 +248,8 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     const bool surrogate = c->cfg.sampler == QED_SAMPLER_SURROGATE;
     if (surrogate && emission && (!sp[0]->tau || !sp[1]->tau)) return QED_ERR_INVALID_ARG;
     if (pairs && !field_ok(fields[2])) return QED_ERR_INVALID_ARG;
+    const bool pair_surr = pairs && c->cfg.pair_sampler == QED_SAMPLER_SURROGATE;
+    if (pair_surr && !sp[2]->tau) return QED_ERR_INVALID_ARG;
     const uint32_t gens = c->cfg.cascade_generations;
     if (gens > 0) {
         for (int s = 0; s < 3; ++s)
@@ -274,6 +276,7 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     for (int s = 0; s < 3; ++s) {
         a.sp[s] = to_dev(*sp[s]);
         if (gens > 0) a.sp[s].birth = sp[s]->birth;
+        if (s == 2 && !pair_surr) a.sp[s].tau = nullptr;  // photons carry tau on that path only
         a.fl[s] = to_dev(fields[s]);
         c->last_n[s] = a.sp[s].n;
     }
@@ -307,7 +310,7 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     const int aux_blocks = grid_for(sp[2]->capacity, c->num_cu * 4);
     const int prec = c->cfg.precision == QED_PREC_F64 ? 0 : 1;
     hipError_t r = launch(c, qed::K_BEGIN, a, prec, 1);
-    if (r == hipSuccess && pairs) r = launch(c, qed::K_PHOTON, a, prec, photon_blocks);
+    if (r == hipSuccess && pairs) r = launch(c, pair_surr ? qed::K_PHOTON_SURR : qed::K_PHOTON, a, prec, photon_blocks);
     const bool tiled = c->cfg.scheduler == QED_SCHED_TILED;
     if (r == hipSuccess && emission && !binned)
         r = launch(c, tiled ? qed::K_TILED : qed::K_LEPTON, a, prec, lepton_blocks);
@@ -351,6 +354,7 @@ qed_status qed_config_default(qed_config *cfg) {
     cfg->sampler = QED_SAMPLER_REJECTION;
     cfg->cascade_generations = 0;
     cfg->surrogate_p_max = 0.1;
+    cfg->pair_sampler = QED_SAMPLER_REJECTION;
     return QED_OK;
 }
 
@@ -369,6 +373,11 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     if (cfg->sampler == QED_SAMPLER_SURROGATE && !(cfg->surrogate_p_max > 0.0 && cfg->surrogate_p_max <= 1.0))
         return QED_ERR_INVALID_ARG;
     if (cfg->cascade_generations > 0 && cfg->sampler != QED_SAMPLER_REJECTION) return QED_ERR_INVALID_ARG;
+    if (cfg->pair_sampler != QED_SAMPLER_REJECTION && cfg->pair_sampler != QED_SAMPLER_SURROGATE)
+        return QED_ERR_INVALID_ARG;
+    if (cfg->pair_sampler == QED_SAMPLER_SURROGATE &&
+        (cfg->precision != QED_PREC_MIXED || cfg->cascade_generations > 0))
+        return QED_ERR_INVALID_ARG;
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (cfg->device < 0 || cfg->device >= ndev) return QED_ERR_INVALID_ARG;
@@ -482,6 +491,10 @@ qed_status qed_get_stats(qed_ctx *c, qed_stats *out) {
     out->fallback_events = h.fallback_events;
     out->fallback_draws = h.fallback_draws;
     out->envelope_clips = h.envelope_clips;
+    out->pair_learned = h.pair_learned;
+    out->pair_fallback = h.pair_fallback;
+    out->pair_fallback_draws = h.pair_fallback_draws;
+    out->pair_envelope_clips = h.pair_envelope_clips;
     double mp;
     memcpy(&mp, &h.max_p_bits, sizeof(mp));
     out->max_p = mp;
@@ -502,6 +515,7 @@ qed_status qed_reset_stats(qed_ctx *c) {
     h.sampled_photons = h.sampled_substeps = 0;
     h.emissions = h.pairs = h.clips = h.capped = 0;
     h.learned_events = h.fallback_events = h.fallback_draws = h.envelope_clips = 0;
+    h.pair_learned = h.pair_fallback = h.pair_fallback_draws = h.pair_envelope_clips = 0;
     h.max_p_bits = 0;
     HIP_TRY(hipMemcpy(c->st, &h, sizeof(h), hipMemcpyHostToDevice));
     return QED_OK;
@@ -662,6 +676,15 @@ qed_status qed_emission_rate(qed_ctx *c, const float *chi, float *chi_q, uint64_
     return QED_OK;
 }
 
+
+qed_status qed_pair_rate(qed_ctx *c, const float *chi, float *T, uint64_t n) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    if (n == 0) return QED_OK;
+    if (!chi || !T) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    if (qed::launch_pair_rate(chi, T, n, grid_for(n, c->num_cu * 8), c->stream) != hipSuccess) return QED_ERR_HIP;
+    return QED_OK;
+}
 
 qed_status qed_emission_cdf(qed_ctx *c, double lo, double hi, uint32_t nchi, uint32_t nx, double *cdf_out,
                             double *total_out) {

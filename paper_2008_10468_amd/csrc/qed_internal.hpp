@@ -45,6 +45,10 @@ struct DevState {
     alignas(128) u64 fallback_events;
     alignas(128) u64 fallback_draws;
     alignas(128) u64 envelope_clips;
+    alignas(128) u64 pair_learned;     // photon optical-depth path: energy splits
+    alignas(128) u64 pair_fallback;    // from the network / by rejection, the
+    alignas(128) u64 pair_fallback_draws;  // candidates used and those above the
+    alignas(128) u64 pair_envelope_clips;  // envelope
     alignas(128) u64 max_p_bits;   // largest acceptance probability (bits of a non-negative double)
     alignas(128) u64 status_bits;  // bit 0: capacity exceeded, bit 1: non-finite input
     u64 required[3];  // largest count requested per species (capacity errors)
@@ -114,6 +118,7 @@ enum KernelId {
     K_SYNCHROTRON,
     K_TILED,    // tile-sorted scheduler: the whole lepton pass
     K_GEN,      // cascades: advance the pass ranges to the particles of the previous pass
+    K_PHOTON_SURR,  // photon optical-depth path
     K_COUNT
 };
 
@@ -156,6 +161,7 @@ struct ReduceArgs {
 };
 
 hipError_t launch_rate(const float *chi, float *out, u64 n, int blocks, hipStream_t s);
+hipError_t launch_pair_rate(const float *chi, float *out, u64 n, int blocks, hipStream_t s);
 hipError_t launch_cdf_table(const CdfTableDev &t, hipStream_t s);
 hipError_t launch_mlp_data(const CdfTableDev &t, Sample *out, u64 n, uint64_t seed, uint32_t step,
                            double lo10, double hi10, int blocks, hipStream_t s);

@@ -29,6 +29,7 @@
 #include "qed_device.hpp"
 #include "qed_internal.hpp"
 #include "qed_mlp.hpp"
+#include "qed_pair.hpp"
 #include "qed_rate.hpp"
 #include "qed_synchro.hpp"
 
@@ -127,10 +128,11 @@ __device__ __forceinline__ void flush_tally(const Tally<R> &t, DevState *st, int
             for (int k = 0; k < kN; ++k) tot[k] += red[w][k];
             mb = red[w][kN] > mb ? red[w][kN] : mb;
         }
-        if (tot[6]) atomicAdd(&st->learned_events, tot[6]);
-        if (tot[7]) atomicAdd(&st->fallback_events, tot[7]);
-        if (tot[8]) atomicAdd(&st->fallback_draws, tot[8]);
-        if (tot[9]) atomicAdd(&st->envelope_clips, tot[9]);
+        const bool ph = species == 2;
+        if (tot[6]) atomicAdd(ph ? &st->pair_learned : &st->learned_events, tot[6]);
+        if (tot[7]) atomicAdd(ph ? &st->pair_fallback : &st->fallback_events, tot[7]);
+        if (tot[8]) atomicAdd(ph ? &st->pair_fallback_draws : &st->fallback_draws, tot[8]);
+        if (tot[9]) atomicAdd(ph ? &st->pair_envelope_clips : &st->envelope_clips, tot[9]);
         if (tot[0]) atomicAdd(&st->substeps[species], tot[0]);
         if (tot[1]) atomicAdd(species == 2 ? &st->pairs : &st->emissions, tot[1]);
         if (tot[2]) atomicAdd(&st->clips, tot[2]);
@@ -189,6 +191,7 @@ __device__ __forceinline__ void flush_children(ChildBuf<R, TB> &cb, const Specie
             if (dst.parent) dst.parent[slot] = cb.parent[e];
             if constexpr (TB)
                 if (dst.birth) dst.birth[slot] = cb.tb[e];
+            if (dst.tau) dst.tau[slot] = -1.0;
         }
     }
     __syncwarp();
@@ -788,6 +791,7 @@ __device__ __forceinline__ void flush_children_block(ChildBuf<R, TB> *cbs, const
             if (dst.parent) dst.parent[slot] = cb.parent[k];
             if constexpr (TB)
                 if (dst.birth) dst.birth[slot] = cb.tb[k];
+            if (dst.tau) dst.tau[slot] = -1.0;
         }
     }
 }
@@ -1248,6 +1252,184 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
     flush_tally(ts, a.st, 2, 2);
 }
 
+// ---------------------------------------------------------------------------
+// Photon optical-depth path (pair sampler = surrogate, mixed precision).  In the
+// frozen field of a step a photon's chi and energy are constant, so its decay rate
+// W = alpha (chi / eps) T(chi) is too, and the time of its decay follows from the
+// optical depth without sub-steps: with tau left, it decays at t = tau / W if that
+// falls inside the step (else tau -= W dt).  The electron's energy fraction is
+// drawn from eq. (2) at that chi by rejection against the fitted envelope.
+// ---------------------------------------------------------------------------
+// Key tag of the photon path's random stream: the draws of photon id in step
+// `step` are Philox blocks (id_lo, id_hi, step, j) under the seed key xor'ed with
+// this tag, j counting the photon's draws within the step.
+constexpr uint32_t kPairTagLo = 0x7F4A7C15u, kPairTagHi = 0xBB67AE85u;
+
+// Electron energy fraction d in (0, 1) from the Baier-Katkov density at chi by
+// rejection; every candidate costs one half of a Philox block.
+__device__ __forceinline__ float pair_split_reject(float chi, const SynTable<float> &tab, const PairTable &pt,
+                                                   uint32_t idlo, uint32_t idhi, uint32_t step, uint32_t klo,
+                                                   uint32_t khi, uint32_t &j, Tally<float> &tl) {
+    const float env = pair_envelope(chi, pt);
+    u32x4 w = {0u, 0u, 0u, 0u};
+    float d = 0.5f;
+    for (uint32_t it = 0; it < kMaxRejections; ++it) {
+        if ((it & 1u) == 0u) w = philox10(idlo, idhi, step, j++, klo, khi);
+        const bool odd = (it & 1u) != 0u;
+        d = u24(odd ? w.z : w.x);
+        const float y = u24(odd ? w.w : w.y);
+        const float dd = d * (1.0f - d);
+        float F, G;
+        syn_eval((2.0f / 3.0f) * rcp(chi * dd), tab, F, G);
+        const float dens = 1.5f * chi * (G - dd * F);
+        tl.fb_draws++;
+        tl.env_clips += dens > env;
+        if (y * env < dens) break;
+    }
+    return d;
+}
+
+__global__ __launch_bounds__(kBlock) void k_photon_surr(StepArgs a) {
+    __shared__ SynTable<float> tab;
+    __shared__ PairTable pt;
+    pair_stage(pt);
+    syn_stage(tab);
+    using R = float;
+    const u64 n = a.st->hi[2];
+    const SpeciesDev &sp = a.sp[2];
+    const SpeciesDev &el = a.sp[0];
+    const SpeciesDev &po = a.sp[1];
+    const FieldDev &fl = a.fl[2];
+    const uint32_t step = step_of(a);
+    const uint32_t klo = (uint32_t)a.seed ^ kPairTagLo, khi = (uint32_t)(a.seed >> 32) ^ kPairTagHi;
+    Tally<R> t, ts;  // all photons; those that decayed (their split draws)
+    for (u64 i0 = (u64)blockIdx.x * kBlock + (threadIdx.x & ~63u); i0 < n; i0 += (u64)gridDim.x * kBlock) {
+        const u64 i = i0 + __lane_id();
+        const bool in = i < n;
+        bool decay = false, ok = false;
+        double ts_move = 0.0, tau = 1.0, eps = 0.0;
+        float chi = 0.0f;
+        R kx = 0, ky = 0, kz = 0;
+        uint64_t pid = 0;
+        uint32_t j = 0;
+        if (in) {
+            kx = ((const R *)sp.ux)[i];
+            ky = ((const R *)sp.uy)[i];
+            kz = ((const R *)sp.uz)[i];
+            const u64 f = i * fl.stride;
+            const R ex = ((const R *)fl.ex)[f], ey = ((const R *)fl.ey)[f], ez = ((const R *)fl.ez)[f];
+            const R bx = ((const R *)fl.bx)[f], by = ((const R *)fl.by)[f], bz = ((const R *)fl.bz)[f];
+            ok = finite3(kx, ky, kz) && finite3(ex, ey, ez) && finite3(bx, by, bz);
+            if (!ok) {
+                t.nonfinite++;
+                a.alive[i] = 1;
+                if (sp.events) sp.events[i] = 0;
+            } else {
+                pid = sp.id[i];
+                eps = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
+                chi = (float)chi_def(eps, kx, ky, kz, ex, ey, ez, bx, by, bz);
+                tau = sp.tau[i];
+                if (!(tau > 0.0)) {
+                    const u32x4 w = philox10((uint32_t)pid, (uint32_t)(pid >> 32), step, j++, klo, khi);
+                    tau = -log(u53(w.x, w.y));
+                }
+                // rate per unit time; photons of zero energy do not decay
+                const double W = eps > 0.0 ? kAlpha * (double)chi / eps * (double)pair_t(chi, pt) : 0.0;
+                const double Wdt = W * a.dt;
+                decay = tau <= Wdt;
+                ts_move = decay ? tau / W : a.dt;
+                tau = decay ? tau : tau - Wdt;
+                t.substeps += 1;
+                t.particles++;
+            }
+        }
+        // the electron's energy fraction of the decaying photons
+        float d = 0.5f;
+        if (decay) {
+            d = pair_split_reject(chi, tab, pt, (uint32_t)pid, (uint32_t)(pid >> 32), step, klo, khi, j, ts);
+            ts.fallback++;
+            ts.particles++;
+            t.events++;
+        }
+        // move (straight line over the time it lived in this step)
+        double dirx = 0.0, diry = 0.0, dirz = 0.0;
+        if (in && ok) {
+            const double inv = eps > 0.0 ? 1.0 / eps : 0.0;
+            dirx = kx * inv;
+            diry = ky * inv;
+            dirz = kz * inv;
+            sp.x[i] += dirx * ts_move;
+            sp.y[i] += diry * ts_move;
+            sp.z[i] += dirz * ts_move;
+            sp.tau[i] = tau;
+            a.alive[i] = decay ? 0 : 1;
+            if (sp.events) sp.events[i] = decay ? 1u : 0u;
+        }
+        // pair creation: electron with d eps, positron with (1 - d) eps, along k
+        const u64 m = __ballot(decay);
+        if (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            u64 be = 0, bp = 0, bd = 0;
+            if (__lane_id() == leader) {
+                const u64 c = (u64)__popcll(m);
+                be = atomicAdd(el.n, c);
+                bp = atomicAdd(po.n, c);
+                bd = atomicAdd(&a.st->dead, c);
+            }
+            be = __shfl(be, leader);
+            bp = __shfl(bp, leader);
+            bd = __shfl(bd, leader);
+            if (decay) {
+                const u64 r = (u64)__popcll(m & lanemask_lt());
+                a.dead_idx[bd + r] = i;
+                const double px = sp.x[i], py = sp.y[i], pz = sp.z[i];
+                const R w = ((const R *)sp.w)[i];
+                const R epsr = (R)eps;
+                const R ge = d * epsr, gp = (1.0f - d) * epsr;
+                const R ue = sqrt_(fmaxf(ge * ge - 1.0f, 0.0f));
+                const R up = sqrt_(fmaxf(gp * gp - 1.0f, 0.0f));
+                const R fx = (R)dirx, fy = (R)diry, fz = (R)dirz;
+                if (be + r < el.cap) {
+                    const u64 q = be + r;
+                    el.x[q] = px;
+                    el.y[q] = py;
+                    el.z[q] = pz;
+                    ((R *)el.ux)[q] = ue * fx;
+                    ((R *)el.uy)[q] = ue * fy;
+                    ((R *)el.uz)[q] = ue * fz;
+                    ((R *)el.w)[q] = w;
+                    el.id[q] = child_id(a.seed, pid, step, 0, 0);
+                    if (el.parent) el.parent[q] = pid;
+                    if (el.tau) el.tau[q] = -1.0;
+                }
+                if (bp + r < po.cap) {
+                    const u64 q = bp + r;
+                    po.x[q] = px;
+                    po.y[q] = py;
+                    po.z[q] = pz;
+                    ((R *)po.ux)[q] = up * fx;
+                    ((R *)po.uy)[q] = up * fy;
+                    ((R *)po.uz)[q] = up * fz;
+                    ((R *)po.w)[q] = w;
+                    po.id[q] = child_id(a.seed, pid, step, 0, 1);
+                    if (po.parent) po.parent[q] = pid;
+                    if (po.tau) po.tau[q] = -1.0;
+                }
+            }
+        }
+    }
+    flush_tally(t, a.st, 2);
+    flush_tally(ts, a.st, 2, 2);
+}
+
+// Elementwise T(chi) of the pair-rate fit.
+__global__ __launch_bounds__(kBlock) void k_pair_rate(const float *__restrict__ chi, float *__restrict__ out, u64 n) {
+    __shared__ PairTable t;
+    pair_stage(t);
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock)
+        out[i] = pair_t(chi[i], t);
+}
+
 __global__ void k_begin(StepArgs a) {
     DevState *st = a.st;
     for (int k = threadIdx.x; k < 2 * kBins; k += blockDim.x) st->hist[k / kBins][k % kBins] = 0;
@@ -1349,6 +1531,7 @@ __global__ __launch_bounds__(kBlock) void k_move(StepArgs a) {
         sp.id[d] = sp.id[s];
         if (sp.parent) sp.parent[d] = sp.parent[s];
         if (sp.birth) sp.birth[d] = sp.birth[s];
+        if (sp.tau) sp.tau[d] = sp.tau[s];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *sp.n = st->S;
 }
@@ -1432,6 +1615,12 @@ hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
             break;
         case K_END: hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, s, a); break;
         case K_GEN: hipLaunchKernelGGL(k_gen, dim3(1), dim3(64), 0, s, a); break;
+        case K_PHOTON_SURR:
+            if constexpr (std::is_same<R, float>::value) {
+                hipLaunchKernelGGL(k_photon_surr, g1, blk, 0, s, a);
+                break;
+            }
+            return hipErrorInvalidValue;
         case K_FILL: hipLaunchKernelGGL(k_fill, g1, blk, 0, s, a); break;
         case K_MOVE: hipLaunchKernelGGL(k_move<R>, g1, blk, 0, s, a); break;
         default: return hipErrorInvalidValue;
@@ -1448,6 +1637,11 @@ hipError_t launch_kernel(int id, const StepArgs &a, int precision, int blocks, h
 
 hipError_t launch_rate(const float *chi, float *out, u64 n, int blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_rate, dim3(blocks), dim3(kBlock), 0, s, chi, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_rate(const float *chi, float *out, u64 n, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_rate, dim3(blocks), dim3(kBlock), 0, s, chi, out, n);
     return hipGetLastError();
 }
 

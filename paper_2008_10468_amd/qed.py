@@ -44,7 +44,7 @@ class qed_config(C.Structure):
                 ("p_max", C.c_double), ("emission", C.c_int), ("pairs", C.c_int),
                 ("scheduler", C.c_int), ("pair_bound_coef", C.c_double),
                 ("max_substeps", C.c_uint32), ("sampler", C.c_int), ("cascade_generations", C.c_uint32),
-                ("surrogate_p_max", C.c_double)]
+                ("surrogate_p_max", C.c_double), ("pair_sampler", C.c_int)]
 
 
 class qed_report(C.Structure):
@@ -58,7 +58,9 @@ class qed_stats(C.Structure):
                 ("sampled_photons", C.c_uint64), ("sampled_substeps", C.c_uint64), ("emissions", C.c_uint64),
                 ("pairs", C.c_uint64), ("clips", C.c_uint64), ("capped", C.c_uint64),
                 ("max_p", C.c_double), ("learned_events", C.c_uint64), ("fallback_events", C.c_uint64),
-                ("fallback_draws", C.c_uint64), ("envelope_clips", C.c_uint64)]
+                ("fallback_draws", C.c_uint64), ("envelope_clips", C.c_uint64),
+                ("pair_learned", C.c_uint64), ("pair_fallback", C.c_uint64),
+                ("pair_fallback_draws", C.c_uint64), ("pair_envelope_clips", C.c_uint64)]
 
 
 class qed_tuning(C.Structure):
@@ -86,7 +88,7 @@ EXPORTS = ("qed_config_default", "qed_init", "qed_step", "qed_sync", "qed_synchr
            "qed_get_stats", "qed_reset_stats", "qed_get_tuning", "qed_set_tuning",
            "qed_profile_enable", "qed_profile_read", "qed_graph_begin", "qed_graph_end",
            "qed_graph_launch", "qed_graph_destroy",
-           "qed_step_counted", "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
+           "qed_step_counted", "qed_pair_rate", "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
            "qed_train_config_default", "qed_train_sampler", "qed_mlp_gradient",
            "qed_finalize", "qed_status_string")
 
@@ -123,6 +125,7 @@ def load(path: str = LIB_PATH):
     L.qed_sampler_set.argtypes = [C.c_void_p, C.POINTER(qed_sampler_model)]
     L.qed_sampler_infer.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
     L.qed_emission_rate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
+    L.qed_pair_rate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
     L.qed_emission_cdf.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_uint32, C.c_uint32, C.c_void_p,
                                    C.c_void_p]
     L.qed_train_config_default.argtypes = [C.POINTER(qed_train_config)]
@@ -265,6 +268,10 @@ def qed_sampler_infer(ctx, chi, u, x, n):
 
 def qed_emission_rate(ctx, chi, out, n):
     return load().qed_emission_rate(ctx, chi, out, int(n))
+
+
+def qed_pair_rate(ctx, chi, out, n):
+    return load().qed_pair_rate(ctx, chi, out, int(n))
 
 
 def qed_emission_cdf(ctx, lo, hi, nchi, nx):
@@ -415,7 +422,8 @@ class Generator:
     def __init__(self, precision=QED_PREC_MIXED, capacity=(1 << 20, 1 << 20, 1 << 20), emission=True,
                  pairs=True, p_max=0.01, scheduler=QED_SCHED_NAIVE, pair_bound_coef=0.1,
                  max_substeps=1 << 24, device=0, stream=None, parent=True, events=True,
-                 sampler=QED_SAMPLER_REJECTION, cascade_generations=0, surrogate_p_max=0.1):
+                 sampler=QED_SAMPLER_REJECTION, cascade_generations=0, surrogate_p_max=0.1,
+                 pair_sampler=QED_SAMPLER_REJECTION):
         torch = _torch()
         self.real = torch.float64 if precision == QED_PREC_F64 else torch.float32
         self.precision = precision
@@ -432,10 +440,12 @@ class Generator:
         cfg.sampler = sampler
         cfg.cascade_generations = cascade_generations
         cfg.surrogate_p_max = surrogate_p_max
+        cfg.pair_sampler = pair_sampler
         self.cfg = cfg
         self.ctx = qed_init(cfg)
         surr = sampler == QED_SAMPLER_SURROGATE
-        self.sp = [SpeciesBuffers(c, self.real, parent=parent, events=events, tau=surr and k < 2,
+        psurr = pair_sampler == QED_SAMPLER_SURROGATE
+        self.sp = [SpeciesBuffers(c, self.real, parent=parent, events=events, tau=(surr and k < 2) or (psurr and k == 2),
                                   birth=cascade_generations > 0)
                    for k, c in enumerate(capacity)]
         self.fields = [None, None, None]
