@@ -50,11 +50,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def c2_setup(torch, qed, workloads, steps_total, sched, stream=None):
+def c2_setup(torch, qed, workloads, steps_total, sched, stream=None, surrogate=False):
     w = workloads.c2()
+    sur = qed.QED_SAMPLER_SURROGATE if surrogate else qed.QED_SAMPLER_REJECTION
     g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 23, 1 << 23, 1 << 25),
                       parent=False, events=False, scheduler=sched,
-                      stream=None if stream is None else stream.cuda_stream)
+                      stream=None if stream is None else stream.cuda_stream, sampler=sur, pair_sampler=sur)
+    if surrogate:
+        m = np.load(os.path.join(ROOT, "paper_2008_10468_amd", "models", "sampler_gfx950.npz"))
+        st = qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
+                                 float(m["log10_chi_hi"]))
+        assert st == qed.QED_OK, st
     # one frozen field per global step, resident on the device: step s reads entry s
     E = np.array([[workloads.c2_field(s)[k][0] for k in ("ex", "ey", "ez", "bx", "by", "bz")]
                   for s in range(steps_total)], np.float64)
@@ -312,6 +318,40 @@ def bench_c2(args, torch, qed, workloads):
     return out
 
 
+def bench_c2s(args, torch, qed, workloads):
+    """C2 on the optical-depth paths (leptons: optical depth, network shipped for gfx950,
+    sub-step target 0.1; photons: exact decay time, no sub-steps) against the plain
+    generator on the same population and fields."""
+    K, W = args.steps, args.warmup
+    runs = {}
+    for name, surrogate in (("plain_naive", False), ("surrogate_naive", True)):
+        stream = torch.cuda.Stream()
+        w, g, field = c2_setup(torch, qed, workloads, max(K, W), qed.QED_SCHED_NAIVE, stream, surrogate)
+        tuned = load_tuning(qed, g, "c2/naive", args.tuning)
+        log(f"bench: C2 {name}")
+        fields = lambda s: (qed.qed_field * 3)(field(s), field(s), field(s))
+        ms, stats, stats_p, kt, graphed = stepped(torch, qed, g, stream, fields, w, w["dt"], w["seed"], K, W,
+                                                  not args.no_graph)
+        runs[name] = {"ms_per_step": ms / K, "substeps_per_step": sum(stats.substeps) / K,
+                      "substeps_per_s": sum(stats.substeps) / (ms * 1e-3),
+                      "events_per_s": (stats.emissions + stats.pairs) / (ms * 1e-3),
+                      "emissions": stats.emissions, "pairs": stats.pairs, "tuning": tuned,
+                      "kernel_us": {k: v[1] * 1e3 / max(v[0], 1) for k, v in kt.items()}}
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    best = runs["surrogate_naive"]
+    out = header(args, best["substeps_per_s"], best["ms_per_step"] * K, K, W, "f32+bf16", {
+        "workload": "C2 on the optical-depth paths: 1,048,576 e- + 262,144 photons, uniform E = 1e-3 E_S "
+                    "rotating with period 200 steps; leptons by optical depth with the learned sampler "
+                    "(sub-step target 0.1), photons by exact decay time; plain generator beside it",
+        "steps": K, "dt_hbar_over_mc2": workloads.DT_C2, "seed": 1})
+    out["runs"] = runs
+    out["step_speedup_vs_plain"] = runs["plain_naive"]["ms_per_step"] / best["ms_per_step"]
+    out["events_per_s"] = best["events_per_s"]
+    return out
+
+
 def bench_c1(args, torch, qed, workloads):
     """FP64 correctness configuration: 16,384 electrons in a uniform static B field."""
     K, W = (args.steps if args.steps_given else 100), args.warmup
@@ -506,7 +546,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=("c2", "c1", "c3", "c4", "c5"), default="c2")
+    ap.add_argument("--workload", choices=("c2", "c1", "c3", "c4", "c5", "c2s"), default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--scheduler", choices=("naive", "binned", "tiled"), default="naive")
@@ -533,7 +573,8 @@ def main():
     from paper_2008_10468_amd import qed
 
     torch.cuda.set_device(0)
-    fn = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload]
+    fn = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
+          "c2s": bench_c2s}[args.workload]
     out = fn(args, torch, qed, workloads)
     if args.copy_probe:
         out["copy_probe"] = copy_probe(torch, args.copy_probe)

@@ -180,7 +180,9 @@ typedef struct qed_stats {
     uint64_t pairs;       /* photons that decayed into pairs */
     uint64_t clips;       /* sub-steps whose acceptance probability exceeded 1 */
     uint64_t capped;      /* particle-steps whose sub-step count hit max_substeps */
-    double max_p;         /* largest acceptance probability evaluated */
+    double max_p;         /* largest acceptance probability evaluated (a sub-step whose
+                             test value lies above a cheap bound of it is rejected
+                             without evaluating it) */
     uint64_t learned_events;  /* surrogate: energies drawn from the learned inverse CDF */
     uint64_t fallback_events; /* surrogate: energies drawn by rejection */
     uint64_t fallback_draws;  /* surrogate: candidates those rejections used */

@@ -100,56 +100,75 @@ struct Tally {
     R max_p = 0;
 };
 
-// Block-wide reduction of the tallies, then one atomic per counter and block.
-// Every thread of the block must call it.
-// work: 1 = heavy-queue kernel, 2 = photon sampling pass (their particles and
-// sub-steps are also counted separately).
-template <class R>
-__device__ __forceinline__ void flush_tally(const Tally<R> &t, DevState *st, int species,
-                                            int work = 0) {
+// Sum over the wave, skipped (no cross-lane traffic) when the counter is zero in
+// every lane, which is the common case for the rare-event counters.
+template <class T>
+__device__ __forceinline__ T wave_sum_nz(T v) {
+    if (__ballot(v != T(0)) == 0) return T(0);
+    return wave_sum(v);
+}
+
+// Block-wide reduction of NT tallies, then one atomic per non-zero counter and
+// block.  Every thread of the block must call it.  work[q] of tally q: 0 = plain,
+// 1 = heavy-queue kernel, 2 = photon sampling pass (their particles and sub-steps
+// are also counted separately).
+template <class R, int NT>
+__device__ __forceinline__ void flush_tallies(const Tally<R> *tt, const int *work, DevState *st, int species) {
     constexpr int kN = 10;
-    __shared__ u64 red[kBlock / 64][kN + 1];
-    const u64 v[kN] = {wave_sum(t.substeps), (u64)wave_sum(t.events), (u64)wave_sum(t.clips),
-                       (u64)wave_sum(t.capped), (u64)wave_sum(t.nonfinite),
-                       (u64)wave_sum(t.particles), (u64)wave_sum(t.learned),
-                       (u64)wave_sum(t.fallback), (u64)wave_sum(t.fb_draws),
-                       (u64)wave_sum(t.env_clips)};
-    const double mp = wave_max((double)t.max_p);
+    __shared__ u64 red[NT][kBlock / 64][kN + 1];
     const int wv = threadIdx.x / 64;
     __syncthreads();
-    if (__lane_id() == 0) {
-        for (int k = 0; k < kN; ++k) red[wv][k] = v[k];
-        red[wv][kN] = (u64)__double_as_longlong(mp);
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        const Tally<R> &t = tt[q];
+        const u64 v[kN] = {wave_sum_nz(t.substeps), (u64)wave_sum_nz(t.events), (u64)wave_sum_nz(t.clips),
+                           (u64)wave_sum_nz(t.capped), (u64)wave_sum_nz(t.nonfinite),
+                           (u64)wave_sum_nz(t.particles), (u64)wave_sum_nz(t.learned),
+                           (u64)wave_sum_nz(t.fallback), (u64)wave_sum_nz(t.fb_draws),
+                           (u64)wave_sum_nz(t.env_clips)};
+        const double mp = __ballot(t.max_p > R(0)) ? wave_max((double)t.max_p) : 0.0;
+        if (__lane_id() == 0) {
+            for (int k = 0; k < kN; ++k) red[q][wv][k] = v[k];
+            red[q][wv][kN] = (u64)__double_as_longlong(mp);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        u64 tot[kN] = {}, mb = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
-            for (int k = 0; k < kN; ++k) tot[k] += red[w][k];
-            mb = red[w][kN] > mb ? red[w][kN] : mb;
-        }
         const bool ph = species == 2;
-        if (tot[6]) atomicAdd(ph ? &st->pair_learned : &st->learned_events, tot[6]);
-        if (tot[7]) atomicAdd(ph ? &st->pair_fallback : &st->fallback_events, tot[7]);
-        if (tot[8]) atomicAdd(ph ? &st->pair_fallback_draws : &st->fallback_draws, tot[8]);
-        if (tot[9]) atomicAdd(ph ? &st->pair_envelope_clips : &st->envelope_clips, tot[9]);
-        if (tot[0]) atomicAdd(&st->substeps[species], tot[0]);
-        if (tot[1]) atomicAdd(species == 2 ? &st->pairs : &st->emissions, tot[1]);
-        if (tot[2]) atomicAdd(&st->clips, tot[2]);
-        if (tot[3]) atomicAdd(&st->capped, tot[3]);
-        if (tot[4]) {
-            atomicAdd(&st->nonfinite, tot[4]);
-            atomicOr(&st->status_bits, 2ull);
+        for (int q = 0; q < NT; ++q) {
+            u64 tot[kN] = {}, mb = 0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                for (int k = 0; k < kN; ++k) tot[k] += red[q][w][k];
+                mb = red[q][w][kN] > mb ? red[q][w][kN] : mb;
+            }
+            if (tot[6]) atomicAdd(ph ? &st->pair_learned : &st->learned_events, tot[6]);
+            if (tot[7]) atomicAdd(ph ? &st->pair_fallback : &st->fallback_events, tot[7]);
+            if (tot[8]) atomicAdd(ph ? &st->pair_fallback_draws : &st->fallback_draws, tot[8]);
+            if (tot[9]) atomicAdd(ph ? &st->pair_envelope_clips : &st->envelope_clips, tot[9]);
+            if (tot[0]) atomicAdd(&st->substeps[species], tot[0]);
+            if (tot[1]) atomicAdd(ph ? &st->pairs : &st->emissions, tot[1]);
+            if (tot[2]) atomicAdd(&st->clips, tot[2]);
+            if (tot[3]) atomicAdd(&st->capped, tot[3]);
+            if (tot[4]) {
+                atomicAdd(&st->nonfinite, tot[4]);
+                atomicOr(&st->status_bits, 2ull);
+            }
+            if (work[q] == 1) {
+                if (tot[5]) atomicAdd(&st->heavy_particles, tot[5]);
+                if (tot[0]) atomicAdd(&st->heavy_substeps, tot[0]);
+            } else if (work[q] == 2) {
+                if (tot[5]) atomicAdd(&st->sampled_photons, tot[5]);
+                if (tot[0]) atomicAdd(&st->sampled_substeps, tot[0]);
+            }
+            if (mb) atomicMax(&st->max_p_bits, mb);
         }
-        if (work == 1) {
-            if (tot[5]) atomicAdd(&st->heavy_particles, tot[5]);
-            if (tot[0]) atomicAdd(&st->heavy_substeps, tot[0]);
-        } else if (work == 2) {
-            if (tot[5]) atomicAdd(&st->sampled_photons, tot[5]);
-            if (tot[0]) atomicAdd(&st->sampled_substeps, tot[0]);
-        }
-        if (mb) atomicMax(&st->max_p_bits, mb);
     }
+}
+
+template <class R>
+__device__ __forceinline__ void flush_tally(const Tally<R> &t, DevState *st, int species, int work = 0) {
+    const int w[1] = {work};
+    flush_tallies<R, 1>(&t, w, st, species);
 }
 
 // Children of one wave staged in LDS and written out with one atomic per flush.
@@ -642,7 +661,7 @@ struct PhotonStart {
 template <class R>
 __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R ky, R kz,
                                               const PhotonStart &ps, const SynTable<R> &tab,
-                                              Tally<R> &tl) {
+                                              const PairTable &pt, Tally<R> &tl) {
     const SpeciesDev &sp = a.sp[2];
     const SpeciesDev &el = a.sp[0];
     const SpeciesDev &po = a.sp[1];
@@ -655,6 +674,12 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
     const R A = (R)(kAlpha * st * kSqrt3 / (2.0 * kPi) * ps.chi / ps.eps);
     const R chir = (R)ps.chi;
     const R epsr = (R)ps.eps;
+    // Exact squeeze: P_p <= A env / (3/2 chi) for every x (the fitted envelope of
+    // G - x(1-x) F, 5% above its maximum), so a test value y at or above that bound
+    // rejects without evaluating F and G: the decision is the one eq. (2) gives.
+    // chi below the envelope's table: no squeeze (such photons never get here).
+    const R squeeze = ps.chi >= 0x1p-6 ? A * (R)(pair_envelope((float)ps.chi, pt) / (1.5f * (float)ps.chi))
+                                       : R(2);
     const uint64_t pid = sp.id[i];
     const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
     const uint32_t klo = (uint32_t)a.seed, khi = (uint32_t)(a.seed >> 32);
@@ -672,14 +697,17 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
         // candidate x, test value y, acceptance against eq. (2)
         R x, y;
         draw.get(k, idlo, idhi, step, klo, khi, x, y);
-        const R xx = x * (R(1) - x);
-        const R z = R(2.0 / 3.0) * rcp(chir * xx);
-        R F, G;
-        syn_eval(z, tab, F, G);
-        const R pp = A * (G - xx * F);
-        tl.max_p = fmax(tl.max_p, pp);
-        tl.clips += pp > R(1);
-        const bool acc = y < pp;
+        bool acc = false;
+        if (y < squeeze) {
+            const R xx = x * (R(1) - x);
+            const R z = R(2.0 / 3.0) * rcp(chir * xx);
+            R F, G;
+            syn_eval(z, tab, F, G);
+            const R pp = A * (G - xx * F);
+            tl.max_p = fmax(tl.max_p, pp);
+            tl.clips += pp > R(1);
+            acc = y < pp;
+        }
         // pair creation: electron with x eps, positron with (1-x) eps, along k; delete
         const u64 m = __ballot(acc);
         if (m) {
@@ -1097,10 +1125,10 @@ __global__ __launch_bounds__(kBlock, 3) void k_heavy(StepArgs a) {
 // values (its momentum is read again, from the cache).
 template <class R>
 __device__ __forceinline__ void photon_sample_one(const StepArgs &a, u64 i, const PhotonStart &ps,
-                                                  const SynTable<R> &tab, Tally<R> &ts) {
+                                                  const SynTable<R> &tab, const PairTable &pt, Tally<R> &ts) {
     const SpeciesDev &sp = a.sp[2];
     const R kx = ((const R *)sp.ux)[i], ky = ((const R *)sp.uy)[i], kz = ((const R *)sp.uz)[i];
-    photon_sample<R>(a, i, kx, ky, kz, ps, tab, ts);
+    photon_sample<R>(a, i, kx, ky, kz, ps, tab, pt, ts);
     ts.particles++;
 }
 
@@ -1123,6 +1151,8 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
     __shared__ double qchi_sh[kBlock / 64][kPhotonQueue], qeps_sh[kBlock / 64][kPhotonQueue];
     __shared__ double qt0_sh[kBlock / 64][kPhotonQueue];
     __shared__ uint32_t qn_sh[kBlock / 64][kPhotonQueue];
+    __shared__ PairTable pt;
+    pair_stage(pt);
     syn_stage(tab);
     const u64 lo = a.st->lo[2], n = a.st->hi[2];
     const SpeciesDev &sp = a.sp[2];
@@ -1142,7 +1172,8 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
         fu[4] = ((const R *)fl.by)[0];
         fu[5] = ((const R *)fl.bz)[0];
     }
-    Tally<R> t, ts;  // all photons; the sampled ones
+    Tally<R> tt[2];  // all photons; the sampled ones
+    Tally<R> &t = tt[0], &ts = tt[1];
     const u64 G = (u64)gridDim.x * kBlock;
     // wave-uniform loop: photon b of this lane is slot wbase + lane + b G
     for (u64 wbase = lo + (u64)blockIdx.x * kBlock + (threadIdx.x & ~63u); wbase < n; wbase += G * kPhotonBatch) {
@@ -1240,16 +1271,16 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
             queued -= 64;
             const uint32_t q = queued + lane;
             const PhotonStart ps = {qeps[q], qchi[q], qt0[q], qn[q]};
-            photon_sample_one<R>(a, queue[q], ps, tab, ts);
+            photon_sample_one<R>(a, queue[q], ps, tab, pt, ts);
             __syncwarp();
         }
     }
     if (lane < queued) {
         const PhotonStart ps = {qeps[lane], qchi[lane], qt0[lane], qn[lane]};
-        photon_sample_one<R>(a, queue[lane], ps, tab, ts);
+        photon_sample_one<R>(a, queue[lane], ps, tab, pt, ts);
     }
-    flush_tally(t, a.st, 2);
-    flush_tally(ts, a.st, 2, 2);
+    const int work[2] = {0, 2};
+    flush_tallies<R, 2>(tt, work, a.st, 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -1302,7 +1333,8 @@ __global__ __launch_bounds__(kBlock) void k_photon_surr(StepArgs a) {
     const FieldDev &fl = a.fl[2];
     const uint32_t step = step_of(a);
     const uint32_t klo = (uint32_t)a.seed ^ kPairTagLo, khi = (uint32_t)(a.seed >> 32) ^ kPairTagHi;
-    Tally<R> t, ts;  // all photons; those that decayed (their split draws)
+    Tally<R> tt[2];  // all photons; those that decayed (their split draws)
+    Tally<R> &t = tt[0], &ts = tt[1];
     for (u64 i0 = (u64)blockIdx.x * kBlock + (threadIdx.x & ~63u); i0 < n; i0 += (u64)gridDim.x * kBlock) {
         const u64 i = i0 + __lane_id();
         const bool in = i < n;
@@ -1418,8 +1450,8 @@ __global__ __launch_bounds__(kBlock) void k_photon_surr(StepArgs a) {
             }
         }
     }
-    flush_tally(t, a.st, 2);
-    flush_tally(ts, a.st, 2, 2);
+    const int work[2] = {0, 2};
+    flush_tallies<R, 2>(tt, work, a.st, 2);
 }
 
 // Elementwise T(chi) of the pair-rate fit.
