@@ -331,6 +331,16 @@ QED_API qed_status qed_emission_rate(qed_ctx *ctx, const float *chi, float *chi_
  * chi ~ 0.03, where the value underflows). */
 QED_API qed_status qed_pair_rate(qed_ctx *ctx, const float *chi, float *T, uint64_t n);
 
+/* Event-gap diagnostic (Sec. 3.1.1, Fig. 1: how many sub-steps pass between a
+ * particle's events).  hist is a DEVICE array of 2 * nbins uint64 owned by the
+ * caller: [0, nbins) counts emissions (Algorithm 1), [nbins, 2 nbins) pair creations
+ * (Algorithm 2) by the number of sub-steps since the particle's previous event in
+ * the same step, or since the step start for its first one (1 = the next sub-step);
+ * larger gaps go to the last bin.  Every following qed_step adds to it (the caller
+ * clears it); NULL disables it (the default).  The optical-depth paths do not count.
+ * nbins >= 2, else QED_ERR_INVALID_ARG. */
+QED_API qed_status qed_event_gaps(qed_ctx *ctx, uint64_t *hist, uint32_t nbins);
+
 /* The normalised CDF of eq. (1) over the candidate x, as the trainer tabulates it
  * (double, from the double fits of F and G, trapezoid rule): nchi (>= 2) values
  * of chi log-uniform over [10^lo, 10^hi], each at the nx + 1 points

@@ -411,6 +411,31 @@ def photon_step(state, fields, dt, seed, step, p_max=0.01, rng_bits=53, pair_coe
 
 # ---------------------------------------------------------------- cascades
 
+def event_gaps(lepton_children, photon_children, nbins):
+    """Fig. 1's diagnostic (Sec. 3.1.1): events counted by the number of sub-steps since
+    the particle's previous event in the step (since the step start for its first one).
+    lepton_children: children dicts of lepton_step (emissions); photon_children: of
+    photon_step (pairs; both children of a decay carry its sub-step).  Gaps >= nbins go
+    to the last bin.  Returns (emission histogram, pair histogram), int64 arrays."""
+    he = np.zeros(nbins, np.int64)
+    hp = np.zeros(nbins, np.int64)
+    for ch in lepton_children:
+        par = np.asarray(ch["parent"], np.uint64)
+        sub = np.asarray(ch["sub"], np.int64)
+        order = np.lexsort((sub, par))
+        prev_par, prev_sub = None, -1
+        for j in order:
+            p, k = int(par[j]), int(sub[j])
+            gap = k + 1 if p != prev_par else k - prev_sub
+            he[min(gap, nbins - 1)] += 1
+            prev_par, prev_sub = p, k
+    if photon_children is not None:
+        sel = np.asarray(photon_children["kind"]) == 1
+        for k in np.asarray(photon_children["sub"], np.int64)[sel]:
+            hp[min(int(k) + 1, nbins - 1)] += 1
+    return he, hp
+
+
 def _append(dst, ch, sel):
     for k, ck in zip(("x", "y", "z", "ux", "uy", "uz", "w", "id"), ("x", "y", "z", "px", "py", "pz", "w", "id")):
         dst[k] = np.concatenate([dst[k], ch[ck][sel]])

@@ -33,6 +33,8 @@ struct qed_ctx {
     size_t rec_used;          // event pairs in use
     bool capturing;           // between qed_graph_begin and qed_graph_end
     qed::MlpModel *model;     // surrogate sampler's network (device)
+    uint64_t *gap_hist;       // event-gap diagnostic (caller's device array) and its bins
+    uint32_t gap_bins;
     bool have_model;
 };
 
@@ -301,6 +303,8 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
         a.nsub[s] = c->nsub[s];
         a.queue[s] = c->queue[s];
     }
+    a.gap_hist = reinterpret_cast<u64 *>(c->gap_hist);
+    a.gap_bins = c->gap_bins;
     a.sampler = surrogate ? 1 : 0;
     a.model = c->have_model ? c->model : nullptr;
     const u64 lep_cap = sp[0]->capacity > sp[1]->capacity ? sp[0]->capacity : sp[1]->capacity;
@@ -676,6 +680,14 @@ qed_status qed_emission_rate(qed_ctx *c, const float *chi, float *chi_q, uint64_
     return QED_OK;
 }
 
+
+qed_status qed_event_gaps(qed_ctx *c, uint64_t *hist, uint32_t nbins) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    if (hist && nbins < 2) return QED_ERR_INVALID_ARG;
+    c->gap_hist = hist;
+    c->gap_bins = hist ? nbins : 0;
+    return QED_OK;
+}
 
 qed_status qed_pair_rate(qed_ctx *c, const float *chi, float *T, uint64_t n) {
     if (!c) return QED_ERR_INVALID_ARG;

@@ -97,7 +97,15 @@ struct StepArgs {
     uint32_t gen;          // 0: main pass; g >= 1: cascade pass g over DevState's lo..hi,
                            // each particle starting at its birth time
     uint32_t *step_dev;    // non-null: the step number is *step_dev (k_end increments it)
+    u64 *gap_hist;         // non-null: event-gap histograms [2][gap_bins] (emissions, pairs)
+    uint32_t gap_bins;
 };
+
+// Event-gap diagnostic: one more event whose particle had gap sub-steps since its
+// previous event in the step (or since the step start); gaps >= bins go to the last bin.
+__device__ __forceinline__ void count_gap(const StepArgs &a, int kind, uint32_t gap) {
+    if (a.gap_hist) atomicAdd(&a.gap_hist[kind * a.gap_bins + (gap < a.gap_bins ? gap : a.gap_bins - 1)], 1ull);
+}
 
 // The step number of the random streams and child ids.
 __device__ __forceinline__ uint32_t step_of(const StepArgs &a) { return a.step_dev ? *a.step_dev : a.step; }

@@ -366,6 +366,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
     R ux = p.ux, uy = p.uy, uz = p.uz;
     R dx = 0, dy = 0, dz = 0;
     uint32_t nev = 0;
+    uint32_t last = 0;  // sub-steps done at this particle's previous event
     Draw<R> draw;
     for (uint32_t k = 0; k < N; ++k) {
         // push: Boris rotation and move
@@ -396,9 +397,14 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
         const bool acc = y < pm;
         // emission: stage the photon in the wave's LDS buffer, recoil on the parent
         const u64 m = __ballot(acc);
-        if (m)
+        if (m) {
             stage_emission<R>(a, sp, i, pid, k, k, acc, m, x3, omx3, g, u2, dx, dy, dz, ux, uy, uz, cb, nev, t0,
                               st, step);
+            if (acc && a.gap_hist) {
+                count_gap(a, 0, k + 1 - last);
+                last = k + 1;
+            }
+        }
     }
     ((R *)sp.ux)[i] = ux;
     ((R *)sp.uy)[i] = uy;
@@ -761,6 +767,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
                     if (po.birth) po.birth[j] = tb;
                 }
                 dead = true;
+                count_gap(a, 1, k + 1);
             }
         }
     }

@@ -88,7 +88,7 @@ EXPORTS = ("qed_config_default", "qed_init", "qed_step", "qed_sync", "qed_synchr
            "qed_get_stats", "qed_reset_stats", "qed_get_tuning", "qed_set_tuning",
            "qed_profile_enable", "qed_profile_read", "qed_graph_begin", "qed_graph_end",
            "qed_graph_launch", "qed_graph_destroy",
-           "qed_step_counted", "qed_pair_rate", "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
+           "qed_step_counted", "qed_pair_rate", "qed_event_gaps", "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
            "qed_train_config_default", "qed_train_sampler", "qed_mlp_gradient",
            "qed_finalize", "qed_status_string")
 
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH):
     L.qed_sampler_infer.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
     L.qed_emission_rate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
     L.qed_pair_rate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
+    L.qed_event_gaps.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32]
     L.qed_emission_cdf.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_uint32, C.c_uint32, C.c_void_p,
                                    C.c_void_p]
     L.qed_train_config_default.argtypes = [C.POINTER(qed_train_config)]
@@ -272,6 +273,11 @@ def qed_emission_rate(ctx, chi, out, n):
 
 def qed_pair_rate(ctx, chi, out, n):
     return load().qed_pair_rate(ctx, chi, out, int(n))
+
+
+def qed_event_gaps(ctx, hist_ptr, nbins):
+    """hist_ptr: device address of 2 * nbins uint64 (or None to disable)."""
+    return load().qed_event_gaps(ctx, hist_ptr, int(nbins))
 
 
 def qed_emission_cdf(ctx, lo, hi, nchi, nx):

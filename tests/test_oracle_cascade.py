@@ -82,3 +82,27 @@ def test_cascade_creates_second_generation_pairs():
     # without cascades the same step has no pairs
     _, pp0, _, _ = oracle.cascade_step(e, _empty(), _empty(), f, dt, 9, 0, generations=0)
     assert pp0["id"].size == 0
+
+
+def test_event_gap_histogram_definition():
+    """Gaps: the first event of a particle counts the sub-steps since the step start, the
+    next ones the sub-steps since its previous event; pairs count from the step start."""
+    ch = {"parent": np.array([7, 7, 3, 7, 3], np.uint64), "sub": np.array([4, 0, 2, 9, 30], np.uint32)}
+    ph = {"kind": np.array([1, 2, 1, 2], np.int32), "sub": np.array([0, 0, 5, 5], np.uint32)}
+    he, hp = oracle.event_gaps([ch], ph, 16)
+    # particle 7: subs 0, 4, 9 -> gaps 1, 4, 5; particle 3: subs 2, 30 -> gaps 3, 28 (last bin)
+    exp = np.zeros(16, np.int64)
+    for gp in (1, 4, 5, 3, 15):
+        exp[gp] += 1
+    assert np.array_equal(he, exp)
+    assert hp[1] == 1 and hp[6] == 1 and hp.sum() == 2
+
+
+def test_event_gaps_of_an_oracle_step_sum_to_its_events():
+    f = _field(bz=1e-3)
+    e = _species(3000.0, 500, 0)
+    ch, nsub, nev, tl = oracle.lepton_step(e, f, -1.0, 3e5, 2, 0)
+    he, _ = oracle.event_gaps([ch], None, 32)
+    assert he.sum() == nev.sum() == ch["id"].size
+    # with N sub-steps no gap exceeds N
+    assert he[int(nsub.max()) + 1:].sum() == 0 or nsub.max() + 1 >= 32
