@@ -331,6 +331,37 @@ QED_API qed_status qed_emission_rate(qed_ctx *ctx, const float *chi, float *chi_
  * chi ~ 0.03, where the value underflows). */
 QED_API qed_status qed_pair_rate(qed_ctx *ctx, const float *chi, float *T, uint64_t n);
 
+/* Grid coupling: the PIC stages around the particle push (Sec. 2.1: stage 2, field
+ * interpolation from the grid to the particles; stage 4, current deposition), on a
+ * periodic Cartesian Yee grid of nx * ny * nz cells of size dx, dy, dz from the
+ * origin (x0, y0, z0).  Arrays hold nx * ny * nz values indexed (k ny + j) nx + i;
+ * each component sits at its Yee position, in cells from node (i, j, k): Ex and Jx
+ * (1/2, 0, 0), Ey and Jy (0, 1/2, 0), Ez and Jz (0, 0, 1/2), Bx (0, 1/2, 1/2),
+ * By (1/2, 0, 1/2), Bz (1/2, 1/2, 0).  Both stages use linear (cloud-in-cell)
+ * weights on the component's lattice, periodic in every direction, computed in
+ * double.  Field arrays are DEVICE pointers in the context's float type; nx, ny,
+ * nz >= 1 with nx ny nz < 2^31, dx, dy, dz > 0, else QED_ERR_INVALID_ARG.
+ * Stream-ordered on the context's stream, like qed_step. */
+typedef struct qed_grid {
+    const void *ex, *ey, *ez, *bx, *by, *bz;
+    uint32_t nx, ny, nz, pad;
+    double x0, y0, z0, dx, dy, dz;
+} qed_grid;
+
+/* Stage 2: E and B at every particle of the species (slots below its live count,
+ * read on the device), written to out[0..5] = Ex, Ey, Ez, Bx, By, Bz (DEVICE arrays
+ * of at least capacity values, the context's float type): the per-slot fields
+ * (stride 1) that qed_step reads.  The species needs n, x, y, z. */
+QED_API qed_status qed_gather(qed_ctx *ctx, const qed_grid *grid, const qed_species *sp, void *const out[3 + 3]);
+
+/* Stage 4: adds every particle's current density charge * w * u / gamma / (dx dy dz),
+ * spread with the same weights, to jx, jy, jz (DEVICE double arrays on the Ex, Ey, Ez
+ * lattices; the caller clears them).  charge: -1 for electrons, +1 for positrons (in
+ * units of e; the velocity is in units of c).  The grid's field pointers are not
+ * used.  The species needs n, x, y, z, ux, uy, uz, w. */
+QED_API qed_status qed_deposit(qed_ctx *ctx, const qed_grid *grid, const qed_species *sp, double charge,
+                               double *jx, double *jy, double *jz);
+
 /* Event-gap diagnostic (Sec. 3.1.1, Fig. 1: how many sub-steps pass between a
  * particle's events).  hist is a DEVICE array of 2 * nbins uint64 owned by the
  * caller: [0, nbins) counts emissions (Algorithm 1), [nbins, 2 nbins) pair creations

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqed.so")
 ARCH = os.environ.get("QED_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["qed_kernels.hip", "qed_train.hip", "qed_capi.hip"]
+SOURCES = ["qed_kernels.hip", "qed_train.hip", "qed_grid.hip", "qed_capi.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

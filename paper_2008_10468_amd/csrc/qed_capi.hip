@@ -455,6 +455,76 @@ qed_status qed_sync(qed_ctx *c, qed_report *rep) {
     return s;
 }
 
+namespace {
+bool grid_ok(const qed_grid &g, qed::GridDev &d) {
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1) return false;
+    if ((u64)g.nx * g.ny * g.nz >= (1ull << 31)) return false;
+    if (!(g.dx > 0.0 && g.dy > 0.0 && g.dz > 0.0) || !isfinite(g.dx) || !isfinite(g.dy) || !isfinite(g.dz))
+        return false;
+    if (!isfinite(g.x0) || !isfinite(g.y0) || !isfinite(g.z0)) return false;
+    const void *f[6] = {g.ex, g.ey, g.ez, g.bx, g.by, g.bz};
+    for (int k = 0; k < 6; ++k) d.f[k] = f[k];
+    d.nx = g.nx;
+    d.ny = g.ny;
+    d.nz = g.nz;
+    d.x0 = g.x0;
+    d.y0 = g.y0;
+    d.z0 = g.z0;
+    d.idx = 1.0 / g.dx;
+    d.idy = 1.0 / g.dy;
+    d.idz = 1.0 / g.dz;
+    return true;
+}
+}  // namespace
+
+qed_status qed_gather(qed_ctx *c, const qed_grid *grid, const qed_species *sp, void *const out[6]) {
+    if (!c || !grid || !sp || !out) return QED_ERR_INVALID_ARG;
+    qed::GridDev g;
+    if (!grid_ok(*grid, g)) return QED_ERR_INVALID_ARG;
+    for (int k = 0; k < 6; ++k)
+        if (!g.f[k] || !out[k]) return QED_ERR_INVALID_ARG;
+    if (!sp->n || !sp->x || !sp->y || !sp->z) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    qed::GatherArgs a;
+    a.n = reinterpret_cast<const u64 *>(sp->n);
+    a.cap = sp->capacity;
+    a.x = sp->x;
+    a.y = sp->y;
+    a.z = sp->z;
+    for (int k = 0; k < 6; ++k) a.out[k] = out[k];
+    const int dtype = c->cfg.precision == QED_PREC_F64 ? 1 : 0;
+    if (qed::launch_gather(g, a, dtype, grid_for(sp->capacity, c->num_cu * 8), c->stream) != hipSuccess)
+        return QED_ERR_HIP;
+    return QED_OK;
+}
+
+qed_status qed_deposit(qed_ctx *c, const qed_grid *grid, const qed_species *sp, double charge, double *jx,
+                       double *jy, double *jz) {
+    if (!c || !grid || !sp || !jx || !jy || !jz || !isfinite(charge)) return QED_ERR_INVALID_ARG;
+    qed::GridDev g;
+    if (!grid_ok(*grid, g)) return QED_ERR_INVALID_ARG;
+    if (!sp->n || !sp->x || !sp->y || !sp->z || !sp->ux || !sp->uy || !sp->uz || !sp->w) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    qed::DepositArgs a;
+    a.n = reinterpret_cast<const u64 *>(sp->n);
+    a.cap = sp->capacity;
+    a.x = sp->x;
+    a.y = sp->y;
+    a.z = sp->z;
+    a.ux = sp->ux;
+    a.uy = sp->uy;
+    a.uz = sp->uz;
+    a.w = sp->w;
+    a.charge = charge;
+    a.j[0] = jx;
+    a.j[1] = jy;
+    a.j[2] = jz;
+    const int dtype = c->cfg.precision == QED_PREC_F64 ? 1 : 0;
+    if (qed::launch_deposit(g, a, dtype, grid_for(sp->capacity, c->num_cu * 8), c->stream) != hipSuccess)
+        return QED_ERR_HIP;
+    return QED_OK;
+}
+
 qed_status qed_synchrotron(qed_ctx *c, const void *x, void *F, void *G, uint64_t n, int dtype) {
     if (!c) return QED_ERR_INVALID_ARG;
     if (dtype != QED_F32 && dtype != QED_F64) return QED_ERR_INVALID_ARG;

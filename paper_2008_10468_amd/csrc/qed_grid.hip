@@ -1,0 +1,119 @@
+// Grid coupling: the PIC stages around the particle push (Sec. 2.1: stage 2, field
+// interpolation from the grid to the particles; stage 4, deposition of the
+// particles' currents to the grid), on a periodic Cartesian Yee grid.
+//
+// Each component lives on its own lattice, shifted by half a cell in some
+// directions (Ex and Jx by (1/2, 0, 0), Ey, Jy (0, 1/2, 0), Ez, Jz (0, 0, 1/2),
+// Bx (0, 1/2, 1/2), By (1/2, 0, 1/2), Bz (1/2, 1/2, 0)); both stages use linear
+// (cloud-in-cell) weights on that lattice, computed in double from the double
+// positions.  One lane per particle; the grid arrays are read through the cache
+// (neighbouring particles share cells), the currents are added with double atomics.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "qed_internal.hpp"
+
+namespace qed {
+namespace {
+
+constexpr int kGridBlock = 256;
+
+struct Corners {
+    uint32_t idx[8];
+    double w[8];
+};
+
+// The 8 lattice points around (x, y, z) on the lattice shifted by (ox, oy, oz) cells,
+// with their weights (periodic).
+__device__ __forceinline__ Corners corners(const GridDev &g, double x, double y, double z, double ox, double oy,
+                                           double oz) {
+    const double sx = (x - g.x0) * g.idx - ox, sy = (y - g.y0) * g.idy - oy, sz = (z - g.z0) * g.idz - oz;
+    const double fx0 = floor(sx), fy0 = floor(sy), fz0 = floor(sz);
+    const double fx = sx - fx0, fy = sy - fy0, fz = sz - fz0;
+    // periodic wrap of the lower corner (positions may lie outside the box)
+    long long ix = (long long)fx0 % (long long)g.nx, iy = (long long)fy0 % (long long)g.ny,
+              iz = (long long)fz0 % (long long)g.nz;
+    ix += ix < 0 ? g.nx : 0;
+    iy += iy < 0 ? g.ny : 0;
+    iz += iz < 0 ? g.nz : 0;
+    const uint32_t i0 = (uint32_t)ix, j0 = (uint32_t)iy, k0 = (uint32_t)iz;
+    const uint32_t i1 = i0 + 1 == g.nx ? 0 : i0 + 1, j1 = j0 + 1 == g.ny ? 0 : j0 + 1,
+                   k1 = k0 + 1 == g.nz ? 0 : k0 + 1;
+    Corners c;
+    int q = 0;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx, ++q) {
+                const uint32_t i = cx ? i1 : i0, j = cy ? j1 : j0, k = cz ? k1 : k0;
+                c.idx[q] = (k * g.ny + j) * g.nx + i;
+                c.w[q] = (cx ? fx : 1.0 - fx) * (cy ? fy : 1.0 - fy) * (cz ? fz : 1.0 - fz);
+            }
+    return c;
+}
+
+__device__ __constant__ const double kStagger[6][3] = {
+    {0.5, 0.0, 0.0}, {0.0, 0.5, 0.0}, {0.0, 0.0, 0.5},   // Ex, Ey, Ez (and Jx, Jy, Jz)
+    {0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0}};  // Bx, By, Bz
+
+template <class R>
+__global__ __launch_bounds__(kGridBlock) void k_gather(GridDev g, GatherArgs a) {
+    const u64 n0 = *a.n;
+    const u64 n = n0 < a.cap ? n0 : a.cap;
+    for (u64 p = (u64)blockIdx.x * kGridBlock + threadIdx.x; p < n; p += (u64)gridDim.x * kGridBlock) {
+        const double x = a.x[p], y = a.y[p], z = a.z[p];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const Corners cr = corners(g, x, y, z, kStagger[c][0], kStagger[c][1], kStagger[c][2]);
+            const R *f = (const R *)g.f[c];
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v += cr.w[q] * (double)f[cr.idx[q]];
+            ((R *)a.out[c])[p] = (R)v;
+        }
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(kGridBlock) void k_deposit(GridDev g, DepositArgs a) {
+    const u64 n0 = *a.n;
+    const u64 n = n0 < a.cap ? n0 : a.cap;
+    const double scale = a.charge * g.idx * g.idy * g.idz;   // q / cell volume
+    for (u64 p = (u64)blockIdx.x * kGridBlock + threadIdx.x; p < n; p += (u64)gridDim.x * kGridBlock) {
+        const double ux = (double)((const R *)a.ux)[p], uy = (double)((const R *)a.uy)[p],
+                     uz = (double)((const R *)a.uz)[p];
+        const double w = (double)((const R *)a.w)[p];
+        const double gi = 1.0 / sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+        const double cur[3] = {scale * w * ux * gi, scale * w * uy * gi, scale * w * uz * gi};
+        const double x = a.x[p], y = a.y[p], z = a.z[p];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (cur[c] == 0.0) continue;
+            const Corners cr = corners(g, x, y, z, kStagger[c][0], kStagger[c][1], kStagger[c][2]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) atomicAdd(&a.j[c][cr.idx[q]], cr.w[q] * cur[c]);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gather(const GridDev &g, const GatherArgs &a, int dtype, int blocks, hipStream_t s) {
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_gather<float>, dim3(blocks), dim3(kGridBlock), 0, s, g, a);
+    else
+        hipLaunchKernelGGL(k_gather<double>, dim3(blocks), dim3(kGridBlock), 0, s, g, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit(const GridDev &g, const DepositArgs &a, int dtype, int blocks, hipStream_t s) {
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_deposit<float>, dim3(blocks), dim3(kGridBlock), 0, s, g, a);
+    else
+        hipLaunchKernelGGL(k_deposit<double>, dim3(blocks), dim3(kGridBlock), 0, s, g, a);
+    return hipGetLastError();
+}
+
+}  // namespace qed

@@ -181,6 +181,35 @@ hipError_t launch_mlp_validate(const MlpModel *model, const CdfTableDev &t, int 
 hipError_t launch_mlp_infer(const MlpModel *model, const float *chi, const float *u, float *x, u64 n,
                             int blocks, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Grid coupling (qed_grid.hip).
+// ---------------------------------------------------------------------------
+struct GridDev {
+    const void *f[6];               // Ex, Ey, Ez, Bx, By, Bz (gather only)
+    uint32_t nx, ny, nz;
+    double x0, y0, z0, idx, idy, idz;  // origin and inverse cell sizes
+};
+
+struct GatherArgs {
+    const u64 *n;
+    u64 cap;
+    const double *x, *y, *z;
+    void *out[6];                   // per-slot Ex .. Bz
+};
+
+struct DepositArgs {
+    const u64 *n;
+    u64 cap;
+    const double *x, *y, *z;
+    const void *ux, *uy, *uz, *w;
+    double charge;
+    double *j[3];                   // Jx, Jy, Jz on the E lattices
+};
+
+// dtype: 0 = float, 1 = double (the context's momentum and field type).
+hipError_t launch_gather(const GridDev &g, const GatherArgs &a, int dtype, int blocks, hipStream_t s);
+hipError_t launch_deposit(const GridDev &g, const DepositArgs &a, int dtype, int blocks, hipStream_t s);
+
 // Enqueue the elementwise synchrotron kernel (dtype: 0 = float, 1 = double).
 hipError_t launch_synchrotron(const void *x, void *F, void *G, u64 n, int dtype, DevState *st,
                               int blocks, hipStream_t s);

@@ -39,6 +39,12 @@ class qed_field(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("ex", "ey", "ez", "bx", "by", "bz")] + [("stride", C.c_uint64)]
 
 
+class qed_grid(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("ex", "ey", "ez", "bx", "by", "bz")] + \
+        [("nx", C.c_uint32), ("ny", C.c_uint32), ("nz", C.c_uint32), ("pad", C.c_uint32)] + \
+        [(k, C.c_double) for k in ("x0", "y0", "z0", "dx", "dy", "dz")]
+
+
 class qed_config(C.Structure):
     _fields_ = [("device", C.c_int), ("stream", C.c_void_p), ("precision", C.c_int),
                 ("p_max", C.c_double), ("emission", C.c_int), ("pairs", C.c_int),
@@ -88,7 +94,7 @@ EXPORTS = ("qed_config_default", "qed_init", "qed_step", "qed_sync", "qed_synchr
            "qed_get_stats", "qed_reset_stats", "qed_get_tuning", "qed_set_tuning",
            "qed_profile_enable", "qed_profile_read", "qed_graph_begin", "qed_graph_end",
            "qed_graph_launch", "qed_graph_destroy",
-           "qed_step_counted", "qed_pair_rate", "qed_event_gaps", "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
+           "qed_step_counted", "qed_pair_rate", "qed_event_gaps", "qed_gather", "qed_deposit", "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
            "qed_train_config_default", "qed_train_sampler", "qed_mlp_gradient",
            "qed_finalize", "qed_status_string")
 
@@ -127,6 +133,9 @@ def load(path: str = LIB_PATH):
     L.qed_emission_rate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
     L.qed_pair_rate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
     L.qed_event_gaps.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32]
+    L.qed_gather.argtypes = [C.c_void_p, C.POINTER(qed_grid), C.POINTER(qed_species), C.c_void_p * 6]
+    L.qed_deposit.argtypes = [C.c_void_p, C.POINTER(qed_grid), C.POINTER(qed_species), C.c_double,
+                              C.c_void_p, C.c_void_p, C.c_void_p]
     L.qed_emission_cdf.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_uint32, C.c_uint32, C.c_void_p,
                                    C.c_void_p]
     L.qed_train_config_default.argtypes = [C.POINTER(qed_train_config)]
@@ -273,6 +282,15 @@ def qed_emission_rate(ctx, chi, out, n):
 
 def qed_pair_rate(ctx, chi, out, n):
     return load().qed_pair_rate(ctx, chi, out, int(n))
+
+
+def qed_gather(ctx, grid, species, out_ptrs):
+    """grid: qed_grid; species: qed_species; out_ptrs: six device addresses (Ex .. Bz)."""
+    return load().qed_gather(ctx, C.byref(grid), C.byref(species), (C.c_void_p * 6)(*out_ptrs))
+
+
+def qed_deposit(ctx, grid, species, charge, jx, jy, jz):
+    return load().qed_deposit(ctx, C.byref(grid), C.byref(species), float(charge), jx, jy, jz)
 
 
 def qed_event_gaps(ctx, hist_ptr, nbins):

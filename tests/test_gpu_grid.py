@@ -1,0 +1,152 @@
+"""Grid coupling on the GPU (qed_gather, qed_deposit) against the oracle's definition:
+interpolation of every Yee component to the particles, deposition of their currents,
+both periodic; and one PIC cycle (gather, step, deposit) with the total current of the
+grid equal to the particles'."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import grid as og
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+COMP = ("ex", "ey", "ez", "bx", "by", "bz")
+
+
+def _grid(qed, real, rng, nx=17, ny=9, nz=12, scale=1e-3):
+    g = {"nx": nx, "ny": ny, "nz": nz, "dx": 0.8, "dy": 1.3, "dz": 1.1, "x0": -3.0, "y0": 2.0, "z0": -7.5}
+    dev = {}
+    for c in COMP:
+        v = rng.normal(size=(nz, ny, nx)) * scale
+        t = torch.from_numpy(v).to(real).cuda()
+        dev[c] = t
+        g[c] = t.double().cpu().numpy()          # the values as the GPU holds them
+    s = qed.qed_grid()
+    for c in COMP:
+        setattr(s, c, dev[c].data_ptr())
+    s.nx, s.ny, s.nz = nx, ny, nz
+    for k in ("x0", "y0", "z0", "dx", "dy", "dz"):
+        setattr(s, k, g[k])
+    return g, s, dev
+
+
+def _particles(g, rng, n):
+    # positions inside and outside the box (periodic), momenta of all directions
+    span = np.array([g["nx"] * g["dx"], g["ny"] * g["dy"], g["nz"] * g["dz"]])
+    x = g["x0"] + rng.uniform(-1.0, 2.0, n) * span[0]
+    y = g["y0"] + rng.uniform(-1.0, 2.0, n) * span[1]
+    z = g["z0"] + rng.uniform(-1.0, 2.0, n) * span[2]
+    u = rng.normal(size=(3, n)) * 30.0
+    return {"x": x, "y": y, "z": z, "ux": u[0], "uy": u[1], "uz": u[2], "w": rng.uniform(0.5, 2.0, n),
+            "id": np.arange(n, dtype=np.uint64)}
+
+
+@pytest.mark.parametrize("prec_name", ["F64", "MIXED"])
+def test_gather_matches_oracle(prec_name):
+    from paper_2008_10468_amd import qed
+    prec = getattr(qed, "QED_PREC_" + prec_name)
+    rng = np.random.default_rng(1)
+    gen = qed.Generator(precision=prec, capacity=(50000, 16, 16))
+    g, s, dev = _grid(qed, gen.real, rng)
+    p = _particles(g, rng, 40000)
+    gen.sp[0].upload(p)
+    out = [torch.full((50000,), float("nan"), dtype=gen.real, device="cuda") for _ in COMP]
+    assert qed.qed_gather(gen.ctx, s, gen.sp[0].struct(), [t.data_ptr() for t in out]) == qed.QED_OK
+    torch.cuda.synchronize()
+    ref = og.gather(g, p["x"], p["y"], p["z"])
+    tol = 1e-12 if prec_name == "F64" else 2e-6
+    for c, t in zip(COMP, out):
+        got = t.double().cpu().numpy()
+        assert np.all(np.isnan(got[40000:]))                     # slots past the count untouched
+        err = np.abs(got[:40000] - ref[c]).max() / np.abs(g[c]).max()
+        assert err < tol, (c, err)
+    gen.close()
+
+
+@pytest.mark.parametrize("prec_name", ["F64", "MIXED"])
+def test_deposit_matches_oracle(prec_name):
+    from paper_2008_10468_amd import qed
+    prec = getattr(qed, "QED_PREC_" + prec_name)
+    rng = np.random.default_rng(2)
+    gen = qed.Generator(precision=prec, capacity=(60000, 16, 16))
+    g, s, _ = _grid(qed, gen.real, rng, nx=11, ny=7, nz=5)
+    p = _particles(g, rng, 60000)
+    gen.sp[0].upload(p)
+    q = gen.sp[0].download()                                     # momenta and weights as stored
+    ncell = g["nx"] * g["ny"] * g["nz"]
+    j = [torch.zeros(ncell, dtype=torch.float64, device="cuda") for _ in range(3)]
+    assert qed.qed_deposit(gen.ctx, s, gen.sp[0].struct(), -1.0, *[t.data_ptr() for t in j]) == qed.QED_OK
+    torch.cuda.synchronize()
+    ref = og.deposit(g, q["x"], q["y"], q["z"], q["ux"], q["uy"], q["uz"], q["w"], -1.0)
+    for t, r in zip(j, ref):
+        got = t.cpu().numpy()
+        assert np.abs(got - r).max() <= 1e-10 * np.abs(r).max()
+    gen.close()
+
+
+def test_pic_cycle_gather_step_deposit():
+    """One PIC cycle on the C2 population placed in a grid holding C2's field: gather,
+    a generator step with the gathered per-slot fields, deposition of the electrons'
+    currents; the grid's total current equals the particles' (weights sum to one)."""
+    from paper_2008_10468_amd import qed
+    w = workloads.c2(n_e=30000, n_g=8000, seed=9)
+    gen = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 16, 1 << 15, 1 << 17))
+    gen.load_state({k: w[k] for k in ("electrons", "positrons", "photons")})
+    rng = np.random.default_rng(3)
+    nx, ny, nz = 16, 16, 16
+    gd = {"nx": nx, "ny": ny, "nz": nz, "dx": 2e3, "dy": 2e3, "dz": 2e3, "x0": -1.6e4, "y0": -1.6e4, "z0": -1.6e4}
+    dev = {c: torch.full((nz, ny, nx), float(w["fields"][c][0]), dtype=torch.float32, device="cuda") for c in COMP}
+    s = qed.qed_grid()
+    for c in COMP:
+        setattr(s, c, dev[c].data_ptr())
+    s.nx, s.ny, s.nz = nx, ny, nz
+    for k in ("x0", "y0", "z0", "dx", "dy", "dz"):
+        setattr(s, k, gd[k])
+    # per-slot fields of every species from the grid
+    per = []
+    for sp in gen.sp:
+        arrs = [torch.empty(sp.capacity, dtype=torch.float32, device="cuda") for _ in COMP]
+        assert qed.qed_gather(gen.ctx, s, sp.struct(), [t.data_ptr() for t in arrs]) == qed.QED_OK
+        f = qed.qed_field()
+        for c, t in zip(COMP, arrs):
+            setattr(f, c, t.data_ptr())
+        f.stride = 1
+        per.append((f, arrs))
+    torch.cuda.synchronize()
+    # a uniform grid field interpolates to the uniform value
+    e0 = per[0][1][0][:30000].double().cpu().numpy()
+    assert np.allclose(e0, w["fields"]["ex"][0], rtol=1e-6)
+    assert qed.qed_step(gen.ctx, gen.particles(), [per[0][0], per[1][0], per[2][0]], w["dt"], 1, 0) == qed.QED_OK
+    assert gen.sync()[0] == qed.QED_OK
+    ncell = nx * ny * nz
+    j = [torch.zeros(ncell, dtype=torch.float64, device="cuda") for _ in range(3)]
+    assert qed.qed_deposit(gen.ctx, s, gen.sp[0].struct(), -1.0, *[t.data_ptr() for t in j]) == qed.QED_OK
+    torch.cuda.synchronize()
+    e = gen.sp[0].download()
+    gam = np.sqrt(1 + e["ux"] ** 2 + e["uy"] ** 2 + e["uz"] ** 2)
+    vol = gd["dx"] * gd["dy"] * gd["dz"]
+    for t, u in zip(j, ("ux", "uy", "uz")):
+        total = t.cpu().numpy().sum() * vol
+        assert np.isclose(total, np.sum(-e["w"] * e[u] / gam), rtol=1e-9)
+    gen.close()
+
+
+def test_grid_rejects_bad_arguments():
+    from paper_2008_10468_amd import qed
+    gen = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(16, 16, 16))
+    rng = np.random.default_rng(4)
+    g, s, dev = _grid(qed, gen.real, rng, nx=4, ny=4, nz=4)
+    out = [torch.empty(16, dtype=torch.float32, device="cuda") for _ in COMP]
+    ptrs = [t.data_ptr() for t in out]
+    s.dx = 0.0
+    assert qed.qed_gather(gen.ctx, s, gen.sp[0].struct(), ptrs) == qed.QED_ERR_INVALID_ARG
+    s.dx = 1.0
+    s.nz = 0
+    assert qed.qed_gather(gen.ctx, s, gen.sp[0].struct(), ptrs) == qed.QED_ERR_INVALID_ARG
+    s.nz = 4
+    assert qed.qed_gather(gen.ctx, s, gen.sp[0].struct(), ptrs[:5] + [None]) == qed.QED_ERR_INVALID_ARG
+    assert qed.qed_deposit(gen.ctx, s, gen.sp[0].struct(), float("nan"), ptrs[0], ptrs[1], ptrs[2]) == \
+        qed.QED_ERR_INVALID_ARG
+    gen.close()
