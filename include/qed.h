@@ -398,9 +398,27 @@ typedef struct qed_train_config {
     uint64_t seed;                     /* data and initial weights; 1 */
     int32_t nbins, per_bin;            /* validation; 50, 5 */
     double tolerance;                  /* CDF error above which a bin falls back; 1e-3 */
+    int32_t target;                    /* 0: the emitted energy (eq. (1)); 1: the energy
+                                          split of pair creation (eq. (2)); 0 */
+    int32_t pad;
 } qed_train_config;
 
 QED_API qed_status qed_train_config_default(qed_train_config *cfg);
+
+/* The photon path's learned energy split (pair_sampler QED_SAMPLER_SURROGATE): a
+ * network of the same shape trained with target 1 on the half-distribution of the
+ * electron's fraction d about 1/2 (eq. (2) is symmetric): inputs s as above and
+ * v = sqrt(-ln(1 - u')) - 1 of u' in [0, 1); output y with |d - 1/2| = y w(chi),
+ * w(chi) = sqrt(3 chi / 64) / sqrt(1 + 3 chi / 16).  A decaying photon draws u,
+ * takes u' = |2u - 1| and the side of 1/2 from u < 1/2.  Bins flagged to fall back,
+ * and chi outside the range, use rejection against the fitted envelope.  NULL
+ * removes it.  The model struct is that of qed_sampler_set; HOST pointers, copied. */
+QED_API qed_status qed_pair_sampler_set(qed_ctx *ctx, const qed_sampler_model *m);
+
+/* d for n (chi, u) (float DEVICE arrays) as the photon path draws it with the
+ * installed split network; NaN where it falls back.  QED_ERR_STATE without a model. */
+QED_API qed_status qed_pair_sampler_infer(qed_ctx *ctx, const float *chi, const float *u, float *d,
+                                          uint64_t n);
 
 /* Synchronous.  init_params (HOST, QED_MLP_NPARAMS floats) may be NULL for a
  * seeded initialisation.  Outputs (HOST): params_out (QED_MLP_NPARAMS), and,

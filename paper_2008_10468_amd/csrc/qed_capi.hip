@@ -33,6 +33,8 @@ struct qed_ctx {
     size_t rec_used;          // event pairs in use
     bool capturing;           // between qed_graph_begin and qed_graph_end
     qed::MlpModel *model;     // surrogate sampler's network (device)
+    qed::MlpModel *pair_model;  // the photon path's network of the energy split (device)
+    bool have_pair_model;
     uint64_t *gap_hist;       // event-gap diagnostic (caller's device array) and its bins
     uint32_t gap_bins;
     bool have_model;
@@ -197,7 +199,8 @@ bool table_args_ok(double lo, double hi, uint32_t nchi, uint32_t nx) {
 }
 
 qed_status build_table(qed_ctx *c, DevBufs &B, double lo, double hi, uint32_t nchi, uint32_t nx,
-                       qed::CdfTableDev &t) {
+                       qed::CdfTableDev &t, int kind = 0) {
+    t.kind = kind;
     t.nchi = (int)nchi;
     t.nx = (int)nx;
     t.lo10 = lo;
@@ -307,6 +310,7 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     a.gap_bins = c->gap_bins;
     a.sampler = surrogate ? 1 : 0;
     a.model = c->have_model ? c->model : nullptr;
+    a.pair_model = c->have_pair_model ? c->pair_model : nullptr;
     const u64 lep_cap = sp[0]->capacity > sp[1]->capacity ? sp[0]->capacity : sp[1]->capacity;
     const int lepton_blocks = grid_for(lep_cap, c->num_cu * (int)c->tune.lepton_blocks_per_cu);
     const int heavy_blocks = c->num_cu * (int)c->tune.heavy_blocks_per_cu;
@@ -337,6 +341,50 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     if (r == hipSuccess && pairs) r = launch(c, qed::K_FILL, a, prec, aux_blocks);
     if (r == hipSuccess && pairs) r = launch(c, qed::K_MOVE, a, prec, aux_blocks);
     return r == hipSuccess ? QED_OK : QED_ERR_HIP;
+}
+
+}  // namespace
+
+namespace {
+
+qed_status set_model(qed_ctx *c, const qed_sampler_model *m, qed::MlpModel *dst, bool &have) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    if (c->capturing) return QED_ERR_STATE;
+    if (!m) {
+        HIP_TRY(hipSetDevice(c->cfg.device));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        have = false;
+        return QED_OK;
+    }
+    if (!m->params || m->nbins < 1 || m->nbins > QED_MLP_MAX_BINS || !m->fallback) return QED_ERR_INVALID_ARG;
+    if (!(m->log10_chi_hi > m->log10_chi_lo) || !isfinite(m->log10_chi_lo) || !isfinite(m->log10_chi_hi))
+        return QED_ERR_INVALID_ARG;
+    for (int k = 0; k < QED_MLP_NPARAMS; ++k)
+        if (!isfinite(m->params[k])) return QED_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->cfg.device));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    float *dp = nullptr;
+    HIP_TRY(hipMalloc(&dp, QED_MLP_NPARAMS * sizeof(float)));
+    qed_status st = QED_OK;
+    if (hipMemcpy(dp, m->params, QED_MLP_NPARAMS * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        qed::launch_mlp_pack(dp, dst, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        st = QED_ERR_HIP;
+    (void)hipFree(dp);
+    if (st != QED_OK) return st;
+    // the range, bins and fallback flags
+    struct {
+        float lo, inv_span;
+        int nbins;
+    } head = {(float)m->log10_chi_lo, (float)(1.0 / (m->log10_chi_hi - m->log10_chi_lo)), m->nbins};
+    uint8_t fb[QED_MLP_MAX_BINS];
+    memset(fb, 1, sizeof(fb));
+    for (int k = 0; k < m->nbins; ++k) fb[k] = m->fallback[k] ? 1 : 0;
+    char *base = reinterpret_cast<char *>(dst);
+    HIP_TRY(hipMemcpy(base + offsetof(qed::MlpModel, lo), &head, sizeof(head), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + offsetof(qed::MlpModel, fallback), fb, sizeof(fb), hipMemcpyHostToDevice));
+    have = true;
+    return QED_OK;
 }
 
 }  // namespace
@@ -403,9 +451,11 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     c->tune.chunk = 256;
     if (hipMalloc(&c->st, sizeof(qed::DevState)) != hipSuccess ||
         hipMemset(c->st, 0, sizeof(qed::DevState)) != hipSuccess ||
-        hipMalloc(&c->model, sizeof(qed::MlpModel)) != hipSuccess) {
+        hipMalloc(&c->model, sizeof(qed::MlpModel)) != hipSuccess ||
+        hipMalloc(&c->pair_model, sizeof(qed::MlpModel)) != hipSuccess) {
         if (c->st) (void)hipFree(c->st);
         if (c->model) (void)hipFree(c->model);
+        if (c->pair_model) (void)hipFree(c->pair_model);
         delete c;
         return QED_ERR_HIP;
     }
@@ -692,41 +742,22 @@ qed_status qed_profile_read(qed_ctx *c, qed_kernel_time *out, int max, int *coun
 // ---------------------------------------------------------------------------
 qed_status qed_sampler_set(qed_ctx *c, const qed_sampler_model *m) {
     if (!c) return QED_ERR_INVALID_ARG;
-    if (c->capturing) return QED_ERR_STATE;
-    if (!m) {
-        HIP_TRY(hipSetDevice(c->cfg.device));
-        HIP_TRY(hipStreamSynchronize(c->stream));
-        c->have_model = false;
-        return QED_OK;
-    }
-    if (!m->params || m->nbins < 1 || m->nbins > QED_MLP_MAX_BINS || !m->fallback) return QED_ERR_INVALID_ARG;
-    if (!(m->log10_chi_hi > m->log10_chi_lo) || !isfinite(m->log10_chi_lo) || !isfinite(m->log10_chi_hi))
-        return QED_ERR_INVALID_ARG;
-    for (int k = 0; k < QED_MLP_NPARAMS; ++k)
-        if (!isfinite(m->params[k])) return QED_ERR_INVALID_ARG;
+    return set_model(c, m, c->model, c->have_model);
+}
+
+qed_status qed_pair_sampler_set(qed_ctx *c, const qed_sampler_model *m) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    return set_model(c, m, c->pair_model, c->have_pair_model);
+}
+
+qed_status qed_pair_sampler_infer(qed_ctx *c, const float *chi, const float *u, float *d, uint64_t n) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    if (n == 0) return QED_OK;
+    if (!chi || !u || !d) return QED_ERR_INVALID_ARG;
+    if (!c->have_pair_model) return QED_ERR_STATE;
     HIP_TRY(hipSetDevice(c->cfg.device));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    float *dp = nullptr;
-    HIP_TRY(hipMalloc(&dp, QED_MLP_NPARAMS * sizeof(float)));
-    qed_status st = QED_OK;
-    if (hipMemcpy(dp, m->params, QED_MLP_NPARAMS * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-        qed::launch_mlp_pack(dp, c->model, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
-        st = QED_ERR_HIP;
-    (void)hipFree(dp);
-    if (st != QED_OK) return st;
-    // the range, bins and fallback flags
-    struct {
-        float lo, inv_span;
-        int nbins;
-    } head = {(float)m->log10_chi_lo, (float)(1.0 / (m->log10_chi_hi - m->log10_chi_lo)), m->nbins};
-    uint8_t fb[QED_MLP_MAX_BINS];
-    memset(fb, 1, sizeof(fb));
-    for (int k = 0; k < m->nbins; ++k) fb[k] = m->fallback[k] ? 1 : 0;
-    char *base = reinterpret_cast<char *>(c->model);
-    HIP_TRY(hipMemcpy(base + offsetof(qed::MlpModel, lo), &head, sizeof(head), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(base + offsetof(qed::MlpModel, fallback), fb, sizeof(fb), hipMemcpyHostToDevice));
-    c->have_model = true;
+    if (qed::launch_mlp_infer(c->pair_model, chi, u, d, n, grid_for(n, c->num_cu * 8), c->stream, 1) != hipSuccess)
+        return QED_ERR_HIP;
     return QED_OK;
 }
 
@@ -812,11 +843,13 @@ qed_status qed_train_sampler(qed_ctx *c, const qed_train_config *cfg, const floa
     if (cfg->nbins < 1 || cfg->nbins > QED_MLP_MAX_BINS || cfg->per_bin < 2 || cfg->per_bin > 64)
         return QED_ERR_INVALID_ARG;
     if (!(cfg->lr > 0.0f) || !(cfg->lr_final > 0.0f) || !(cfg->tolerance > 0.0)) return QED_ERR_INVALID_ARG;
+    if (cfg->target != 0 && cfg->target != 1) return QED_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(c->cfg.device));
     HIP_TRY(hipStreamSynchronize(c->stream));
     DevBufs B;
     qed::CdfTableDev t;
-    qed_status st = build_table(c, B, cfg->log10_chi_lo, cfg->log10_chi_hi, cfg->table_chi, cfg->table_x, t);
+    qed_status st =
+        build_table(c, B, cfg->log10_chi_lo, cfg->log10_chi_hi, cfg->table_chi, cfg->table_x, t, cfg->target);
     if (st != QED_OK) return st;
     const u64 batch = (u64)cfg->blocks * 64 * cfg->batch_tiles;
     float *params, *m, *v, *partials, *loss, *bin_err;
@@ -944,6 +977,7 @@ void qed_finalize(qed_ctx *c) {
     }
     release(c->st);
     release(c->model);
+    release(c->pair_model);
     delete c;
 }
 

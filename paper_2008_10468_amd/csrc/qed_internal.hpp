@@ -94,6 +94,7 @@ struct StepArgs {
     uint32_t *queue[2];    // binned scheduler: heavy lepton slots sorted by bin, heaviest first
     int sampler;           // 0 rejection, 1 surrogate
     const MlpModel *model; // surrogate: installed network (nullptr: rejection for every chi)
+    const MlpModel *pair_model;  // photon path: network of the energy split (nullptr: rejection)
     uint32_t gen;          // 0: main pass; g >= 1: cascade pass g over DevState's lo..hi,
                            // each particle starting at its birth time
     uint32_t *step_dev;    // non-null: the step number is *step_dev (k_end increments it)
@@ -145,6 +146,8 @@ struct CdfTableDev {
     double *total;
     int nchi, nx;
     double lo10, hi10;
+    int kind;  // 0: emission, rows over x = 1 - (1 - k/nx)^2; 1: pair creation, rows of
+               // the half-distribution H(D) = P(|d - 1/2| <= D) over D = k / (2 nx)
 };
 
 struct Sample {
@@ -179,7 +182,7 @@ hipError_t launch_mlp_pack(const float *params, MlpModel *out, hipStream_t s);
 hipError_t launch_mlp_validate(const MlpModel *model, const CdfTableDev &t, int nbins, int per_bin,
                                float *bin_err, hipStream_t s);
 hipError_t launch_mlp_infer(const MlpModel *model, const float *chi, const float *u, float *x, u64 n,
-                            int blocks, hipStream_t s);
+                            int blocks, hipStream_t s, int kind = 0);
 
 // ---------------------------------------------------------------------------
 // Grid coupling (qed_grid.hip).

@@ -1327,9 +1327,21 @@ __device__ __forceinline__ float pair_split_reject(float chi, const SynTable<flo
     return d;
 }
 
+// Network of the energy split in LDS (NET instance only).
+template <bool NET>
+struct PairNetLds {};
+template <>
+struct PairNetLds<true> {
+    MlpLds M;
+    MlpWave ws[kBlock / 64];
+};
+
+template <bool NET>
 __global__ __launch_bounds__(kBlock) void k_photon_surr(StepArgs a) {
     __shared__ SynTable<float> tab;
     __shared__ PairTable pt;
+    __shared__ PairNetLds<NET> net;
+    if constexpr (NET) mlp_stage(a.pair_model, net.M);
     pair_stage(pt);
     syn_stage(tab);
     using R = float;
@@ -1382,11 +1394,36 @@ __global__ __launch_bounds__(kBlock) void k_photon_surr(StepArgs a) {
                 t.particles++;
             }
         }
-        // the electron's energy fraction of the decaying photons
+        // the electron's energy fraction of the decaying photons: from the network
+        // (batched over the wave's decaying lanes) where it serves this chi, else by
+        // rejection
         float d = 0.5f;
+        bool use_net = false;
+        if constexpr (NET) {
+            float sin = 0.0f, up = 0.0f;
+            bool upper = false;
+            if (decay) {
+                const u32x4 w = philox10((uint32_t)pid, (uint32_t)(pid >> 32), step, j++, klo, khi);
+                const float u = u24(w.x);
+                upper = u >= 0.5f;
+                up = fabsf(2.0f * u - 1.0f);
+                bool in_range;
+                int bin;
+                sin = mlp_input_s(net.M, chi, in_range, bin);
+                use_net = in_range && !net.M.fallback[bin];
+            }
+            if (__ballot(use_net)) {
+                const float y = mlp_infer_wave(net.M, net.ws[threadIdx.x / 64], use_net, sin, mlp_input_v_pair(up));
+                if (use_net) d = pair_d_of_y(y, chi, upper);
+            }
+        }
         if (decay) {
-            d = pair_split_reject(chi, tab, pt, (uint32_t)pid, (uint32_t)(pid >> 32), step, klo, khi, j, ts);
-            ts.fallback++;
+            if (use_net) {
+                ts.learned++;
+            } else {
+                d = pair_split_reject(chi, tab, pt, (uint32_t)pid, (uint32_t)(pid >> 32), step, klo, khi, j, ts);
+                ts.fallback++;
+            }
             ts.particles++;
             t.events++;
         }
@@ -1656,7 +1693,10 @@ hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
         case K_GEN: hipLaunchKernelGGL(k_gen, dim3(1), dim3(64), 0, s, a); break;
         case K_PHOTON_SURR:
             if constexpr (std::is_same<R, float>::value) {
-                hipLaunchKernelGGL(k_photon_surr, g1, blk, 0, s, a);
+                if (a.pair_model)
+                    hipLaunchKernelGGL(k_photon_surr<true>, g1, blk, 0, s, a);
+                else
+                    hipLaunchKernelGGL(k_photon_surr<false>, g1, blk, 0, s, a);
                 break;
             }
             return hipErrorInvalidValue;

@@ -250,6 +250,25 @@ __device__ __forceinline__ float mlp_input_v(float u) {
     return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(fmaxf(L, 0x1p-100f)) * (1.0f / 3.0f)) - 1.0f;
 }
 
+// Pair creation's energy split (the network of the photon path): the electron's
+// fraction d = 1/2 +- D, D = y w(chi) with the split's width w(chi) = sqrt(3 chi / 64) /
+// sqrt(1 + 3 chi / 16) (the standard deviation of the Gaussian limit at small chi,
+// 1/2 at large chi); input v = sqrt(-ln(1 - u')) - 1 of u' = |2u - 1|, the sign of
+// d - 1/2 from u < 1/2 (the split is symmetric).
+__device__ __forceinline__ float pair_width(float chi) {
+    return __builtin_amdgcn_sqrtf(0.046875f * chi) * __builtin_amdgcn_rsqf(1.0f + 0.1875f * chi);
+}
+
+__device__ __forceinline__ float mlp_input_v_pair(float up) {
+    const float L = -__builtin_amdgcn_logf(1.0f - up) * 0.69314718056f;   // -ln(1 - u') >= 0
+    return __builtin_amdgcn_sqrtf(fmaxf(L, 0.0f)) - 1.0f;
+}
+
+__device__ __forceinline__ float pair_d_of_y(float y, float chi, bool upper) {
+    const float D = fminf(fmaxf(y * pair_width(chi), 0.0f), 0.5f - 0x1p-24f);
+    return upper ? 0.5f + D : 0.5f - D;
+}
+
 // x = y (b / (1 + b))^(1/3), b = 3 chi / 2, clamped to the open interval (0, 1).
 __device__ __forceinline__ float mlp_x_of_y(float y, float chi) {
     const float b = 1.5f * chi;

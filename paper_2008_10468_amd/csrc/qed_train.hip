@@ -40,21 +40,37 @@ __device__ __forceinline__ double emission_density(double x, double b, const Syn
     return (omx3 * F + x3 * x3 * G) / x;
 }
 
+// Energy split of pair creation: the Baier-Katkov density (3/2) chi (G(z) - d(1-d) F(z)),
+// z = 2/(3 chi d (1-d)), of the electron's fraction d (eq. (2) over its prefactor).
+__device__ __forceinline__ double pair_density(double d, double chi, const SynTable<double> &tab) {
+    const double dd = d * (1.0 - d);
+    if (dd <= 0.0) return 0.0;
+    double F, G;
+    syn_eval(2.0 / (3.0 * chi * dd), tab, F, G);
+    return 1.5 * chi * (G - dd * F);
+}
+
+// Density of the table's variable per unit of xi = k / nx at xi (kind 0: x(xi) with
+// the grid's Jacobian; kind 1: D = xi / 2 of the half-distribution, d = 1/2 + D).
+__device__ __forceinline__ double table_density(int kind, double xi, double l10, const SynTable<double> &tab) {
+    if (kind == 0) return emission_density(cdf_x_of_xi(xi), 1.5 * exp10(l10), tab) * 2.0 * (1.0 - xi);
+    return 0.5 * pair_density(0.5 + 0.5 * xi, exp10(l10), tab);
+}
+
 __global__ __launch_bounds__(kBlock) void k_cdf_table(CdfTableDev t) {
     __shared__ SynTable<double> tab;
     __shared__ double wsum[kBlock / 64];
     syn_stage(tab);
     const int c = blockIdx.x;
     const double l10 = t.lo10 + (t.hi10 - t.lo10) * (double)c / (double)(t.nchi - 1);
-    const double b = 1.5 * exp10(l10);
     const int per = t.nx / kBlock;  // intervals per thread
     const double h = 1.0 / (double)t.nx;
     const int k0 = threadIdx.x * per;
     double part = 0.0;
-    double dprev = emission_density(cdf_x_of_xi(k0 * h), b, tab) * 2.0 * (1.0 - k0 * h);
+    double dprev = table_density(t.kind, k0 * h, l10, tab);
     for (int k = k0; k < k0 + per; ++k) {
         const double xi = (k + 1) * h;
-        const double d = emission_density(cdf_x_of_xi(xi), b, tab) * 2.0 * (1.0 - xi);
+        const double d = table_density(t.kind, xi, l10, tab);
         part += 0.5 * h * (dprev + d);
         dprev = d;
     }
@@ -80,22 +96,24 @@ __global__ __launch_bounds__(kBlock) void k_cdf_table(CdfTableDev t) {
     }
     // second pass: the running sum (same order of additions as above)
     double acc = off;
-    dprev = emission_density(cdf_x_of_xi(k0 * h), b, tab) * 2.0 * (1.0 - k0 * h);
+    dprev = table_density(t.kind, k0 * h, l10, tab);
     for (int k = k0; k < k0 + per; ++k) {
         const double xi = (k + 1) * h;
-        const double d = emission_density(cdf_x_of_xi(xi), b, tab) * 2.0 * (1.0 - xi);
+        const double d = table_density(t.kind, xi, l10, tab);
         acc += 0.5 * h * (dprev + d);
         dprev = d;
         row[k + 1] = k + 1 == t.nx ? 1.0 : fmin(acc / total, 1.0);
     }
 }
 
-// Table CDF at (log10 chi, x), linear in xi and in log10 chi between nodes.
+// Table CDF at (log10 chi, x), linear in xi and in log10 chi between nodes (x: the
+// candidate for kind 0, the distance D from 1/2 for kind 1).
 __device__ __forceinline__ double cdf_lookup(const CdfTableDev &t, double l10, double x) {
     const double cpos = (l10 - t.lo10) / (t.hi10 - t.lo10) * (double)(t.nchi - 1);
     const int j = min(max((int)floor(cpos), 0), t.nchi - 2);
     const double w = fmin(fmax(cpos - j, 0.0), 1.0);
-    const double xi = cdf_xi_of_x(fmin(fmax(x, 0.0), 1.0)) * (double)t.nx;
+    const double xi = (t.kind == 0 ? cdf_xi_of_x(fmin(fmax(x, 0.0), 1.0)) : fmin(fmax(2.0 * x, 0.0), 1.0)) *
+                      (double)t.nx;
     const int k = min((int)xi, t.nx - 1);
     const double f = xi - k;
     const double *r0 = t.cdf + (u64)j * (t.nx + 1), *r1 = r0 + (t.nx + 1);
@@ -125,12 +143,19 @@ __device__ __forceinline__ void cdf_invert(const CdfTableDev &t, double l10, dou
     const double dm = m1 - m0;
     const double f = dm > 0.0 ? (u - m0) / dm : 0.5;
     const double xi = ((double)lo + f) / (double)t.nx;
-    x = cdf_x_of_xi(xi);
-    dens = dm * (double)t.nx / fmax(2.0 * (1.0 - xi), 1e-300);
+    if (t.kind == 0) {
+        x = cdf_x_of_xi(xi);
+        dens = dm * (double)t.nx / fmax(2.0 * (1.0 - xi), 1e-300);
+    } else {
+        x = 0.5 * xi;
+        dens = dm * (double)t.nx * 2.0;
+    }
 }
 
-// Largest network input v: u = 1 - 2^-24, the largest float uniform, gives 1.55.
+// Largest network input v: u = 1 - 2^-24, the largest float uniform, gives 1.55
+// (emission) and 3.08 (pairs, v = sqrt(-ln(1 - u')) - 1).
 constexpr double kVmax = 1.6;
+constexpr double kVmaxPair = 3.1;
 
 __global__ __launch_bounds__(kBlock) void k_mlp_data(CdfTableDev t, Sample *out, u64 n, uint64_t seed,
                                                      uint32_t step, double lo10, double hi10) {
@@ -141,13 +166,15 @@ __global__ __launch_bounds__(kBlock) void k_mlp_data(CdfTableDev t, Sample *out,
         // the network input v = (-ln(1 - u))^(1/3) - 1 is drawn uniformly on
         // [-1, kVmax] (u = 1 - exp(-(v + 1)^3)), so the tails of the spectrum are
         // sampled as densely as its bulk
-        const double v = -1.0 + (kVmax + 1.0) * u53(w.z, w.w);
-        const double u = -expm1(-(v + 1.0) * (v + 1.0) * (v + 1.0));
+        const double vmax = t.kind == 0 ? kVmax : kVmaxPair;
+        const double v = -1.0 + (vmax + 1.0) * u53(w.z, w.w);
+        const double u = t.kind == 0 ? -expm1(-(v + 1.0) * (v + 1.0) * (v + 1.0)) : -expm1(-(v + 1.0) * (v + 1.0));
         const double l10 = lo10 + (hi10 - lo10) * tl;
         double x, dens;
         cdf_invert(t, l10, u, x, dens);
-        const double b = 1.5 * exp10(l10);
-        const double xs = cbrt(b / (1.0 + b));
+        // output scale: (b / (1 + b))^(1/3) of x (emission), the split's width (pairs)
+        const double xs = t.kind == 0 ? cbrt(1.5 * exp10(l10) / (1.0 + 1.5 * exp10(l10)))
+                                      : (double)pair_width((float)exp10(l10));
         Sample s;
         s.s = (float)(2.0 * tl - 1.0);
         s.v = (float)v;
@@ -512,18 +539,21 @@ __global__ __launch_bounds__(kBlock) void k_mlp_pack(const float *params, MlpMod
     if (threadIdx.x == 0) out->b4 = M.b4;
 }
 
-// x of the packed network for (chi, u); NaN where the model does not sample.
-__device__ __forceinline__ float infer_one(const MlpLds &M, MlpWave &W, bool valid, float chi, float u) {
+// x of the packed network for (chi, u) (kind 1: the electron's fraction d); NaN
+// where the model does not sample.
+__device__ __forceinline__ float infer_one(const MlpLds &M, MlpWave &W, bool valid, float chi, float u, int kind) {
     bool in_range;
     int bin;
     const float s = mlp_input_s(M, chi, in_range, bin);
     const bool use = valid && in_range && !M.fallback[bin];
-    const float y = mlp_infer_wave(M, W, use, s, mlp_input_v(u));
-    return use ? mlp_x_of_y(y, chi) : __builtin_nanf("");
+    const float v = kind == 0 ? mlp_input_v(u) : mlp_input_v_pair(fabsf(2.0f * u - 1.0f));
+    const float y = mlp_infer_wave(M, W, use, s, v);
+    if (!use) return __builtin_nanf("");
+    return kind == 0 ? mlp_x_of_y(y, chi) : pair_d_of_y(y, chi, u >= 0.5f);
 }
 
 __global__ __launch_bounds__(kBlock) void k_mlp_infer(const MlpModel *model, const float *chi, const float *u,
-                                                      float *x, u64 n) {
+                                                      float *x, u64 n, int kind) {
     __shared__ MlpLds M;
     __shared__ MlpWave ws[kBlock / 64];
     mlp_stage(model, M);
@@ -532,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_infer(const MlpModel *model, con
     for (u64 i0 = (u64)blockIdx.x * kBlock; i0 < n; i0 += (u64)gridDim.x * kBlock) {
         const u64 i = i0 + threadIdx.x;
         const bool valid = i < n;
-        const float xi = infer_one(M, W, valid, valid ? chi[i] : 1.0f, valid ? u[i] : 0.5f);
+        const float xi = infer_one(M, W, valid, valid ? chi[i] : 1.0f, valid ? u[i] : 0.5f, kind);
         if (valid) x[i] = xi;
     }
 }
@@ -556,8 +586,9 @@ __global__ __launch_bounds__(kBlock) void k_mlp_validate(const MlpModel *model, 
         bool in_range;
         int b;
         const float s = mlp_input_s(M, chi, in_range, b);
-        const float y = mlp_infer_wave(M, W, true, s, mlp_input_v(u));
-        const float x = mlp_x_of_y(y, chi);
+        const float y = mlp_infer_wave(M, W, true, s, t.kind == 0 ? mlp_input_v(u) : mlp_input_v_pair(u));
+        // kind 1: u is u' of the half-distribution, the network gives D
+        const float x = t.kind == 0 ? mlp_x_of_y(y, chi) : fminf(fmaxf(y * pair_width(chi), 0.0f), 0.5f);
         const double c = cdf_lookup(t, log10((double)chi), (double)x);
         emax = fmaxf(emax, (float)fabs(c - (double)u));
     }
@@ -607,8 +638,8 @@ hipError_t launch_mlp_validate(const MlpModel *model, const CdfTableDev &t, int 
 }
 
 hipError_t launch_mlp_infer(const MlpModel *model, const float *chi, const float *u, float *x, u64 n, int blocks,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(kBlock), 0, s, model, chi, u, x, n);
+                            hipStream_t s, int kind) {
+    hipLaunchKernelGGL(k_mlp_infer, dim3(blocks), dim3(kBlock), 0, s, model, chi, u, x, n, kind);
     return hipGetLastError();
 }
 

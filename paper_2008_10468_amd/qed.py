@@ -83,7 +83,8 @@ class qed_train_config(C.Structure):
     _fields_ = [("log10_chi_lo", C.c_double), ("log10_chi_hi", C.c_double),
                 ("table_chi", C.c_uint32), ("table_x", C.c_uint32), ("steps", C.c_uint32),
                 ("blocks", C.c_uint32), ("batch_tiles", C.c_uint32), ("lr", C.c_float), ("lr_final", C.c_float),
-                ("seed", C.c_uint64), ("nbins", C.c_int32), ("per_bin", C.c_int32), ("tolerance", C.c_double)]
+                ("seed", C.c_uint64), ("nbins", C.c_int32), ("per_bin", C.c_int32), ("tolerance", C.c_double),
+                ("target", C.c_int32), ("pad", C.c_int32)]
 
 
 class qed_kernel_time(C.Structure):
@@ -94,7 +95,8 @@ EXPORTS = ("qed_config_default", "qed_init", "qed_step", "qed_sync", "qed_synchr
            "qed_get_stats", "qed_reset_stats", "qed_get_tuning", "qed_set_tuning",
            "qed_profile_enable", "qed_profile_read", "qed_graph_begin", "qed_graph_end",
            "qed_graph_launch", "qed_graph_destroy",
-           "qed_step_counted", "qed_pair_rate", "qed_event_gaps", "qed_gather", "qed_deposit", "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
+           "qed_step_counted", "qed_pair_rate", "qed_event_gaps", "qed_gather", "qed_deposit",
+           "qed_pair_sampler_set", "qed_pair_sampler_infer", "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
            "qed_train_config_default", "qed_train_sampler", "qed_mlp_gradient",
            "qed_finalize", "qed_status_string")
 
@@ -130,6 +132,8 @@ def load(path: str = LIB_PATH):
     L.qed_graph_destroy.restype = None
     L.qed_sampler_set.argtypes = [C.c_void_p, C.POINTER(qed_sampler_model)]
     L.qed_sampler_infer.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
+    L.qed_pair_sampler_set.argtypes = [C.c_void_p, C.POINTER(qed_sampler_model)]
+    L.qed_pair_sampler_infer.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
     L.qed_emission_rate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
     L.qed_pair_rate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
     L.qed_event_gaps.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32]
@@ -261,15 +265,28 @@ def _ptr(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
-def qed_sampler_set(ctx, params=None, fallback=None, log10_chi_lo=-3.0, log10_chi_hi=2.0):
-    """Install a model (numpy float32 params, uint8 fallback flags per bin) or remove it (None)."""
+def _set_model(fn, ctx, params, fallback, log10_chi_lo, log10_chi_hi):
     if params is None:
-        return load().qed_sampler_set(ctx, None)
+        return fn(ctx, None)
     p = np.ascontiguousarray(params, np.float32)
     fb = np.ascontiguousarray(fallback, np.uint8)
     m = qed_sampler_model(params=_ptr(p).value, fallback=_ptr(fb).value, nbins=int(fb.size), pad=0,
                           log10_chi_lo=float(log10_chi_lo), log10_chi_hi=float(log10_chi_hi))
-    return load().qed_sampler_set(ctx, C.byref(m))
+    return fn(ctx, C.byref(m))
+
+
+def qed_sampler_set(ctx, params=None, fallback=None, log10_chi_lo=-3.0, log10_chi_hi=2.0):
+    """Install a model (numpy float32 params, uint8 fallback flags per bin) or remove it (None)."""
+    return _set_model(load().qed_sampler_set, ctx, params, fallback, log10_chi_lo, log10_chi_hi)
+
+
+def qed_pair_sampler_set(ctx, params=None, fallback=None, log10_chi_lo=-1.5, log10_chi_hi=2.5):
+    """Install (or remove) the photon path's network of the energy split."""
+    return _set_model(load().qed_pair_sampler_set, ctx, params, fallback, log10_chi_lo, log10_chi_hi)
+
+
+def qed_pair_sampler_infer(ctx, chi, u, d, n):
+    return load().qed_pair_sampler_infer(ctx, chi, u, d, int(n))
 
 
 def qed_sampler_infer(ctx, chi, u, x, n):

@@ -1,0 +1,103 @@
+"""The photon path's learned energy split (row f2): a network of the emission sampler's
+shape trained on the GPU (target 1) on the half-distribution of the electron's fraction
+about 1/2, checked against the oracle's pair CDF, and used by decaying photons."""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+LO, HI = -1.5, 2.5
+
+
+@pytest.fixture(scope="module")
+def pair_trained():
+    from paper_2008_10468_amd import qed
+    ctx = qed.qed_init(qed.qed_config_default())
+    cfg = qed.qed_train_config_default()
+    cfg.target = 1
+    cfg.log10_chi_lo, cfg.log10_chi_hi = LO, HI
+    cfg.tolerance = 2e-3   # the split's CDF error that a bin may keep before it falls back
+    print("training the split network", flush=True)
+    params, loss, err, fb = qed.qed_train_sampler(ctx, cfg)
+    qed.qed_finalize(ctx)
+    return cfg, params, loss, err, fb
+
+
+def test_split_network_trains(pair_trained):
+    cfg, params, loss, err, fb = pair_trained
+    assert np.all(np.isfinite(params))
+    assert loss[-1] < 1e-2 * loss[0]
+    assert np.mean(err <= cfg.tolerance) >= 0.8, err
+    assert err.max() < 5 * cfg.tolerance, err
+
+
+def test_split_network_against_oracle(pair_trained):
+    """Where the network is used: the oracle's CDF at the drawn d equals u to 3e-3."""
+    from paper_2008_10468_amd import qed
+    cfg, params, loss, err, fb = pair_trained
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(16, 16, 16))
+    assert qed.qed_pair_sampler_set(g.ctx, params, fb, LO, HI) == qed.QED_OK
+    chis = np.array([0.05, 0.3, 2.0, 20.0, 200.0], np.float32)
+    us = (np.arange(1, 400) / 400.0).astype(np.float32)
+    chi = np.repeat(chis, us.size)
+    u = np.tile(us, chis.size)
+    tc, tu = torch.from_numpy(chi).cuda(), torch.from_numpy(u).cuda()
+    out = torch.empty_like(tc)
+    assert qed.qed_pair_sampler_infer(g.ctx, tc.data_ptr(), tu.data_ptr(), out.data_ptr(), chi.size) == qed.QED_OK
+    d = out.cpu().numpy()
+    g.close()
+    used = ~np.isnan(d)
+    assert used.mean() > 0.8
+    errs = [abs(oracle.pair_cdf(float(c), float(x)) - float(q)) for c, x, q in zip(chi[used], d[used], u[used])]
+    assert max(errs) < 3e-3, max(errs)
+
+
+def test_decays_with_the_split_network(pair_trained):
+    from paper_2008_10468_amd import qed
+    cfg, params, loss, err, fb = pair_trained
+    n, eps, chi = 200_000, 2000.0, 2.0
+    W = oracle.pair_prob(chi, eps, 1.0)
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(2 * n, 2 * n, 2 * n), emission=False,
+                      pair_sampler=qed.QED_SAMPLER_SURROGATE)
+    assert qed.qed_pair_sampler_set(g.ctx, params, fb, LO, HI) == qed.QED_OK
+    ph = {"x": np.zeros(n), "y": np.zeros(n), "z": np.zeros(n), "ux": np.full(n, eps), "uy": np.zeros(n),
+          "uz": np.zeros(n), "w": np.ones(n), "id": np.arange(1 << 20, (1 << 20) + n, dtype=np.uint64)}
+    emp = {k: np.zeros(0) for k in ("x", "y", "z", "ux", "uy", "uz", "w")}
+    emp["id"] = np.zeros(0, np.uint64)
+    g.load_state({"electrons": emp, "positrons": emp, "photons": ph})
+    g.set_fields(workloads.uniform_field(bz=chi / eps))
+    g.step(0.7 / W, 3, 0)
+    assert g.sync()[0] == qed.QED_OK
+    el = g.sp[0].download()
+    st = g.stats()
+    g.close()
+    nd = el["id"].size
+    p = 1 - math.exp(-0.7)
+    assert abs(nd / n - p) <= 3.5 * math.sqrt(p * (1 - p) / n)
+    assert st.pair_learned + st.pair_fallback == nd and st.pair_learned > 0.9 * nd
+    d = np.sort(np.sqrt(1 + el["ux"] ** 2 + el["uy"] ** 2 + el["uz"] ** 2) / eps)
+    for q in (0.05, 0.25, 0.5, 0.75, 0.95):
+        c = oracle.pair_cdf(chi, d[int(q * nd)])
+        assert abs(c - q) <= 4 * math.sqrt(q * (1 - q) / nd) + 2e-3, (q, c)
+
+
+def test_split_network_configuration():
+    from paper_2008_10468_amd import qed
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(16, 16, 16))
+    x = torch.zeros(4, device="cuda")
+    assert qed.qed_pair_sampler_infer(g.ctx, x.data_ptr(), x.data_ptr(), x.data_ptr(), 4) == qed.QED_ERR_STATE
+    assert qed.qed_pair_sampler_set(g.ctx, None) == qed.QED_OK
+    cfg = qed.qed_train_config_default()
+    cfg.target = 2
+    params = np.zeros(qed.QED_MLP_NPARAMS, np.float32)
+    st = qed.load().qed_train_sampler(g.ctx, C.byref(cfg), None, params.ctypes.data, None, None, None)
+    assert st == qed.QED_ERR_INVALID_ARG
+    g.close()
