@@ -113,11 +113,11 @@ def lib():
             fld = C.POINTER(_D)
             L.orc_lepton_batch.argtypes = [C.POINTER(Params), C.c_double, C.c_int64,
                                            _D, _D, _D, _D, _D, _D, _D, _U64, _D, fld, C.c_int64,
-                                           _U32, _U32, C.POINTER(Children), C.POINTER(Tally)]
+                                           _U32, _U32, C.POINTER(Children), C.POINTER(Tally), _U32]
             L.orc_lepton_batch.restype = C.c_int64
             L.orc_photon_batch.argtypes = [C.POINTER(Params), C.c_int64,
                                            _D, _D, _D, _D, _D, _D, _D, _U64, _D, fld, C.c_int64,
-                                           _U8, _U32, _U32, C.POINTER(Children), C.POINTER(Tally)]
+                                           _U8, _U32, _U32, C.POINTER(Children), C.POINTER(Tally), _U32]
             L.orc_photon_batch.restype = C.c_int64
             _lib = L
     return _lib
@@ -316,14 +316,22 @@ def _t0_ptr(t0, a):
     return None if t0 is None else C.cast(t0.ctypes.data + 8 * a, _D)
 
 
+def _nf_ptr(nf, a):
+    return None if nf is None else C.cast(nf.ctypes.data + 4 * a, _U32)
+
+
 def lepton_step(state, fields, q, dt, seed, step, p_max=0.01, rng_bits=53, n_cap=1 << 24,
-                threads=None, t0=None):
+                threads=None, t0=None, nsub=None):
     """Algorithm 1 on arrays.  ``state`` has float64 arrays ux,uy,uz,x,y,z,w and uint64 id;
     they are updated in place.  ``t0`` (optional float64 array): each particle's start
-    time within the step (it runs over dt - t0).  Returns (children dict, per-particle
-    nsub, per-particle event counts, tally dict); children carry their birth time tb."""
+    time within the step (it runs over dt - t0).  ``nsub`` (optional uint32 array): the
+    number of sub-steps each particle takes instead of its own (0 keeps its own; see
+    cell_substeps).  Returns (children dict, per-particle nsub, per-particle event
+    counts, tally dict); children carry their birth time tb."""
     if t0 is not None:
         t0 = np.ascontiguousarray(t0, np.float64)
+    if nsub is not None:
+        nsub = np.ascontiguousarray(nsub, np.uint32)
     n = state["id"].size
     for k in ("ux", "uy", "uz", "x", "y", "z", "w"):
         assert state[k].dtype == np.float64 and state[k].flags.c_contiguous
@@ -347,7 +355,7 @@ def lepton_step(state, fields, q, dt, seed, step, p_max=0.01, rng_bits=53, n_cap
                 C.byref(P), q, m, ptr("ux"), ptr("uy"), ptr("uz"), ptr("x"), ptr("y"), ptr("z"),
                 ptr("w"), ptr("id", C.c_uint64), _t0_ptr(t0, a), fp, stride,
                 C.cast(nsub_a.ctypes.data + 4 * a, _U32), C.cast(nev_a.ctypes.data + 4 * a, _U32),
-                C.byref(ch), C.byref(tl))
+                C.byref(ch), C.byref(tl), _nf_ptr(nsub, a))
             if ch.n <= cap:
                 break
             for k, v in saved.items():   # rerun the chunk with room for every child
@@ -367,12 +375,14 @@ def lepton_step(state, fields, q, dt, seed, step, p_max=0.01, rng_bits=53, n_cap
 
 
 def photon_step(state, fields, dt, seed, step, p_max=0.01, rng_bits=53, pair_coef=0.1,
-                n_cap=1 << 24, threads=None, t0=None):
+                n_cap=1 << 24, threads=None, t0=None, nsub=None):
     """Algorithm 2 on arrays (state: photon momentum k in ux,uy,uz, and x,y,z,w float64,
-    id uint64; updated in place; t0 as for lepton_step).
+    id uint64; updated in place; t0 and nsub as for lepton_step).
     Returns (children dict [kind 1 = e-, 2 = e+], alive mask, nsub, events, tally)."""
     if t0 is not None:
         t0 = np.ascontiguousarray(t0, np.float64)
+    if nsub is not None:
+        nsub = np.ascontiguousarray(nsub, np.uint32)
     n = state["id"].size
     fl, stride = _fields(fields, n)
     alive = np.ones(n, np.uint8)
@@ -394,7 +404,7 @@ def photon_step(state, fields, dt, seed, step, p_max=0.01, rng_bits=53, pair_coe
             ptr("w"), ptr("id", C.c_uint64), _t0_ptr(t0, a), fp, stride,
             C.cast(alive.ctypes.data + a, _U8),
             C.cast(nsub_a.ctypes.data + 4 * a, _U32), C.cast(nev_a.ctypes.data + 4 * a, _U32),
-            C.byref(ch), C.byref(tl))
+            C.byref(ch), C.byref(tl), _nf_ptr(nsub, a))
         assert ch.n <= cap
         res = {k: v[:ch.n].copy() for k, v in arrs.items()}
         res["tally"] = (tl.substeps, tl.events, tl.clips, tl.max_p, bad)
@@ -407,6 +417,58 @@ def photon_step(state, fields, dt, seed, step, p_max=0.01, rng_bits=53, pair_coe
                  max_p=max([r["tally"][3] for r in results], default=0.0),
                  nonfinite=sum(r["tally"][4] for r in results))
     return _merge(results), alive, nsub_a, nev_a, tally
+
+
+# ---------------------------------------------------------------- sub-steps per cell
+
+def own_substeps(state, fields, dt, photons=False, p_max=0.01, pair_coef=0.1, n_cap=1 << 24):
+    """Step 1 of Algorithm 1 (leptons) or 2 (photons=True) for each particle on its own:
+    the sub-step count N = max(1, ceil(f / P_max)) from the bound f of Sec. 3.1.1 over dt,
+    one particle at a time; 0 for a particle with non-finite momentum or field."""
+    n = state["id"].size
+    fl, stride = _fields(fields, n)
+    out = np.zeros(n, np.uint32)
+    for i in range(n):
+        u = np.array([state["ux"][i], state["uy"][i], state["uz"][i]], np.float64)
+        E = np.array([fl[0][i * stride], fl[1][i * stride], fl[2][i * stride]])
+        B = np.array([fl[3][i * stride], fl[4][i * stride], fl[5][i * stride]])
+        if not (np.all(np.isfinite(u)) and np.all(np.isfinite(E)) and np.all(np.isfinite(B))):
+            continue
+        if photons:
+            eps = float(np.sqrt(u @ u))
+            out[i] = 1 if eps == 0.0 else nsub(bound_pair(chi_photon(u, E, B), eps, dt, pair_coef), p_max, n_cap)
+        else:
+            gamma = float(np.sqrt(1.0 + u @ u))
+            out[i] = nsub(bound_emission(chi_lepton(u, E, B), gamma, dt), p_max, n_cap)
+    return out
+
+
+def cell_substeps(electrons, positrons, photons, fields, cells, dt, p_max=0.01, pair_coef=0.1,
+                  n_cap=1 << 24):
+    """Algorithms 1 and 2, step 1, with the sub-step chosen for the current cell: every
+    particle's own count (own_substeps, over the whole step dt), then in each cell of
+    ``cells`` (a grid geometry, oracle.grid.cell_index) the largest count among its
+    electrons and positrons together (Algorithm 1) and, separately, among its photons
+    (Algorithm 2).  fields: the three species' fields.  Returns, per species, the count
+    each particle takes: its cell's, or its own where its position is not finite or its
+    own count is 0 (non-finite input)."""
+    from oracle import grid as _grid
+    ncell = cells["nx"] * cells["ny"] * cells["nz"]
+    sp = (electrons, positrons, photons)
+    own = [own_substeps(sp[s], fields[s], dt, photons=(s == 2), p_max=p_max, pair_coef=pair_coef, n_cap=n_cap)
+           for s in range(3)]
+    cell = [_grid.cell_index(cells, sp[s]["x"], sp[s]["y"], sp[s]["z"]) for s in range(3)]
+    best = [np.zeros(ncell, np.uint32), np.zeros(ncell, np.uint32)]   # leptons, photons
+    for s in range(3):
+        ok = (cell[s] >= 0) & (own[s] > 0)
+        np.maximum.at(best[s // 2], cell[s][ok], own[s][ok])
+    out = []
+    for s in range(3):
+        ok = (cell[s] >= 0) & (own[s] > 0)
+        n = own[s].copy()
+        n[ok] = best[s // 2][cell[s][ok]]
+        out.append(n)
+    return out
 
 
 # ---------------------------------------------------------------- cascades

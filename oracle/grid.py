@@ -13,9 +13,13 @@ Interpolation: linear (cloud-in-cell) in each direction on the component's own
 lattice, periodic.  Deposition: every particle adds q w u / gamma (its current, with
 u/gamma its velocity in units of c) times the same weights, divided by the cell
 volume, to Jx, Jy, Jz.  Written as the definition, one particle and one corner at a
-time (numpy over particles).  Pinned in tests/test_oracle_grid.py.
+time (numpy over particles).  Cells (for sub-steps chosen per cell): the node cells
+[x0 + i dx, x0 + (i + 1) dx) x ..., periodic.  Pinned in tests/test_oracle_grid.py and
+tests/test_oracle_cells.py.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -41,6 +45,24 @@ def _corners(grid, x, y, z, off):
                 w = ((fr[0] if cx else 1.0 - fr[0]) * (fr[1] if cy else 1.0 - fr[1]) *
                      (fr[2] if cz else 1.0 - fr[2]))
                 out.append(((k * n[1] + j) * n[0] + i, w))
+    return out
+
+
+def cell_index(grid, x, y, z):
+    """Flat index (k ny + j) nx + i of the grid cell [x0 + i dx, x0 + (i + 1) dx) x (same in
+    y, z) that holds each position, periodic (i = floor((x - x0) / dx) mod nx, exact integer
+    arithmetic); -1 where a coordinate or (x - x0) / dx is not finite."""
+    x, y, z = (np.atleast_1d(np.asarray(v, np.float64)) for v in (x, y, z))
+    out = np.full(x.size, -1, np.int64)
+    for p in range(x.size):
+        idx = []
+        for v, o, d, n in ((x[p], "x0", "dx", "nx"), (y[p], "y0", "dy", "ny"), (z[p], "z0", "dz", "nz")):
+            s = (float(v) - grid[o]) / grid[d]
+            if not math.isfinite(s):
+                break
+            idx.append(math.floor(s) % grid[n])
+        if len(idx) == 3:
+            out[p] = (idx[2] * grid["ny"] + idx[1]) * grid["nx"] + idx[0]
     return out
 
 

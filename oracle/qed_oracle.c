@@ -364,9 +364,11 @@ static int all_finite(const double *v, int n)
 /* Returns 0, or -1 if the particle had non-finite input and was left alone.
  * t0: the time within the step at which the particle starts (0 for particles
  * present at the step start; the birth time of a child in a cascade pass); it
- * runs Algorithm 1 over the remaining time dt - t0. */
+ * runs Algorithm 1 over the remaining time dt - t0.  nforce: 0, or the number of
+ * sub-steps to take instead of the particle's own (a sub-step chosen for the
+ * particle's cell). */
 static int lepton_one(const orc_params *P, double t0, double q, double u[3], double pos[3], double w,
-                      uint64_t id, const double E[3], const double B[3], uint32_t *nsub_out,
+                      uint64_t id, const double E[3], const double B[3], uint32_t nforce, uint32_t *nsub_out,
                       uint32_t *nev_out, orc_children *ch, orc_tally *tl)
 {
     if (!all_finite(u, 3) || !all_finite(E, 3) || !all_finite(B, 3)) {
@@ -379,6 +381,7 @@ static int lepton_one(const orc_params *P, double t0, double q, double u[3], dou
     double chi0 = orc_chi_lepton(u, E, B);
     double dt = P->dt - t0;
     uint32_t N = orc_nsub(orc_bound_emission(chi0, gamma0, dt), P->p_max, P->n_cap);
+    if (nforce) N = nforce;
     double st = dt / (double)N;
     uint32_t nev = 0;
     for (uint32_t i = 0; i < N; ++i) {
@@ -429,10 +432,10 @@ static int lepton_one(const orc_params *P, double t0, double q, double u[3], dou
 }
 
 /* Algorithm 2 for one photon.  Returns 1 if it decayed, 0 if it survived,
- * -1 for non-finite input (left alone, alive). */
+ * -1 for non-finite input (left alone, alive).  nforce as for lepton_one. */
 static int photon_one(const orc_params *P, double t0, double k[3], double pos[3], double w, uint64_t id,
-                      const double E[3], const double B[3], uint32_t *nsub_out, uint32_t *nev_out,
-                      orc_children *ch, orc_tally *tl)
+                      const double E[3], const double B[3], uint32_t nforce, uint32_t *nsub_out,
+                      uint32_t *nev_out, orc_children *ch, orc_tally *tl)
 {
     if (!all_finite(k, 3) || !all_finite(E, 3) || !all_finite(B, 3)) {
         *nsub_out = 0;
@@ -444,6 +447,7 @@ static int photon_one(const orc_params *P, double t0, double k[3], double pos[3]
     double dt = P->dt - t0;
     uint32_t N = 1;
     if (eps > 0.0) N = orc_nsub(orc_bound_pair(chi0, eps, dt, P->pair_coef), P->p_max, P->n_cap);
+    if (nforce) N = nforce;
     double st = dt / (double)N;
     double dir[3] = {0.0, 0.0, 0.0};
     if (eps > 0.0) {
@@ -493,12 +497,13 @@ static int photon_one(const orc_params *P, double t0, double k[3], double pos[3]
 
 /* Batch drivers.  Fields are six arrays (Ex,Ey,Ez,Bx,By,Bz) read at index
  * i*fstride (fstride 0: one field for all).  t0 (may be NULL: all zero) gives each
- * particle's start time within the step.  Children are appended in particle
+ * particle's start time within the step; nforce (may be NULL: all zero) forced
+ * sub-step counts (0: the particle's own).  Children are appended in particle
  * order, then sub-step order.  Return value: number of non-finite particles. */
 int64_t orc_lepton_batch(const orc_params *P, double q, int64_t n, double *ux, double *uy, double *uz,
                          double *x, double *y, double *z, const double *w, const uint64_t *id,
                          const double *t0, const double *const fld[6], int64_t fstride, uint32_t *nsub,
-                         uint32_t *nev, orc_children *ch, orc_tally *tl)
+                         uint32_t *nev, orc_children *ch, orc_tally *tl, const uint32_t *nforce)
 {
     int64_t bad = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -507,7 +512,8 @@ int64_t orc_lepton_batch(const orc_params *P, double q, int64_t n, double *ux, d
         double B[3] = {fld[3][f], fld[4][f], fld[5][f]};
         double u[3] = {ux[i], uy[i], uz[i]};
         double pos[3] = {x[i], y[i], z[i]};
-        if (lepton_one(P, t0 ? t0[i] : 0.0, q, u, pos, w[i], id[i], E, B, &nsub[i], &nev[i], ch, tl) < 0) {
+        if (lepton_one(P, t0 ? t0[i] : 0.0, q, u, pos, w[i], id[i], E, B, nforce ? nforce[i] : 0u, &nsub[i],
+                       &nev[i], ch, tl) < 0) {
             bad++;
             continue;
         }
@@ -524,7 +530,7 @@ int64_t orc_lepton_batch(const orc_params *P, double q, int64_t n, double *ux, d
 int64_t orc_photon_batch(const orc_params *P, int64_t n, double *kx, double *ky, double *kz, double *x,
                          double *y, double *z, const double *w, const uint64_t *id, const double *t0,
                          const double *const fld[6], int64_t fstride, uint8_t *alive, uint32_t *nsub,
-                         uint32_t *nev, orc_children *ch, orc_tally *tl)
+                         uint32_t *nev, orc_children *ch, orc_tally *tl, const uint32_t *nforce)
 {
     int64_t bad = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -533,7 +539,8 @@ int64_t orc_photon_batch(const orc_params *P, int64_t n, double *kx, double *ky,
         double B[3] = {fld[3][f], fld[4][f], fld[5][f]};
         double k[3] = {kx[i], ky[i], kz[i]};
         double pos[3] = {x[i], y[i], z[i]};
-        int r = photon_one(P, t0 ? t0[i] : 0.0, k, pos, w[i], id[i], E, B, &nsub[i], &nev[i], ch, tl);
+        int r = photon_one(P, t0 ? t0[i] : 0.0, k, pos, w[i], id[i], E, B, nforce ? nforce[i] : 0u, &nsub[i],
+                           &nev[i], ch, tl);
         if (r < 0) {
             bad++;
             alive[i] = 1;
