@@ -372,6 +372,24 @@ QED_API qed_status qed_deposit(qed_ctx *ctx, const qed_grid *grid, const qed_spe
  * nbins >= 2, else QED_ERR_INVALID_ARG. */
 QED_API qed_status qed_event_gaps(qed_ctx *ctx, uint64_t *hist, uint32_t nbins);
 
+/* Sub-steps chosen per cell (Algorithms 1 and 2, step 1: the sub-step is computed for
+ * the current cell).  With a cell geometry set, every following qed_step first finds
+ * each particle's own count N of Sec. 3.1.1 (as without cells), then runs every
+ * particle with the largest N of its group in its cell: electrons and positrons form
+ * one group (Algorithm 1), photons another (Algorithm 2).  Cell (i, j, k) is
+ * [x0 + i dx, x0 + (i + 1) dx) x [y0 + j dy, ...) x [z0 + k dz, ...), periodic in all three
+ * indices (the node cells of the qed_gather grid); a particle's cell is taken from
+ * its position at the step start (exactly while |(x - x0) / dx| < 2^53 / nx).  A
+ * particle with a non-finite position, momentum or field keeps its own count and
+ * joins no cell.  The field pointers of cells are not used.  NULL returns to
+ * per-particle counts (the default).  Needs the rejection samplers and no cascades
+ * (QED_ERR_STATE otherwise, and while a graph is being recorded); INVALID_ARG for
+ * nx, ny or nz < 1, nx ny nz > 2^28, cell sizes that are not positive and finite, or
+ * a non-finite origin.  The library allocates 2 nx ny nz uint32 counts (HOST-side
+ * geometry, copied); a graph keeps the geometry in force when it was recorded, and
+ * buffers it may use stay allocated until qed_finalize. */
+QED_API qed_status qed_substep_cells(qed_ctx *ctx, const qed_grid *cells);
+
 /* The normalised CDF of eq. (1) over the candidate x, as the trainer tabulates it
  * (double, from the double fits of F and G, trapezoid rule): nchi (>= 2) values
  * of chi log-uniform over [10^lo, 10^hi], each at the nx + 1 points

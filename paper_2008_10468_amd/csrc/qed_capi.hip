@@ -38,6 +38,12 @@ struct qed_ctx {
     uint64_t *gap_hist;       // event-gap diagnostic (caller's device array) and its bins
     uint32_t gap_bins;
     bool have_model;
+    qed::CellDev cells;       // sub-steps per cell (cells.n[0] null: per particle)
+    uint32_t *cell_buf;       // 2 * cell_cap counts (device)
+    u64 cell_cap;
+    uint32_t *cell_slot[3];   // per-slot cell of each species, sized by cell_slot_cap
+    u64 cell_slot_cap[3];
+    std::vector<void *> retired;  // replaced scratch: recorded graphs may still use it
 };
 
 struct qed_graph {
@@ -104,14 +110,22 @@ void release(T *&p) {
     p = nullptr;
 }
 
+// Scratch that is replaced by a larger buffer stays allocated until qed_finalize: a
+// recorded graph keeps the addresses it was recorded with.
+template <class T>
+void retire(qed_ctx *c, T *&p) {
+    if (p) c->retired.push_back(reinterpret_cast<void *>(p));
+    p = nullptr;
+}
+
 qed_status ensure_photon_scratch(qed_ctx *c, u64 cap) {
     if (cap <= c->photon_cap) return QED_OK;
     if (c->capturing) return QED_ERR_STATE;
     HIP_TRY(hipStreamSynchronize(c->stream));
-    release(c->alive);
-    release(c->dead_idx);
-    release(c->hole_idx);
-    release(c->mover_idx);
+    retire(c, c->alive);
+    retire(c, c->dead_idx);
+    retire(c, c->hole_idx);
+    retire(c, c->mover_idx);
     c->photon_cap = 0;
     HIP_TRY(hipMalloc(&c->alive, cap));
     HIP_TRY(hipMalloc(&c->dead_idx, cap * sizeof(u64)));
@@ -125,12 +139,23 @@ qed_status ensure_lepton_scratch(qed_ctx *c, int s, u64 cap) {
     if (cap <= c->lepton_cap[s]) return QED_OK;
     if (c->capturing) return QED_ERR_STATE;
     HIP_TRY(hipStreamSynchronize(c->stream));
-    release(c->nsub[s]);
-    release(c->queue[s]);
+    retire(c, c->nsub[s]);
+    retire(c, c->queue[s]);
     c->lepton_cap[s] = 0;
     HIP_TRY(hipMalloc(&c->nsub[s], cap * sizeof(uint32_t)));
     HIP_TRY(hipMalloc(&c->queue[s], cap * sizeof(uint32_t)));
     c->lepton_cap[s] = cap;
+    return QED_OK;
+}
+
+qed_status ensure_cell_slots(qed_ctx *c, int s, u64 cap) {
+    if (cap <= c->cell_slot_cap[s]) return QED_OK;
+    if (c->capturing) return QED_ERR_STATE;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    retire(c, c->cell_slot[s]);
+    c->cell_slot_cap[s] = 0;
+    HIP_TRY(hipMalloc(&c->cell_slot[s], cap * sizeof(uint32_t)));
+    c->cell_slot_cap[s] = cap;
     return QED_OK;
 }
 
@@ -143,7 +168,7 @@ bool tuning_ok(const qed_tuning &t) {
 const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_prepass",
                                          "k_scan",  "k_scatter", "k_light", "k_heavy",
                                          "k_end",   "k_fill",   "k_move",  "k_synchrotron", "k_tiled",
-                                         "k_gen", "k_photon_surr"};
+                                         "k_gen", "k_photon_surr", "k_cell_clear", "k_cell_max"};
 
 // Event pair for one profiled launch (grown on demand, reused after a read).
 bool prof_pair(qed_ctx *c, int id, hipEvent_t *a, hipEvent_t *b) {
@@ -276,6 +301,14 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
             if (r != QED_OK) return r;
         }
     }
+    const bool cells = c->cells.n[0] != nullptr;
+    if (cells) {
+        for (int s = 0; s < 3; ++s) {
+            if (!need[s]) continue;
+            qed_status r = ensure_cell_slots(c, s, sp[s]->capacity > 0 ? sp[s]->capacity : 1);
+            if (r != QED_OK) return r;
+        }
+    }
     qed::StepArgs a;
     memset(&a, 0, sizeof(a));
     for (int s = 0; s < 3; ++s) {
@@ -311,6 +344,8 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     a.sampler = surrogate ? 1 : 0;
     a.model = c->have_model ? c->model : nullptr;
     a.pair_model = c->have_pair_model ? c->pair_model : nullptr;
+    a.cells = c->cells;
+    for (int s = 0; s < 3; ++s) a.cells.slot[s] = c->cell_slot[s];
     const u64 lep_cap = sp[0]->capacity > sp[1]->capacity ? sp[0]->capacity : sp[1]->capacity;
     const int lepton_blocks = grid_for(lep_cap, c->num_cu * (int)c->tune.lepton_blocks_per_cu);
     const int heavy_blocks = c->num_cu * (int)c->tune.heavy_blocks_per_cu;
@@ -318,6 +353,12 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     const int aux_blocks = grid_for(sp[2]->capacity, c->num_cu * 4);
     const int prec = c->cfg.precision == QED_PREC_F64 ? 0 : 1;
     hipError_t r = launch(c, qed::K_BEGIN, a, prec, 1);
+    if (r == hipSuccess && a.cells.n[0]) {
+        const u64 ncell = (u64)a.cells.nx * a.cells.ny * a.cells.nz;
+        u64 cap = lep_cap > sp[2]->capacity ? lep_cap : sp[2]->capacity;
+        r = launch(c, qed::K_CELL_CLEAR, a, prec, grid_for(ncell, c->num_cu * 4));
+        if (r == hipSuccess) r = launch(c, qed::K_CELL_MAX, a, prec, grid_for(cap, c->num_cu * 8));
+    }
     if (r == hipSuccess && pairs) r = launch(c, pair_surr ? qed::K_PHOTON_SURR : qed::K_PHOTON, a, prec, photon_blocks);
     const bool tiled = c->cfg.scheduler == QED_SCHED_TILED;
     if (r == hipSuccess && emission && !binned)
@@ -782,6 +823,44 @@ qed_status qed_emission_rate(qed_ctx *c, const float *chi, float *chi_q, uint64_
 }
 
 
+qed_status qed_substep_cells(qed_ctx *c, const qed_grid *g) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    if (c->capturing) return QED_ERR_STATE;
+    if (!g) {
+        c->cells.n[0] = c->cells.n[1] = nullptr;
+        return QED_OK;
+    }
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return QED_ERR_INVALID_ARG;
+    const u64 ncell = (u64)g->nx * g->ny * g->nz;
+    if (ncell > (1ull << 28)) return QED_ERR_INVALID_ARG;
+    if (!(g->dx > 0.0 && g->dy > 0.0 && g->dz > 0.0) || !isfinite(g->dx) || !isfinite(g->dy) || !isfinite(g->dz))
+        return QED_ERR_INVALID_ARG;
+    if (!isfinite(g->x0) || !isfinite(g->y0) || !isfinite(g->z0)) return QED_ERR_INVALID_ARG;
+    if (c->cfg.sampler != QED_SAMPLER_REJECTION || c->cfg.pair_sampler != QED_SAMPLER_REJECTION ||
+        c->cfg.cascade_generations != 0)
+        return QED_ERR_STATE;
+    if (ncell > c->cell_cap) {
+        HIP_TRY(hipSetDevice(c->cfg.device));
+        uint32_t *buf = nullptr;
+        HIP_TRY(hipMalloc(&buf, 2 * ncell * sizeof(uint32_t)));
+        retire(c, c->cell_buf);
+        c->cell_buf = buf;
+        c->cell_cap = ncell;
+    }
+    c->cells.n[0] = c->cell_buf;
+    c->cells.n[1] = c->cell_buf + ncell;
+    c->cells.nx = g->nx;
+    c->cells.ny = g->ny;
+    c->cells.nz = g->nz;
+    c->cells.x0 = g->x0;
+    c->cells.y0 = g->y0;
+    c->cells.z0 = g->z0;
+    c->cells.dx = g->dx;
+    c->cells.dy = g->dy;
+    c->cells.dz = g->dz;
+    return QED_OK;
+}
+
 qed_status qed_event_gaps(qed_ctx *c, uint64_t *hist, uint32_t nbins) {
     if (!c) return QED_ERR_INVALID_ARG;
     if (hist && nbins < 2) return QED_ERR_INVALID_ARG;
@@ -978,6 +1057,9 @@ void qed_finalize(qed_ctx *c) {
     release(c->st);
     release(c->model);
     release(c->pair_model);
+    release(c->cell_buf);
+    for (int s = 0; s < 3; ++s) release(c->cell_slot[s]);
+    for (void *b : c->retired) (void)hipFree(b);
     delete c;
 }
 

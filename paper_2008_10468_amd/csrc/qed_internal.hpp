@@ -75,6 +75,16 @@ struct FieldDev {
     u64 stride;
 };
 
+// Sub-steps chosen per cell: the node cells [x0 + i dx, x0 + (i + 1) dx) x ... of a
+// periodic grid and one count per cell for each group (0: electrons and positrons,
+// 1: photons), rebuilt at every step start.
+struct CellDev {
+    uint32_t *n[2];        // null: every particle takes its own count
+    uint32_t *slot[3];     // per slot of each species: 1 + its cell's index, 0: none
+    uint32_t nx, ny, nz;
+    double x0, y0, z0, dx, dy, dz;
+};
+
 struct StepArgs {
     SpeciesDev sp[3];  // electrons, positrons, photons
     FieldDev fl[3];
@@ -100,6 +110,7 @@ struct StepArgs {
     uint32_t *step_dev;    // non-null: the step number is *step_dev (k_end increments it)
     u64 *gap_hist;         // non-null: event-gap histograms [2][gap_bins] (emissions, pairs)
     uint32_t gap_bins;
+    CellDev cells;         // sub-steps per cell (cells.n[0] null: per particle)
 };
 
 // Event-gap diagnostic: one more event whose particle had gap sub-steps since its
@@ -128,6 +139,8 @@ enum KernelId {
     K_TILED,    // tile-sorted scheduler: the whole lepton pass
     K_GEN,      // cascades: advance the pass ranges to the particles of the previous pass
     K_PHOTON_SURR,  // photon optical-depth path
+    K_CELL_CLEAR,   // sub-steps per cell: clear the per-cell counts
+    K_CELL_MAX,     // sub-steps per cell: largest own count of each group in each cell
     K_COUNT
 };
 

@@ -282,11 +282,53 @@ __device__ __forceinline__ Lepton<R> load_lepton(const StepArgs &a, int s, u64 i
     return p;
 }
 
-// Algorithm 1, step start: the sub-step count from the bound over the interval
-// dt (double).  0 for non-finite input (the particle is left alone).
+// Periodic index of the cell along one axis that holds coordinate v (cells of size
+// d from o); false when (v - o) / d is not finite.  Exact while |(v - o) / d| stays
+// below 2^53 / n; beyond that the index is only kept inside [0, n).
+__device__ __forceinline__ bool wrap_cell(double v, double o, double d, uint32_t n, uint32_t &i) {
+    const double q = (v - o) / d;
+    if (!isfinite(q)) return false;
+    const double f = floor(q);
+    double r = f - (double)n * floor(f / (double)n);
+    r = r < 0.0 ? 0.0 : (r > (double)(n - 1) ? (double)(n - 1) : r);
+    i = (uint32_t)r;
+    return true;
+}
+
+__device__ __forceinline__ bool cell_of(const CellDev &c, double x, double y, double z, uint32_t &cell) {
+    uint32_t i, j, k;
+    if (!wrap_cell(x, c.x0, c.dx, c.nx, i) || !wrap_cell(y, c.y0, c.dy, c.ny, j) ||
+        !wrap_cell(z, c.z0, c.dz, c.nz, k))
+        return false;
+    cell = (k * c.ny + j) * c.nx + i;
+    return true;
+}
+
+// Step 1 of Algorithms 1 and 2 with the sub-step chosen for the cell: the largest
+// own count of the particle's group (g: 0 leptons, 1 photons) in the cell holding
+// its step-start position (slot: 1 + that cell's index, as k_cell_max recorded it).
+// The particle's own count when its input was not finite (own 0) or its position is
+// not finite (slot 0).  The passes read the recorded cell rather than recomputing it
+// from the position, which keeps the sub-step loops' register budget.
+__device__ __forceinline__ uint32_t cell_nsub(const StepArgs &a, int g, uint32_t slot, uint32_t own) {
+    if (own == 0 || slot == 0) return own;
+    const uint32_t v = a.cells.n[g][slot - 1];
+    return v > own ? v : own;
+}
+
+// Algorithm 2, step start: a photon's own sub-step count over dti.
+__device__ __forceinline__ uint32_t photon_nsub(const StepArgs &a, double chi, double eps, double dti,
+                                                bool *capped) {
+    *capped = false;
+    if (!(eps > 0.0)) return 1;
+    return nsub(bound_pair(chi, eps, dti, a.pair_coef), a.p_max, a.max_sub, capped);
+}
+
+// Algorithm 1, step start: the particle's own sub-step count from the bound over the
+// interval dt (double).  0 for non-finite input (the particle is left alone).
 template <class R>
-__device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<R> &p, Tally<R> &tl,
-                                                double dt) {
+__device__ __forceinline__ uint32_t lepton_nsub_own(const StepArgs &a, const Lepton<R> &p, Tally<R> &tl,
+                                                    double dt) {
     if (!(finite3(p.ux, p.uy, p.uz) && finite3(p.ex, p.ey, p.ez) && finite3(p.bx, p.by, p.bz))) {
         tl.nonfinite++;
         return 0;
@@ -297,6 +339,14 @@ __device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, const Lepton<
     const uint32_t N = nsub(bound_emission(chi0, gd, dt), a.p_max_lep, a.max_sub, &capped);
     tl.capped += capped;
     return N;
+}
+
+// The count lepton i of species s runs with: its own, or its cell's.
+template <class R>
+__device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, int s, u64 i, const Lepton<R> &p, Tally<R> &tl,
+                                                double dt) {
+    const uint32_t N = lepton_nsub_own(a, p, tl, dt);
+    return a.cells.n[0] ? cell_nsub(a, 0, a.cells.slot[s][i], N) : N;
 }
 
 // Photon emission of the accepting lanes (acc; m = their ballot): the photon of
@@ -864,7 +914,7 @@ __device__ __forceinline__ uint32_t lepton_fetch(const StepArgs &a, int s, u64 i
         return 0;
     }
     p = load_lepton<R>(a, s, i);
-    return lepton_nsub(a, p, t, dt);
+    return lepton_nsub(a, s, i, p, t, dt);
 }
 
 // Naive scheduler: one lane per particle in buffer order; the loop runs with
@@ -901,7 +951,7 @@ __global__ __launch_bounds__(kBlock) void k_prepass(StepArgs a) {
     Tally<R> t;
     for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
         const Lepton<R> p = load_lepton<R>(a, s, i);
-        const uint32_t N = lepton_nsub(a, p, t, a.dt);
+        const uint32_t N = lepton_nsub(a, s, i, p, t, a.dt);
         a.nsub[s][i] = N;
         if (N)
             atomicAdd(&h[nbin(N, a.light_max)], 1u);
@@ -1227,12 +1277,10 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
             const double chi = chi_def(eps, kx, ky, kz, f[b][0], f[b][1], f[b][2], f[b][3], f[b][4], f[b][5]);
             const double t0 = a.gen ? sp.birth[i] : 0.0;
             const double dti = a.dt - t0;
-            uint32_t N = 1;
-            if (eps > 0.0) {
-                bool capped;
-                N = nsub(bound_pair(chi, eps, dti, a.pair_coef), a.p_max, a.max_sub, &capped);
-                t.capped += capped;
-            }
+            bool capped;
+            uint32_t N = photon_nsub(a, chi, eps, dti, &capped);
+            t.capped += capped;
+            if (a.cells.n[1]) N = cell_nsub(a, 1, a.cells.slot[2][i], N);
             const double st = dti / (double)N;
             if (!photon_quiet<R>(chi, eps, st)) {
                 need |= 1u << b;
@@ -1506,6 +1554,49 @@ __global__ __launch_bounds__(kBlock) void k_pair_rate(const float *__restrict__ 
         out[i] = pair_t(chi[i], t);
 }
 
+// Sub-steps per cell, before the passes of a step: clear the counts, then raise each
+// cell's count of a group to the largest own count among its particles present at the
+// step start (the same own counts the passes compute), and record every slot's cell.
+__global__ __launch_bounds__(kBlock) void k_cell_clear(StepArgs a) {
+    const u64 nc = (u64)a.cells.nx * a.cells.ny * a.cells.nz;
+    for (u64 c = (u64)blockIdx.x * kBlock + threadIdx.x; c < nc; c += (u64)gridDim.x * kBlock) {
+        a.cells.n[0][c] = 0;
+        a.cells.n[1][c] = 0;
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_cell_max(StepArgs a) {
+    const int s = blockIdx.y;
+    if (s < 2 ? !a.emission : !a.pairs) return;
+    const u64 n = a.st->n0[s];
+    const SpeciesDev &sp = a.sp[s];
+    const FieldDev &fl = a.fl[s];
+    uint32_t *cn = a.cells.n[s < 2 ? 0 : 1];
+    Tally<R> t;  // not flushed: the passes count capping and non-finite input
+    for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
+        uint32_t N = 0;
+        if (s < 2) {
+            N = lepton_nsub_own(a, load_lepton<R>(a, s, i), t, a.dt);
+        } else {
+            const R kx = ((const R *)sp.ux)[i], ky = ((const R *)sp.uy)[i], kz = ((const R *)sp.uz)[i];
+            const u64 fi = i * fl.stride;
+            const R f[6] = {((const R *)fl.ex)[fi], ((const R *)fl.ey)[fi], ((const R *)fl.ez)[fi],
+                            ((const R *)fl.bx)[fi], ((const R *)fl.by)[fi], ((const R *)fl.bz)[fi]};
+            if (finite3(kx, ky, kz) && finite3(f[0], f[1], f[2]) && finite3(f[3], f[4], f[5])) {
+                const double eps = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
+                const double chi = chi_def(eps, kx, ky, kz, f[0], f[1], f[2], f[3], f[4], f[5]);
+                bool capped;
+                N = photon_nsub(a, chi, eps, a.dt, &capped);
+            }
+        }
+        uint32_t cell;
+        const bool in = cell_of(a.cells, sp.x[i], sp.y[i], sp.z[i], cell);
+        a.cells.slot[s][i] = in ? cell + 1 : 0u;
+        if (N && in) atomicMax(&cn[cell], N);
+    }
+}
+
 __global__ void k_begin(StepArgs a) {
     DevState *st = a.st;
     for (int k = threadIdx.x; k < 2 * kBins; k += blockDim.x) st->hist[k / kBins][k % kBins] = 0;
@@ -1691,6 +1782,8 @@ hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
             break;
         case K_END: hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, s, a); break;
         case K_GEN: hipLaunchKernelGGL(k_gen, dim3(1), dim3(64), 0, s, a); break;
+        case K_CELL_CLEAR: hipLaunchKernelGGL(k_cell_clear, g1, blk, 0, s, a); break;
+        case K_CELL_MAX: hipLaunchKernelGGL(k_cell_max<R>, dim3(blocks, 3), blk, 0, s, a); break;
         case K_PHOTON_SURR:
             if constexpr (std::is_same<R, float>::value) {
                 if (a.pair_model)

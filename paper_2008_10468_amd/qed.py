@@ -95,7 +95,7 @@ EXPORTS = ("qed_config_default", "qed_init", "qed_step", "qed_sync", "qed_synchr
            "qed_get_stats", "qed_reset_stats", "qed_get_tuning", "qed_set_tuning",
            "qed_profile_enable", "qed_profile_read", "qed_graph_begin", "qed_graph_end",
            "qed_graph_launch", "qed_graph_destroy",
-           "qed_step_counted", "qed_pair_rate", "qed_event_gaps", "qed_gather", "qed_deposit",
+           "qed_step_counted", "qed_pair_rate", "qed_event_gaps", "qed_substep_cells", "qed_gather", "qed_deposit",
            "qed_pair_sampler_set", "qed_pair_sampler_infer", "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
            "qed_train_config_default", "qed_train_sampler", "qed_mlp_gradient",
            "qed_finalize", "qed_status_string")
@@ -137,6 +137,7 @@ def load(path: str = LIB_PATH):
     L.qed_emission_rate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
     L.qed_pair_rate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64]
     L.qed_event_gaps.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32]
+    L.qed_substep_cells.argtypes = [C.c_void_p, C.POINTER(qed_grid)]
     L.qed_gather.argtypes = [C.c_void_p, C.POINTER(qed_grid), C.POINTER(qed_species), C.c_void_p * 6]
     L.qed_deposit.argtypes = [C.c_void_p, C.POINTER(qed_grid), C.POINTER(qed_species), C.c_double,
                               C.c_void_p, C.c_void_p, C.c_void_p]
@@ -308,6 +309,25 @@ def qed_gather(ctx, grid, species, out_ptrs):
 
 def qed_deposit(ctx, grid, species, charge, jx, jy, jz):
     return load().qed_deposit(ctx, C.byref(grid), C.byref(species), float(charge), jx, jy, jz)
+
+
+def cell_geometry(geom):
+    """qed_grid holding only a geometry: dict with nx, ny, nz, x0, y0, z0, dx, dy, dz."""
+    g = qed_grid()
+    for k in ("nx", "ny", "nz"):
+        setattr(g, k, int(geom[k]))
+    for k in ("x0", "y0", "z0", "dx", "dy", "dz"):
+        setattr(g, k, float(geom[k]))
+    return g
+
+
+def qed_substep_cells(ctx, cells):
+    """cells: qed_grid, a geometry dict (cell_geometry) or None (per-particle sub-steps)."""
+    if cells is None:
+        return load().qed_substep_cells(ctx, None)
+    if isinstance(cells, dict):
+        cells = cell_geometry(cells)
+    return load().qed_substep_cells(ctx, C.byref(cells))
 
 
 def qed_event_gaps(ctx, hist_ptr, nbins):

@@ -29,8 +29,10 @@ def gpu_step(g, fields_host, dt, seed, step):
 
 
 def oracle_step(before, fields_host, dt, seed, step, precision, emission=True, pairs=True, p_max=0.01,
-                pair_coef=0.1, threads=None):
-    """The oracle from the GPU's start-of-step state (float values exact in float64)."""
+                pair_coef=0.1, threads=None, cells=None):
+    """The oracle from the GPU's start-of-step state (float values exact in float64).
+    cells: a cell geometry for sub-steps chosen per cell (oracle.cell_substeps); the
+    counts taken and the particles' own counts are returned as res["forced"], res["own"]."""
     rb = RNG_BITS[precision]
     res = {}
     strip = lambda d: {k: d[k].copy() for k in ("x", "y", "z", "ux", "uy", "uz", "w", "id")}
@@ -38,15 +40,22 @@ def oracle_step(before, fields_host, dt, seed, step, precision, emission=True, p
     fe = fields_host[0]
     fp = fields_host[1]
     fg = fields_host[2]
+    forced = [None, None, None]
+    if cells is not None:
+        fl3 = [fe, fp, fg if fg is not None else fe]
+        forced = oracle.cell_substeps(st_e, st_p, st_g, fl3, cells, dt, p_max=p_max, pair_coef=pair_coef)
+        res["forced"] = forced
+        res["own"] = [oracle.own_substeps(st, f, dt, photons=(s == 2), p_max=p_max, pair_coef=pair_coef)
+                      for s, (st, f) in enumerate(zip((st_e, st_p, st_g), fl3))]
     if pairs:
         ch, alive, nsub, nev, tl = oracle.photon_step(st_g, fg, dt, seed, step, p_max=p_max, rng_bits=rb,
-                                                      pair_coef=pair_coef, threads=threads)
+                                                      pair_coef=pair_coef, threads=threads, nsub=forced[2])
         res["photon"] = (st_g, ch, alive, nsub, nev, tl)
     if emission:
         res["electron"] = (st_e,) + oracle.lepton_step(st_e, fe, -1.0, dt, seed, step, p_max=p_max,
-                                                        rng_bits=rb, threads=threads)
+                                                        rng_bits=rb, threads=threads, nsub=forced[0])
         res["positron"] = (st_p,) + oracle.lepton_step(st_p, fp, +1.0, dt, seed, step, p_max=p_max,
-                                                        rng_bits=rb, threads=threads)
+                                                        rng_bits=rb, threads=threads, nsub=forced[1])
     return res
 
 
@@ -89,3 +98,70 @@ def compare_children(gpu_ids, gpu_mom, gpu_w, orc_ids, orc_mom, orc_w, rtol, max
         assert np.max(d) <= rtol, np.max(d)
         assert np.array_equal(gpu_w[a], orc_w[b])
     return len(common), missing
+
+
+def _mom(d):
+    return np.stack([d["ux"], d["uy"], d["uz"]])
+
+
+def check_step(g, fields, dt, seed, step, precision, emission=True, pairs=True, rtol=1e-9, min_agree=1.0,
+               max_missing=0, rtol_per_substep=0.0, cells=None):
+    """One GPU step checked against the oracle.  Momentum tolerance of a particle:
+    rtol + rtol_per_substep * (its number of sub-steps).  cells: the geometry of
+    sub-steps chosen per cell (set on the GPU context by the caller).  Returns
+    (per-species agreement, the GPU state after the step, the oracle's results)."""
+    before, after, events, st, rep = gpu_step(g, fields, dt, seed, step)
+    assert st == qed.QED_OK, qed.status_string(st)
+    fh = [as_precision(f.host, precision) for f in g.fields]
+    res = oracle_step(before, fh, dt, seed, step, precision, emission=emission, pairs=pairs, cells=cells)
+    out = {}
+    child_rtol = rtol
+    if emission:
+        for s, name in ((0, "electron"), (1, "positron")):
+            n0 = before[s]["id"].size
+            ost, och, onsub, onev, otl = res[name]
+            tol = rtol + rtol_per_substep * onsub[:n0].astype(np.float64)
+            out[name] = compare_leptons(after[s], events[s], ost, onev, n0, tol, min_agree)
+            # positions of particles with the same events
+            same = events[s][:n0] == onev[:n0]
+            for k in ("x", "y", "z"):
+                d = np.abs(after[s][k][:n0] - ost[k][:n0])
+                assert np.all(d[same] <= tol[same] * dt + 1e-12 * np.abs(ost[k][:n0][same]))
+            nmax = int(onsub.max()) if onsub.size else 0
+            child_rtol = max(child_rtol, rtol + rtol_per_substep * nmax)
+    # photons: survivors by id, plus emitted photons by id
+    if emission or pairs:
+        gph = after[2]
+        exp_ids, exp_mom, exp_w = [], [], []
+        if pairs:
+            pst, pch, alive, _, pnev, _ = res["photon"]
+            n0 = before[2]["id"].size
+            same = events[2][:n0] == pnev[:n0]
+            assert np.mean(same) >= min_agree if n0 else True
+            keep = alive.astype(bool)
+            exp_ids.append(pst["id"][keep])
+            exp_mom.append(_mom(pst)[:, keep])
+            exp_w.append(pst["w"][keep])
+            # pair children
+            for s, kind in ((0, 1), (1, 2)):
+                n0s = before[s]["id"].size
+                sel = pch["kind"] == kind
+                compare_children(after[s]["id"][n0s:], _mom(after[s])[:, n0s:], after[s]["w"][n0s:],
+                                 pch["id"][sel], np.stack([pch["px"][sel], pch["py"][sel], pch["pz"][sel]]),
+                                 pch["w"][sel], child_rtol, max_missing)
+        else:
+            n0 = before[2]["id"].size
+            exp_ids.append(before[2]["id"])
+            exp_mom.append(_mom(before[2]))
+            exp_w.append(before[2]["w"])
+        if emission:
+            for name in ("electron", "positron"):
+                och = res[name][1]
+                exp_ids.append(och["id"])
+                exp_mom.append(np.stack([och["px"], och["py"], och["pz"]]))
+                exp_w.append(och["w"])
+        nc, miss = compare_children(gph["id"], _mom(gph), gph["w"], np.concatenate(exp_ids),
+                                    np.concatenate(exp_mom, axis=1), np.concatenate(exp_w), child_rtol,
+                                    max_missing)
+        out["photons_matched"] = nc
+    return out, after, res

@@ -1,0 +1,191 @@
+"""Sub-steps chosen per cell (qed_substep_cells) against the oracle's reading of
+Algorithms 1 and 2, step 1, for the current cell (oracle.cell_substeps): the same
+events particle by particle, under every scheduler and in recorded graphs."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import check_step, gpu_step, oracle_step
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _set_cells(qed, g, cells):
+    assert qed.qed_substep_cells(g.ctx, cells) == qed.QED_OK
+
+
+@pytest.mark.parametrize("sched", ["naive", "binned", "tiled"])
+def test_fp64_cells_match_oracle(sched):
+    """C1 electrons, 8^3 cells (about 6 per cell): identical events every step, and the
+    step's sub-step total is the oracle's sum of the cells' counts."""
+    from paper_2008_10468_amd import qed
+    sc = {"naive": qed.QED_SCHED_NAIVE, "binned": qed.QED_SCHED_BINNED, "tiled": qed.QED_SCHED_TILED}[sched]
+    w = workloads.c1(n=3000, seed=11)
+    cells = workloads.cell_box(8)
+    g = qed.Generator(precision=qed.QED_PREC_F64, capacity=(4096, 16, 1 << 16), pairs=False, scheduler=sc)
+    g.load_state(w)
+    g.set_fields(w["fields"])
+    _set_cells(qed, g, cells)
+    total = 0
+    for step in range(3):
+        print("cells fp64", sched, "step", step, flush=True)
+        out, _, res = check_step(g, w["fields"], w["dt"], 3, step, qed.QED_PREC_F64, pairs=False, rtol=1e-9,
+                                 cells=cells)
+        assert out["electron"] == 1.0
+        total += int(res["forced"][0].sum())
+        assert np.array_equal(res["electron"][2], res["forced"][0])      # the oracle took the cells' counts
+        if step == 0:                                                    # and they raise most own counts
+            assert np.mean(res["forced"][0] > res["own"][0]) > 0.5
+    assert g.stats().substeps[0] == total
+    g.close()
+
+
+def test_mixed_c2_cells_with_pairs():
+    """C2 (rotating E, mixed precision) with pairs, 4^3 cells: per-particle agreement on
+    >= 99.99%, children by id, photons with their cell's count."""
+    from paper_2008_10468_amd import qed
+    w = workloads.c2(n_e=12000, n_g=4000, seed=3)
+    cells = workloads.cell_box(4)
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 15, 1 << 14, 1 << 16))
+    g.load_state(w)
+    _set_cells(qed, g, cells)
+    for step in range(2):
+        print("cells c2 step", step, flush=True)
+        g.set_fields(workloads.c2_field(step))
+        out, _, res = check_step(g, None, w["dt"], 3, step, qed.QED_PREC_MIXED, rtol=2e-5, min_agree=0.9999,
+                                 max_missing=4, rtol_per_substep=2e-7, cells=cells)
+        assert np.all(res["photon"][3] <= res["forced"][2]) and np.all(res["forced"][2] >= res["own"][2])
+        assert np.all(res["forced"][0] >= res["own"][0]) and np.mean(res["forced"][0] > res["own"][0]) > 0.5
+    g.close()
+
+
+def test_one_particle_per_cell_is_per_particle():
+    """Each electron alone in its cell: the step with cells equals the step without,
+    bit for bit."""
+    from paper_2008_10468_amd import qed
+    n = 512
+    w = workloads.c1(n=n, seed=12)
+    cells = workloads.cell_box(8)
+    d = cells["dx"]
+    k = np.arange(n)
+    e = w["electrons"]
+    e["x"] = cells["x0"] + (k % 8 + 0.5) * d
+    e["y"] = cells["y0"] + ((k // 8) % 8 + 0.5) * d
+    e["z"] = cells["z0"] + (k // 64 + 0.5) * d
+    outs = []
+    for with_cells in (False, True):
+        g = qed.Generator(precision=qed.QED_PREC_F64, capacity=(1024, 16, 1 << 15), pairs=False)
+        g.load_state(w)
+        g.set_fields(w["fields"])
+        if with_cells:
+            _set_cells(qed, g, cells)
+        g.step(w["dt"], 5, 0)          # one step: afterwards the electrons may share cells
+        assert g.sync()[0] == qed.QED_OK
+        outs.append((g.sp[0].download(), g.sp[2].download(), g.stats().substeps[0]))
+        g.close()
+    for a, b in zip(outs[0][:2], outs[1][:2]):
+        for key in a:
+            assert np.array_equal(a[key], b[key]), key
+    assert outs[0][2] == outs[1][2]
+
+
+def test_cells_in_a_recorded_graph():
+    """Three counted steps with cells recorded once and replayed: every replay equals
+    the eager steps."""
+    from paper_2008_10468_amd import qed
+    stream = torch.cuda.Stream()
+    w = workloads.c2(n_e=20000, n_g=6000, seed=6)
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 16, 1 << 15, 1 << 17), stream=stream.cuda_stream,
+                      scheduler=qed.QED_SCHED_BINNED)
+    _set_cells(qed, g, workloads.cell_box(6))
+    g.set_fields(workloads.c2_field(0))
+    ctr = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def run():
+        for _ in range(3):
+            st = qed.qed_step_counted(g.ctx, g.particles(), [f.struct() for f in g.fields], w["dt"], 4,
+                                      ctr.data_ptr())
+            assert st == qed.QED_OK
+
+    def state():
+        out = []
+        for s in range(3):
+            d = g.sp[s].download()
+            o = np.argsort(d["id"])
+            out.append({k: v[o] for k, v in d.items() if k != "parent"})
+        return out
+
+    g.load_state(w)
+    ctr.zero_()
+    torch.cuda.synchronize()
+    run()
+    assert g.sync()[0] == qed.QED_OK
+    ref = state()
+    assert qed.qed_graph_begin(g.ctx) == qed.QED_OK
+    run()
+    st, graph = qed.qed_graph_end(g.ctx)
+    assert st == qed.QED_OK
+    for rep in range(3):
+        g.load_state(w)
+        ctr.zero_()
+        torch.cuda.synchronize()
+        torch.randn(1 << 18, device="cuda").sum().item()
+        assert qed.qed_graph_launch(g.ctx, graph) == qed.QED_OK
+        assert g.sync()[0] == qed.QED_OK
+        got = state()
+        for s in range(3):
+            for k in ref[s]:
+                assert np.array_equal(ref[s][k], got[s][k]), (rep, s, k)
+    qed.qed_graph_destroy(graph)
+    g.close()
+
+
+def test_positions_outside_and_not_finite():
+    """Positions whole periods outside the box wrap into it; a non-finite position keeps
+    the particle's own count.  FP64 path against the oracle: identical events, and equal
+    momenta (positions that are not finite stay so on both sides)."""
+    from paper_2008_10468_amd import qed
+    n = 600
+    w = workloads.c1(n=n, seed=13)
+    cells = workloads.cell_box(3)
+    e = w["electrons"]
+    rng = np.random.default_rng(2)
+    e["x"][:200] += rng.integers(-50, 50, 200) * 2.0e4
+    e["y"][200:210] = np.nan
+    e["z"][210:220] = np.inf
+    g = qed.Generator(precision=qed.QED_PREC_F64, capacity=(1024, 16, 1 << 15), pairs=False)
+    g.load_state(w)
+    g.set_fields(w["fields"])
+    _set_cells(qed, g, cells)
+    before, after, events, st, _ = gpu_step(g, None, w["dt"], 8, 0)
+    assert st == qed.QED_OK
+    res = oracle_step(before, [w["fields"]] * 3, w["dt"], 8, 0, qed.QED_PREC_F64, pairs=False, cells=cells)
+    ost, och, onsub, onev, _ = res["electron"]
+    assert np.array_equal(events[0][:n], onev)
+    assert np.array_equal(res["forced"][0][200:220], res["own"][0][200:220])
+    assert np.mean(res["forced"][0][:200] > res["own"][0][:200]) > 0.5
+    u_g = np.stack([after[0][k][:n] for k in ("ux", "uy", "uz")])
+    u_o = np.stack([ost[k] for k in ("ux", "uy", "uz")])
+    assert np.max(np.abs(u_g - u_o) / np.maximum(np.abs(u_o), 1.0)) < 1e-9
+    assert np.array_equal(np.sort(after[2]["id"]), np.sort(och["id"]))
+    g.close()
+
+
+def test_cell_arguments():
+    from paper_2008_10468_amd import qed
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(16, 16, 16))
+    good = workloads.cell_box(4)
+    for bad in ({"nx": 0}, {"dx": 0.0}, {"dy": float("nan")}, {"z0": float("inf")}, {"nx": 1 << 10, "ny": 1 << 10,
+                                                                                      "nz": 1 << 9}):
+        assert qed.qed_substep_cells(g.ctx, {**good, **bad}) == qed.QED_ERR_INVALID_ARG, bad
+    assert qed.qed_substep_cells(g.ctx, good) == qed.QED_OK
+    assert qed.qed_substep_cells(g.ctx, None) == qed.QED_OK
+    g.close()
+    # not with the optical-depth paths or cascades
+    for kw in ({"sampler": qed.QED_SAMPLER_SURROGATE}, {"pair_sampler": qed.QED_SAMPLER_SURROGATE},
+               {"cascade_generations": 1}):
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(16, 16, 16), **kw)
+        assert qed.qed_substep_cells(g.ctx, good) == qed.QED_ERR_STATE, kw
+        g.close()

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads
-from gpu_util import as_precision, compare_children, compare_leptons, gpu_step, oracle_step
+from gpu_util import as_precision, check_step, gpu_step
 
 pytestmark = pytest.mark.gpu
 
@@ -21,71 +21,14 @@ def _mom(d):
     return np.stack([d["ux"], d["uy"], d["uz"]])
 
 
+def _check_step(*args, **kw):
+    out, after, _ = check_step(*args, **kw)
+    return out, after
+
+
 def _gen(precision, capacity, **kw):
     from paper_2008_10468_amd import qed
     return qed.Generator(precision=precision, capacity=capacity, **kw)
-
-
-def _check_step(g, fields, dt, seed, step, precision, emission=True, pairs=True, rtol=1e-9, min_agree=1.0,
-                max_missing=0, rtol_per_substep=0.0):
-    """One GPU step checked against the oracle.  Momentum tolerance of a particle:
-    rtol + rtol_per_substep * (its number of sub-steps)."""
-    before, after, events, st, rep = gpu_step(g, fields, dt, seed, step)
-    from paper_2008_10468_amd import qed
-    assert st == qed.QED_OK, qed.status_string(st)
-    fh = [as_precision(f.host, precision) for f in g.fields]
-    res = oracle_step(before, fh, dt, seed, step, precision, emission=emission, pairs=pairs)
-    out = {}
-    child_rtol = rtol
-    if emission:
-        for s, name in ((0, "electron"), (1, "positron")):
-            n0 = before[s]["id"].size
-            ost, och, onsub, onev, otl = res[name]
-            tol = rtol + rtol_per_substep * onsub[:n0].astype(np.float64)
-            out[name] = compare_leptons(after[s], events[s], ost, onev, n0, tol, min_agree)
-            # positions of particles with the same events
-            same = events[s][:n0] == onev[:n0]
-            for k in ("x", "y", "z"):
-                d = np.abs(after[s][k][:n0] - ost[k][:n0])
-                assert np.all(d[same] <= tol[same] * dt + 1e-12 * np.abs(ost[k][:n0][same]))
-            nmax = int(onsub.max()) if onsub.size else 0
-            child_rtol = max(child_rtol, rtol + rtol_per_substep * nmax)
-    # photons: survivors by id, plus emitted photons by id
-    if emission or pairs:
-        gph = after[2]
-        exp_ids, exp_mom, exp_w = [], [], []
-        if pairs:
-            pst, pch, alive, _, pnev, _ = res["photon"]
-            n0 = before[2]["id"].size
-            same = events[2][:n0] == pnev[:n0]
-            assert np.mean(same) >= min_agree if n0 else True
-            keep = alive.astype(bool)
-            exp_ids.append(pst["id"][keep])
-            exp_mom.append(_mom(pst)[:, keep])
-            exp_w.append(pst["w"][keep])
-            # pair children
-            for s, kind in ((0, 1), (1, 2)):
-                n0s = before[s]["id"].size
-                sel = pch["kind"] == kind
-                compare_children(after[s]["id"][n0s:], _mom(after[s])[:, n0s:], after[s]["w"][n0s:],
-                                 pch["id"][sel], np.stack([pch["px"][sel], pch["py"][sel], pch["pz"][sel]]),
-                                 pch["w"][sel], child_rtol, max_missing)
-        else:
-            n0 = before[2]["id"].size
-            exp_ids.append(before[2]["id"])
-            exp_mom.append(_mom(before[2]))
-            exp_w.append(before[2]["w"])
-        if emission:
-            for name in ("electron", "positron"):
-                och = res[name][1]
-                exp_ids.append(och["id"])
-                exp_mom.append(np.stack([och["px"], och["py"], och["pz"]]))
-                exp_w.append(och["w"])
-        nc, miss = compare_children(gph["id"], _mom(gph), gph["w"], np.concatenate(exp_ids),
-                                    np.concatenate(exp_mom, axis=1), np.concatenate(exp_w), child_rtol,
-                                    max_missing)
-        out["photons_matched"] = nc
-    return out, after
 
 
 def test_c1_fp64_steps_match_oracle():

@@ -66,6 +66,14 @@ def _empty():
     return s
 
 
+def cell_box(n_per_axis, pos_scale=1.0e4):
+    """Cell geometry covering the cube [-pos_scale, pos_scale)^3 in which the workloads
+    place their particles, n_per_axis cells along each axis (for sub-steps per cell)."""
+    d = 2.0 * pos_scale / n_per_axis
+    return {"nx": n_per_axis, "ny": n_per_axis, "nz": n_per_axis, "x0": -pos_scale, "y0": -pos_scale,
+            "z0": -pos_scale, "dx": d, "dy": d, "dz": d}
+
+
 def uniform_field(ex=0.0, ey=0.0, ez=0.0, bx=0.0, by=0.0, bz=0.0):
     return {k: np.array([v], np.float64) for k, v in
             zip(("ex", "ey", "ez", "bx", "by", "bz"), (ex, ey, ez, bx, by, bz))}
