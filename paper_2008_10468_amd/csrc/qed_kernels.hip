@@ -1593,7 +1593,10 @@ __global__ __launch_bounds__(kBlock) void k_cell_max(StepArgs a) {
         uint32_t cell;
         const bool in = cell_of(a.cells, sp.x[i], sp.y[i], sp.z[i], cell);
         a.cells.slot[s][i] = in ? cell + 1 : 0u;
-        if (N && in) atomicMax(&cn[cell], N);
+        // counts only grow during this kernel: a read that already shows N or more
+        // (stale values are smaller) makes the atomic unnecessary; in crowded cells
+        // this spares most of them
+        if (N && in && cn[cell] < N) atomicMax(&cn[cell], N);
     }
 }
 

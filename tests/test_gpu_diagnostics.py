@@ -97,3 +97,21 @@ def test_fp64_and_mixed_agree():
     # the photon spectra span six decades: compare the distributions (two-sample KS)
     from scipy import stats as sps
     assert sps.ks_2samp(a["photon_energies"], b["photon_energies"]).pvalue > 1e-3
+
+
+def test_cell_comparison():
+    """Sub-steps per cell against per particle on a C2 population: the same emission and
+    pair rates and photon energies within statistics, at a cost that grows with the
+    particles per cell (a cell takes its particles' largest count)."""
+    from paper_2008_10468_amd import diagnostics
+    w = workloads.c2(n_e=100000, n_g=25000, seed=9)
+    r = diagnostics.cell_comparison(_state(w), w["fields"], w["dt"], 3, cells=(None, 16, 4))["rows"]
+    ref = r[0]
+    assert ref["cells_per_axis"] is None and ref["emissions"] > 2000
+    for row in r[1:]:
+        for k in ("emissions", "pairs"):
+            assert abs(row[k] - ref[k]) <= 4 * math.sqrt(row[k] + ref[k]) + 0.01 * ref[k] + 5, (k, row, ref)
+        sem = math.hypot(row["photon_energy_sem"], ref["photon_energy_sem"])
+        assert abs(row["mean_photon_energy"] - ref["mean_photon_energy"]) <= 4 * sem, (row, sem)
+    subs = [row["lepton_substeps"] for row in r]
+    assert subs[0] < subs[1] < subs[2], subs
