@@ -39,16 +39,16 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Smallest uniform y of each path: (2k+1) 2^-b with k = 0.
+// Logarithm of the smallest uniform y of each path, (2k+1) 2^-b with k = 0.
 template <class R>
 struct YMin;
 template <>
 struct YMin<float> {
-    static constexpr double value = 0x1p-24;
+    static constexpr float log = -16.6355323f;  // ln 2^-24
 };
 template <>
 struct YMin<double> {
-    static constexpr double value = 0x1p-53;
+    static constexpr float log = -36.7368005f;  // ln 2^-53
 };
 
 // True if no candidate of this photon can be accepted in this step.  With
@@ -58,14 +58,21 @@ struct YMin<double> {
 // (the K_{2/3} asymptotic series truncated after its positive first correction is
 // an upper bound).  If twice that bound is below the smallest uniform y, no y can
 // fall under P_p: the photon only moves, exactly as sampling would leave it.
+// The test runs in float in the log domain, ln(twice the bound) =
+// ln(2 A sqrt(pi z0 / 2) (1 + 7 / (72 z0))) - z0, against ln y_min less a margin of
+// 1e-3, far above the float rounding of these few operations; an overflow or a
+// NaN answers "not quiet", and so does z0 within 1e-3 of the bound's validity
+// limit.  A photon wrongly called not quiet is only sampled, which is always exact.
 template <class R>
 __device__ __forceinline__ bool photon_quiet(double chi, double eps, double st) {
     if (!(chi > 0.0) || !(eps > 0.0)) return true;
-    const double z0 = (8.0 / 3.0) / chi;
-    if (z0 < 1.0) return false;
-    const double A = kAlpha * st * kSqrt3 / (2.0 * kPi) * chi / eps;
-    const double ub = 2.0 * A * sqrt(0.5 * kPi * z0) * exp(-z0) * (1.0 + 7.0 / (72.0 * z0));
-    return ub < YMin<R>::value;
+    const float cf = (float)chi;
+    const float z0 = (8.0f / 3.0f) * __builtin_amdgcn_rcpf(cf);
+    if (!(z0 >= 1.001f)) return false;
+    const float A = (float)(kAlpha * kSqrt3 / (2.0 * kPi)) * (float)st * cf * __builtin_amdgcn_rcpf((float)eps);
+    const float lub = __logf(2.0f * A * __builtin_amdgcn_sqrtf((float)(0.5 * kPi) * z0) *
+                             (1.0f + (7.0f / 72.0f) * __builtin_amdgcn_rcpf(z0))) - z0;
+    return lub < YMin<R>::log - 1e-3f;
 }
 
 __device__ __forceinline__ u64 lanemask_lt() {

@@ -83,7 +83,9 @@ def test_one_particle_per_cell_is_per_particle():
             _set_cells(qed, g, cells)
         g.step(w["dt"], 5, 0)          # one step: afterwards the electrons may share cells
         assert g.sync()[0] == qed.QED_OK
-        outs.append((g.sp[0].download(), g.sp[2].download(), g.stats().substeps[0]))
+        ph = g.sp[2].download()
+        order = np.argsort(ph["id"])       # children are appended in no fixed order
+        outs.append((g.sp[0].download(), {k: v[order] for k, v in ph.items()}, g.stats().substeps[0]))
         g.close()
     for a, b in zip(outs[0][:2], outs[1][:2]):
         for key in a:
