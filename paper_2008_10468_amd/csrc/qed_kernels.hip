@@ -722,8 +722,8 @@ struct PhotonStart {
 
 // Algorithm 2's sub-step loop for one photon that can decay.
 template <class R>
-__device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R ky, R kz,
-                                              const PhotonStart &ps, const SynTable<R> &tab,
+__device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R ky, R kz, double x0, double y0,
+                                              double z0, const PhotonStart &ps, const SynTable<R> &tab,
                                               const PairTable &pt, Tally<R> &tl) {
     const SpeciesDev &sp = a.sp[2];
     const SpeciesDev &el = a.sp[0];
@@ -788,8 +788,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
             if (acc) {
                 const u64 r = (u64)__popcll(m & lanemask_lt());
                 a.dead_idx[bd + r] = i;
-                const double px = sp.x[i] + (double)dx, py = sp.y[i] + (double)dy,
-                             pz = sp.z[i] + (double)dz;
+                const double px = x0 + (double)dx, py = y0 + (double)dy, pz = z0 + (double)dz;
                 const R w = ((const R *)sp.w)[i];
                 const double tb = ps.t0 + (double)(k + 1) * st;
                 const R ge = x * epsr, gp = (R(1) - x) * epsr;
@@ -828,9 +827,8 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
             }
         }
     }
-    sp.x[i] += (double)dx;
-    sp.y[i] += (double)dy;
-    sp.z[i] += (double)dz;
+    // positions: the caller has written the end-of-step position (the survivor's);
+    // the slot of a photon that decayed is removed by the compaction
     a.alive[i] = dead ? 0 : 1;
     if (sp.events) sp.events[i] = dead ? 1u : 0u;
     tl.substeps += used;
@@ -1186,25 +1184,27 @@ __global__ __launch_bounds__(kBlock, 3) void k_heavy(StepArgs a) {
 }
 
 // The sampling loop of one photon that can decay, from its queued step-start
-// values (its momentum is read again, from the cache).
+// values.
 template <class R>
-__device__ __forceinline__ void photon_sample_one(const StepArgs &a, u64 i, const PhotonStart &ps,
-                                                  const SynTable<R> &tab, const PairTable &pt, Tally<R> &ts) {
-    const SpeciesDev &sp = a.sp[2];
-    const R kx = ((const R *)sp.ux)[i], ky = ((const R *)sp.uy)[i], kz = ((const R *)sp.uz)[i];
-    photon_sample<R>(a, i, kx, ky, kz, ps, tab, pt, ts);
+__device__ __forceinline__ void photon_sample_one(const StepArgs &a, u64 i, R kx, R ky, R kz, double x0, double y0,
+                                                  double z0, const PhotonStart &ps, const SynTable<R> &tab,
+                                                  const PairTable &pt, Tally<R> &ts) {
+    photon_sample<R>(a, i, kx, ky, kz, x0, y0, z0, ps, tab, pt, ts);
     ts.particles++;
 }
 
 // Algorithm 2 for every photon, in one pass.  Each lane loads kPhotonBatch
 // photons per round (all loads issued before use; a uniform field, stride 0, is
-// loaded once) and computes the step-start bound.  Photons that cannot decay in
-// this step (photon_quiet) run their sub-step loop in closed form: they only
-// move.  The others go to a wave-local queue, which is drained 64 photons at a
-// time, so the sampling loops run with all lanes busy; their records were read by
-// this wave shortly before, so the second read hits the cache.  The pass covers
-// the slots lo..hi of the device state; in a cascade pass (gen >= 1) each photon
-// runs over the rest of the step from its birth time.
+// loaded once), computes the step-start bound and writes every photon's
+// end-of-step position (the same float sum of sub-step moves the sampling loop
+// takes), with coalesced stores.  Photons that cannot decay in this step
+// (photon_quiet) are then done.  The others go to a wave-local LDS queue with
+// their momentum and start position, which is drained 64 photons at a time, so
+// the sampling loops run with all lanes busy and without reading the photon
+// records again (only the id); a photon that decays leaves its children at its
+// start position plus the moves up to the decay.  The pass covers the slots
+// lo..hi of the device state; in a cascade pass (gen >= 1) each photon runs over
+// the rest of the step from its birth time.
 constexpr int kPhotonBatch = 2;
 constexpr int kPhotonQueue = 64 * (kPhotonBatch + 1);
 
@@ -1213,7 +1213,8 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
     __shared__ SynTable<R> tab;
     __shared__ u64 queue_sh[kBlock / 64][kPhotonQueue];
     __shared__ double qchi_sh[kBlock / 64][kPhotonQueue], qeps_sh[kBlock / 64][kPhotonQueue];
-    __shared__ double qt0_sh[kBlock / 64][kPhotonQueue];
+    __shared__ double qx_sh[kBlock / 64][3][kPhotonQueue];
+    __shared__ R qk_sh[kBlock / 64][3][kPhotonQueue];
     __shared__ uint32_t qn_sh[kBlock / 64][kPhotonQueue];
     __shared__ PairTable pt;
     pair_stage(pt);
@@ -1224,7 +1225,9 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
     const bool uni = fl.stride == 0;
     const uint32_t lane = __lane_id();
     u64 *queue = queue_sh[threadIdx.x / 64];
-    double *qchi = qchi_sh[threadIdx.x / 64], *qeps = qeps_sh[threadIdx.x / 64], *qt0 = qt0_sh[threadIdx.x / 64];
+    double *qchi = qchi_sh[threadIdx.x / 64], *qeps = qeps_sh[threadIdx.x / 64];
+    double(*qx)[kPhotonQueue] = qx_sh[threadIdx.x / 64];
+    R(*qk)[kPhotonQueue] = qk_sh[threadIdx.x / 64];
     uint32_t *qn = qn_sh[threadIdx.x / 64];
     uint32_t queued = 0;  // wave-uniform
     R fu[6] = {0, 0, 0, 0, 0, 0};
@@ -1289,14 +1292,6 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
             t.capped += capped;
             if (a.cells.n[1]) N = cell_nsub(a, 1, a.cells.slot[2][i], N);
             const double st = dti / (double)N;
-            if (!photon_quiet<R>(chi, eps, st)) {
-                need |= 1u << b;
-                pst[b].eps = eps;
-                pst[b].chi = chi;
-                pst[b].t0 = t0;
-                pst[b].N = N;
-                continue;
-            }
             const R inv = eps > 0.0 ? (R)(1.0 / eps) : R(0);
             const R dirx = kx * inv, diry = ky * inv, dirz = kz * inv;
             const R str = (R)st;
@@ -1309,6 +1304,14 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
             sp.x[i] = x[b][0] + (double)dx;
             sp.y[i] = x[b][1] + (double)dy;
             sp.z[i] = x[b][2] + (double)dz;
+            if (!photon_quiet<R>(chi, eps, st)) {
+                need |= 1u << b;
+                pst[b].eps = eps;
+                pst[b].chi = chi;
+                pst[b].t0 = t0;
+                pst[b].N = N;
+                continue;
+            }
             a.alive[i] = 1;
             if (sp.events) sp.events[i] = 0u;
             t.substeps += N;
@@ -1323,8 +1326,12 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
                 queue[q] = i0 + b * G;
                 qchi[q] = pst[b].chi;
                 qeps[q] = pst[b].eps;
-                qt0[q] = pst[b].t0;
                 qn[q] = pst[b].N;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    qx[c][q] = x[b][c];
+                    qk[c][q] = k[b][c];
+                }
             }
             queued += (uint32_t)__popcll(m);
         }
@@ -1332,14 +1339,17 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
         while (queued >= 64) {
             queued -= 64;
             const uint32_t q = queued + lane;
-            const PhotonStart ps = {qeps[q], qchi[q], qt0[q], qn[q]};
-            photon_sample_one<R>(a, queue[q], ps, tab, pt, ts);
+            const u64 iq = queue[q];
+            const PhotonStart ps = {qeps[q], qchi[q], a.gen ? sp.birth[iq] : 0.0, qn[q]};
+            photon_sample_one<R>(a, iq, qk[0][q], qk[1][q], qk[2][q], qx[0][q], qx[1][q], qx[2][q], ps, tab, pt, ts);
             __syncwarp();
         }
     }
     if (lane < queued) {
-        const PhotonStart ps = {qeps[lane], qchi[lane], qt0[lane], qn[lane]};
-        photon_sample_one<R>(a, queue[lane], ps, tab, pt, ts);
+        const u64 iq = queue[lane];
+        const PhotonStart ps = {qeps[lane], qchi[lane], a.gen ? sp.birth[iq] : 0.0, qn[lane]};
+        photon_sample_one<R>(a, iq, qk[0][lane], qk[1][lane], qk[2][lane], qx[0][lane], qx[1][lane], qx[2][lane], ps,
+                             tab, pt, ts);
     }
     const int work[2] = {0, 2};
     flush_tallies<R, 2>(tt, work, a.st, 2);
