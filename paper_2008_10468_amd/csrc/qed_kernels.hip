@@ -1206,7 +1206,10 @@ __device__ __forceinline__ void photon_sample_one(const StepArgs &a, u64 i, R kx
 // lo..hi of the device state; in a cascade pass (gen >= 1) each photon runs over
 // the rest of the step from its birth time.
 constexpr int kPhotonBatch = 2;
-constexpr int kPhotonQueue = 64 * (kPhotonBatch + 1);
+// The queue is drained after each group of 64 photons, so it holds at most 63 + 64
+// entries; at 128 entries the kernel's LDS (35 KB per block) and registers allow 4
+// waves per SIMD.
+constexpr int kPhotonQueue = 128;
 
 template <class R>
 __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
@@ -1316,7 +1319,7 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
             if (sp.events) sp.events[i] = 0u;
             t.substeps += N;
         }
-        // queue the photons that can decay; sample 64 at a time
+        // queue the photons that can decay, group by group; sample 64 at a time
 #pragma unroll
         for (int b = 0; b < kPhotonBatch; ++b) {
             const bool nb = (need >> b) & 1u;
@@ -1334,15 +1337,16 @@ __global__ __launch_bounds__(kBlock) void k_photon(StepArgs a) {
                 }
             }
             queued += (uint32_t)__popcll(m);
-        }
-        __syncwarp();
-        while (queued >= 64) {
-            queued -= 64;
-            const uint32_t q = queued + lane;
-            const u64 iq = queue[q];
-            const PhotonStart ps = {qeps[q], qchi[q], a.gen ? sp.birth[iq] : 0.0, qn[q]};
-            photon_sample_one<R>(a, iq, qk[0][q], qk[1][q], qk[2][q], qx[0][q], qx[1][q], qx[2][q], ps, tab, pt, ts);
             __syncwarp();
+            if (queued >= 64) {  // at most 127 queued here, at most 63 after
+                queued -= 64;
+                const uint32_t q = queued + lane;
+                const u64 iq = queue[q];
+                const PhotonStart ps = {qeps[q], qchi[q], a.gen ? sp.birth[iq] : 0.0, qn[q]};
+                photon_sample_one<R>(a, iq, qk[0][q], qk[1][q], qk[2][q], qx[0][q], qx[1][q], qx[2][q], ps, tab, pt,
+                                     ts);
+                __syncwarp();
+            }
         }
     }
     if (lane < queued) {
@@ -1441,11 +1445,14 @@ __global__ __launch_bounds__(kBlock) void k_photon_surr(StepArgs a) {
                 a.alive[i] = 1;
                 if (sp.events) sp.events[i] = 0;
             } else {
-                pid = sp.id[i];
                 eps = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
                 chi = (float)chi_def(eps, kx, ky, kz, ex, ey, ez, bx, by, bz);
                 tau = sp.tau[i];
-                if (!(tau > 0.0)) {
+                // the id keys the random stream: only a photon that draws a new optical
+                // depth or decays needs it (a few in a hundred), so it is loaded on demand
+                const bool fresh = !(tau > 0.0);
+                if (fresh) {
+                    pid = sp.id[i];
                     const u32x4 w = philox10((uint32_t)pid, (uint32_t)(pid >> 32), step, j++, klo, khi);
                     tau = -log(u53(w.x, w.y));
                 }
@@ -1453,6 +1460,7 @@ __global__ __launch_bounds__(kBlock) void k_photon_surr(StepArgs a) {
                 const double W = eps > 0.0 ? kAlpha * (double)chi / eps * (double)pair_t(chi, pt) : 0.0;
                 const double Wdt = W * a.dt;
                 decay = tau <= Wdt;
+                if (decay && !fresh) pid = sp.id[i];
                 ts_move = decay ? tau / W : a.dt;
                 tau = decay ? tau : tau - Wdt;
                 t.substeps += 1;
