@@ -136,3 +136,51 @@ def test_one_recorded_counted_step_replays_as_consecutive_steps(sched):
             assert np.array_equal(ref[s][k], got[s][k]), (s, k)
     qed.qed_graph_destroy(graph)
     g.close()
+
+
+def test_graph_replay_after_scratch_grows():
+    """A recorded graph keeps the scratch addresses it was recorded with: an eager step on
+    a larger population on the same context, which replaces the library's scratch with
+    larger buffers, leaves the graph's replays equal to the steps it recorded."""
+    from paper_2008_10468_amd import qed
+    stream = torch.cuda.Stream()
+    w = workloads.c2(n_e=20000, n_g=6000, seed=7)
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 15, 1 << 14, 1 << 16),
+                      scheduler=qed.QED_SCHED_BINNED, stream=stream.cuda_stream)
+    fields = qed.FieldBuffers(workloads.c2_field(0), g.real)
+
+    def steps(p):
+        for s in range(2):
+            assert qed.qed_step(g.ctx, p, [fields.struct()] * 3, w["dt"], 9, s) == qed.QED_OK
+
+    g.load_state(w)
+    torch.cuda.synchronize()
+    steps(g.particles())
+    assert g.sync()[0] == qed.QED_OK
+    ref = _state(g)
+    assert qed.qed_graph_begin(g.ctx) == qed.QED_OK
+    steps(g.particles())
+    st, graph = qed.qed_graph_end(g.ctx)
+    assert st == qed.QED_OK
+    # four times the population on the same context: photon and scheduler scratch grow
+    big = [qed.SpeciesBuffers(c, g.real, parent=False, events=False) for c in (1 << 17, 1 << 16, 1 << 18)]
+    w2 = workloads.c2(n_e=80000, n_g=24000, seed=8)
+    pb = qed.qed_particles()
+    for sb, name in zip(big, qed.SPECIES):
+        sb.upload(w2[name])
+        setattr(pb, name, sb.struct())
+    torch.cuda.synchronize()
+    steps(pb)
+    assert g.sync()[0] == qed.QED_OK
+    assert big[2].count() > 24000
+    for rep in range(2):
+        g.load_state(w)
+        torch.cuda.synchronize()
+        assert qed.qed_graph_launch(g.ctx, graph) == qed.QED_OK
+        assert g.sync()[0] == qed.QED_OK
+        got = _state(g)
+        for s in range(3):
+            for k in ref[s]:
+                assert np.array_equal(ref[s][k], got[s][k]), (rep, s, k)
+    qed.qed_graph_destroy(graph)
+    g.close()
