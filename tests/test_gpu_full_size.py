@@ -1,0 +1,127 @@
+"""Parity at the benchmark configurations' full sizes, in the launch configuration the
+benchmark times: C1 (16,384 electrons, FP64) in full, C3 (16,777,216 electrons, binned
+scheduler with its tuned launch shapes) and C4 (2^28 synchrotron evaluations) on sampled
+outputs the oracle computes one by one."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import as_precision
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TUNING = os.path.join(ROOT, "paper_2008_10468_amd", "tuning_gfx950.json")
+
+
+def _mom(d):
+    return np.stack([d["ux"], d["uy"], d["uz"]])
+
+
+def _apply_tuning(qed, g, key):
+    choice = json.load(open(TUNING))[key]["tuning"]
+    t = qed.qed_get_tuning(g.ctx)
+    for k, v in choice.items():
+        setattr(t, k, int(v))
+    assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
+
+
+def test_c1_full_size_fp64_identical_events():
+    """All 16,384 electrons of C1, three steps: identical events and momenta to 1e-9."""
+    from paper_2008_10468_amd import qed
+    w = workloads.c1()
+    n = w["electrons"]["id"].size
+    assert n == 16384
+    g = qed.Generator(precision=qed.QED_PREC_F64, capacity=(n, 16, 1 << 20), pairs=False)
+    g.load_state(w)
+    g.set_fields(w["fields"])
+    ost = {k: v.copy() for k, v in w["electrons"].items()}
+    for step in range(3):
+        print("C1 full size, step", step, flush=True)
+        g.step(w["dt"], w["seed"], step)
+        assert g.sync()[0] == qed.QED_OK
+        ev = g.sp[0].events_host(n)
+        _, nsub, nev, _ = oracle.lepton_step(ost, w["fields"], -1.0, w["dt"], w["seed"], step, rng_bits=53)
+        assert np.array_equal(ev, nev)
+        assert nsub.max() > 20
+    e = g.sp[0].download()
+    du = np.linalg.norm(_mom(e) - _mom(ost), axis=0) / np.linalg.norm(_mom(ost), axis=0)
+    assert du.max() < 1e-9
+    g.close()
+
+
+def test_c3_full_size_sampled_against_oracle():
+    """C3 at 16,777,216 electrons (10% in the hot spot), binned with the tuned launch
+    shapes, one step; 3,000 hot and 3,000 cold electrons checked by the oracle."""
+    from paper_2008_10468_amd import qed
+    print("C3 full size: building the population", flush=True)
+    w = workloads.c3()
+    n = w["electrons"]["id"].size
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, int(0.65 * n) + (1 << 23)), pairs=False,
+                      parent=False, events=True, scheduler=qed.QED_SCHED_BINNED)
+    _apply_tuning(qed, g, "c3/binned")
+    zero = workloads.uniform_field()
+    g.set_fields(None, per_species=[w["fields"], zero, zero])
+    g.load_state(w)
+    rng = np.random.default_rng(0)
+    hot = np.flatnonzero(w["hot"])
+    cold = np.flatnonzero(~w["hot"])
+    sel = np.sort(np.concatenate([rng.choice(hot, 3000, replace=False), rng.choice(cold, 3000, replace=False)]))
+    sub = workloads.subset(w["electrons"], sel)
+    sub = {k: (v.astype(np.float32).astype(np.float64) if k in ("ux", "uy", "uz", "w") else v.copy())
+           for k, v in sub.items()}
+    print("C3 full size: one step on the GPU", flush=True)
+    g.step(w["dt"], w["seed"], 0)
+    assert g.sync()[0] == qed.QED_OK
+    ev = g.sp[0].events_host(n)[sel]
+    uxg = g.sp[0].ux[torch.from_numpy(sel).cuda()].double().cpu().numpy()
+    uyg = g.sp[0].uy[torch.from_numpy(sel).cuda()].double().cpu().numpy()
+    uzg = g.sp[0].uz[torch.from_numpy(sel).cuda()].double().cpu().numpy()
+    st = g.stats()
+    g.close()
+    fh = as_precision(workloads.field_subset(w["fields"], sel), qed.QED_PREC_MIXED)
+    print("C3 full size: the oracle on the sample", flush=True)
+    _, nsub, nev, _ = oracle.lepton_step(sub, fh, -1.0, w["dt"], w["seed"], 0, rng_bits=24)
+    assert nsub.max() > 300                               # the sample reaches into the heavy tail
+    same = nev == ev
+    assert np.mean(same) >= 0.999, np.mean(same)
+    ug = np.stack([uxg, uyg, uzg])
+    du = np.linalg.norm(ug - _mom(sub), axis=0) / np.linalg.norm(_mom(sub), axis=0)
+    assert np.all(du[same] <= 2e-5 + 2e-7 * nsub[same])
+    assert st.heavy_particles > 0 and st.emissions > 0
+
+
+@pytest.mark.parametrize("dtype,tol", [("float32", 2e-6), ("float64", 1e-12)])
+def test_c4_full_size_sampled_against_oracle(dtype, tol):
+    """2^28 log-uniform x in [1e-4, 50] as the benchmark draws them; 20,000 sampled
+    outputs of F and G against the oracle's quadrature."""
+    from paper_2008_10468_amd import qed
+    n = 1 << 28
+    td = getattr(torch, dtype)
+    ctx = qed.qed_init(qed.qed_config_default())
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    u = torch.rand(n, generator=gen, device="cuda", dtype=torch.float64)
+    x = (10.0 ** (-4.0 + u * (math.log10(50.0) + 4.0))).to(td)
+    del u
+    F = torch.empty_like(x)
+    G = torch.empty_like(x)
+    qd = qed.QED_F32 if dtype == "float32" else qed.QED_F64
+    assert qed.qed_synchrotron(ctx, x.data_ptr(), F.data_ptr(), G.data_ptr(), n, qd) == qed.QED_OK
+    assert qed.qed_sync(ctx)[0] == qed.QED_OK
+    idx = torch.from_numpy(np.random.default_rng(1).choice(n, 20000, replace=False)).cuda()
+    xs = x[idx].double().cpu().numpy()
+    Fs = F[idx].double().cpu().numpy()
+    Gs = G[idx].double().cpu().numpy()
+    qed.qed_finalize(ctx)
+    del x, F, G
+    Fo, Go = oracle.synchrotron_parallel(xs)
+    assert np.max(np.abs(Fs / Fo - 1)) <= tol
+    assert np.max(np.abs(Gs / Go - 1)) <= tol
