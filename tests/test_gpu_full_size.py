@@ -1,7 +1,8 @@
 """Parity at the benchmark configurations' full sizes, in the launch configuration the
 benchmark times: C1 (16,384 electrons, FP64) in full, C3 (16,777,216 electrons, binned
 scheduler with its tuned launch shapes) and C4 (2^28 synchrotron evaluations) on sampled
-outputs the oracle computes one by one."""
+outputs the oracle computes one by one, and C5 (the shipped network in the C3 hot spot)
+against the plain generator in distribution."""
 import json
 import math
 import os
@@ -125,3 +126,47 @@ def test_c4_full_size_sampled_against_oracle(dtype, tol):
     Fo, Go = oracle.synchrotron_parallel(xs)
     assert np.max(np.abs(Fs / Fo - 1)) <= tol
     assert np.max(np.abs(Gs / Go - 1)) <= tol
+
+
+def test_c5_full_size_surrogate_against_plain():
+    """C5: the shipped network deployed in the 16.8M-electron hot spot (optical-depth path,
+    sub-step target 0.1, binned with its tuned shapes) against the plain rejection
+    generator on the same population, one step each: the same number of emissions within
+    statistics, the network serving most of them, and the same photon spectrum (KS)."""
+    from paper_2008_10468_amd import qed
+    from scipy import stats as sps
+    m = np.load(os.path.join(ROOT, "paper_2008_10468_amd", "models", "sampler_gfx950.npz"))
+    w = workloads.c3()
+    n = w["electrons"]["id"].size
+    zero = workloads.uniform_field()
+    out = {}
+    for name, sampler, key in (("plain", qed.QED_SAMPLER_REJECTION, "c3/binned"),
+                               ("surrogate", qed.QED_SAMPLER_SURROGATE, "c5/binned")):
+        print("C5 full size:", name, flush=True)
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, int(0.65 * n) + (1 << 23)), pairs=False,
+                          parent=False, events=False, scheduler=qed.QED_SCHED_BINNED, sampler=sampler,
+                          surrogate_p_max=0.1)
+        if sampler == qed.QED_SAMPLER_SURROGATE:
+            assert qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
+                                       float(m["log10_chi_hi"])) == qed.QED_OK
+        _apply_tuning(qed, g, key)
+        g.set_fields(None, per_species=[w["fields"], zero, zero])
+        g.load_state(w)
+        g.step(w["dt"], w["seed"], 0)
+        assert g.sync()[0] == qed.QED_OK
+        st = g.stats()
+        k = g.sp[2]
+        kk = torch.sqrt(k.ux[:k.count()].double() ** 2 + k.uy[:k.count()].double() ** 2 +
+                        k.uz[:k.count()].double() ** 2)
+        idx = torch.from_numpy(np.random.default_rng(3).choice(k.count(), 200000, replace=False)).cuda()
+        out[name] = (st.emissions, st.learned_events, sum(st.substeps), kk[idx].cpu().numpy())
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    ep, _, sp_, kp = out["plain"]
+    es, ls, ss, ks = out["surrogate"]
+    assert ep > 1e6
+    assert abs(ep - es) <= 4.5 * math.sqrt(ep + es), (ep, es)
+    assert ls > 0.9 * es
+    assert ss < 0.5 * sp_                        # the optical-depth path runs far fewer sub-steps
+    assert sps.ks_2samp(kp, ks).pvalue > 1e-3
