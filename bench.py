@@ -163,8 +163,9 @@ def measured_traffic(kernel, workload):
     return val
 
 
-def roofline(kt, st, K):
-    """Roofline of the kernel with the largest share of the profiled time."""
+def roofline(kt, st, K, workload):
+    """Roofline of the kernel with the largest share of the profiled time; `traffic` from
+    that workload's committed counter summary, if there is one."""
     cand = {k: v for k, v in kt.items()
             if k in ("k_lepton", "k_tiled", "k_light", "k_heavy", "k_photon")}
     name = max(cand, key=lambda k: cand[k][1])
@@ -187,8 +188,8 @@ def roofline(kt, st, K):
         byts = BYTES_PER_LEPTON_STEP * part + 4 * lep_part + BYTES_PER_EMISSION * em
         flops = FLOPS_PER_LEPTON_SUBSTEP * sub
     else:  # k_photon: every photon is read and written back (position, flag); the ones
-        # that can decay also run the sampling loop (their second read of the record
-        # hits the cache); each pair writes two lepton records and a dead-list entry
+        # that can decay also run the sampling loop (from their record kept in LDS);
+        # each pair writes two lepton records and a dead-list entry
         part, sub, em = st.particles[2], st.substeps[2], st.pairs
         byts = (BYTES_PER_PHOTON_READ + BYTES_PER_PHOTON_WRITE) * part + BYTES_PER_PAIR * em
         flops = FLOPS_PER_PHOTON_MOVE * (sub - st.sampled_substeps) + FLOPS_PER_PHOTON_SUBSTEP * st.sampled_substeps
@@ -202,7 +203,7 @@ def roofline(kt, st, K):
         roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(name, "c2")
+    roof["traffic"] = measured_traffic(name, workload)
     roof["kernel"] = name
     roof["avg_launch_us"] = avg_s * 1e6
     roof["per_launch"] = {"particles": part / max(nl, 1), "substeps": sub / max(nl, 1),
@@ -311,7 +312,7 @@ def bench_c2(args, torch, qed, workloads):
         "scheduler": args.scheduler, "tuning": tuned,
         "launch": "one HIP graph of all timed steps" if graphed else "eager"})
     out["events_per_s"] = (stats.emissions + stats.pairs) / (ms * 1e-3)
-    out["roofline"] = roofline(kt, stats_p, K)
+    out["roofline"] = roofline(kt, stats_p, K, "c2")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(workloads, args.cpu_seconds)
     g.close()
@@ -399,7 +400,7 @@ def bench_c3(args, torch, qed, workloads):
         "scheduler": args.scheduler, "tuning": tuned,
         "launch": "one HIP graph of all timed steps" if graphed else "eager"})
     out["events_per_s"] = stats.emissions / (ms * 1e-3)
-    out["roofline"] = roofline(kt, stats_p, K)
+    out["roofline"] = roofline(kt, stats_p, K, "c3")
     g.close()
     return out
 
@@ -541,12 +542,111 @@ def copy_probe(torch, mib):
     return {"bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms, "GBps": 8 * n / (ms * 1e-3) / 1e9}
 
 
+def bench_shower(args, torch, qed, workloads):
+    """In-step cascades: 65,536 electrons, positrons and photons each seeding a shower
+    (energies 1e4 to 3e5, B = 2e-3 E_S); every step runs the main pass and five
+    follow-up passes over the particles created in the previous pass."""
+    K, W = (args.steps if args.steps_given else 1), 1    # the population grows several-fold per step
+    gens = 5
+    n = 1 << 16
+    w = workloads.shower(n=n)
+    stream = torch.cuda.Stream()
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 22, 1 << 22, 1 << 23), parent=False,
+                      events=False, stream=stream.cuda_stream, cascade_generations=gens)
+    g.set_fields(w["fields"])
+    f = g.fields[0].struct()
+    fields = lambda s: (qed.qed_field * 3)(f, f, f)
+    log(f"bench: shower workload, {n} of each species, dt={w['dt']}, {gens} cascade passes, steps={K}")
+    ms, stats, stats_p, kt, graphed = stepped(torch, qed, g, stream, fields, w, w["dt"], w["seed"], K, W,
+                                              not args.no_graph)
+    out = header(args, sum(stats.substeps) / (ms * 1e-3), ms, K, W, "f32", {
+        "workload": f"shower: {n} electrons, {n} positrons, {n} photons, energies log-uniform [1e4, 3e5], "
+                    f"isotropic, uniform B = 2e-3 E_S, {gens} in-step cascade passes, mixed precision",
+        "steps": K, "dt_hbar_over_mc2": w["dt"], "cascade_generations": gens,
+        "launch": "one HIP graph of all timed steps" if graphed else "eager"})
+    out["particle_steps"] = list(stats.particles)
+    out["events"] = {"emissions": stats.emissions, "pairs": stats.pairs}
+    out["roofline"] = roofline(kt, stats_p, K, "shower")
+    g.close()
+    return out
+
+
+def bench_grid(args, torch, qed, workloads):
+    """Grid coupling: gather of the six Yee-grid field components to the particles and
+    deposition of their currents, 1,048,576 electrons (the C2 population) in a periodic
+    box of 32^3 cells by default (32 particles per cell; --grid-cells 128 gives 0.5), stored in
+    cell order as a PIC code keeps them (the figure) and in random order (the worst case)."""
+    K = args.steps if args.steps_given else 50
+    n, nc = 1 << 20, int(args.grid_cells)
+    w = workloads.c2(n_e=n, n_g=16)
+    geom = workloads.cell_box(nc)
+    e = w["electrons"]
+    cell = ((np.floor((e["z"] - geom["z0"]) / geom["dz"]).astype(np.int64) % nc) * nc +
+            (np.floor((e["y"] - geom["y0"]) / geom["dy"]).astype(np.int64) % nc)) * nc + \
+        (np.floor((e["x"] - geom["x0"]) / geom["dx"]).astype(np.int64) % nc)
+    by_cell = workloads.subset(e, np.argsort(cell, kind="stable"))
+    stream = torch.cuda.Stream()
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, 16), parent=False, events=False,
+                      stream=stream.cuda_stream)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    comps = [torch.randn((nc, nc, nc), generator=gen, device="cuda", dtype=torch.float32) * 1e-3 for _ in range(6)]
+    grid = qed.cell_geometry(geom)
+    grid.ex, grid.ey, grid.ez, grid.bx, grid.by, grid.bz = [c.data_ptr() for c in comps]
+    outs = [torch.empty(n, device="cuda", dtype=torch.float32) for _ in range(6)]
+    j = [torch.zeros(nc ** 3, device="cuda", dtype=torch.float64) for _ in range(3)]
+    sp = g.sp[0].struct()
+    ptrs = [o.data_ptr() for o in outs]
+
+    def timed(fn):
+        for _ in range(3):
+            assert fn() == qed.QED_OK
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(K):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K
+
+    times = {}
+    for order, pop in (("random", e), ("cell", by_cell)):
+        g.load_state({"electrons": pop, "positrons": w["positrons"], "photons": w["photons"]})
+        torch.cuda.synchronize()
+        times[order] = (timed(lambda: qed.qed_gather(g.ctx, grid, sp, ptrs)),
+                        timed(lambda: qed.qed_deposit(g.ctx, grid, sp, -1.0, *[t.data_ptr() for t in j])))
+        assert g.sync()[0] == qed.QED_OK
+    ms_g, ms_d = times["cell"]
+    grid_bytes = 6 * 4 * nc ** 3
+    j_bytes = 3 * 8 * nc ** 3
+    bytes_g = n * (24 + 6 * 4) + grid_bytes          # positions read, six floats written, the grid once
+    bytes_d = n * (24 + 3 * 4 + 4) + 2 * j_bytes     # positions, momenta and weight read, J read and written once
+    for order, (tg, td) in times.items():
+        log(f"bench: grid {nc}^3, {n} electrons in {order} order: gather {tg * 1e3:.1f} us, "
+            f"deposit {td * 1e3:.1f} us per call")
+    out = header(args, n / ((ms_g + ms_d) * 1e-3), (ms_g + ms_d) * K, K, 3, "f32+f64", {
+        "workload": f"grid coupling: {n} electrons (C2 population, positions uniform over the box, stored in "
+                    f"cell order), periodic Yee grid of {nc}^3 cells, float fields, double currents; one gather "
+                    f"and one deposit per step", "cells": nc ** 3}, metric="particles/s")
+    rd = lambda b, ms: {"bound": "hbm", "achieved": b / (ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                        "frac": b / (ms * 1e-3) / 8e12, "traffic": None,
+                        "avg_launch_us": ms * 1e3, "algorithmic_bytes": b}
+    out["gather"] = rd(bytes_g, ms_g)
+    out["deposit"] = rd(bytes_d, ms_d)
+    out["random_order_us"] = {"gather": times["random"][0] * 1e3, "deposit": times["random"][1] * 1e3}
+    dom = "gather" if ms_g >= ms_d else "deposit"
+    out["roofline"] = dict(out[dom], kernel=f"k_{dom}")
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=("c2", "c1", "c3", "c4", "c5", "c2s"), default="c2")
+    ap.add_argument("--workload", choices=("c2", "c1", "c3", "c4", "c5", "c2s", "shower", "grid"), default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--scheduler", choices=("naive", "binned", "tiled"), default="naive")
@@ -554,6 +654,7 @@ def main():
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2008_10468_amd", "tuning_gfx950.json"))
     ap.add_argument("--c3-particles", type=float, default=16777216)
     ap.add_argument("--c4-log2n", type=int, default=28)
+    ap.add_argument("--grid-cells", type=int, default=32, help="grid: cells per axis of the periodic box")
     ap.add_argument("--save-model", default=None, help="c5: write the trained network to this .npz")
     ap.add_argument("--surrogate-p-max", type=float, default=0.1,
                     help="c5: the surrogate's lepton sub-step target")
@@ -574,7 +675,7 @@ def main():
 
     torch.cuda.set_device(0)
     fn = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
-          "c2s": bench_c2s}[args.workload]
+          "c2s": bench_c2s, "shower": bench_shower, "grid": bench_grid}[args.workload]
     out = fn(args, torch, qed, workloads)
     if args.copy_probe:
         out["copy_probe"] = copy_probe(torch, args.copy_probe)

@@ -356,7 +356,9 @@ QED_API qed_status qed_gather(qed_ctx *ctx, const qed_grid *grid, const qed_spec
 
 /* Stage 4: adds every particle's current density charge * w * u / gamma / (dx dy dz),
  * spread with the same weights, to jx, jy, jz (DEVICE double arrays on the Ex, Ey, Ez
- * lattices; the caller clears them).  charge: -1 for electrons, +1 for positrons (in
+ * lattices, in ordinary device memory such as hipMalloc returns: the sums use the
+ * hardware's double atomic add, which fine-grained or host memory does not support; the
+ * caller clears them; the order of the additions, hence the last bits, may vary).  charge: -1 for electrons, +1 for positrons (in
  * units of e; the velocity is in units of c).  The grid's field pointers are not
  * used.  The species needs n, x, y, z, ux, uy, uz, w. */
 QED_API qed_status qed_deposit(qed_ctx *ctx, const qed_grid *grid, const qed_species *sp, double charge,

@@ -7,7 +7,10 @@
 // Bx (0, 1/2, 1/2), By (1/2, 0, 1/2), Bz (1/2, 1/2, 0)); both stages use linear
 // (cloud-in-cell) weights on that lattice, computed in double from the double
 // positions.  One lane per particle; the grid arrays are read through the cache
-// (neighbouring particles share cells), the currents are added with double atomics.
+// (neighbouring particles share cells), the currents are added with the hardware's
+// double-precision atomic add (ordinary device memory; the default compare-and-swap
+// loop of atomicAdd on doubles is several times slower), combined first across the
+// lanes of a wave that share a cell.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -76,24 +79,85 @@ __global__ __launch_bounds__(kGridBlock) void k_gather(GridDev g, GatherArgs a) 
     }
 }
 
+// Deposition.  Lanes whose particles share a component's lattice cell (the usual case
+// when particles are stored in cell order, as PIC codes keep them) have the same eight
+// corners: the wave then sums their contributions per distinct cell with cross-lane
+// reductions and one lane adds the eight sums, so same-address atomics do not
+// serialise.  A wave whose lanes fall into many different cells (particles in random
+// order) adds directly.  The choice is made per wave from the number of changes of the
+// particles' node cell between neighbouring lanes (each node cell spans at most two
+// cells of a staggered lattice per axis); kMaxRuns is the largest count for which the
+// wave combines first.
+constexpr int kMaxRuns = 12;
+
+// Node cell (i, j, k) of a position, flattened, as corners() wraps it.
+__device__ __forceinline__ uint32_t node_cell(const GridDev &g, double x, double y, double z) {
+    const double fx0 = floor((x - g.x0) * g.idx), fy0 = floor((y - g.y0) * g.idy), fz0 = floor((z - g.z0) * g.idz);
+    long long ix = (long long)fx0 % (long long)g.nx, iy = (long long)fy0 % (long long)g.ny,
+              iz = (long long)fz0 % (long long)g.nz;
+    ix += ix < 0 ? g.nx : 0;
+    iy += iy < 0 ? g.ny : 0;
+    iz += iz < 0 ? g.nz : 0;
+    return ((uint32_t)iz * g.ny + (uint32_t)iy) * g.nx + (uint32_t)ix;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 template <class R>
 __global__ __launch_bounds__(kGridBlock) void k_deposit(GridDev g, DepositArgs a) {
     const u64 n0 = *a.n;
     const u64 n = n0 < a.cap ? n0 : a.cap;
     const double scale = a.charge * g.idx * g.idy * g.idz;   // q / cell volume
-    for (u64 p = (u64)blockIdx.x * kGridBlock + threadIdx.x; p < n; p += (u64)gridDim.x * kGridBlock) {
-        const double ux = (double)((const R *)a.ux)[p], uy = (double)((const R *)a.uy)[p],
-                     uz = (double)((const R *)a.uz)[p];
-        const double w = (double)((const R *)a.w)[p];
-        const double gi = 1.0 / sqrt(1.0 + ux * ux + uy * uy + uz * uz);
-        const double cur[3] = {scale * w * ux * gi, scale * w * uy * gi, scale * w * uz * gi};
-        const double x = a.x[p], y = a.y[p], z = a.z[p];
+    const uint32_t lane = __lane_id();
+    // wave-uniform loop: lane l of the wave takes particle p0 + l
+    for (u64 p0 = (u64)blockIdx.x * kGridBlock + (threadIdx.x & ~63u); p0 < n; p0 += (u64)gridDim.x * kGridBlock) {
+        const u64 p = p0 + lane;
+        const bool has = p < n;
+        double cur[3] = {0.0, 0.0, 0.0};
+        double x = g.x0, y = g.y0, z = g.z0;
+        if (has) {
+            const double ux = (double)((const R *)a.ux)[p], uy = (double)((const R *)a.uy)[p],
+                         uz = (double)((const R *)a.uz)[p];
+            const double w = (double)((const R *)a.w)[p];
+            const double gi = 1.0 / sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+            cur[0] = scale * w * ux * gi;
+            cur[1] = scale * w * uy * gi;
+            cur[2] = scale * w * uz * gi;
+            x = a.x[p];
+            y = a.y[p];
+            z = a.z[p];
+        }
+        const uint32_t node = node_cell(g, x, y, z);
+        const uint32_t prev_node = __shfl_up(node, 1);
+        const bool prev_has = __shfl_up(has ? 1 : 0, 1) != 0;
+        const bool combine = __popcll(__ballot(has && (lane == 0 || !prev_has || prev_node != node))) <= kMaxRuns;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            if (cur[c] == 0.0) continue;
+            const bool act = has && cur[c] != 0.0;
             const Corners cr = corners(g, x, y, z, kStagger[c][0], kStagger[c][1], kStagger[c][2]);
+            const uint32_t key = cr.idx[0];   // the corners follow from the first one
+            if (!combine) {
+                if (act)
 #pragma unroll
-            for (int q = 0; q < 8; ++q) atomicAdd(&a.j[c][cr.idx[q]], cr.w[q] * cur[c]);
+                    for (int q = 0; q < 8; ++q) unsafeAtomicAdd(&a.j[c][cr.idx[q]], cr.w[q] * cur[c]);
+                continue;
+            }
+            u64 pending = __ballot(act);
+            while (pending) {
+                const int leader = __ffsll((long long)pending) - 1;
+                const uint32_t lk = __shfl(key, leader);
+                const bool mine = ((pending >> lane) & 1ull) && key == lk;
+                pending &= ~__ballot(mine);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const double v = wave_sum_d(mine ? cr.w[q] * cur[c] : 0.0);
+                    if ((int)lane == leader) unsafeAtomicAdd(&a.j[c][cr.idx[q]], v);
+                }
+            }
         }
     }
 }
