@@ -351,16 +351,19 @@ typedef struct qed_grid {
 /* Stage 2: E and B at every particle of the species (slots below its live count,
  * read on the device), written to out[0..5] = Ex, Ey, Ez, Bx, By, Bz (DEVICE arrays
  * of at least capacity values, the context's float type): the per-slot fields
- * (stride 1) that qed_step reads.  The species needs n, x, y, z. */
+ * (stride 1) that qed_step reads.  A particle whose position is not finite gets NaN
+ * fields (qed_step then skips it as non-finite input).  The species needs n, x, y, z. */
 QED_API qed_status qed_gather(qed_ctx *ctx, const qed_grid *grid, const qed_species *sp, void *const out[3 + 3]);
 
 /* Stage 4: adds every particle's current density charge * w * u / gamma / (dx dy dz),
- * spread with the same weights, to jx, jy, jz (DEVICE double arrays on the Ex, Ey, Ez
- * lattices, in ordinary device memory such as hipMalloc returns: the sums use the
- * hardware's double atomic add, which fine-grained or host memory does not support; the
- * caller clears them; the order of the additions, hence the last bits, may vary).  charge: -1 for electrons, +1 for positrons (in
- * units of e; the velocity is in units of c).  The grid's field pointers are not
- * used.  The species needs n, x, y, z, ux, uy, uz, w. */
+ * spread with the same weights, to jx, jy, jz: DEVICE double arrays on the Ex, Ey, Ez
+ * lattices, in ordinary device memory such as hipMalloc returns (the sums use the
+ * hardware's double atomic add, which fine-grained or host memory does not support);
+ * the caller clears them, and the order of the additions, hence the last bits, may
+ * vary.  charge: -1 for electrons, +1 for positrons (in units of e; the velocity is in
+ * units of c).  The grid's field pointers are not used.  Particles with a non-finite
+ * position, momentum or weight deposit nothing.  The species needs n, x, y, z, ux, uy,
+ * uz, w. */
 QED_API qed_status qed_deposit(qed_ctx *ctx, const qed_grid *grid, const qed_species *sp, double charge,
                                double *jx, double *jy, double *jz);
 

@@ -26,20 +26,29 @@ struct Corners {
     double w[8];
 };
 
+// Periodic index in [0, n) of the lattice point at or below f = floor(s), computed in
+// double (exact while |f| < 2^53 / n; beyond that only kept in range).  Callers pass
+// finite s.
+__device__ __forceinline__ uint32_t wrap_index(double f, uint32_t n) {
+    double r = f - (double)n * floor(f / (double)n);
+    r = r < 0.0 ? 0.0 : (r > (double)(n - 1) ? (double)(n - 1) : r);
+    return (uint32_t)r;
+}
+
+// A position whose lattice coordinates are finite (the others are skipped).
+__device__ __forceinline__ bool on_grid(const GridDev &g, double x, double y, double z) {
+    return isfinite((x - g.x0) * g.idx) && isfinite((y - g.y0) * g.idy) && isfinite((z - g.z0) * g.idz);
+}
+
 // The 8 lattice points around (x, y, z) on the lattice shifted by (ox, oy, oz) cells,
-// with their weights (periodic).
+// with their weights (periodic).  The position must be on_grid.
 __device__ __forceinline__ Corners corners(const GridDev &g, double x, double y, double z, double ox, double oy,
                                            double oz) {
     const double sx = (x - g.x0) * g.idx - ox, sy = (y - g.y0) * g.idy - oy, sz = (z - g.z0) * g.idz - oz;
     const double fx0 = floor(sx), fy0 = floor(sy), fz0 = floor(sz);
     const double fx = sx - fx0, fy = sy - fy0, fz = sz - fz0;
     // periodic wrap of the lower corner (positions may lie outside the box)
-    long long ix = (long long)fx0 % (long long)g.nx, iy = (long long)fy0 % (long long)g.ny,
-              iz = (long long)fz0 % (long long)g.nz;
-    ix += ix < 0 ? g.nx : 0;
-    iy += iy < 0 ? g.ny : 0;
-    iz += iz < 0 ? g.nz : 0;
-    const uint32_t i0 = (uint32_t)ix, j0 = (uint32_t)iy, k0 = (uint32_t)iz;
+    const uint32_t i0 = wrap_index(fx0, g.nx), j0 = wrap_index(fy0, g.ny), k0 = wrap_index(fz0, g.nz);
     const uint32_t i1 = i0 + 1 == g.nx ? 0 : i0 + 1, j1 = j0 + 1 == g.ny ? 0 : j0 + 1,
                    k1 = k0 + 1 == g.nz ? 0 : k0 + 1;
     Corners c;
@@ -67,6 +76,11 @@ __global__ __launch_bounds__(kGridBlock) void k_gather(GridDev g, GatherArgs a) 
     const u64 n = n0 < a.cap ? n0 : a.cap;
     for (u64 p = (u64)blockIdx.x * kGridBlock + threadIdx.x; p < n; p += (u64)gridDim.x * kGridBlock) {
         const double x = a.x[p], y = a.y[p], z = a.z[p];
+        if (!on_grid(g, x, y, z)) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) ((R *)a.out[c])[p] = (R)NAN;
+            continue;
+        }
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             const Corners cr = corners(g, x, y, z, kStagger[c][0], kStagger[c][1], kStagger[c][2]);
@@ -90,15 +104,11 @@ __global__ __launch_bounds__(kGridBlock) void k_gather(GridDev g, GatherArgs a) 
 // wave combines first.
 constexpr int kMaxRuns = 12;
 
-// Node cell (i, j, k) of a position, flattened, as corners() wraps it.
+// Node cell (i, j, k) of an on_grid position, flattened, wrapped as corners() wraps.
 __device__ __forceinline__ uint32_t node_cell(const GridDev &g, double x, double y, double z) {
-    const double fx0 = floor((x - g.x0) * g.idx), fy0 = floor((y - g.y0) * g.idy), fz0 = floor((z - g.z0) * g.idz);
-    long long ix = (long long)fx0 % (long long)g.nx, iy = (long long)fy0 % (long long)g.ny,
-              iz = (long long)fz0 % (long long)g.nz;
-    ix += ix < 0 ? g.nx : 0;
-    iy += iy < 0 ? g.ny : 0;
-    iz += iz < 0 ? g.nz : 0;
-    return ((uint32_t)iz * g.ny + (uint32_t)iy) * g.nx + (uint32_t)ix;
+    const uint32_t i = wrap_index(floor((x - g.x0) * g.idx), g.nx), j = wrap_index(floor((y - g.y0) * g.idy), g.ny),
+                   k = wrap_index(floor((z - g.z0) * g.idz), g.nz);
+    return (k * g.ny + j) * g.nx + i;
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -124,12 +134,15 @@ __global__ __launch_bounds__(kGridBlock) void k_deposit(GridDev g, DepositArgs a
                          uz = (double)((const R *)a.uz)[p];
             const double w = (double)((const R *)a.w)[p];
             const double gi = 1.0 / sqrt(1.0 + ux * ux + uy * uy + uz * uz);
-            cur[0] = scale * w * ux * gi;
-            cur[1] = scale * w * uy * gi;
-            cur[2] = scale * w * uz * gi;
-            x = a.x[p];
-            y = a.y[p];
-            z = a.z[p];
+            const double px = a.x[p], py = a.y[p], pz = a.z[p];
+            if (on_grid(g, px, py, pz) && isfinite(w * gi * (ux + uy + uz))) {
+                cur[0] = scale * w * ux * gi;
+                cur[1] = scale * w * uy * gi;
+                cur[2] = scale * w * uz * gi;
+                x = px;
+                y = py;
+                z = pz;
+            }
         }
         const uint32_t node = node_cell(g, x, y, z);
         const uint32_t prev_node = __shfl_up(node, 1);

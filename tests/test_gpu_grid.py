@@ -150,3 +150,41 @@ def test_grid_rejects_bad_arguments():
     assert qed.qed_deposit(gen.ctx, s, gen.sp[0].struct(), float("nan"), ptrs[0], ptrs[1], ptrs[2]) == \
         qed.QED_ERR_INVALID_ARG
     gen.close()
+
+
+def test_non_finite_positions():
+    """A particle whose position is not finite gets NaN fields and deposits nothing;
+    the others are unaffected (against the oracle on the finite particles)."""
+    from paper_2008_10468_amd import qed
+    rng = np.random.default_rng(6)
+    gen = qed.Generator(precision=qed.QED_PREC_F64, capacity=(4096, 16, 16))
+    g, s, _ = _grid(qed, gen.real, rng, nx=9, ny=6, nz=5)
+    p = _particles(g, rng, 4000)
+    bad = np.zeros(4000, bool)
+    bad[[3, 100, 2500]] = True
+    p["x"][3], p["y"][100], p["z"][2500] = np.nan, np.inf, -np.inf
+    p["x"][7] = 1e300                                       # finite but far away: wraps
+    gen.sp[0].upload(p)
+    out = [torch.empty(4096, dtype=gen.real, device="cuda") for _ in COMP]
+    assert qed.qed_gather(gen.ctx, s, gen.sp[0].struct(), [t.data_ptr() for t in out]) == qed.QED_OK
+    ncell = g["nx"] * g["ny"] * g["nz"]
+    j = [torch.zeros(ncell, dtype=torch.float64, device="cuda") for _ in range(3)]
+    assert qed.qed_deposit(gen.ctx, s, gen.sp[0].struct(), 1.0, *[t.data_ptr() for t in j]) == qed.QED_OK
+    torch.cuda.synchronize()
+    ok = ~bad
+    ok[7] = False                                           # beyond 2^53 cells only kept in range
+    ref = og.gather(g, p["x"][ok], p["y"][ok], p["z"][ok])
+    for c, t in zip(COMP, out):
+        got = t.cpu().numpy()[:4000]
+        assert np.all(np.isnan(got[bad])) and np.isfinite(got[7])
+        assert np.abs(got[ok] - ref[c]).max() <= 1e-12 * np.abs(g[c]).max()
+    keep = ~bad
+    q = {k: v[keep] for k, v in p.items()}
+    # the far particle deposits somewhere in the box: compare the totals
+    gam = np.sqrt(1 + q["ux"] ** 2 + q["uy"] ** 2 + q["uz"] ** 2)
+    vol = g["dx"] * g["dy"] * g["dz"]
+    for t, u in zip(j, ("ux", "uy", "uz")):
+        got = t.cpu().numpy()
+        assert np.all(np.isfinite(got))
+        assert np.isclose(got.sum() * vol, np.sum(q["w"] * q[u] / gam), rtol=1e-9)
+    gen.close()
