@@ -93,29 +93,16 @@ __global__ __launch_bounds__(kGridBlock) void k_gather(GridDev g, GatherArgs a) 
     }
 }
 
-// Deposition.  Lanes whose particles share a component's lattice cell (the usual case
-// when particles are stored in cell order, as PIC codes keep them) have the same eight
-// corners: the wave then sums their contributions per distinct cell with cross-lane
-// reductions and one lane adds the eight sums, so same-address atomics do not
-// serialise.  A wave whose lanes fall into many different cells (particles in random
-// order) adds directly.  The choice is made per wave from the number of changes of the
-// particles' node cell between neighbouring lanes (each node cell spans at most two
-// cells of a staggered lattice per axis); kMaxRuns is the largest count for which the
-// wave combines first.
-constexpr int kMaxRuns = 12;
-
-// Node cell (i, j, k) of an on_grid position, flattened, wrapped as corners() wraps.
-__device__ __forceinline__ uint32_t node_cell(const GridDev &g, double x, double y, double z) {
-    const uint32_t i = wrap_index(floor((x - g.x0) * g.idx), g.nx), j = wrap_index(floor((y - g.y0) * g.idy), g.ny),
-                   k = wrap_index(floor((z - g.z0) * g.idz), g.nz);
-    return (k * g.ny + j) * g.nx + i;
-}
-
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
+// Deposition.  Particles stored in cell order (as PIC codes keep them) put neighbouring
+// lanes into the same node cell.  Relative to its node cell a particle's contribution
+// to current component c falls on 12 lattice points: three along the axis on which
+// the component's lattice is shifted by half a cell (offsets -1, 0, +1) and two along
+// each other axis (0, +1).  The wave sums those 12 values over each run of lanes in
+// the same node cell with a segmented scan, and the run's last lane adds the 12 sums
+// with the hardware's double atomic add, so same-address atomics do not serialise.
+// A wave with more than kMaxRuns runs (particles in random order, or sparser than
+// about two per cell) adds each particle's 8 corners directly.
+constexpr int kMaxRuns = 32;
 
 template <class R>
 __global__ __launch_bounds__(kGridBlock) void k_deposit(GridDev g, DepositArgs a) {
@@ -123,6 +110,7 @@ __global__ __launch_bounds__(kGridBlock) void k_deposit(GridDev g, DepositArgs a
     const u64 n = n0 < a.cap ? n0 : a.cap;
     const double scale = a.charge * g.idx * g.idy * g.idz;   // q / cell volume
     const uint32_t lane = __lane_id();
+    const uint32_t dims[3] = {g.nx, g.ny, g.nz};
     // wave-uniform loop: lane l of the wave takes particle p0 + l
     for (u64 p0 = (u64)blockIdx.x * kGridBlock + (threadIdx.x & ~63u); p0 < n; p0 += (u64)gridDim.x * kGridBlock) {
         const u64 p = p0 + lane;
@@ -144,31 +132,86 @@ __global__ __launch_bounds__(kGridBlock) void k_deposit(GridDev g, DepositArgs a
                 z = pz;
             }
         }
-        const uint32_t node = node_cell(g, x, y, z);
-        const uint32_t prev_node = __shfl_up(node, 1);
-        const bool prev_has = __shfl_up(has ? 1 : 0, 1) != 0;
-        const bool combine = __popcll(__ballot(has && (lane == 0 || !prev_has || prev_node != node))) <= kMaxRuns;
+        // node cell and the fractions within it (lanes without a particle sit at the
+        // origin with zero current)
+        const double s3[3] = {(x - g.x0) * g.idx, (y - g.y0) * g.idy, (z - g.z0) * g.idz};
+        uint32_t nd[3];
+        double ph[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double f = floor(s3[d]);
+            nd[d] = wrap_index(f, dims[d]);
+            ph[d] = s3[d] - f;
+        }
+        const uint32_t node = (nd[2] * g.ny + nd[1]) * g.nx + nd[0];
+        const uint32_t prev = __shfl_up(node, 1);
+        const u64 starts = __ballot(lane == 0 || prev != node);
+        if (__popcll(starts) > kMaxRuns) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (!(has && cur[c] != 0.0)) continue;
+                const Corners cr = corners(g, x, y, z, kStagger[c][0], kStagger[c][1], kStagger[c][2]);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) unsafeAtomicAdd(&a.j[c][cr.idx[q]], cr.w[q] * cur[c]);
+            }
+            continue;
+        }
+        // run of this lane (1-based count of run starts up to it) and scan masks
+        const uint32_t rid = (uint32_t)__popcll(starts & ((2ull << lane) - 1ull));
+        bool same[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            const uint32_t o = 1u << t;
+            const uint32_t r = __shfl_up(rid, o);   // every lane takes part in the shuffle
+            same[t] = lane >= o && r == rid;
+        }
+        const bool last = lane == 63 || (((starts >> lane) >> 1) & 1ull);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const bool act = has && cur[c] != 0.0;
-            const Corners cr = corners(g, x, y, z, kStagger[c][0], kStagger[c][1], kStagger[c][2]);
-            const uint32_t key = cr.idx[0];   // the corners follow from the first one
-            if (!combine) {
-                if (act)
+            // weights along each axis: the shifted axis c over offsets -1, 0, +1
+            double wa[3][3];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) unsafeAtomicAdd(&a.j[c][cr.idx[q]], cr.w[q] * cur[c]);
-                continue;
+            for (int d = 0; d < 3; ++d) {
+                const double f = ph[d];
+                if (d == c) {
+                    const bool up = f >= 0.5;
+                    wa[d][0] = up ? 0.0 : 0.5 - f;
+                    wa[d][1] = up ? 1.5 - f : f + 0.5;
+                    wa[d][2] = up ? f - 0.5 : 0.0;
+                } else {
+                    wa[d][0] = 1.0 - f;
+                    wa[d][1] = f;
+                    wa[d][2] = 0.0;
+                }
             }
-            u64 pending = __ballot(act);
-            while (pending) {
-                const int leader = __ffsll((long long)pending) - 1;
-                const uint32_t lk = __shfl(key, leader);
-                const bool mine = ((pending >> lane) & 1ull) && key == lk;
-                pending &= ~__ballot(mine);
+            // the 12 values: shifted axis slot a (0..2), the other two axes slots b, e
+            const int d1 = c == 0 ? 1 : 0, d2 = c == 2 ? 1 : 2;
+            double v[12];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const double v = wave_sum_d(mine ? cr.w[q] * cur[c] : 0.0);
-                    if ((int)lane == leader) unsafeAtomicAdd(&a.j[c][cr.idx[q]], v);
+            for (int q = 0; q < 12; ++q) v[q] = cur[c] * wa[c][q / 4] * wa[d1][(q / 2) & 1] * wa[d2][q & 1];
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+#pragma unroll
+                for (int q = 0; q < 12; ++q) {
+                    const double o = __shfl_up(v[q], 1u << t);
+                    if (same[t]) v[q] += o;
+                }
+            }
+            if (last) {
+#pragma unroll
+                for (int q = 0; q < 12; ++q) {
+                    if (v[q] == 0.0) continue;
+                    int off[3];
+                    off[c] = q / 4 - 1;
+                    off[d1] = (q / 2) & 1;
+                    off[d2] = q & 1;
+                    uint32_t id[3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const int ii = (int)nd[d] + off[d];
+                        id[d] = ii < 0 ? (uint32_t)(ii + (int)dims[d]) : ((uint32_t)ii >= dims[d] ? (uint32_t)ii - dims[d] : (uint32_t)ii);
+                    }
+                    unsafeAtomicAdd(&a.j[c][(id[2] * g.ny + id[1]) * g.nx + id[0]], v[q]);
                 }
             }
         }
