@@ -1,5 +1,7 @@
 // C ABI of the QED event generator: argument checks, context and scratch
-// management, launch sizing.  All device work is in qed_kernels.hip.
+// management, launch sizing.  All device work is in the kernels of qed_kernels.hip
+// (the step), qed_train.hip (the networks and their tables) and qed_grid.hip (grid
+// coupling).
 #include <hip/hip_runtime.h>
 
 #include <math.h>

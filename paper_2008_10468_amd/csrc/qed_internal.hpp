@@ -1,5 +1,5 @@
 // Internal interface between the C ABI (qed_capi.hip) and the kernels
-// (qed_kernels.hip).  Not installed, not part of the ABI.
+// (qed_kernels.hip, qed_train.hip, qed_grid.hip).  Not installed, not part of the ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -2,28 +2,37 @@
 //
 // One global step (Sec. 2.2) is the sequence
 //   k_begin    snapshot the live counts (particles appended later in the step wait
-//              for the next step) and clear the per-step counters;
-//   k_photon   Algorithm 2 for every photon: straight-line sub-steps, pair creation
-//              with density eq. (2) (photons that provably cannot decay in the step
-//              skip the sampling); pairs are appended to the e-/e+ buffers, the
-//              photon is flagged dead and its slot is put on the dead list;
+//              for the next step or a cascade pass) and clear the per-step counters;
+//   k_cell_clear / k_cell_max   only with sub-steps chosen per cell: the largest
+//              own sub-step count of each group in each cell, and each slot's cell;
+//   k_photon   Algorithm 2 for every photon: one streaming pass moves every photon
+//              and writes its end-of-step position; the photons that provably cannot
+//              decay in the step are then done, the others are queued per wave in LDS
+//              and sampled 64 at a time (pair creation with density eq. (2)); pairs
+//              are appended to the e-/e+ buffers, the photon is flagged dead and its
+//              slot is put on the dead list.  On the photon optical-depth path
+//              k_photon_surr replaces it (exact decay time, no sub-steps);
 //   Algorithm 1 for every electron and positron (Boris sub-steps, emission with
-//   density eq. (1), recoil, photons appended), scheduled one of two ways:
+//   density eq. (1), recoil, photons appended), scheduled one of three ways:
 //     naive:   k_lepton, one lane per particle in buffer order;
 //     binned:  k_prepass computes each particle's sub-step count N and a histogram
 //              over quarter-octave bins of N; k_scan and k_scatter build a work
 //              queue of the heavy particles (N > light_max) sorted by bin, heaviest
-//              first; k_light runs the light particles in buffer order; k_heavy is
-//              a persistent kernel whose waves claim chunks of the queue, so the
+//              first; k_light runs the light particles in tiles sorted by N; k_heavy
+//              is a persistent kernel whose waves claim chunks of the queue, so the
 //              64 lanes of a wave carry nearly the same N;
+//     tiled:   k_tiled sorts 256-slot tiles by N in LDS and runs them heaviest first;
+//   each has an instance for the lepton optical-depth path (surrogate sampler);
+//   cascade passes (cascade_generations > 0): k_gen, then k_photon and k_lepton over
+//              the particles created by the previous pass, from their birth times;
 //   k_end      clamp counts to capacity (reporting overflow), size the compaction;
 //   k_fill / k_move  fill the holes left by decayed photons in [0, S) with the
 //              survivors found in [S, n): both scans are O(decays).
-// Appends use one atomic per wavefront: the accepting lanes are found with a
-// ballot, the lowest one reserves popcount slots and each lane takes its rank.
-// Random numbers are keyed by (seed, id, step, sub-step), so every schedule gives
-// the same per-particle result.  The sub-step count of a particle comes from the
-// bounds f(b) of Sec. 3.1.1, evaluated in double at the step start.
+// Children are staged per wave in LDS and appended with one atomic per flush; pairs
+// take one atomic per wave and sub-step with a decay.  Random numbers are keyed by
+// (seed, id, step, sub-step), so every schedule gives the same per-particle result.
+// The sub-step count of a particle comes from the bounds f(b) of Sec. 3.1.1,
+// evaluated in double at the step start.
 #include <type_traits>
 
 #include "qed_device.hpp"

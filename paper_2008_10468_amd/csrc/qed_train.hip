@@ -1,8 +1,11 @@
-// Training of the surrogate sampler's network on the GPU.
+// Training of the optical-depth paths' networks on the GPU: the inverse CDF of the
+// emitted energy (target 0) and of the pair's energy split (target 1, the
+// half-distribution of |d - 1/2|), same network shape and kernels.
 //
 //   k_cdf_table    the normalised CDF of the emitted energy, eq. (1) integrated over
-//                  the candidate x, on a grid of chi (double, from the double fits
-//                  of the synchrotron functions);
+//                  the candidate x (or of the split, eq. (2) integrated over d), on a
+//                  grid of chi (double, from the double fits of the synchrotron
+//                  functions);
 //   k_mlp_data     training samples (chi, u) -> x = CDF_chi^{-1}(u) from the table;
 //   k_mlp_train    forward and backward passes on the matrix cores, gradients
 //                  reduced per block;
