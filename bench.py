@@ -328,7 +328,7 @@ def bench_c2s(args, torch, qed, workloads):
     for name, surrogate in (("plain_naive", False), ("surrogate_naive", True)):
         stream = torch.cuda.Stream()
         w, g, field = c2_setup(torch, qed, workloads, max(K, W), qed.QED_SCHED_NAIVE, stream, surrogate)
-        tuned = load_tuning(qed, g, "c2/naive", args.tuning)
+        tuned = load_tuning(qed, g, "c2s/naive" if surrogate else "c2/naive", args.tuning)
         log(f"bench: C2 {name}")
         fields = lambda s: (qed.qed_field * 3)(field(s), field(s), field(s))
         ms, stats, stats_p, kt, graphed = stepped(torch, qed, g, stream, fields, w, w["dt"], w["seed"], K, W,

@@ -138,11 +138,20 @@ def tune(torch, g, stream, state, fields_for_step, dt, seed, steps, keys, passes
 
 def _workload(name, torch, workloads, sched, stream, steps):
     """Generator, state, per-step fields, dt and seed of a named workload."""
-    if name == "c2":
-        w = workloads.c2()
-        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 23, 1 << 23, 1 << 25),
-                          parent=False, events=False, scheduler=sched, stream=stream.cuda_stream)
+    if name in ("c2", "c2s"):
+        # c2s: the same population on both optical-depth paths, with the shipped network
         import numpy as np
+        w = workloads.c2()
+        sur = qed.QED_SAMPLER_SURROGATE if name == "c2s" else qed.QED_SAMPLER_REJECTION
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 23, 1 << 23, 1 << 25),
+                          parent=False, events=False, scheduler=sched, stream=stream.cuda_stream,
+                          sampler=sur, pair_sampler=sur)
+        if name == "c2s":
+            m = np.load(MODEL)
+            st = qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
+                                     float(m["log10_chi_hi"]))
+            if st != qed.QED_OK:
+                raise qed.QedError(st, "qed_sampler_set")
         E = np.array([[workloads.c2_field(s)[k][0] for k in ("ex", "ey", "ez", "bx", "by", "bz")]
                       for s in range(steps)], np.float64)
         table = [torch.from_numpy(E[:, j].copy()).to(torch.float32).cuda() for j in range(6)]
@@ -187,7 +196,7 @@ def _workload(name, torch, workloads, sched, stream, steps):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Tune launch shapes of the QED generator on this GPU")
-    ap.add_argument("--workload", choices=("c2", "c3", "c5"), action="append")
+    ap.add_argument("--workload", choices=("c2", "c2s", "c3", "c5"), action="append")
     ap.add_argument("--scheduler", choices=("naive", "binned", "tiled"), action="append")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--passes", type=int, default=2)

@@ -173,6 +173,15 @@ def test_full_c2_size_sampled_against_oracle():
     from paper_2008_10468_amd import qed
     w = workloads.c2()
     g = _gen(qed.QED_PREC_MIXED, (1 << 22, 1 << 21, 1 << 22))
+    # the benchmark's launch shapes for this workload
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2008_10468_amd",
+                        "tuning_gfx950.json")
+    t = qed.qed_get_tuning(g.ctx)
+    for k, v in json.load(open(path))["c2/naive"]["tuning"].items():
+        setattr(t, k, int(v))
+    assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
     g.load_state(w)
     g.set_fields(workloads.c2_field(0))
     before, after, events, st, rep = gpu_step(g, None, w["dt"], 1, 0)
