@@ -9,7 +9,7 @@ buffers growing by appends for all timed steps.  Metric: particle-sub-steps per
 second (sub-steps of the adaptive generator summed over all particles), with
 events per second beside it.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -662,7 +662,7 @@ def main():
                     help="after the run, copy a MIB-MiB float buffer once (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the path runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     args.steps_given = args.steps is not None
     if args.steps is None:
