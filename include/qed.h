@@ -191,6 +191,9 @@ typedef struct qed_stats {
     uint64_t pair_fallback;   /* by rejection, */
     uint64_t pair_fallback_draws;  /* the candidates those rejections used */
     uint64_t pair_envelope_clips;  /* and the candidates above the envelope */
+    uint64_t chi_guard;       /* mixed precision: lepton sub-steps whose chi was recomputed in
+                                 double because its float form would cancel (crossed fields,
+                                 momentum along E x B; chi as defined beside eq. (1)) */
 } qed_stats;
 
 typedef struct qed_ctx qed_ctx;

@@ -662,6 +662,7 @@ qed_status qed_get_stats(qed_ctx *c, qed_stats *out) {
     out->pair_fallback = h.pair_fallback;
     out->pair_fallback_draws = h.pair_fallback_draws;
     out->pair_envelope_clips = h.pair_envelope_clips;
+    out->chi_guard = h.chi_guard;
     double mp;
     memcpy(&mp, &h.max_p_bits, sizeof(mp));
     out->max_p = mp;
@@ -683,6 +684,7 @@ qed_status qed_reset_stats(qed_ctx *c) {
     h.emissions = h.pairs = h.clips = h.capped = 0;
     h.learned_events = h.fallback_events = h.fallback_draws = h.envelope_clips = 0;
     h.pair_learned = h.pair_fallback = h.pair_fallback_draws = h.pair_envelope_clips = 0;
+    h.chi_guard = 0;
     h.max_p_bits = 0;
     HIP_TRY(hipMemcpy(c->st, &h, sizeof(h), hipMemcpyHostToDevice));
     return QED_OK;

@@ -78,11 +78,11 @@ __device__ __forceinline__ double chi_def(double en, double px, double py, doubl
 // definition rearranges to |E|^2 + |u x E|^2 + 2 gamma E.(u x B) + |u x B|^2
 // (Lagrange's identity), which has no cancellation in a pure E field.  Only the
 // cross term can cancel (crossed fields with u along E x B); then the value is
-// recomputed in double from the definition.
+// recomputed in double from the definition, and guard counts it.
 template <int FK = 0>
 __device__ __forceinline__ float chi_lepton_f32(float ux, float uy, float uz, float gamma, float ex,
                                                 float ey, float ez, float bx, float by, float bz,
-                                                float e2) {
+                                                float e2, uint32_t &guard) {
     // FK = 1 (B = 0): |E|^2 + |u x E|^2;  FK = 2 (E = 0): |u x B|^2
     if constexpr (FK == 1) {
         const float cex = uy * ez - uz * ey, cey = uz * ex - ux * ez, cez = ux * ey - uy * ex;
@@ -99,6 +99,7 @@ __device__ __forceinline__ float chi_lepton_f32(float ux, float uy, float uz, fl
     const float t = e2 + (cex * cex + cey * cey + cez * cez) + (cbx * cbx + cby * cby + cbz * cbz);
     const float xt = 2.0f * gamma * (ex * cbx + ey * cby + ez * cbz);
     if (xt < -0.5f * t) {
+        ++guard;
         const double gd = sqrt(1.0 + (double)ux * ux + (double)uy * uy + (double)uz * uz);
         return (float)chi_def(gd, ux, uy, uz, ex, ey, ez, bx, by, bz);
     }

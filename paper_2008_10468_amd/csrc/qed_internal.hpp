@@ -49,6 +49,7 @@ struct DevState {
     alignas(128) u64 pair_fallback;    // from the network / by rejection, the
     alignas(128) u64 pair_fallback_draws;  // candidates used and those above the
     alignas(128) u64 pair_envelope_clips;  // envelope
+    alignas(128) u64 chi_guard;    // float chi sub-steps recomputed in double (cancellation)
     alignas(128) u64 max_p_bits;   // largest acceptance probability (bits of a non-negative double)
     alignas(128) u64 status_bits;  // bit 0: capacity exceeded, bit 1: non-finite input
     u64 required[3];  // largest count requested per species (capacity errors)

@@ -113,6 +113,7 @@ struct Tally {
     u64 substeps = 0;
     uint32_t events = 0, clips = 0, capped = 0, nonfinite = 0, particles = 0;
     uint32_t learned = 0, fallback = 0, fb_draws = 0, env_clips = 0;  // surrogate sampler
+    uint32_t guard = 0;  // float chi recomputed in double (crossed-field cancellation)
     R max_p = 0;
 };
 
@@ -130,7 +131,7 @@ __device__ __forceinline__ T wave_sum_nz(T v) {
 // are also counted separately).
 template <class R, int NT>
 __device__ __forceinline__ void flush_tallies(const Tally<R> *tt, const int *work, DevState *st, int species) {
-    constexpr int kN = 10;
+    constexpr int kN = 11;
     __shared__ u64 red[NT][kBlock / 64][kN + 1];
     const int wv = threadIdx.x / 64;
     __syncthreads();
@@ -141,7 +142,7 @@ __device__ __forceinline__ void flush_tallies(const Tally<R> *tt, const int *wor
                            (u64)wave_sum_nz(t.capped), (u64)wave_sum_nz(t.nonfinite),
                            (u64)wave_sum_nz(t.particles), (u64)wave_sum_nz(t.learned),
                            (u64)wave_sum_nz(t.fallback), (u64)wave_sum_nz(t.fb_draws),
-                           (u64)wave_sum_nz(t.env_clips)};
+                           (u64)wave_sum_nz(t.env_clips), (u64)wave_sum_nz(t.guard)};
         const double mp = __ballot(t.max_p > R(0)) ? wave_max((double)t.max_p) : 0.0;
         if (__lane_id() == 0) {
             for (int k = 0; k < kN; ++k) red[q][wv][k] = v[k];
@@ -161,6 +162,7 @@ __device__ __forceinline__ void flush_tallies(const Tally<R> *tt, const int *wor
             if (tot[7]) atomicAdd(ph ? &st->pair_fallback : &st->fallback_events, tot[7]);
             if (tot[8]) atomicAdd(ph ? &st->pair_fallback_draws : &st->fallback_draws, tot[8]);
             if (tot[9]) atomicAdd(ph ? &st->pair_envelope_clips : &st->envelope_clips, tot[9]);
+            if (tot[10]) atomicAdd(&st->chi_guard, tot[10]);
             if (tot[0]) atomicAdd(&st->substeps[species], tot[0]);
             if (tot[1]) atomicAdd(ph ? &st->pairs : &st->emissions, tot[1]);
             if (tot[2]) atomicAdd(&st->clips, tot[2]);
@@ -265,13 +267,13 @@ struct Draw<double> {
 // chi inside the sub-step loop.
 template <int FK>
 __device__ __forceinline__ float chi_sub(float ux, float uy, float uz, float g, float ex, float ey,
-                                         float ez, float bx, float by, float bz, float e2) {
-    return chi_lepton_f32<FK>(ux, uy, uz, g, ex, ey, ez, bx, by, bz, e2);
+                                         float ez, float bx, float by, float bz, float e2, uint32_t &guard) {
+    return chi_lepton_f32<FK>(ux, uy, uz, g, ex, ey, ez, bx, by, bz, e2, guard);
 }
 template <int FK>
 __device__ __forceinline__ double chi_sub(double ux, double uy, double uz, double g, double ex,
                                           double ey, double ez, double bx, double by, double bz,
-                                          double) {
+                                          double, uint32_t &) {
     return chi_def(g, ux, uy, uz, ex, ey, ez, bx, by, bz);
 }
 
@@ -445,7 +447,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
         dy += uy * vs;
         dz += uz * vs;
         // quantum parameter after the push
-        const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
+        const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
         // candidate x and test value y
         R x, y;
         draw.get(k, idlo, idhi, step, klo, khi, x, y);
@@ -601,7 +603,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
             dx += ux * vs;
             dy += uy * vs;
             dz += uz * vs;
-            const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
+            const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
             const R rw = rate_chi_q(chi, S.rate) * ig;
             tau -= (double)(wk * rw);
             if (tau <= 0.0) {
@@ -624,7 +626,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
             cu2 = ux * ux + uy * uy + uz * uz;
             const R ig = rsqrt_(R(1) + cu2);
             cg = (R(1) + cu2) * ig;
-            cchi = chi_sub<FK>(ux, uy, uz, cg, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
+            cchi = chi_sub<FK>(ux, uy, uz, cg, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
             crw = rate_chi_q(cchi, S.rate) * ig;
         }
         bool use_net = false;
@@ -661,7 +663,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
             const R u2 = ux * ux + uy * uy + uz * uz;
             const R ig = rsqrt_(R(1) + u2);
             const R g = (R(1) + u2) * ig;
-            const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2);
+            const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
             const R rw = rate_chi_q(chi, S.rate) * ig;
             tau = ptau + pover * (double)(rw / crw);
             if (tau <= 0.0) {

@@ -66,7 +66,8 @@ class qed_stats(C.Structure):
                 ("max_p", C.c_double), ("learned_events", C.c_uint64), ("fallback_events", C.c_uint64),
                 ("fallback_draws", C.c_uint64), ("envelope_clips", C.c_uint64),
                 ("pair_learned", C.c_uint64), ("pair_fallback", C.c_uint64),
-                ("pair_fallback_draws", C.c_uint64), ("pair_envelope_clips", C.c_uint64)]
+                ("pair_fallback_draws", C.c_uint64), ("pair_envelope_clips", C.c_uint64),
+                ("chi_guard", C.c_uint64)]
 
 
 class qed_tuning(C.Structure):

@@ -107,7 +107,8 @@ def _mom(d):
 def check_step(g, fields, dt, seed, step, precision, emission=True, pairs=True, rtol=1e-9, min_agree=1.0,
                max_missing=0, rtol_per_substep=0.0, cells=None):
     """One GPU step checked against the oracle.  Momentum tolerance of a particle:
-    rtol + rtol_per_substep * (its number of sub-steps).  cells: the geometry of
+    rtol + rtol_per_substep * (its number of sub-steps); rtol may be an array over the
+    electrons (the positrons then take its largest value).  cells: the geometry of
     sub-steps chosen per cell (set on the GPU context by the caller).  Returns
     (per-species agreement, the GPU state after the step, the oracle's results)."""
     before, after, events, st, rep = gpu_step(g, fields, dt, seed, step)
@@ -115,12 +116,15 @@ def check_step(g, fields, dt, seed, step, precision, emission=True, pairs=True, 
     fh = [as_precision(f.host, precision) for f in g.fields]
     res = oracle_step(before, fh, dt, seed, step, precision, emission=emission, pairs=pairs, cells=cells)
     out = {}
-    child_rtol = rtol
+    child_rtol = float(np.max(rtol))
     if emission:
         for s, name in ((0, "electron"), (1, "positron")):
             n0 = before[s]["id"].size
             ost, och, onsub, onev, otl = res[name]
-            tol = rtol + rtol_per_substep * onsub[:n0].astype(np.float64)
+            r = np.asarray(rtol, np.float64)
+            if r.ndim:   # a per-particle array gives the electrons' tolerances
+                r = r[:n0] if s == 0 else np.float64(r.max())
+            tol = r + rtol_per_substep * onsub[:n0].astype(np.float64)
             out[name] = compare_leptons(after[s], events[s], ost, onev, n0, tol, min_agree)
             # positions of particles with the same events
             same = events[s][:n0] == onev[:n0]
@@ -128,7 +132,7 @@ def check_step(g, fields, dt, seed, step, precision, emission=True, pairs=True, 
                 d = np.abs(after[s][k][:n0] - ost[k][:n0])
                 assert np.all(d[same] <= tol[same] * dt + 1e-12 * np.abs(ost[k][:n0][same]))
             nmax = int(onsub.max()) if onsub.size else 0
-            child_rtol = max(child_rtol, rtol + rtol_per_substep * nmax)
+            child_rtol = max(child_rtol, float(np.max(rtol)) + rtol_per_substep * nmax)
     # photons: survivors by id, plus emitted photons by id
     if emission or pairs:
         gph = after[2]

@@ -177,3 +177,83 @@ def field_subset(fields, idx):
     for k, v in fields.items():
         out[k] = v if v.size == 1 else np.ascontiguousarray(v[idx])
     return out
+
+
+# ---------------------------------------------------------------------------
+# General electromagnetic fields (E and B both non-zero, at general angles), as a
+# field interpolated from a PIC grid gives them.
+# ---------------------------------------------------------------------------
+DT_GENERAL = 3.0e4      # mean emission probability per step about 0.3
+DT_CROSSED = 1.0e7      # crossed fields near |E| = |B|: the rate is small, the step long
+
+
+def _field_modes(seed, m=4):
+    """Random plane-wave-like modes: amplitude vector, wave vector and phase of each
+    component field (E then B)."""
+    rng = np.random.default_rng(seed)
+    modes = []
+    for _ in range(2):
+        a = [np.array(_isotropic(rng, 1))[:, 0] * 10.0 ** rng.uniform(-3.5, -2.5) for _ in range(m)]
+        k = [np.array(_isotropic(rng, 1))[:, 0] * 10.0 ** rng.uniform(-4.5, -3.5) for _ in range(m)]
+        ph = rng.uniform(0.0, 2.0 * math.pi, m)
+        modes.append((a, k, ph))
+    return modes
+
+
+def general_field_at(x, y, z, seed=21):
+    """E(r) = sum_m a_m cos(k_m . r + phi_m), B likewise with its own modes: smooth,
+    non-zero, E and B at general angles.  Positions as float64 arrays; returns the
+    six per-slot field arrays."""
+    out = {}
+    for (a, k, ph), names in zip(_field_modes(seed), (("ex", "ey", "ez"), ("bx", "by", "bz"))):
+        acc = np.zeros((3, np.size(x)))
+        for am, km, pm in zip(a, k, ph):
+            acc += am[:, None] * np.cos(km[0] * x + km[1] * y + km[2] * z + pm)[None, :]
+        for j, nm in enumerate(names):
+            out[nm] = np.ascontiguousarray(acc[j])
+    return out
+
+
+def general(n_e=24576, n_p=8192, n_g=8192, seed=22, field_seed=21):
+    """Electrons, positrons and photons (gamma or photon energy log-uniform in
+    [1e1, 10^3.5], isotropic) in the field of general_field_at at their positions."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    id0 = 0
+    for name, n in (("electrons", n_e), ("positrons", n_p), ("photons", n_g)):
+        s = _species(n, id0, rng)
+        id0 += n
+        energy = 10.0 ** rng.uniform(1.0, 3.5, n)
+        u = energy if name == "photons" else np.sqrt(energy * energy - 1.0)
+        dx, dy, dz = _isotropic(rng, n)
+        s["ux"], s["uy"], s["uz"] = u * dx, u * dy, u * dz
+        out[name] = s
+    out.update({"field_seed": field_seed, "dt": DT_GENERAL, "seed": 1, "p_max": P_MAX})
+    return out
+
+
+def crossed(n=16384, seed=23, e0=1.0e-3):
+    """Electrons in crossed fields just below the light-like limit: per particle a random
+    orthonormal frame (e1, e2, e3), E = e0 e1, B = e0 (1 + eps) e2 with eps log-uniform
+    in [1e-4, 1e-2], and u of magnitude log-uniform in [1e3, 10^4.5] along E x B = e3
+    tilted by an angle log-uniform in [1e-5, 1e-3].  Returns the population and its
+    per-slot fields."""
+    rng = np.random.default_rng(seed)
+    e = _species(n, 0, rng)
+    e1 = np.stack(_isotropic(rng, n))
+    r = np.stack(_isotropic(rng, n))
+    e2 = np.cross(e1.T, r.T).T
+    e2 /= np.linalg.norm(e2, axis=0)
+    e3 = np.cross(e1.T, e2.T).T
+    eps = 10.0 ** rng.uniform(-4.0, -2.0, n)
+    tilt = 10.0 ** rng.uniform(-5.0, -3.0, n)
+    az = rng.uniform(0.0, 2.0 * math.pi, n)
+    umag = 10.0 ** rng.uniform(3.0, 4.5, n)
+    d = e3 * np.cos(tilt) + (e1 * np.cos(az) + e2 * np.sin(az)) * np.sin(tilt)
+    e["ux"], e["uy"], e["uz"] = umag * d[0], umag * d[1], umag * d[2]
+    E = e0 * e1
+    B = e0 * (1.0 + eps) * e2
+    fields = {k: np.ascontiguousarray(v) for k, v in
+              zip(("ex", "ey", "ez", "bx", "by", "bz"), (E[0], E[1], E[2], B[0], B[1], B[2]))}
+    return {"electrons": e, "positrons": _empty(), "photons": _empty(), "fields": fields,
+            "dt": DT_CROSSED, "seed": 1, "p_max": P_MAX}
