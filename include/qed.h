@@ -43,7 +43,8 @@ typedef enum qed_status {
     QED_ERR_CAPACITY = -2,    /* appends exceeded a species' capacity (see qed_report) */
     QED_ERR_NONFINITE = -3,   /* non-finite input; affected particles/values skipped */
     QED_ERR_HIP = -4,         /* a HIP runtime call failed */
-    QED_ERR_STATE = -5        /* call not valid in the context's current state */
+    QED_ERR_STATE = -5,       /* call not valid in the context's current state */
+    QED_ERR_SCRATCH = -6      /* qed_step_static: a capacity above QED_STATIC_MAX_SLOTS */
 } qed_status;
 
 typedef enum qed_dtype { QED_F32 = 0, QED_F64 = 1 } qed_dtype;
@@ -227,6 +228,33 @@ QED_API qed_status qed_step(qed_ctx *ctx, qed_particles *p, const qed_field fiel
  * owns the counter; NULL: QED_ERR_INVALID_ARG.  Otherwise as qed_step. */
 QED_API qed_status qed_step_counted(qed_ctx *ctx, qed_particles *p, const qed_field fields[3], double dt,
                                     uint64_t seed, uint32_t *step);
+
+/* Largest capacity per species that qed_step_static serves (its per-slot scratch,
+ * 53 MiB per GPU, held from the library's first qed_init on that GPU until the
+ * process ends). */
+#define QED_STATIC_MAX_SLOTS (1u << 20)
+
+/* qed_step for callers that cannot allocate device memory or wait on the host
+ * inside the call: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Identical results to qed_step (the same kernels);
+ * differences:
+ *   - the per-slot scratch of the step (photon flags, the dead list and the
+ *     compaction lists; the binned scheduler's sub-step counts and queues; the
+ *     per-slot cell records of qed_substep_cells) lives in one static device
+ *     array per GPU instead of context buffers, so the call never allocates,
+ *     frees or synchronises;
+ *   - every species whose scratch the step uses (photons when pairs run, e- and
+ *     e+ with the binned scheduler, all species with sub-steps per cell) must have
+ *     capacity <= QED_STATIC_MAX_SLOTS, else QED_ERR_SCRATCH and nothing is
+ *     enqueued;
+ *   - the array is shared by every context and stream on one GPU and keeps the
+ *     last call's contents: calls that overlap in time on one GPU race (order
+ *     them on one stream, or with events).
+ * The context (qed_init) and any network or cell geometry (qed_sampler_set,
+ * qed_substep_cells) must be set up beforehand; those calls allocate.  Other
+ * errors as qed_step. */
+QED_API qed_status qed_step_static(qed_ctx *ctx, qed_particles *p, const qed_field fields[3], double dt,
+                                   uint64_t seed, uint32_t step);
 
 /* Wait for the context's stream; fill *rep (may be NULL) and return its status.
  * Clears the sticky device status. */

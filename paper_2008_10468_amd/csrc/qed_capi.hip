@@ -9,6 +9,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -52,6 +53,70 @@ struct qed_graph {
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
+
+// ---------------------------------------------------------------------------
+// Per-slot scratch of qed_step_static: one file-scope device array, resolved to
+// a device address once per GPU (qed_init), never allocated at call time.  The
+// step's kernels read every entry of these lists only after writing it in the
+// same step, so nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kStaticSlots = QED_STATIC_MAX_SLOTS;
+constexpr size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+constexpr size_t kOffAlive = 0;                                            // uint8 per photon slot
+constexpr size_t kOffDead = align256(kOffAlive + kStaticSlots);            // u64 per photon slot
+constexpr size_t kOffHole = align256(kOffDead + 8 * kStaticSlots);
+constexpr size_t kOffMover = align256(kOffHole + 8 * kStaticSlots);
+constexpr size_t kOffNsub = align256(kOffMover + 8 * kStaticSlots);        // 2 x uint32 per lepton slot
+constexpr size_t kOffQueue = align256(kOffNsub + 2 * 4 * kStaticSlots);    // 2 x uint32 per lepton slot
+constexpr size_t kOffCell = align256(kOffQueue + 2 * 4 * kStaticSlots);    // 3 x uint32 per slot
+constexpr size_t kStaticBytes = align256(kOffCell + 3 * 4 * kStaticSlots);
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices];  // device address of scratch on each GPU
+
+// With `dev` current: the device address of this GPU's copy of scratch.
+qed_status resolve_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return QED_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return QED_OK;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return QED_ERR_HIP;
+    g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    return QED_OK;
+}
+
+// Per-slot scratch of one step: the context's buffers or the static array.
+struct SlotScratch {
+    uint8_t *alive;
+    u64 *dead_idx, *hole_idx, *mover_idx;
+    uint32_t *nsub[2], *queue[2];
+    uint32_t *cell_slot[3];
+};
+
+SlotScratch static_scratch(unsigned char *base) {
+    SlotScratch x;
+    x.alive = base + kOffAlive;
+    x.dead_idx = reinterpret_cast<u64 *>(base + kOffDead);
+    x.hole_idx = reinterpret_cast<u64 *>(base + kOffHole);
+    x.mover_idx = reinterpret_cast<u64 *>(base + kOffMover);
+    for (int s = 0; s < 2; ++s) {
+        x.nsub[s] = reinterpret_cast<uint32_t *>(base + kOffNsub) + s * kStaticSlots;
+        x.queue[s] = reinterpret_cast<uint32_t *>(base + kOffQueue) + s * kStaticSlots;
+    }
+    for (int s = 0; s < 3; ++s) x.cell_slot[s] = reinterpret_cast<uint32_t *>(base + kOffCell) + s * kStaticSlots;
+    return x;
+}
+
+}  // namespace
 
 namespace {
 
@@ -264,8 +329,10 @@ void init_params(float *p, uint64_t seed) {
 
 namespace {
 
+// fixed: nullptr to use (and grow) the context's scratch; else the static array's
+// lists, within QED_STATIC_MAX_SLOTS per species (no allocation, no host wait).
 qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], double dt, uint64_t seed,
-                     uint32_t step, uint32_t *step_dev) {
+                     uint32_t step, uint32_t *step_dev, const SlotScratch *fixed = nullptr) {
     if (!c || !p || !fields) return QED_ERR_INVALID_ARG;
     if (!(dt > 0.0) || !isfinite(dt)) return QED_ERR_INVALID_ARG;
     const bool emission = c->cfg.emission != 0, pairs = c->cfg.pairs != 0;
@@ -292,24 +359,46 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     const bool binned = c->cfg.scheduler == QED_SCHED_BINNED && emission;
     if (binned && (sp[0]->capacity > 0xFFFFFFFFull || sp[1]->capacity > 0xFFFFFFFFull))
         return QED_ERR_INVALID_ARG;
+    const bool cells = c->cells.n[0] != nullptr;
+    if (fixed) {
+        // every slot a kernel of this step can touch lies below a species' capacity
+        if (pairs && sp[2]->capacity > kStaticSlots) return QED_ERR_SCRATCH;
+        for (int s = 0; s < 2; ++s)
+            if (binned && sp[s]->capacity > kStaticSlots) return QED_ERR_SCRATCH;
+        for (int s = 0; s < 3; ++s)
+            if (cells && need[s] && sp[s]->capacity > kStaticSlots) return QED_ERR_SCRATCH;
+    }
     HIP_TRY(hipSetDevice(c->cfg.device));
-    if (pairs) {
+    if (pairs && !fixed) {
         qed_status r = ensure_photon_scratch(c, sp[2]->capacity > 0 ? sp[2]->capacity : 1);
         if (r != QED_OK) return r;
     }
-    if (binned) {
+    if (binned && !fixed) {
         for (int s = 0; s < 2; ++s) {
             qed_status r = ensure_lepton_scratch(c, s, sp[s]->capacity > 0 ? sp[s]->capacity : 1);
             if (r != QED_OK) return r;
         }
     }
-    const bool cells = c->cells.n[0] != nullptr;
-    if (cells) {
+    if (cells && !fixed) {
         for (int s = 0; s < 3; ++s) {
             if (!need[s]) continue;
             qed_status r = ensure_cell_slots(c, s, sp[s]->capacity > 0 ? sp[s]->capacity : 1);
             if (r != QED_OK) return r;
         }
+    }
+    SlotScratch x;
+    if (fixed) {
+        x = *fixed;
+    } else {
+        x.alive = c->alive;
+        x.dead_idx = c->dead_idx;
+        x.hole_idx = c->hole_idx;
+        x.mover_idx = c->mover_idx;
+        for (int s = 0; s < 2; ++s) {
+            x.nsub[s] = c->nsub[s];
+            x.queue[s] = c->queue[s];
+        }
+        for (int s = 0; s < 3; ++s) x.cell_slot[s] = c->cell_slot[s];
     }
     qed::StepArgs a;
     memset(&a, 0, sizeof(a));
@@ -333,13 +422,13 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     a.pairs = pairs;
     a.light_max = c->tune.light_max;
     a.chunk = c->tune.chunk;
-    a.alive = c->alive;
-    a.dead_idx = c->dead_idx;
-    a.hole_idx = c->hole_idx;
-    a.mover_idx = c->mover_idx;
+    a.alive = x.alive;
+    a.dead_idx = x.dead_idx;
+    a.hole_idx = x.hole_idx;
+    a.mover_idx = x.mover_idx;
     for (int s = 0; s < 2; ++s) {
-        a.nsub[s] = c->nsub[s];
-        a.queue[s] = c->queue[s];
+        a.nsub[s] = x.nsub[s];
+        a.queue[s] = x.queue[s];
     }
     a.gap_hist = reinterpret_cast<u64 *>(c->gap_hist);
     a.gap_bins = c->gap_bins;
@@ -347,7 +436,7 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     a.model = c->have_model ? c->model : nullptr;
     a.pair_model = c->have_pair_model ? c->pair_model : nullptr;
     a.cells = c->cells;
-    for (int s = 0; s < 3; ++s) a.cells.slot[s] = c->cell_slot[s];
+    for (int s = 0; s < 3; ++s) a.cells.slot[s] = x.cell_slot[s];
     const u64 lep_cap = sp[0]->capacity > sp[1]->capacity ? sp[0]->capacity : sp[1]->capacity;
     const int lepton_blocks = grid_for(lep_cap, c->num_cu * (int)c->tune.lepton_blocks_per_cu);
     const int heavy_blocks = c->num_cu * (int)c->tune.heavy_blocks_per_cu;
@@ -477,6 +566,10 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (cfg->device < 0 || cfg->device >= ndev) return QED_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(cfg->device));
+    {
+        const qed_status r = resolve_scratch(cfg->device);
+        if (r != QED_OK) return r;
+    }
     qed_ctx *c = new (std::nothrow) qed_ctx();
     if (!c) return QED_ERR_HIP;
     c->cfg = *cfg;
@@ -515,6 +608,19 @@ qed_status qed_step_counted(qed_ctx *c, qed_particles *p, const qed_field fields
                             uint32_t *step) {
     if (!step) return QED_ERR_INVALID_ARG;
     return step_impl(c, p, fields, dt, seed, 0, step);
+}
+
+qed_status qed_step_static(qed_ctx *c, qed_particles *p, const qed_field fields[3], double dt, uint64_t seed,
+                           uint32_t step) {
+    if (!c) return QED_ERR_INVALID_ARG;
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (c->cfg.device >= 0 && c->cfg.device < kMaxDevices) base = g_scratch_ptr[c->cfg.device];
+    }
+    if (!base) return QED_ERR_STATE;  // qed_init resolves it for the context's device
+    const SlotScratch x = static_scratch(base);
+    return step_impl(c, p, fields, dt, seed, step, nullptr, &x);
 }
 
 qed_status qed_sync(qed_ctx *c, qed_report *rep) {
@@ -1075,6 +1181,7 @@ const char *qed_status_string(qed_status s) {
         case QED_ERR_NONFINITE: return "non-finite input";
         case QED_ERR_HIP: return "HIP runtime error";
         case QED_ERR_STATE: return "invalid state";
+        case QED_ERR_SCRATCH: return "size beyond the static scratch of qed_step_static";
     }
     return "unknown status";
 }

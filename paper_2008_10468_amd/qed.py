@@ -13,6 +13,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqed.so")
 
 QED_OK, QED_ERR_INVALID_ARG, QED_ERR_CAPACITY, QED_ERR_NONFINITE, QED_ERR_HIP, QED_ERR_STATE = 0, -1, -2, -3, -4, -5
+QED_ERR_SCRATCH = -6
+QED_STATIC_MAX_SLOTS = 1 << 20
 QED_F32, QED_F64 = 0, 1
 QED_PREC_F64, QED_PREC_MIXED = 0, 1
 QED_SCHED_NAIVE, QED_SCHED_BINNED, QED_SCHED_TILED = 0, 1, 2
@@ -96,7 +98,7 @@ EXPORTS = ("qed_config_default", "qed_init", "qed_step", "qed_sync", "qed_synchr
            "qed_get_stats", "qed_reset_stats", "qed_get_tuning", "qed_set_tuning",
            "qed_profile_enable", "qed_profile_read", "qed_graph_begin", "qed_graph_end",
            "qed_graph_launch", "qed_graph_destroy",
-           "qed_step_counted", "qed_pair_rate", "qed_event_gaps", "qed_substep_cells", "qed_gather", "qed_deposit",
+           "qed_step_counted", "qed_step_static", "qed_pair_rate", "qed_event_gaps", "qed_substep_cells", "qed_gather", "qed_deposit",
            "qed_pair_sampler_set", "qed_pair_sampler_infer", "qed_sampler_set", "qed_sampler_infer", "qed_emission_rate", "qed_emission_cdf",
            "qed_train_config_default", "qed_train_sampler", "qed_mlp_gradient",
            "qed_finalize", "qed_status_string")
@@ -118,6 +120,8 @@ def load(path: str = LIB_PATH):
                            C.c_uint64, C.c_uint32]
     L.qed_step_counted.argtypes = [C.c_void_p, C.POINTER(qed_particles), C.POINTER(qed_field), C.c_double,
                                    C.c_uint64, C.c_void_p]
+    L.qed_step_static.argtypes = [C.c_void_p, C.POINTER(qed_particles), C.POINTER(qed_field), C.c_double,
+                                  C.c_uint64, C.c_uint32]
     L.qed_sync.argtypes = [C.c_void_p, C.POINTER(qed_report)]
     L.qed_synchrotron.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_int]
     L.qed_get_stats.argtypes = [C.c_void_p, C.POINTER(qed_stats)]
@@ -191,6 +195,11 @@ def qed_init(cfg):
 def qed_step(ctx, particles, fields, dt, seed, step):
     arr = (qed_field * 3)(*fields)
     return load().qed_step(ctx, C.byref(particles), arr, float(dt), int(seed), int(step))
+
+
+def qed_step_static(ctx, particles, fields, dt, seed, step):
+    arr = (qed_field * 3)(*fields)
+    return load().qed_step_static(ctx, C.byref(particles), arr, float(dt), int(seed), int(step))
 
 
 def qed_step_counted(ctx, particles, fields, dt, seed, step_ptr):
@@ -426,6 +435,10 @@ class SpeciesBuffers:
         for k in ("ux", "uy", "uz", "w"):
             getattr(self, k)[:n].copy_(torch.from_numpy(np.ascontiguousarray(host[k], np.float64)).to(self.real))
         self.id[:n].copy_(torch.from_numpy(np.ascontiguousarray(host["id"]).view(np.int64)))
+        if self.parent is not None:   # uploaded particles have no parent in this run (0) unless given
+            self.parent.zero_()
+            if "parent" in host:
+                self.parent[:n].copy_(torch.from_numpy(np.ascontiguousarray(host["parent"]).view(np.int64)))
         if self.tau is not None:
             self.tau.fill_(-1.0)
             if "tau" in host:
