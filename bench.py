@@ -1,13 +1,18 @@
 #!/usr/bin/env python3
 """Throughput of the QED event generator on one MI355X.
 
-A step is one global QED-PIC step of the whole generator (Algorithm 2 on all
-photons, Algorithm 1 on all electrons and positrons, appends, photon compaction)
-over the default workload: 1,048,576 electrons + 262,144 photons in a uniform E
-field of 1e-3 Schwinger units rotating with period 200 steps, mixed precision,
-buffers growing by appends for all timed steps.  Metric: particle-sub-steps per
-second (sub-steps of the adaptive generator summed over all particles), with
-events per second beside it.  Inputs are resident in HBM before timing starts.
+Default workload (``--workload hotspot``): the uneven batch of 16,777,216 electrons
+(90% in a weak field with one sub-step each, 10% in a Gaussian hot spot of chi up to
+about 100 with up to 1000 sub-steps), per-particle static magnetic fields, emission
+only, mixed precision.  A step is one global step of Algorithm 1 over every
+electron, run four ways on the same population: the plain generator with the naive
+and the binned (persistent, chi-binned) schedulers, and the optical-depth path
+(surrogate) with the binned scheduler, its photon energies by rejection and by the
+learned inverse CDF (the network shipped for gfx950).  ``value`` is the surrogate's
+throughput in the plain generator's unit of work: the particle-sub-steps Algorithm 1
+takes for this population (P_max = 0.01, counted on the device in the plain binned
+run) per second of surrogate step time; events/s and every run's own figures sit
+beside it.  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line.  --gpus above 1 is refused: the path runs on one GPU.
 """
@@ -26,22 +31,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (packed) peak
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FP32)
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 # Algorithmic work per unit, counted from the kernel source (mixed precision).
 # Floating-point operations: FMA = 2, each reciprocal / square root / cube root /
-# exponential = 1.  HBM bytes: the arrays a kernel must touch for one particle.
-FLOPS_PER_LEPTON_SUBSTEP = 170      # Boris push 52, gamma and move 15, chi 40, candidate 14,
-                                    # F and G 37, acceptance 12
+# logarithm / exponential = 1.  Lepton sub-steps by field kind (the kernels run a
+# specialised push and chi for a pure E and a pure B field):
+#   Boris push: general 52, pure E 6, pure B 46; gamma and move 15;
+#   chi: general 40, pure E 16, pure B 15;
+#   plain (Algorithm 1): candidate 14, F and G 37, acceptance 12;
+#   optical depth: rate fit 17, rate times 1/gamma 1, optical-depth update 2.
+FLOPS_PUSH = {"general": 52, "pure_e": 6, "pure_b": 46}
+FLOPS_CHI = {"general": 40, "pure_e": 16, "pure_b": 15}
+FLOPS_MOVE = 15
+FLOPS_PLAIN_TEST = 14 + 37 + 12
+FLOPS_SURR_RATE = 17 + 1 + 2
+FLOPS_MLP_PER_EVENT = 2 * (2 * 64 + 64 * 64 + 64 * 64 + 64)   # matrix cores (bf16), reported apart
 FLOPS_PER_PHOTON_SUBSTEP = 62       # move 6, candidate 6, F and G 37, acceptance 13
 BYTES_PER_LEPTON_STEP = 80          # read u 12 + id 8 + position 24; write u 12 + position 24
+BYTES_FIELD_PER_PARTICLE = 24       # six float field values, per-particle (stride 1) fields only
+BYTES_TAU = 16                      # optical depth read and written (double)
 BYTES_PER_EMISSION = 52             # weight read 4; position 24 + k 12 + weight 4 + id 8 written
 BYTES_PER_PHOTON_READ = 36          # k 12 + position 24
 BYTES_PER_PHOTON_WRITE = 25         # position 24 + flag 1
 FLOPS_PER_PHOTON_MOVE = 6           # three fused multiply-adds per sub-step
 BYTES_PER_BINNED_EXTRA = 8          # sub-step count read 4 + queue entry read 4 (heavy pass)
 BYTES_PER_PAIR = 104                # two lepton records (position 24, u 12, weight 4, id 8) + dead-list entry 8
+
+
+def flops_per_lepton_substep(field_kind, surrogate=False):
+    base = FLOPS_PUSH[field_kind] + FLOPS_MOVE + FLOPS_CHI[field_kind]
+    return base + (FLOPS_SURR_RATE if surrogate else FLOPS_PLAIN_TEST)
+
+
 SCHEDULERS = {"naive": lambda q: q.QED_SCHED_NAIVE, "binned": lambda q: q.QED_SCHED_BINNED,
               "tiled": lambda q: q.QED_SCHED_TILED}
 
@@ -163,51 +186,75 @@ def measured_traffic(kernel, workload):
     return val
 
 
-def roofline(kt, st, K, workload):
-    """Roofline of the kernel with the largest share of the profiled time; `traffic` from
-    that workload's committed counter summary, if there is one."""
+def roofline(kt, st, K, workload, field_kind="general", surrogate=False, field_bytes=0, peaks=None,
+             kernel=None):
+    """Roofline of the kernel with the largest share of the profiled time (or `kernel`):
+    its algorithmic bytes and flops per launch from the device counters and the unit
+    costs above, against 8 TB/s or the FP32 vector peak (and the measured peaks, if
+    given); `traffic` from that workload's committed counter summary, if there is one."""
     cand = {k: v for k, v in kt.items()
             if k in ("k_lepton", "k_tiled", "k_light", "k_heavy", "k_photon")}
-    name = max(cand, key=lambda k: cand[k][1])
+    name = kernel if kernel in cand else max(cand, key=lambda k: cand[k][1])
     nl, tms = cand[name]
     avg_s = tms * 1e-3 / max(nl, 1)
     lep_sub = st.substeps[0] + st.substeps[1]
     lep_part = st.particles[0] + st.particles[1]
+    f_sub = flops_per_lepton_substep(field_kind, surrogate)
+    rec = BYTES_PER_LEPTON_STEP + field_bytes + (BYTES_TAU if surrogate else 0)
+    mfma = 0.0
     if name in ("k_lepton", "k_tiled"):
         sub, part, em = lep_sub, lep_part, st.emissions
-        byts = BYTES_PER_LEPTON_STEP * part + BYTES_PER_EMISSION * em
-        flops = FLOPS_PER_LEPTON_SUBSTEP * sub
+        byts = rec * part + BYTES_PER_EMISSION * em
+        flops = f_sub * sub
+        learned = st.learned_events
     elif name == "k_heavy":
         sub, part = st.heavy_substeps, st.heavy_particles
-        em = st.emissions * sub / max(lep_sub, 1)      # emissions shared in proportion to sub-steps
-        byts = (BYTES_PER_LEPTON_STEP + BYTES_PER_BINNED_EXTRA) * part + BYTES_PER_EMISSION * em
-        flops = FLOPS_PER_LEPTON_SUBSTEP * sub
+        share = sub / max(lep_sub, 1)
+        em = st.emissions * share                      # emissions shared in proportion to sub-steps
+        learned = st.learned_events * share
+        byts = (rec + BYTES_PER_BINNED_EXTRA) * part + BYTES_PER_EMISSION * em
+        flops = f_sub * sub
     elif name == "k_light":
         sub, part = lep_sub - st.heavy_substeps, lep_part - st.heavy_particles
-        em = st.emissions * sub / max(lep_sub, 1)
-        byts = BYTES_PER_LEPTON_STEP * part + 4 * lep_part + BYTES_PER_EMISSION * em
-        flops = FLOPS_PER_LEPTON_SUBSTEP * sub
+        share = sub / max(lep_sub, 1)
+        em = st.emissions * share
+        learned = st.learned_events * share
+        byts = rec * part + 4 * lep_part + BYTES_PER_EMISSION * em
+        flops = f_sub * sub
     else:  # k_photon: every photon is read and written back (position, flag); the ones
         # that can decay also run the sampling loop (from their record kept in LDS);
         # each pair writes two lepton records and a dead-list entry
         part, sub, em = st.particles[2], st.substeps[2], st.pairs
+        learned = 0
         byts = (BYTES_PER_PHOTON_READ + BYTES_PER_PHOTON_WRITE) * part + BYTES_PER_PAIR * em
         flops = FLOPS_PER_PHOTON_MOVE * (sub - st.sampled_substeps) + FLOPS_PER_PHOTON_SUBSTEP * st.sampled_substeps
+    if surrogate:
+        mfma = FLOPS_MLP_PER_EVENT * learned
     byts /= max(nl, 1)
     flops /= max(nl, 1)
+    mfma /= max(nl, 1)
     t_mem = byts / (HBM_PEAK_GBS * 1e9)
     t_alu = flops / (FP32_VECTOR_PEAK_TFLOPS * 1e12)
     if t_mem >= t_alu:
         roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        meas = peaks.get("hbm_copy_GBps") if peaks else None
     else:
         roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
+        meas = peaks.get("fp32_fma_TFLOPs") if peaks else None
     roof["frac"] = roof["achieved"] / roof["peak"]
+    if meas:
+        roof["measured_peak"] = meas
+        roof["frac_of_measured_peak"] = roof["achieved"] / meas
     roof["traffic"] = measured_traffic(name, workload)
     roof["kernel"] = name
     roof["avg_launch_us"] = avg_s * 1e6
     roof["per_launch"] = {"particles": part / max(nl, 1), "substeps": sub / max(nl, 1),
-                          "events": em / max(nl, 1), "algorithmic_bytes": byts, "algorithmic_flops": flops}
+                          "events": em / max(nl, 1), "algorithmic_bytes": byts, "algorithmic_flops": flops,
+                          "flops_per_substep": f_sub}
+    if surrogate:
+        roof["per_launch"]["mfma_flops"] = mfma
+        roof["mfma_tflops"] = mfma / avg_s / 1e12
     return roof
 
 
@@ -292,6 +339,177 @@ def header(args, value, ms, K, W, dtype, config, metric="particle-sub-steps/s"):
             "dtype": dtype, "data": "synthetic", "config": config}
 
 
+def host_cpu():
+    """The host's CPU model and core counts (for the oracle baseline's record)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cores": affinity,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def measure_peaks(torch, stream):
+    """Measured peaks of this GPU (libqed_peaks.so): HBM copy bandwidth over 2 x 4 GiB,
+    and the issue rates of non-packed FP32 and of FP64 fused multiply-adds."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_2008_10468_amd", "libqed_peaks.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2008_10468_amd.build`")
+    L = C.CDLL(path)
+    L.qed_peak_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_int, C.c_void_p, C.POINTER(C.c_float)]
+    L.qed_peak_fma.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_uint64, C.c_void_p, C.POINTER(C.c_float),
+                               C.POINTER(C.c_double)]
+    nbytes = 4 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    ms = C.c_float()
+    assert L.qed_peak_copy(a.data_ptr(), b.data_ptr(), nbytes, 10, C.c_void_p(stream.cuda_stream), C.byref(ms)) == 0
+    del a, b
+    torch.cuda.empty_cache()
+    out = {"hbm_copy_GBps": 2 * nbytes / (ms.value * 1e-3) / 1e9}
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    for dtype, key, iters in ((0, "fp32_fma_TFLOPs", 4000), (1, "fp64_fma_TFLOPs", 4000)):
+        blocks = ncu * 16
+        sink = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+        fl = C.c_double()
+        assert L.qed_peak_fma(dtype, sink.data_ptr(), blocks, iters, C.c_void_p(stream.cuda_stream),
+                              C.byref(ms), C.byref(fl)) == 0
+        out[key] = fl.value / (ms.value * 1e-3) / 1e12
+        del sink
+    out["spec"] = {"hbm_GBps": HBM_PEAK_GBS, "fp32_vector_TFLOPs": FP32_VECTOR_PEAK_TFLOPS,
+                   "fp32_vector_non_packed_TFLOPs": FP32_VECTOR_PEAK_TFLOPS / 2,
+                   "fp64_vector_TFLOPs": FP64_VECTOR_PEAK_TFLOPS}
+    log(f"bench: measured peaks {out}")
+    return out
+
+
+def cpu_baseline_hotspot(workloads, budget_s, n_sample=1 << 16):
+    """The oracle (plain Algorithm 1, FP64, 24-bit uniforms as the mixed path draws
+    them) on a stratified sample of the hot-spot population: 2^16 electrons, hot and
+    cold in the population's proportions (10% / 90%), with their own per-particle
+    fields and float momenta, step after step until the budget is used (at most the
+    workload's 50 steps); particle-sub-steps per second of wall time on the threads
+    the oracle runs (every core this process may use, within OMP_NUM_THREADS)."""
+    import oracle
+    w = workloads.c3()
+    rng = np.random.default_rng(12345)
+    hot = np.flatnonzero(w["hot"])
+    cold = np.flatnonzero(~w["hot"])
+    n_hot = int(round(n_sample * hot.size / (hot.size + cold.size)))
+    sel = np.sort(np.concatenate([rng.choice(hot, n_hot, replace=False),
+                                  rng.choice(cold, n_sample - n_hot, replace=False)]))
+    st = workloads.subset(w["electrons"], sel)
+    for k in ("ux", "uy", "uz", "w"):
+        st[k] = st[k].astype(np.float32).astype(np.float64)
+    fl = {k: v.astype(np.float32).astype(np.float64)
+          for k, v in workloads.field_subset(w["fields"], sel).items()}
+    del w
+    threads = oracle.default_threads()
+    sub = ev = steps = 0
+    t0 = time.perf_counter()
+    while steps < 50 and (steps == 0 or time.perf_counter() - t0 < budget_s):
+        _, _, _, tl = oracle.lepton_step(st, fl, -1.0, workloads.DT_C3, 1, steps, rng_bits=24, threads=threads)
+        sub += tl["substeps"]
+        ev += tl["events"]
+        steps += 1
+    dt = time.perf_counter() - t0
+    out = {"value": sub / dt, "unit": "particle-sub-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"stratified 2^16-electron sample of the hot-spot population ({n_hot} hot, "
+                     f"{n_sample - n_hot} cold), plain Algorithm 1 in FP64 with the same random streams, "
+                     f"{steps} steps, {dt:.1f} s wall, {sub} particle-sub-steps",
+           "events_per_s": ev / dt}
+    out.update(host_cpu())
+    return out
+
+
+def bench_hotspot(args, torch, qed, workloads):
+    """The hot-spot workload (16.8M electrons, 10% hot), four runs on the same population:
+    plain naive, plain binned, surrogate binned with rejection energies, surrogate binned
+    with the shipped network (the `value`)."""
+    K, W = (args.steps if args.steps_given else 20), args.warmup
+    n = int(args.c3_particles)
+    stream = torch.cuda.Stream()
+    peaks = measure_peaks(torch, stream)
+    m = np.load(os.path.join(ROOT, "paper_2008_10468_amd", "models", "sampler_gfx950.npz"))
+    w = workloads.c3(n=n)
+    zero = workloads.uniform_field()
+    cap_ph = int(min(0.65 * n * max(K, W) + (1 << 23), 1 << 31))   # about 0.55 photons per e- per step
+    p_s = args.surrogate_p_max
+    rej, sur = qed.QED_SAMPLER_REJECTION, qed.QED_SAMPLER_SURROGATE
+    runs, rooflines = {}, {}
+    # name, scheduler, sampler, network installed
+    plan = (("plain_naive", qed.QED_SCHED_NAIVE, rej, False), ("plain_binned", qed.QED_SCHED_BINNED, rej, False),
+            ("surrogate_rejection_binned", qed.QED_SCHED_BINNED, sur, False),
+            ("surrogate_binned", qed.QED_SCHED_BINNED, sur, True))
+    for name, sched, sampler, net in plan:
+        if args.skip_naive and name == "plain_naive":
+            continue
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, cap_ph), pairs=False, parent=False,
+                          events=False, scheduler=sched, stream=stream.cuda_stream, sampler=sampler,
+                          surrogate_p_max=p_s)
+        if net:
+            assert qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
+                                       float(m["log10_chi_hi"])) == qed.QED_OK
+        sname = "naive" if sched == qed.QED_SCHED_NAIVE else "binned"
+        tuned = load_tuning(qed, g, f"{'c5' if sampler == sur else 'c3'}/{sname}", args.tuning)
+        g.set_fields(None, per_species=[w["fields"], zero, zero])
+        fl = [f.struct() for f in g.fields]
+        fields = lambda s: (qed.qed_field * 3)(*fl)
+        log(f"bench: hot spot, {name}, {n} e-, steps={K}, warmup={W}, tuning={tuned}")
+        ms, stats, stats_p, kt, graphed = stepped(torch, qed, g, stream, fields, w, w["dt"], w["seed"], K, W,
+                                                  not args.no_graph)
+        surr = sampler == sur
+        runs[name] = {"ms_per_step": ms / K, "substeps_per_step": sum(stats.substeps) / K,
+                      "substeps_per_s": sum(stats.substeps) / (ms * 1e-3),
+                      "events_per_s": stats.emissions / (ms * 1e-3), "emissions_per_step": stats.emissions / K,
+                      "lepton_substep_target": p_s if surr else 0.01, "tuning": tuned,
+                      "learned_events": stats.learned_events, "fallback_events": stats.fallback_events,
+                      "fallback_draws": stats.fallback_draws,
+                      "kernel_us": {k: v[1] * 1e3 / max(v[0], 1) for k, v in kt.items()},
+                      "launch": "one HIP graph of all timed steps" if graphed else "eager"}
+        rooflines[name] = roofline(kt, stats_p, K, "hotspot", field_kind="pure_b", surrogate=surr,
+                                   field_bytes=BYTES_FIELD_PER_PARTICLE, peaks=peaks, kernel="k_heavy")
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    best = runs["surrogate_binned"]
+    plain_sub = runs["plain_binned"]["substeps_per_step"]
+    value = plain_sub / (best["ms_per_step"] * 1e-3)
+    out = header(args, value, best["ms_per_step"] * K, K, W, "f32+bf16", {
+        "workload": f"hot spot: {n} electrons, gamma log-uniform [1e3, 1e4], isotropic; 90% in B = 5e-7 E_S, "
+                    f"10% in a Gaussian hot spot B = 1e-2 exp(-r^2/2) E_S (chi up to ~100, up to 1000 "
+                    f"sub-steps), per-particle static fields, emission only, mixed precision; optical-depth "
+                    f"path with the learned sampler (sub-step target {p_s}), binned scheduler",
+        "value_counts": "the particle-sub-steps Algorithm 1 takes for this population at P_max = 0.01 "
+                        "(device count of the plain binned run) per second of the surrogate's step time",
+        "steps": K, "dt_hbar_over_mc2": w["dt"], "seed": w["seed"], "scheduler": "binned",
+        "tuning": best["tuning"], "launch": best["launch"]})
+    out["events_per_s"] = best["events_per_s"]
+    out["runs"] = runs
+    speed = lambda a, b: runs[b]["ms_per_step"] / runs[a]["ms_per_step"]
+    if "plain_naive" in runs:
+        out["step_speedup_vs_plain_naive"] = speed("surrogate_binned", "plain_naive")
+    out["step_speedup_vs_plain_binned"] = speed("surrogate_binned", "plain_binned")
+    out["network_gain_vs_rejection"] = speed("surrogate_binned", "surrogate_rejection_binned")
+    out["roofline"] = rooflines["surrogate_binned"]
+    out["roofline_plain_binned"] = rooflines["plain_binned"]
+    out["peaks"] = peaks
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_hotspot(workloads, args.cpu_seconds)
+    return out
+
+
 def bench_c2(args, torch, qed, workloads):
     K, W = args.steps, args.warmup
     sched = SCHEDULERS[args.scheduler](qed)
@@ -312,7 +530,7 @@ def bench_c2(args, torch, qed, workloads):
         "scheduler": args.scheduler, "tuning": tuned,
         "launch": "one HIP graph of all timed steps" if graphed else "eager"})
     out["events_per_s"] = (stats.emissions + stats.pairs) / (ms * 1e-3)
-    out["roofline"] = roofline(kt, stats_p, K, "c2")
+    out["roofline"] = roofline(kt, stats_p, K, "c2", field_kind="pure_e")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(workloads, args.cpu_seconds)
     g.close()
@@ -400,7 +618,7 @@ def bench_c3(args, torch, qed, workloads):
         "scheduler": args.scheduler, "tuning": tuned,
         "launch": "one HIP graph of all timed steps" if graphed else "eager"})
     out["events_per_s"] = stats.emissions / (ms * 1e-3)
-    out["roofline"] = roofline(kt, stats_p, K, "c3")
+    out["roofline"] = roofline(kt, stats_p, K, "c3", field_kind="pure_b", field_bytes=BYTES_FIELD_PER_PARTICLE)
     g.close()
     return out
 
@@ -566,7 +784,7 @@ def bench_shower(args, torch, qed, workloads):
         "launch": "one HIP graph of all timed steps" if graphed else "eager"})
     out["particle_steps"] = list(stats.particles)
     out["events"] = {"emissions": stats.emissions, "pairs": stats.pairs}
-    out["roofline"] = roofline(kt, stats_p, K, "shower")
+    out["roofline"] = roofline(kt, stats_p, K, "shower", field_kind="pure_b")
     g.close()
     return out
 
@@ -646,7 +864,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=("c2", "c1", "c3", "c4", "c5", "c2s", "shower", "grid"), default="c2")
+    ap.add_argument("--workload", choices=("hotspot", "c2", "c1", "c3", "c4", "c5", "c2s", "shower", "grid"),
+                    default="hotspot")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--scheduler", choices=("naive", "binned", "tiled"), default="naive")
@@ -658,6 +877,7 @@ def main():
     ap.add_argument("--save-model", default=None, help="c5: write the trained network to this .npz")
     ap.add_argument("--surrogate-p-max", type=float, default=0.1,
                     help="c5: the surrogate's lepton sub-step target")
+    ap.add_argument("--skip-naive", action="store_true", help="hotspot: leave out the plain naive run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-MiB float buffer once (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -674,7 +894,7 @@ def main():
     from paper_2008_10468_amd import qed
 
     torch.cuda.set_device(0)
-    fn = {"c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
+    fn = {"hotspot": bench_hotspot, "c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
           "c2s": bench_c2s, "shower": bench_shower, "grid": bench_grid}[args.workload]
     out = fn(args, torch, qed, workloads)
     if args.copy_probe:

@@ -171,7 +171,7 @@ def synchrotron_parallel(x, threads=None):
     x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
     F = np.empty_like(x)
     G = np.empty_like(x)
-    threads = threads or os.cpu_count() or 1
+    threads = threads or default_threads()
     chunks = np.array_split(np.arange(x.size), threads * 4)
 
     def run(ix):
@@ -293,8 +293,21 @@ def _fields(fields, n):
     return arrs, stride
 
 
+def default_threads():
+    """Host threads the oracle uses by default: the cores this process may run on,
+    capped by OMP_NUM_THREADS when it is set (a shared host's allotment)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.strip().isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
 def _run_chunks(n, fn, threads):
-    threads = max(1, threads or os.cpu_count() or 1)
+    threads = max(1, threads or default_threads())
     nchunk = min(max(1, n // 64), threads * 8) if n else 0
     bounds = np.linspace(0, n, nchunk + 1).astype(np.int64) if nchunk else np.array([0, 0])
     jobs = [(int(bounds[j]), int(bounds[j + 1])) for j in range(len(bounds) - 1)]

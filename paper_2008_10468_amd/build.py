@@ -12,9 +12,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqed.so")
+PEAKS_LIB = os.path.join(HERE, "libqed_peaks.so")
 ARCH = os.environ.get("QED_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["qed_kernels.hip", "qed_train.hip", "qed_grid.hip", "qed_capi.hip"]
+PEAKS_SOURCES = ["qed_peaks.hip"]   # measurement microbenchmarks, a library of their own
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -36,23 +38,28 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    cc = hipcc()
+def _link(cc, sources, lib, verbose):
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = []
-    for src in SOURCES:
+    for src in sources:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
         cmd = [cc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    cc = hipcc()
+    _link(cc, PEAKS_SOURCES, PEAKS_LIB, verbose)
+    return _link(cc, SOURCES, LIB, verbose)
 
 
 if __name__ == "__main__":
