@@ -24,9 +24,9 @@ extern "C" {
 #define QED_PEAKS_API __attribute__((visibility("default")))
 
 /* Copy `bytes` (a multiple of 16, src and dst 16-byte aligned, not overlapping) from
- * src to dst `reps` times with 16-byte vector loads and stores, one grid-stride
- * pass per copy; *ms = mean milliseconds per copy (HIP events on `stream`).  HBM
- * rate: 2 * bytes / (*ms * 1e-3). */
+ * src to dst `reps` times with 16-byte vector loads and stores, one element per
+ * thread over a grid covering the buffer; *ms = mean milliseconds per copy (HIP
+ * events on `stream`).  HBM rate: 2 * bytes / (*ms * 1e-3). */
 QED_PEAKS_API int qed_peak_copy(const void *src, void *dst, uint64_t bytes, int reps, void *stream, float *ms);
 
 /* Fused multiply-adds in registers: `blocks` blocks of 256 threads, each thread

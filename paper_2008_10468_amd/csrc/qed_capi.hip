@@ -227,9 +227,10 @@ qed_status ensure_cell_slots(qed_ctx *c, int s, u64 cap) {
 }
 
 bool tuning_ok(const qed_tuning &t) {
-    return t.lepton_blocks_per_cu >= 1 && t.lepton_blocks_per_cu <= 64 && t.heavy_blocks_per_cu >= 1 &&
-           t.heavy_blocks_per_cu <= 64 && t.photon_blocks_per_cu >= 1 && t.photon_blocks_per_cu <= 64 &&
-           t.light_max >= 1 && t.chunk >= 64 && t.chunk % 64 == 0 && t.chunk <= (1u << 20);
+    return t.lepton_blocks_per_cu >= 1 && t.lepton_blocks_per_cu <= 1024 && t.heavy_blocks_per_cu >= 1 &&
+           t.heavy_blocks_per_cu <= 64 && t.photon_blocks_per_cu >= 1 && t.photon_blocks_per_cu <= 1024 &&
+           t.light_max >= 1 && t.chunk >= 64 && t.chunk % 64 == 0 && t.chunk <= (1u << 20) &&
+           t.resolve_batch >= 1 && t.resolve_batch <= 64 && t.prepass_finish <= 1;
 }
 
 const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_prepass",
@@ -422,6 +423,8 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     a.pairs = pairs;
     a.light_max = c->tune.light_max;
     a.chunk = c->tune.chunk;
+    a.resolve_batch = c->tune.resolve_batch;
+    a.prepass_finish = c->tune.prepass_finish;
     a.alive = x.alive;
     a.dead_idx = x.dead_idx;
     a.hole_idx = x.hole_idx;
@@ -585,6 +588,8 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     c->tune.photon_blocks_per_cu = 8;
     c->tune.light_max = 48;
     c->tune.chunk = 256;
+    c->tune.resolve_batch = 16;
+    c->tune.prepass_finish = 1;
     if (hipMalloc(&c->st, sizeof(qed::DevState)) != hipSuccess ||
         hipMemset(c->st, 0, sizeof(qed::DevState)) != hipSuccess ||
         hipMalloc(&c->model, sizeof(qed::MlpModel)) != hipSuccess ||

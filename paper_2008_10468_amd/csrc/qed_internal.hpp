@@ -97,6 +97,8 @@ struct StepArgs {
     int emission, pairs;   // which algorithms run in this step
     uint32_t light_max;    // binned scheduler: largest N handled by the light pass
     uint32_t chunk;        // binned scheduler: queue entries claimed per wave (multiple of 64)
+    uint32_t resolve_batch;  // surrogate: waiting emissions that trigger a batched resolve (1..64)
+    uint32_t prepass_finish; // binned: the pre-pass finishes particles of one quiet sub-step
     uint8_t *alive;        // photon flags, one per slot: 0 decayed, 1 alive
     u64 *dead_idx;         // slots of the photons that decayed this step
     u64 *hole_idx;         // compaction lists

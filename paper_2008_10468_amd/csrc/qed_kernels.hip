@@ -190,12 +190,16 @@ __device__ __forceinline__ void flush_tally(const Tally<R> &t, DevState *st, int
 }
 
 // Children of one wave staged in LDS and written out with one atomic per flush.
+// A child's id (a Philox block of its parent's id and counter) is formed when the
+// buffer is written out, by all the flushing lanes together, rather than by the
+// few lanes that emit in one sub-step.
 // TB: with birth times (the surrogate path, which runs no cascades, saves the LDS).
 template <class R, bool TB = true>
 struct ChildBuf {
     double x[64], y[64], z[64];
     R px[64], py[64], pz[64], w[64];
-    uint64_t id[64], parent[64];
+    uint64_t parent[64];
+    uint32_t ctr[64];        // the id's counter word (the event's index)
     double tb[TB ? 64 : 1];  // birth time within the step
     uint32_t count;
 };
@@ -203,7 +207,8 @@ struct ChildBuf {
 // Write the staged children to the species' tail.  Called by the active lanes of
 // a wave (any subset); they share the writes.
 template <class R, bool TB>
-__device__ __forceinline__ void flush_children(ChildBuf<R, TB> &cb, const SpeciesDev &dst) {
+__device__ __forceinline__ void flush_children(ChildBuf<R, TB> &cb, const SpeciesDev &dst, uint64_t seed,
+                                               uint32_t step) {
     __syncwarp();
     const uint32_t n = cb.count;
     if (n == 0) return;
@@ -224,7 +229,7 @@ __device__ __forceinline__ void flush_children(ChildBuf<R, TB> &cb, const Specie
             ((R *)dst.uy)[slot] = cb.py[e];
             ((R *)dst.uz)[slot] = cb.pz[e];
             ((R *)dst.w)[slot] = cb.w[e];
-            dst.id[slot] = cb.id[e];
+            dst.id[slot] = child_id(seed, cb.parent[e], step, cb.ctr[e], 0);
             if (dst.parent) dst.parent[slot] = cb.parent[e];
             if constexpr (TB)
                 if (dst.birth) dst.birth[slot] = cb.tb[e];
@@ -382,7 +387,7 @@ __device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesD
                                                uint32_t &nev, double t0, double st, uint32_t step) {
     const uint32_t c = (uint32_t)__popcll(m);
     __syncwarp();
-    if (cb.count + c > 64) flush_children(cb, a.sp[2]);
+    if (cb.count + c > 64) flush_children(cb, a.sp[2], a.seed, step);
     const uint32_t n0 = cb.count;
     if (acc) {
         const uint32_t e = n0 + (uint32_t)__popcll(m & lanemask_lt());
@@ -396,7 +401,7 @@ __device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesD
         cb.py[e] = uy * eph;
         cb.pz[e] = uz * eph;
         cb.w[e] = ((const R *)sp.w)[i];
-        cb.id[e] = child_id(a.seed, pid, step, ctr, 0);
+        cb.ctr[e] = ctr;
         cb.parent[e] = pid;
         if constexpr (TB) cb.tb[e] = t0 + (double)(k + 1) * st;
         // gamma' = (1 - delta) gamma, same direction
@@ -413,6 +418,67 @@ __device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesD
     __syncwarp();
 }
 
+// One sub-step of Algorithm 1 after the push constants are set: Boris push and
+// move, chi after the push, the candidate (x, y) of sub-step k and the acceptance
+// probability of eq. (1), y < 3 x^2 P(x^3) = (c b / x) ((1 - x^3) F(z) + x^6 G(z)),
+// z = x^3 / (b (1 - x^3)).  Shared by the sub-step loop and the pre-pass (which
+// finishes particles of one quiet sub-step), so both round identically.
+template <class R, int FK>
+struct SubStep {
+    R u2, g, x3, omx3, pm, y;
+};
+
+template <class R, int FK>
+__device__ __forceinline__ SubStep<R, FK> substep(const Lepton<R> &p, R hex, R hey, R hez, R hq, R e2, R str, R kcb,
+                                                  uint32_t k, uint32_t idlo, uint32_t idhi, uint32_t step,
+                                                  uint32_t klo, uint32_t khi, Draw<R> &draw, const SynTable<R> &tab,
+                                                  R &ux, R &uy, R &uz, R &dx, R &dy, R &dz, uint32_t &guard) {
+    SubStep<R, FK> o;
+    // push: Boris rotation and move
+    boris<R, FK>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
+    o.u2 = ux * ux + uy * uy + uz * uz;
+    const R ig = rsqrt_(R(1) + o.u2);
+    o.g = (R(1) + o.u2) * ig;
+    const R vs = str * ig;
+    dx += ux * vs;
+    dy += uy * vs;
+    dz += uz * vs;
+    // quantum parameter after the push
+    const R chi = chi_sub<FK>(ux, uy, uz, o.g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, guard);
+    // candidate x and test value y
+    R x;
+    draw.get(k, idlo, idhi, step, klo, khi, x, o.y);
+    const R x2 = x * x;
+    o.x3 = x2 * x;
+    o.omx3 = (R(1) - x) * (R(1) + x + x2);
+    const R b = R(1.5) * chi;
+    const R z = o.x3 * rcp(b * o.omx3);
+    R F, G;
+    syn_eval(z, tab, F, G);
+    o.pm = kcb * chi * ig * rcp(x) * (o.omx3 * F + o.x3 * o.x3 * G);
+    return o;
+}
+
+// Push constants of a lepton (s = 0: q = -1, s = 1: q = +1) over sub-steps of st.
+template <class R>
+struct PushConst {
+    R hq, hex, hey, hez, e2, str, kcb;
+};
+
+template <class R>
+__device__ __forceinline__ PushConst<R> push_const(const Lepton<R> &p, int s, double st) {
+    PushConst<R> c;
+    c.hq = (R)((s == 0 ? -0.5 : 0.5) * st);
+    c.hex = c.hq * p.ex;
+    c.hey = c.hq * p.ey;
+    c.hez = c.hq * p.ez;
+    c.e2 = p.ex * p.ex + p.ey * p.ey + p.ez * p.ez;
+    c.str = (R)st;
+    // c b = kcb chi / gamma, with c = sqrt(3) alpha st / (pi gamma) and b = 3 chi / 2
+    c.kcb = (R)(1.5 * kSqrt3 * kAlpha / kPi * st);
+    return c;
+}
+
 // Algorithm 1's sub-step loop for one electron (s = 0, q = -1) or positron (s = 1,
 // q = +1) with N >= 1 sub-steps.  s is uniform across the wave.  FK: field kind
 // (0 general, 1 pure E, 2 pure B), see boris().
@@ -422,12 +488,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
     const SpeciesDev &sp = a.sp[s];
     const uint64_t pid = sp.id[i];
     const double st = (a.dt - t0) / (double)N;
-    const R hq = (R)((s == 0 ? -0.5 : 0.5) * st);
-    const R hex = hq * p.ex, hey = hq * p.ey, hez = hq * p.ez;
-    const R e2 = p.ex * p.ex + p.ey * p.ey + p.ez * p.ez;
-    const R str = (R)st;
-    // c b = kcb chi / gamma, with c = sqrt(3) alpha st / (pi gamma) and b = 3 chi / 2
-    const R kcb = (R)(1.5 * kSqrt3 * kAlpha / kPi * st);
+    const PushConst<R> c = push_const(p, s, st);
     const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
     const uint32_t klo = (uint32_t)a.seed, khi = (uint32_t)(a.seed >> 32);
     const uint32_t step = step_of(a);
@@ -437,37 +498,16 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
     uint32_t last = 0;  // sub-steps done at this particle's previous event
     Draw<R> draw;
     for (uint32_t k = 0; k < N; ++k) {
-        // push: Boris rotation and move
-        boris<R, FK>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
-        const R u2 = ux * ux + uy * uy + uz * uz;
-        const R ig = rsqrt_(R(1) + u2);
-        const R g = (R(1) + u2) * ig;
-        const R vs = str * ig;
-        dx += ux * vs;
-        dy += uy * vs;
-        dz += uz * vs;
-        // quantum parameter after the push
-        const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
-        // candidate x and test value y
-        R x, y;
-        draw.get(k, idlo, idhi, step, klo, khi, x, y);
-        // acceptance (eq. (1)): y < 3 x^2 P(x^3) = (c b / x) ((1 - x^3) F(z) + x^6 G(z)),
-        //         z = x^3 / (b (1 - x^3))
-        const R x2 = x * x, x3 = x2 * x;
-        const R omx3 = (R(1) - x) * (R(1) + x + x2);
-        const R b = R(1.5) * chi;
-        const R z = x3 * rcp(b * omx3);
-        R F, G;
-        syn_eval(z, tab, F, G);
-        const R pm = kcb * chi * ig * rcp(x) * (omx3 * F + x3 * x3 * G);
-        tl.max_p = fmax(tl.max_p, pm);
-        tl.clips += pm > R(1);
-        const bool acc = y < pm;
+        const SubStep<R, FK> o = substep<R, FK>(p, c.hex, c.hey, c.hez, c.hq, c.e2, c.str, c.kcb, k, idlo, idhi, step,
+                                                klo, khi, draw, tab, ux, uy, uz, dx, dy, dz, tl.guard);
+        tl.max_p = fmax(tl.max_p, o.pm);
+        tl.clips += o.pm > R(1);
+        const bool acc = o.y < o.pm;
         // emission: stage the photon in the wave's LDS buffer, recoil on the parent
         const u64 m = __ballot(acc);
         if (m) {
-            stage_emission<R>(a, sp, i, pid, k, k, acc, m, x3, omx3, g, u2, dx, dy, dz, ux, uy, uz, cb, nev, t0,
-                              st, step);
+            stage_emission<R>(a, sp, i, pid, k, k, acc, m, o.x3, o.omx3, o.g, o.u2, dx, dy, dz, ux, uy, uz, cb, nev,
+                              t0, st, step);
             if (acc && a.gap_hist) {
                 count_gap(a, 0, k + 1 - last);
                 last = k + 1;
@@ -547,16 +587,39 @@ __device__ __forceinline__ float surr_reject(float chi, const SurrLds &S, const 
     return x;
 }
 
-// Emissions are resolved in batches: a lane whose optical depth runs out draws its
-// random numbers and waits (it does not advance) while the other lanes go on;
-// once kResolveBatch lanes wait, or no lane can advance, the wave evaluates the
-// network for all waiting lanes together (rows of matrix-core passes), stages the
-// photons, applies the recoils and releases the lanes.  A lane's own sequence of
-// operations and draws does not depend on when its emission is resolved, so the
-// result is the same for any batching and any scheduler.  N: this lane's
-// sub-steps (0 for a lane without a particle).  All 64 lanes of the wave call it.
-constexpr int kResolveBatch = 16;
+// One sub-step of the optical-depth path: Boris push and move, chi after the
+// push, and the optical depth used up, alpha sub_t chi q(chi) / gamma (float
+// product, double accumulation).  Shared by the sub-step loop and the pre-pass.
+template <int FK>
+__device__ __forceinline__ void substep_surr(const Lepton<float> &p, const PushConst<float> &c, float wk,
+                                             const RateTable &rate, float &ux, float &uy, float &uz, float &dx,
+                                             float &dy, float &dz, double &tau, uint32_t &guard) {
+    using R = float;
+    boris<R, FK>(ux, uy, uz, c.hex, c.hey, c.hez, c.hq, p.bx, p.by, p.bz);
+    const R u2 = ux * ux + uy * uy + uz * uz;
+    const R ig = rsqrt_(R(1) + u2);
+    const R g = (R(1) + u2) * ig;
+    const R vs = c.str * ig;
+    dx += ux * vs;
+    dy += uy * vs;
+    dz += uz * vs;
+    const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, c.e2, guard);
+    const R rw = rate_chi_q(chi, rate) * ig;
+    tau -= (double)(wk * rw);
+}
 
+// Emissions are resolved in batches: a lane whose optical depth runs out only
+// marks the crossing and waits (it does not advance) while the other lanes go on;
+// once a.resolve_batch lanes wait, or no lane can advance, the waiting lanes
+// together draw their random numbers, take their energies (network rows on the
+// matrix cores, or rejection), stage the photons, apply the recoils and go on.
+// Everything a crossing costs beyond the sub-step itself (the Philox blocks, the
+// double logarithm of the next optical depth, the energy, the photon) thus runs
+// with the waiting lanes together instead of stalling the wave at every crossing.
+// A lane's own sequence of operations and draws does not depend on when its
+// emission is resolved, so the result is the same for any batch size and any
+// scheduler.  N: this lane's sub-steps (0 for a lane without a particle).  All
+// 64 lanes of the wave call it.
 template <int FK>
 __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i, uint32_t N,
                                                  const Lepton<float> &p, const SynTable<float> &tab, SurrLds &S,
@@ -566,15 +629,14 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
     const bool has = N > 0;
     const uint64_t pid = has ? sp.id[i] : 0ull;
     const double st = has ? a.dt / (double)N : 0.0;
-    const R hq = (R)((s == 0 ? -0.5 : 0.5) * st);
-    const R hex = hq * p.ex, hey = hq * p.ey, hez = hq * p.ez;
-    const R e2 = p.ex * p.ex + p.ey * p.ey + p.ez * p.ez;
-    const R str = (R)st;
+    const PushConst<R> c = push_const(p, s, st);
+    const R e2 = c.e2;
     // W sub_t = alpha sub_t chi q(chi) / gamma
     const R wk = (R)(kAlpha * st);
     const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
     const uint32_t klo = (uint32_t)a.seed ^ kSurrTagLo, khi = (uint32_t)(a.seed >> 32) ^ kSurrTagHi;
     const uint32_t step = step_of(a);
+    const int batch = (int)a.resolve_batch;
     MlpWave &ws = S.ws[threadIdx.x / 64];
     uint32_t j = 0;
     double tau = has ? sp.tau[i] : 1.0;
@@ -588,41 +650,28 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
     uint32_t k = 0;     // next sub-step of this lane
     bool pend = false;  // an emission waits for its energy
     uint32_t pk = 0;    // its sub-step
-    // A pending lane keeps its momentum at the crossing, so chi, gamma and the rate
-    // there are recomputed when the emission is resolved instead of held.
-    R pu = 0.5f;         // the uniform of the emitted energy
-    double pover = 0.0;  // the optical depth's overshoot (<= 0) in the sub-step that crossed
-    double ptau = 1.0;   // the optical depth drawn for after the emission
+    // A waiting lane keeps its momentum at the crossing, so chi, gamma and the rate
+    // there are recomputed when the emission is resolved instead of held; tau then
+    // holds the overshoot (<= 0) of the sub-step that crossed.
     for (;;) {
         if (k < N && !pend) {
-            boris<R, FK>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
-            const R u2 = ux * ux + uy * uy + uz * uz;
-            const R ig = rsqrt_(R(1) + u2);
-            const R g = (R(1) + u2) * ig;
-            const R vs = str * ig;
-            dx += ux * vs;
-            dy += uy * vs;
-            dz += uz * vs;
-            const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
-            const R rw = rate_chi_q(chi, S.rate) * ig;
-            tau -= (double)(wk * rw);
-            if (tau <= 0.0) {
-                const u32x4 w = philox10(idlo, idhi, step, j++, klo, khi);
-                pend = true;
-                pk = k;
-                pu = u24(w.x);
-                pover = tau;
-                ptau = -log(u53(w.z, w.w));
-            }
+            substep_surr<FK>(p, c, wk, S.rate, ux, uy, uz, dx, dy, dz, tau, tl.guard);
+            pend = tau <= 0.0;
+            pk = k;
             ++k;
         }
         const u64 mp = __ballot(pend);
         const u64 mr = __ballot(k < N && !pend);
         if (mp == 0 && mr == 0) break;
-        if (mp == 0 || (__popcll(mp) < kResolveBatch && mr != 0)) continue;
-        // the pending lanes' state at the crossing
-        R cu2 = 0, cg = 1, cchi = 0, crw = 1;
+        if (mp == 0 || (__popcll(mp) < batch && mr != 0)) continue;
+        // The waiting lanes: the uniform of the energy and the next optical depth,
+        // then their state at the crossing.
+        R pu = 0.5f, cu2 = 0, cg = 1, cchi = 0, crw = 1;
+        double ptau = 1.0;
         if (pend) {
+            const u32x4 w = philox10(idlo, idhi, step, j++, klo, khi);
+            pu = u24(w.x);
+            ptau = -log(u53(w.z, w.w));
             cu2 = ux * ux + uy * uy + uz * uz;
             const R ig = rsqrt_(R(1) + cu2);
             cg = (R(1) + cu2) * ig;
@@ -657,24 +706,17 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
                           0.0, st, step);
         // The part of the sub-step after the crossing (the overshoot, at the rate before
         // the emission) counts against the new optical depth at the rate after the
-        // recoil.  If that crosses it again, the particle emits again before moving on.
-        bool again = false;
+        // recoil.  If that crosses it again, the lane waits for another emission
+        // before moving on.
         if (pend) {
             const R u2 = ux * ux + uy * uy + uz * uz;
             const R ig = rsqrt_(R(1) + u2);
             const R g = (R(1) + u2) * ig;
             const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
             const R rw = rate_chi_q(chi, S.rate) * ig;
-            tau = ptau + pover * (double)(rw / crw);
-            if (tau <= 0.0) {
-                const u32x4 w = philox10(idlo, idhi, step, j++, klo, khi);
-                pu = u24(w.x);
-                pover = tau;
-                ptau = -log(u53(w.z, w.w));
-                again = true;
-            }
+            tau = ptau + tau * (double)(rw / crw);
+            pend = tau <= 0.0;
         }
-        pend = again;
     }
     if (has) {
         ((R *)sp.ux)[i] = ux;
@@ -859,7 +901,8 @@ __device__ __forceinline__ int nbin(uint32_t N, uint32_t light_max) {
 // End-of-kernel flush of all wave buffers of the block with one atomic: every
 // thread of the block must call it.
 template <class R, bool TB>
-__device__ __forceinline__ void flush_children_block(ChildBuf<R, TB> *cbs, const SpeciesDev &dst) {
+__device__ __forceinline__ void flush_children_block(ChildBuf<R, TB> *cbs, const SpeciesDev &dst, uint64_t seed,
+                                                     uint32_t step) {
     __shared__ u64 base_sh;
     __shared__ uint32_t pre[kBlock / 64 + 1];
     __syncthreads();
@@ -888,7 +931,7 @@ __device__ __forceinline__ void flush_children_block(ChildBuf<R, TB> *cbs, const
             ((R *)dst.uy)[slot] = cb.py[k];
             ((R *)dst.uz)[slot] = cb.pz[k];
             ((R *)dst.w)[slot] = cb.w[k];
-            dst.id[slot] = cb.id[k];
+            dst.id[slot] = child_id(seed, cb.parent[k], step, cb.ctr[k], 0);
             if (dst.parent) dst.parent[slot] = cb.parent[k];
             if constexpr (TB)
                 if (dst.birth) dst.birth[slot] = cb.tb[k];
@@ -953,32 +996,143 @@ __global__ __launch_bounds__(kBlock) void k_lepton(StepArgs a) {
         if (has && N == 0 && a.sp[s].events) a.sp[s].events[i] = 0;
         LeptonRunner<R, SURR>::run(a, s, i, N, p, L, cb, t, t0);
     }
-    flush_children_block(L.cb, a.sp[2]);
+    flush_children_block(L.cb, a.sp[2], a.seed, step_of(a));
     flush_tally(t, a.st, s);
 }
 
-template <class R>
+// A particle whose step has a single sub-step (N = 1, main pass) runs it here.  If
+// it ends without an event the particle is finished: it is stored as the sub-step
+// loop would store it (the same shared sub-step code, so bit for bit the same) and
+// true is returned.  If it emits (or its optical depth runs out), nothing is
+// written and false is returned: the light pass then runs the particle in full.
+template <class R, int FK>
+__device__ __forceinline__ bool finish_single_fk(const StepArgs &a, int s, u64 i, const Lepton<R> &p,
+                                                 const SynTable<R> &tab, Tally<R> &tl) {
+    const SpeciesDev &sp = a.sp[s];
+    const uint64_t pid = sp.id[i];
+    const double st = a.dt;
+    const PushConst<R> c = push_const(p, s, st);
+    R ux = p.ux, uy = p.uy, uz = p.uz;
+    R dx = 0, dy = 0, dz = 0;
+    uint32_t guard = 0;
+    Draw<R> draw;
+    const SubStep<R, FK> o = substep<R, FK>(p, c.hex, c.hey, c.hez, c.hq, c.e2, c.str, c.kcb, 0u, (uint32_t)pid,
+                                            (uint32_t)(pid >> 32), step_of(a), (uint32_t)a.seed,
+                                            (uint32_t)(a.seed >> 32), draw, tab, ux, uy, uz, dx, dy, dz, guard);
+    if (o.y < o.pm) return false;
+    tl.max_p = fmax(tl.max_p, o.pm);
+    tl.clips += o.pm > R(1);
+    tl.guard += guard;
+    ((R *)sp.ux)[i] = ux;
+    ((R *)sp.uy)[i] = uy;
+    ((R *)sp.uz)[i] = uz;
+    sp.x[i] += (double)dx;
+    sp.y[i] += (double)dy;
+    sp.z[i] += (double)dz;
+    if (sp.events) sp.events[i] = 0;
+    tl.substeps += 1;
+    return true;
+}
+
+template <int FK>
+__device__ __forceinline__ bool finish_single_surr_fk(const StepArgs &a, int s, u64 i, const Lepton<float> &p,
+                                                      const RateTable &rate, Tally<float> &tl) {
+    const SpeciesDev &sp = a.sp[s];
+    const uint64_t pid = sp.id[i];
+    const double st = a.dt;
+    const PushConst<float> c = push_const(p, s, st);
+    const float wk = (float)(kAlpha * st);
+    double tau = sp.tau[i];
+    if (!(tau > 0.0)) {
+        const u32x4 w = philox10((uint32_t)pid, (uint32_t)(pid >> 32), step_of(a), 0u, (uint32_t)a.seed ^ kSurrTagLo,
+                                 (uint32_t)(a.seed >> 32) ^ kSurrTagHi);
+        tau = -log(u53(w.x, w.y));
+    }
+    float ux = p.ux, uy = p.uy, uz = p.uz;
+    float dx = 0, dy = 0, dz = 0;
+    uint32_t guard = 0;
+    substep_surr<FK>(p, c, wk, rate, ux, uy, uz, dx, dy, dz, tau, guard);
+    if (tau <= 0.0) return false;
+    tl.guard += guard;
+    ((float *)sp.ux)[i] = ux;
+    ((float *)sp.uy)[i] = uy;
+    ((float *)sp.uz)[i] = uz;
+    sp.x[i] += (double)dx;
+    sp.y[i] += (double)dy;
+    sp.z[i] += (double)dz;
+    sp.tau[i] = tau;
+    if (sp.events) sp.events[i] = 0;
+    tl.substeps += 1;
+    return true;
+}
+
+// LDS of the pre-pass: the histogram and the table the single-sub-step particles
+// need (the synchrotron fits, or the total-rate fit on the optical-depth path).
+template <class R, bool SURR>
+struct PrepassLds {
+    uint32_t h[kBins];
+    SynTable<R> tab;
+};
+
+template <>
+struct PrepassLds<float, true> {
+    uint32_t h[kBins];
+    RateTable rate;
+};
+
+template <class R, bool SURR>
+__device__ __forceinline__ bool finish_single(const StepArgs &a, int s, u64 i, const Lepton<R> &p,
+                                              const PrepassLds<R, SURR> &L, Tally<R> &tl) {
+    // the field kind of the push and chi as the loops choose it (every kind gives the
+    // general form's result for its fields)
+    const bool noB = p.bx == R(0) && p.by == R(0) && p.bz == R(0);
+    const bool noE = p.ex == R(0) && p.ey == R(0) && p.ez == R(0);
+    if constexpr (SURR) {
+        if (noB) return finish_single_surr_fk<1>(a, s, i, p, L.rate, tl);
+        if (noE) return finish_single_surr_fk<2>(a, s, i, p, L.rate, tl);
+        return finish_single_surr_fk<0>(a, s, i, p, L.rate, tl);
+    } else {
+        if (noB) return finish_single_fk<R, 1>(a, s, i, p, L.tab, tl);
+        if (noE) return finish_single_fk<R, 2>(a, s, i, p, L.tab, tl);
+        return finish_single_fk<R, 0>(a, s, i, p, L.tab, tl);
+    }
+}
+
+// Pre-pass of the binned scheduler: every lepton's sub-step count N (the bound of
+// Sec. 3.1.1 in double) and the histogram of the bins.  With a.prepass_finish,
+// particles of a single quiet sub-step are finished here (N recorded as 0, like a
+// skipped particle), so the light pass does not read them again.
+template <class R, bool SURR>
 __global__ __launch_bounds__(kBlock) void k_prepass(StepArgs a) {
-    __shared__ uint32_t h[kBins];
+    __shared__ PrepassLds<R, SURR> L;
+    uint32_t *h = L.h;
     const int s = blockIdx.y;
     for (int b = threadIdx.x; b < kBins; b += kBlock) h[b] = 0;
-    __syncthreads();
+    if (a.prepass_finish) {
+        if constexpr (SURR)
+            rate_stage(L.rate);  // ends with a barrier
+        else
+            syn_stage(L.tab);    // ends with a barrier
+    } else {
+        __syncthreads();
+    }
     const u64 n = a.st->n0[s];
     Tally<R> t;
     for (u64 i = (u64)blockIdx.x * kBlock + threadIdx.x; i < n; i += (u64)gridDim.x * kBlock) {
         const Lepton<R> p = load_lepton<R>(a, s, i);
-        const uint32_t N = lepton_nsub(a, s, i, p, t, a.dt);
+        uint32_t N = lepton_nsub(a, s, i, p, t, a.dt);
+        const bool done = N == 1 && a.prepass_finish && finish_single<R, SURR>(a, s, i, p, L, t);
+        if (done) N = 0;
         a.nsub[s][i] = N;
         if (N)
             atomicAdd(&h[nbin(N, a.light_max)], 1u);
-        else if (a.sp[s].events)
+        else if (!done && a.sp[s].events)
             a.sp[s].events[i] = 0;
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kBins; b += kBlock)
         if (h[b]) atomicAdd(&a.st->hist[s][b], h[b]);
-    // only the skipped (non-finite) and capped counts are reported here
-    t.substeps = 0;
+    // finished particles' sub-steps, the skipped (non-finite) and the capped counts
     flush_tally(t, a.st, s);
 }
 
@@ -1089,7 +1243,7 @@ __global__ __launch_bounds__(kBlock) void k_light(StepArgs a) {
         }
         __syncwarp();
     }
-    flush_children_block(L.cb, a.sp[2]);
+    flush_children_block(L.cb, a.sp[2], a.seed, step_of(a));
     flush_tally(t, a.st, s);
 }
 
@@ -1157,7 +1311,7 @@ __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
         }
         __syncwarp();
     }
-    flush_children_block(L.cb, a.sp[2]);
+    flush_children_block(L.cb, a.sp[2], a.seed, step_of(a));
     flush_tally(t, a.st, s);
 }
 
@@ -1190,7 +1344,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_heavy(StepArgs a) {
         if (__lane_id() == 0) nb = nwaves * chunk + atomicAdd(&a.st->queue[s], (u64)chunk);
         base = __shfl(nb, 0);
     }
-    flush_children_block(L.cb, a.sp[2]);
+    flush_children_block(L.cb, a.sp[2], a.seed, step_of(a));
     flush_tally(t, a.st, s, 1);
 }
 
@@ -1792,7 +1946,14 @@ hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
                 }
             hipLaunchKernelGGL((k_lepton<R, false>), g2, blk, 0, s, a);
             break;
-        case K_PREPASS: hipLaunchKernelGGL(k_prepass<R>, g2, blk, 0, s, a); break;
+        case K_PREPASS:
+            if constexpr (std::is_same<R, float>::value)
+                if (a.sampler) {
+                    hipLaunchKernelGGL((k_prepass<float, true>), g2, blk, 0, s, a);
+                    break;
+                }
+            hipLaunchKernelGGL((k_prepass<R, false>), g2, blk, 0, s, a);
+            break;
         case K_SCAN: hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, a); break;
         case K_SCATTER: hipLaunchKernelGGL(k_scatter, g2, blk, 0, s, a); break;
         case K_LIGHT:
