@@ -275,9 +275,9 @@ QED_API qed_status qed_reset_stats(qed_ctx *ctx);
 /* Launch shape of the kernels (the autotuner's search space).  Results never
  * depend on it: random numbers are keyed by particle, not by lane. */
 typedef struct qed_tuning {
-    uint32_t lepton_blocks_per_cu; /* grid of the naive lepton kernel, the light pass and
-                                      the pre-pass, in 256-thread blocks per CU (1..1024;
-                                      the grid never exceeds one thread per particle) */
+    uint32_t lepton_blocks_per_cu; /* grid of the naive lepton kernel and the light pass, in
+                                      256-thread blocks per CU (1..1024; no grid exceeds one
+                                      thread per particle slot) */
     uint32_t heavy_blocks_per_cu;  /* persistent heavy-queue kernel, blocks per CU (1..64) */
     uint32_t photon_blocks_per_cu; /* photon kernel, blocks per CU (1..1024) */
     uint32_t light_max;            /* binned scheduler: particles with at most this many
@@ -288,6 +288,7 @@ typedef struct qed_tuning {
     uint32_t resolve_batch;        /* surrogate sampler: emissions a wave lets wait before it
                                       resolves them together (1..64; results do not depend
                                       on it) */
+    uint32_t prepass_blocks_per_cu; /* binned scheduler: grid of the pre-pass (1..1024) */
     uint32_t prepass_finish;       /* binned scheduler, 0 or 1: the pre-pass itself finishes
                                       particles whose step is a single sub-step without an
                                       event, instead of the light pass reading them again

@@ -6,6 +6,10 @@ depends on the workload: blocks per compute unit of each kernel, the largest N
 handled by the light pass of the binned scheduler, and the number of queue
 entries a wave claims at a time in its persistent heavy pass.
 
+The surrogate path adds the number of emissions a wave lets wait before
+resolving them together, and the binned scheduler whether its pre-pass finishes
+particles of one quiet sub-step.
+
 `tune` measures candidate settings on the real workload and device with
 coordinate descent: starting from the library's defaults, it sweeps one
 parameter at a time over its candidate values, keeps the fastest, and repeats
@@ -29,15 +33,20 @@ import sys
 from . import qed
 
 SPACE = {
-    "lepton_blocks_per_cu": (1, 2, 4, 8, 16, 32),
-    "photon_blocks_per_cu": (1, 2, 4, 8, 16, 32),
-    "heavy_blocks_per_cu": (1, 2, 4, 8, 16),
+    "lepton_blocks_per_cu": (1, 2, 4, 8, 16, 32, 64, 128, 256),
+    "photon_blocks_per_cu": (1, 2, 4, 8, 16, 32, 64, 128),
+    "heavy_blocks_per_cu": (1, 2, 3, 4, 8, 16),
     "light_max": (1, 2, 4, 8, 16, 32, 48, 64, 128, 256),
     "chunk": (64, 128, 256, 512, 1024, 4096),
+    "resolve_batch": (4, 8, 12, 16, 24, 32, 48, 64),
+    "prepass_blocks_per_cu": (4, 8, 16, 32, 64, 128, 256, 512),
+    "prepass_finish": (0, 1),
 }
 NAIVE_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu")
 MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "sampler_gfx950.npz")
-BINNED_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu", "heavy_blocks_per_cu", "light_max", "chunk")
+BINNED_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu", "heavy_blocks_per_cu", "light_max", "chunk",
+               "prepass_blocks_per_cu", "prepass_finish")
+SURROGATE_KEYS = ("resolve_batch",)   # added for workloads on the lepton optical-depth path
 
 
 def _settings(g):
@@ -216,6 +225,8 @@ def main(argv=None):
             stream = torch.cuda.Stream()
             g, w, fields = _workload(wl, torch, workloads, sched, stream, args.steps)
             keys = BINNED_KEYS if sn == "binned" else NAIVE_KEYS
+            if wl in ("c2s", "c5"):
+                keys = keys + SURROGATE_KEYS
             best, ms, ms0, hist = tune(torch, g, stream, w, fields, w["dt"], w["seed"], args.steps, keys,
                                        passes=args.passes, log=lambda *a: print(*a, flush=True))
             table[f"{wl}/{sn}"] = {"tuning": best, "ms_per_step": ms / args.steps,

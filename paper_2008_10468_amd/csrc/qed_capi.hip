@@ -230,7 +230,8 @@ bool tuning_ok(const qed_tuning &t) {
     return t.lepton_blocks_per_cu >= 1 && t.lepton_blocks_per_cu <= 1024 && t.heavy_blocks_per_cu >= 1 &&
            t.heavy_blocks_per_cu <= 64 && t.photon_blocks_per_cu >= 1 && t.photon_blocks_per_cu <= 1024 &&
            t.light_max >= 1 && t.chunk >= 64 && t.chunk % 64 == 0 && t.chunk <= (1u << 20) &&
-           t.resolve_batch >= 1 && t.resolve_batch <= 64 && t.prepass_finish <= 1;
+           t.resolve_batch >= 1 && t.resolve_batch <= 64 && t.prepass_finish <= 1 &&
+           t.prepass_blocks_per_cu >= 1 && t.prepass_blocks_per_cu <= 1024;
 }
 
 const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_prepass",
@@ -458,7 +459,8 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     if (r == hipSuccess && emission && !binned)
         r = launch(c, tiled ? qed::K_TILED : qed::K_LEPTON, a, prec, lepton_blocks);
     if (binned) {
-        if (r == hipSuccess) r = launch(c, qed::K_PREPASS, a, prec, lepton_blocks);
+        if (r == hipSuccess)
+            r = launch(c, qed::K_PREPASS, a, prec, grid_for(lep_cap, c->num_cu * (int)c->tune.prepass_blocks_per_cu));
         if (r == hipSuccess) r = launch(c, qed::K_SCAN, a, prec, 1);
         if (r == hipSuccess) r = launch(c, qed::K_SCATTER, a, prec, lepton_blocks);
         if (r == hipSuccess) r = launch(c, qed::K_LIGHT, a, prec, lepton_blocks);
@@ -590,6 +592,7 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     c->tune.chunk = 256;
     c->tune.resolve_batch = 16;
     c->tune.prepass_finish = 1;
+    c->tune.prepass_blocks_per_cu = 8;
     if (hipMalloc(&c->st, sizeof(qed::DevState)) != hipSuccess ||
         hipMemset(c->st, 0, sizeof(qed::DevState)) != hipSuccess ||
         hipMalloc(&c->model, sizeof(qed::MlpModel)) != hipSuccess ||
