@@ -101,3 +101,67 @@ def test_envelope_is_not_loose(orc):
     chis = 2.0 ** (l0 + 2 + np.arange((nseg - 2) * 8 + 1) / 8.0)
     ratios = [_envelope_kernel_f32(chi, l0, env, shrink=0) / _density_max(orc, chi) for chi in chis]
     assert max(ratios) < 1.35, max(ratios)
+
+
+# ---------------------------------------------------------------------------
+# The emission envelope of the optical-depth path's rejection sampler: on segment j
+# of log2 chi, ((1 - x^3) F(z) + x^6 G(z)) / x <= env_j b^(-1/3) for every x in (0, 1),
+# z = x^3 / (b (1 - x^3)), b = 3 chi / 2 (eq. (1) over c b); a constant above the table.
+# A candidate above the envelope is counted (envelope_clips) rather than lost, but a
+# bound that holds keeps the sampler exact.
+# ---------------------------------------------------------------------------
+RATE_INC = os.path.join(ROOT, "paper_2008_10468_amd", "csrc", "rate_coeffs.inc")
+
+
+def _rate_table():
+    src = open(RATE_INC).read()
+    l0 = int(re.search(r"#define QED_RATE_L0 (-?\d+)", src).group(1))
+    nseg = int(re.search(r"#define QED_RATE_NSEG (\d+)", src).group(1))
+    top = float(re.search(r"#define QED_RATE_ENV_TOP ([-+0-9.eE]+)f", src).group(1))
+    body = re.search(r"qed_rate_env\[\d+\] = \{(.*?)\};", src, re.S).group(1)
+    env = np.array([float(v.rstrip("f")) for v in re.findall(r"[-+0-9.eE]+f", body)], np.float32)
+    assert env.size == nseg
+    return l0, nseg, top, env
+
+
+def _rate_envelope_f32(chi, l0, nseg, top, env, shrink=8):
+    c = np.float32(chi)
+    l = np.log2(np.float64(c))
+    if l >= l0 + nseg:
+        return top * (1.0 - shrink * 2.0 ** -24)
+    segs = {min(max(int(math.floor(l)) - l0, 0), nseg - 1)}
+    if abs(l - round(l)) < 1e-5:
+        segs.add(min(max(int(round(l)) - l0 - 1, 0), nseg - 1))
+        segs.add(min(max(int(round(l)) - l0, 0), nseg - 1))
+    bm13 = np.float32(np.exp2(-(np.float32(l) + np.float32(0.58496250072)) * np.float32(1.0 / 3.0)))
+    return min(float(np.float32(env[j] * bm13)) for j in segs) * (1.0 - shrink * 2.0 ** -24)
+
+
+def _emission_density_max(orc, chi):
+    """max over x in (0, 1) of ((1 - x^3) F(z) + x^6 G(z)) / x, z = x^3 / (b (1 - x^3))."""
+    b = 1.5 * chi
+
+    def dens(x):
+        x3 = x ** 3
+        om = (1.0 - x) * (1.0 + x + x * x)
+        F, G = orc.synchrotron(x3 / (b * om))
+        return (om * F + x3 * x3 * G) / x
+    lx = np.linspace(math.log(1e-12), math.log(1.0 - 1e-9), 600)
+    v = dens(np.exp(lx))
+    k = int(np.argmax(v))
+    lo, hi = lx[max(k - 1, 0)], lx[min(k + 1, lx.size - 1)]
+    r = minimize_scalar(lambda t: -float(dens(np.exp([t]))[0]), bounds=(lo, hi), method="bounded",
+                        options={"xatol": 1e-12})
+    return max(float(v.max()), -float(r.fun))
+
+
+def test_emission_envelope_bounds_eq1(orc):
+    """16 chi per octave over the table [2^-30, 2^16] and four octaves above it."""
+    l0, nseg, top, env = _rate_table()
+    chis = 2.0 ** (l0 + np.arange((nseg + 4) * 16 + 1) / 16.0)
+    worst, where = np.inf, None
+    for chi in chis:
+        r = _rate_envelope_f32(chi, l0, nseg, top, env) / _emission_density_max(orc, chi)
+        if r < worst:
+            worst, where = r, chi
+    assert worst >= 1.0 + 1e-5, (worst, where)
