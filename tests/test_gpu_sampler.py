@@ -84,16 +84,18 @@ def test_mlp_gradient_matches_reference():
     smp = np.stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(0, 2, n),
                     rng.uniform(0.1, 2.0, n)], axis=1).astype(np.float32)
     loss, grad = qed.qed_mlp_gradient(ctx, p, smp)
-    L, g = mlp_ref.gradient(p, smp.astype(np.float64), round_bf16=True)
-    assert abs(loss / L - 1) <= 2e-3, (loss, L)
-    sizes = {"W1": 128, "b1": 64, "W2": 4096, "b2": 64, "W3": 4096, "b3": 64, "W4": 64, "b4": 1}
-    for name, off in mlp_ref.OFF.items():
-        a, r = grad[off:off + sizes[name]], g[off:off + sizes[name]]
-        e = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
-        assert e <= 1e-2, (name, e)
-    # and against the unrounded FP64 network: the bfloat16 layers cost < 3%
+    # against the plain FP64 network (no rounding mirrored): loss and every tensor's
+    # gradient within 1e-2 (the bfloat16 matrix-core layers are the only difference)
     L0, g0 = mlp_ref.gradient(p, smp.astype(np.float64), round_bf16=False)
-    assert np.linalg.norm(grad - g0) / np.linalg.norm(g0) <= 3e-2
+    sizes = {"W1": 128, "b1": 64, "W2": 4096, "b2": 64, "W3": 4096, "b3": 64, "W4": 64, "b4": 1}
+    errs = {}
+    for name, off in mlp_ref.OFF.items():
+        a, r = grad[off:off + sizes[name]], g0[off:off + sizes[name]]
+        errs[name] = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+    print("gradient relative error per tensor against the unrounded network:", errs, "loss", loss / L0 - 1,
+          flush=True)
+    assert abs(loss / L0 - 1) <= 2e-3, (loss, L0)
+    assert max(errs.values()) <= 1e-2, errs
     qed.qed_finalize(ctx)
 
 
