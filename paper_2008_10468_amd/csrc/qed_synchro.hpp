@@ -68,7 +68,23 @@ __device__ __forceinline__ float syn_cbrt(float z) {
     t = t > 0.0f ? fmaf(t, 2.0f / 3.0f, zs * r * (1.0f / 3.0f)) : 0.0f;
     return tiny ? t * 0x1p-30f : t;
 }
-__device__ __forceinline__ double syn_cbrt(double z) { return cbrt(z); }
+// Double z^(1/3) for z >= 0: z = m 2^(3q) with m in [0.5, 4) (from the exponent),
+// then Newton's iteration for y = m^(-1/3), y <- y (4 - m y^3) / 3 (no division;
+// the error squares each time), from the float seed 2^(-log2(m)/3) (about 1e-6):
+// two steps leave about 1e-23, and m^(1/3) = m y^2 rounds to a few ulps.
+// z = 0 gives 0, z = +inf gives +inf.
+__device__ __forceinline__ double syn_cbrt(double z) {
+    if (!(z > 0.0)) return 0.0;
+    if (!(z <= 1.0e300)) return z;
+    int e;
+    const double m0 = frexp(z, &e);            // z = m0 2^e, m0 in [0.5, 1)
+    const int q = (e + 3072) / 3 - 1024;       // floor(e / 3)
+    const double m = ldexp(m0, e - 3 * q);     // in [0.5, 4)
+    double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)m) * (-1.0f / 3.0f));
+    y = y * fma(-m * y, y * y, 4.0) * (1.0 / 3.0);
+    y = y * fma(-m * y, y * y, 4.0) * (1.0 / 3.0);
+    return ldexp(m * y * y, q);
+}
 
 // Float e^{-z} for z >= 0: z = n ln2 + r with ln2 split in a 16-bit high part
 // (n ln2_hi exact) and a low part, |r| <= ln2/2, e^{-r} = 2^(-r log2 e) from the
@@ -81,7 +97,34 @@ __device__ __forceinline__ float syn_expm(float z) {
     r = fmaf(-n, 1.42860682030941723e-6f, r);
     return ldexpf(__builtin_amdgcn_exp2f(-r * 1.44269504088896341f), -(int)n);
 }
-__device__ __forceinline__ double syn_expm(double z) { return exp(-z); }
+// Double e^{-z} for z >= 0: z = k ln2 + r (Cody-Waite: ln2 in a high part with
+// trailing zeros, so k ln2_hi is exact, and a low part), |r| <= ln2/2, e^{-r} by
+// its Taylor series to degree 13 (truncation below 1e-17), scaled by 2^-k.  Arguments
+// above 746 give 0 (below the smallest double).
+__device__ __forceinline__ double syn_expm(double z) {
+    constexpr double kLn2Hi = 6.93147180369123816490e-01;
+    constexpr double kLn2Lo = 1.90821492927058770002e-10;
+    constexpr double kLog2e = 1.44269504088896338700;
+    const double zc = fmin(z, 746.0);
+    const double k = rint(zc * kLog2e);
+    double r = fma(-k, kLn2Hi, zc);
+    r = -fma(-k, kLn2Lo, r);                   // e^{-z} = 2^-k e^{r}, r = -(z - k ln2)
+    double p = 1.0 / 6227020800.0;             // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, -(int)k);
+}
 
 // F, G at z >= 0 (z = +inf gives 0).  Caller guarantees z is not NaN / negative.
 __device__ __forceinline__ void syn_eval(float z, const SynTable<float> &tab, float &F, float &G) {

@@ -56,7 +56,7 @@ def test_lepton_passes(usage):
     assert _one(usage, "k_lepton", "IfLb0E")["occ"] >= 3
     assert _one(usage, "k_heavy", "IfLb0E")["occ"] >= 3
     assert _one(usage, "k_light", "IfLb0E")["occ"] >= 3
-    assert _one(usage, "k_synchrotron", "IfE")["occ"] == 8
+    assert _one(usage, "k_synchrotron", "IfLb1E")["occ"] == 8
 
 
 def test_no_scratch_on_the_plain_paths(usage):
