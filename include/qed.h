@@ -282,7 +282,9 @@ typedef struct qed_tuning {
     uint32_t photon_blocks_per_cu; /* photon kernel, blocks per CU (1..1024) */
     uint32_t light_max;            /* binned scheduler: particles with at most this many
                                       sub-steps run in tiles sorted by sub-step count; the
-                                      rest go through the global heavy queue (>= 1) */
+                                      rest go through the global heavy queue (0: every
+                                      particle the pre-pass did not finish goes through the
+                                      queue, and the tile pass is not launched) */
     uint32_t chunk;                /* binned scheduler: queue entries a wave claims at once
                                       (a multiple of 64, >= 64) */
     uint32_t resolve_batch;        /* surrogate sampler: emissions a wave lets wait before it

@@ -36,7 +36,7 @@ SPACE = {
     "lepton_blocks_per_cu": (1, 2, 4, 8, 16, 32, 64, 128, 256),
     "photon_blocks_per_cu": (1, 2, 4, 8, 16, 32, 64, 128),
     "heavy_blocks_per_cu": (1, 2, 3, 4, 8, 16),
-    "light_max": (1, 2, 4, 8, 16, 32, 48, 64, 128, 256),
+    "light_max": (0, 1, 2, 4, 8, 16, 32, 48, 64, 128, 256),
     "chunk": (64, 128, 256, 512, 1024, 4096),
     "resolve_batch": (4, 8, 12, 16, 24, 32, 48, 64),
     "prepass_blocks_per_cu": (4, 8, 16, 32, 64, 128, 256, 512),

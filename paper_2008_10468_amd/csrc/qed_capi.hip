@@ -229,7 +229,7 @@ qed_status ensure_cell_slots(qed_ctx *c, int s, u64 cap) {
 bool tuning_ok(const qed_tuning &t) {
     return t.lepton_blocks_per_cu >= 1 && t.lepton_blocks_per_cu <= 1024 && t.heavy_blocks_per_cu >= 1 &&
            t.heavy_blocks_per_cu <= 64 && t.photon_blocks_per_cu >= 1 && t.photon_blocks_per_cu <= 1024 &&
-           t.light_max >= 1 && t.chunk >= 64 && t.chunk % 64 == 0 && t.chunk <= (1u << 20) &&
+           t.chunk >= 64 && t.chunk % 64 == 0 && t.chunk <= (1u << 20) &&
            t.resolve_batch >= 1 && t.resolve_batch <= 64 && t.prepass_finish <= 1 &&
            t.prepass_blocks_per_cu >= 1 && t.prepass_blocks_per_cu <= 1024;
 }
@@ -463,7 +463,7 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
             r = launch(c, qed::K_PREPASS, a, prec, grid_for(lep_cap, c->num_cu * (int)c->tune.prepass_blocks_per_cu));
         if (r == hipSuccess) r = launch(c, qed::K_SCAN, a, prec, 1);
         if (r == hipSuccess) r = launch(c, qed::K_SCATTER, a, prec, lepton_blocks);
-        if (r == hipSuccess) r = launch(c, qed::K_LIGHT, a, prec, lepton_blocks);
+        if (r == hipSuccess && a.light_max > 0) r = launch(c, qed::K_LIGHT, a, prec, lepton_blocks);
         if (r == hipSuccess) r = launch(c, qed::K_HEAVY, a, prec, heavy_blocks);
     }
     // cascade passes: the particles of the previous pass, from their birth time

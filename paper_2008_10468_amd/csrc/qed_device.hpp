@@ -108,17 +108,19 @@ __device__ __forceinline__ float chi_lepton_f32(float ux, float uy, float uz, fl
 }
 
 // ---------------------------------------------------------------------------
-// b^p for finite b > 0 in double, relative error below 4e-15 for |p ln b| < 30
-// (the rounding of y = p ln b dominates): ln b from the exponent and the
-// series 2 atanh(s) = ln((1+s)/(1-s)) on the reduced mantissa (|s| < 0.172, terms
-// to s^23), then e^y = 2^k e^r with |r| <= ln(2)/2 and the Taylor series to r^14.
-// (One code path and about 60 double operations, against a few hundred for the
-// general pow, which also handles every special case.)
+// ln b for finite b > 0 in double as hi + lo parts of e ln2 + ln m: b = m 2^e
+// with m in [sqrt(1/2), sqrt(2)) from the exponent, ln m = 2 atanh(s) =
+// 2 (s + s^3/3 + ... + s^23/23), s = (m - 1)/(m + 1), |s| < 0.172 (truncation
+// below 1e-20); ln 2 split so that e ln2_hi is exact.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double pow_pos(double b, double p) {
-    constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 split for exact k ln2
-    constexpr double kLn2Lo = 1.90821492927058770002e-10;
-    constexpr double kLog2e = 1.44269504088896338700;
+constexpr double kLn2Hi = 6.93147180369123816490e-01;
+constexpr double kLn2Lo = 1.90821492927058770002e-10;
+
+struct Ln {
+    double hi, e;  // ln b = hi + e ln2_lo
+};
+
+__device__ __forceinline__ Ln ln_pos(double b) {
     int e;
     double m = frexp(b, &e);  // b = m 2^e, m in [0.5, 1)
     if (m < 0.70710678118654752440) {
@@ -139,10 +141,29 @@ __device__ __forceinline__ double pow_pos(double b, double p) {
     t = fma(t, s2, 1.0 / 5.0);
     t = fma(t, s2, 1.0 / 3.0);
     const double lnm = 2.0 * s + 2.0 * s * s2 * t;
-    // y = p ln b = p (e ln2 + ln m), kept as hi + lo
     const double ed = (double)e;
-    const double yh = p * fma(ed, kLn2Hi, lnm);
-    const double yl = p * ed * kLn2Lo;
+    return {fma(ed, kLn2Hi, lnm), ed};
+}
+
+// -ln u for u in (0, 1] (an exponentially distributed optical depth from a uniform).
+__device__ __forceinline__ double neg_ln(double u) {
+    const Ln l = ln_pos(u);
+    return -(l.hi + l.e * kLn2Lo);
+}
+
+// ---------------------------------------------------------------------------
+// b^p for finite b > 0 in double, relative error below 4e-15 for |p ln b| < 30
+// (the rounding of y = p ln b dominates): ln b as above, then e^y = 2^k e^r with
+// |r| <= ln(2)/2 and the Taylor series to r^14.  (One code path and about 60
+// double operations, against a few hundred for the general pow, which also
+// handles every special case.)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double pow_pos(double b, double p) {
+    constexpr double kLog2e = 1.44269504088896338700;
+    const Ln l = ln_pos(b);
+    // y = p ln b = p (e ln2 + ln m), kept as hi + lo
+    const double yh = p * l.hi;
+    const double yl = p * l.e * kLn2Lo;
     const double y = yh + yl;
     const double k = rint(y * kLog2e);
     double r = fma(-k, kLn2Hi, yh);

@@ -642,7 +642,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
     double tau = has ? sp.tau[i] : 1.0;
     if (has && !(tau > 0.0)) {
         const u32x4 w = philox10(idlo, idhi, step, j++, klo, khi);
-        tau = -log(u53(w.x, w.y));
+        tau = neg_ln(u53(w.x, w.y));
     }
     R ux = p.ux, uy = p.uy, uz = p.uz;
     R dx = 0, dy = 0, dz = 0;
@@ -671,7 +671,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
         if (pend) {
             const u32x4 w = philox10(idlo, idhi, step, j++, klo, khi);
             pu = u24(w.x);
-            ptau = -log(u53(w.z, w.w));
+            ptau = neg_ln(u53(w.z, w.w));
             cu2 = ux * ux + uy * uy + uz * uz;
             const R ig = rsqrt_(R(1) + cu2);
             cg = (R(1) + cu2) * ig;
@@ -1046,7 +1046,7 @@ __device__ __forceinline__ bool finish_single_surr_fk(const StepArgs &a, int s, 
     if (!(tau > 0.0)) {
         const u32x4 w = philox10((uint32_t)pid, (uint32_t)(pid >> 32), step_of(a), 0u, (uint32_t)a.seed ^ kSurrTagLo,
                                  (uint32_t)(a.seed >> 32) ^ kSurrTagHi);
-        tau = -log(u53(w.x, w.y));
+        tau = neg_ln(u53(w.x, w.y));
     }
     float ux = p.ux, uy = p.uy, uz = p.uz;
     float dx = 0, dy = 0, dz = 0;
@@ -1619,7 +1619,7 @@ __global__ __launch_bounds__(kBlock) void k_photon_surr(StepArgs a) {
                 if (fresh) {
                     pid = sp.id[i];
                     const u32x4 w = philox10((uint32_t)pid, (uint32_t)(pid >> 32), step, j++, klo, khi);
-                    tau = -log(u53(w.x, w.y));
+                    tau = neg_ln(u53(w.x, w.y));
                 }
                 // rate per unit time; photons of zero energy do not decay
                 const double W = eps > 0.0 ? kAlpha * (double)chi / eps * (double)pair_t(chi, pt) : 0.0;

@@ -471,35 +471,42 @@ __global__ __launch_bounds__(kBlock) void k_mlp_train(TrainArgs ta) {
             gw4[n] += __shfl_xor(gw4[n], o);
         }
     }
-    float* red = L.red;
-    if (g == 0) {
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            const int u = 16 * n + r;
-            atomicAdd(&red[kOffW1 + 2 * u], gw1[n][0]);
-            atomicAdd(&red[kOffW1 + 2 * u + 1], gw1[n][1]);
-            atomicAdd(&red[kOffB1 + u], gb1[n]);
-            atomicAdd(&red[kOffB2 + u], gb2[n]);
-            atomicAdd(&red[kOffB3 + u], gb3[n]);
-            atomicAdd(&red[kOffW4 + u], gw4[n]);
-        }
-    }
+    // The block's sum: the four waves add their partial sums in a fixed order (one
+    // wave at a time, its lanes writing distinct entries), so the float sums, and
+    // with them a training run, are the same on every run.
+    float *red = L.red;
     gb4 = wave_sum_f(gb4);
     loss = wave_sum_f(loss);
-    if (lane == 0) {
-        atomicAdd(&red[kOffB4], gb4);
-        atomicAdd(&red[kMlpParams], loss);
-    }
+    for (int turn = 0; turn < kBlock / 64; ++turn) {
+        __syncthreads();
+        if ((int)(threadIdx.x / 64) != turn) continue;
+        if (g == 0) {
 #pragma unroll
-    for (int ci = 0; ci < 4; ++ci)
-#pragma unroll
-        for (int cj = 0; cj < 4; ++cj)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int idx = (16 * ci + 4 * g + q) * kHid + 16 * cj + r;
-                atomicAdd(&red[kOffW2 + idx], gw2[ci * 4 + cj][q]);
-                atomicAdd(&red[kOffW3 + idx], gw3[ci * 4 + cj][q]);
+            for (int n = 0; n < 4; ++n) {
+                const int u = 16 * n + r;
+                red[kOffW1 + 2 * u] += gw1[n][0];
+                red[kOffW1 + 2 * u + 1] += gw1[n][1];
+                red[kOffB1 + u] += gb1[n];
+                red[kOffB2 + u] += gb2[n];
+                red[kOffB3 + u] += gb3[n];
+                red[kOffW4 + u] += gw4[n];
             }
+        }
+        if (lane == 0) {
+            red[kOffB4] += gb4;
+            red[kMlpParams] += loss;
+        }
+#pragma unroll
+        for (int ci = 0; ci < 4; ++ci)
+#pragma unroll
+            for (int cj = 0; cj < 4; ++cj)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int idx = (16 * ci + 4 * g + q) * kHid + 16 * cj + r;
+                    red[kOffW2 + idx] += gw2[ci * 4 + cj][q];
+                    red[kOffW3 + idx] += gw3[ci * 4 + cj][q];
+                }
+    }
     __syncthreads();
     float *dst = ta.partials + (u64)blockIdx.x * (kMlpParams + 1);
     for (int i = threadIdx.x; i <= kMlpParams; i += kBlock) dst[i] = red[i];

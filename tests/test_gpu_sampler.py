@@ -111,6 +111,18 @@ def trained():
     return cfg, params, loss, err, fb
 
 
+def test_training_is_deterministic():
+    """Two short training runs give the same parameters bit for bit (fixed-order sums)."""
+    from paper_2008_10468_amd import qed
+    ctx = qed.qed_init(qed.qed_config_default())
+    cfg = qed.qed_train_config_default()
+    cfg.steps = 500
+    a = qed.qed_train_sampler(ctx, cfg)
+    b = qed.qed_train_sampler(ctx, cfg)
+    qed.qed_finalize(ctx)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 def test_training_reduces_loss(trained):
     cfg, params, loss, err, fb = trained
     assert np.all(np.isfinite(loss)) and np.all(np.isfinite(params))

@@ -44,7 +44,9 @@ def _run(w, sched, tuning=None, steps=3, precision=None, fields_fn=None, per_spe
 
 @pytest.mark.parametrize("tuning", [None, {"light_max": 1, "chunk": 64, "heavy_blocks_per_cu": 1},
                                     {"light_max": 6, "chunk": 1024, "lepton_blocks_per_cu": 2,
-                                     "photon_blocks_per_cu": 1}])
+                                     "photon_blocks_per_cu": 1},
+                                    {"light_max": 0, "prepass_finish": 1, "prepass_blocks_per_cu": 1},
+                                    {"light_max": 0, "prepass_finish": 0, "chunk": 128}])
 def test_binned_equals_naive_c2(tuning):
     from paper_2008_10468_amd import qed
     w = workloads.c2(n_e=20000, n_g=5000, seed=3)
@@ -107,8 +109,17 @@ def test_tuning_validation():
     t.chunk = 100      # not a multiple of 64
     assert qed.qed_set_tuning(g.ctx, t) == qed.QED_ERR_INVALID_ARG
     t.chunk = 128
-    t.light_max = 0
+    t.resolve_batch = 0       # 1..64
     assert qed.qed_set_tuning(g.ctx, t) == qed.QED_ERR_INVALID_ARG
+    t.resolve_batch = 16
+    t.prepass_finish = 2      # 0 or 1
+    assert qed.qed_set_tuning(g.ctx, t) == qed.QED_ERR_INVALID_ARG
+    t.prepass_finish = 1
+    t.prepass_blocks_per_cu = 0
+    assert qed.qed_set_tuning(g.ctx, t) == qed.QED_ERR_INVALID_ARG
+    t.prepass_blocks_per_cu = 8
+    t.light_max = 0           # no tile pass: the heavy queue takes every particle
+    assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
     t.light_max = 3
     assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
     g.close()
