@@ -828,12 +828,21 @@ def bench_grid(args, torch, qed, workloads):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / K
 
-    times = {}
+    def sort_min(v):
+        t = qed.qed_get_tuning(g.ctx)
+        t.deposit_sort_min = v
+        assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
+
+    times, wave = {}, {}
+    default_sort = qed.qed_get_tuning(g.ctx).deposit_sort_min
     for order, pop in (("random", e), ("cell", by_cell)):
         g.load_state({"electrons": pop, "positrons": w["positrons"], "photons": w["photons"]})
         torch.cuda.synchronize()
-        times[order] = (timed(lambda: qed.qed_gather(g.ctx, grid, sp, ptrs)),
-                        timed(lambda: qed.qed_deposit(g.ctx, grid, sp, -1.0, *[t.data_ptr() for t in j])))
+        dep = lambda: qed.qed_deposit(g.ctx, grid, sp, -1.0, *[t.data_ptr() for t in j])
+        times[order] = (timed(lambda: qed.qed_gather(g.ctx, grid, sp, ptrs)), timed(dep))
+        sort_min(0xFFFFFFFF)            # the per-wave kernel without the tile sort, for comparison
+        wave[order] = timed(dep)
+        sort_min(default_sort)
         assert g.sync()[0] == qed.QED_OK
     ms_g, ms_d = times["cell"]
     grid_bytes = 6 * 4 * nc ** 3
@@ -842,7 +851,7 @@ def bench_grid(args, torch, qed, workloads):
     bytes_d = n * (24 + 3 * 4 + 4) + 2 * j_bytes     # positions, momenta and weight read, J read and written once
     for order, (tg, td) in times.items():
         log(f"bench: grid {nc}^3, {n} electrons in {order} order: gather {tg * 1e3:.1f} us, "
-            f"deposit {td * 1e3:.1f} us per call")
+            f"deposit {td * 1e3:.1f} us per call (per-wave kernel without the sort {wave[order] * 1e3:.1f} us)")
     out = header(args, n / ((ms_g + ms_d) * 1e-3), (ms_g + ms_d) * K, K, 3, "f32+f64", {
         "workload": f"grid coupling: {n} electrons (C2 population, positions uniform over the box, stored in "
                     f"cell order), periodic Yee grid of {nc}^3 cells, float fields, double currents; one gather "
@@ -853,6 +862,7 @@ def bench_grid(args, torch, qed, workloads):
     out["gather"] = rd(bytes_g, ms_g)
     out["deposit"] = rd(bytes_d, ms_d)
     out["random_order_us"] = {"gather": times["random"][0] * 1e3, "deposit": times["random"][1] * 1e3}
+    out["deposit_without_tile_sort_us"] = {o: v * 1e3 for o, v in wave.items()}
     dom = "gather" if ms_g >= ms_d else "deposit"
     out["roofline"] = dict(out[dom], kernel=f"k_{dom}")
     g.close()

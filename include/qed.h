@@ -295,6 +295,11 @@ typedef struct qed_tuning {
                                       particles whose step is a single sub-step without an
                                       event, instead of the light pass reading them again
                                       (results do not depend on it) */
+    uint32_t deposit_sort_min;     /* qed_deposit sorts the particles by grid tile (4^3 cells)
+                                      and sums dense tiles in LDS when the species' capacity
+                                      is at least this (0: always; 0xffffffff: never, every
+                                      call adds per wave of 64 particles); results agree up to
+                                      the order of the additions */
 } qed_tuning;
 
 /* Read / replace the context's launch shape; INVALID_ARG if a field is out of range. */
@@ -405,7 +410,12 @@ QED_API qed_status qed_gather(qed_ctx *ctx, const qed_grid *grid, const qed_spec
  * vary.  charge: -1 for electrons, +1 for positrons (in units of e; the velocity is in
  * units of c).  The grid's field pointers are not used.  Particles with a non-finite
  * position, momentum or weight deposit nothing.  The species needs n, x, y, z, ux, uy,
- * uz, w. */
+ * uz, w.  From a capacity of qed_tuning.deposit_sort_min slots (and for grids of at most
+ * 2^18 tiles of 4^3 cells) the call sorts the particles by tile, sums each tile's
+ * currents in LDS and adds every grid point once, without atomic adds on the grid, in
+ * scratch the context allocates on first use and keeps (about 70 bytes per slot and
+ * 5 KB per tile); where that scratch cannot be had (while a graph is being recorded,
+ * or out of memory) it adds per wave of particles with atomic adds instead. */
 QED_API qed_status qed_deposit(qed_ctx *ctx, const qed_grid *grid, const qed_species *sp, double charge,
                                double *jx, double *jy, double *jz);
 

@@ -47,6 +47,12 @@ struct qed_ctx {
     uint32_t *cell_slot[3];   // per-slot cell of each species, sized by cell_slot_cap
     u64 cell_slot_cap[3];
     std::vector<void *> retired;  // replaced scratch: recorded graphs may still use it
+    // tile-sorted deposition: per-slot ranks and records (dep_cap slots), tile counts (zero between calls) and offsets (dep_tiles tiles), the
+    // parts' tiles and staged regions (dep_parts parts)
+    uint32_t *dep_pos, *dep_count, *dep_off, *dep_part_off, *dep_part_tile;
+    qed::DepRecord *dep_rec;
+    double *dep_stage;
+    u64 dep_cap, dep_tiles, dep_parts;
 };
 
 struct qed_graph {
@@ -224,6 +230,45 @@ qed_status ensure_cell_slots(qed_ctx *c, int s, u64 cap) {
     HIP_TRY(hipMalloc(&c->cell_slot[s], cap * sizeof(uint32_t)));
     c->cell_slot_cap[s] = cap;
     return QED_OK;
+}
+
+// Scratch of the tile-sorted deposition; false if it cannot be had now (recording a
+// graph, or out of memory: the caller then adds per wave).
+bool ensure_deposit_scratch(qed_ctx *c, u64 cap, u64 tiles) {
+    const u64 parts = qed::dep_max_parts(cap, tiles);
+    if (cap <= c->dep_cap && tiles <= c->dep_tiles && parts <= c->dep_parts) return true;
+    if (c->capturing) return false;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return false;
+    bool ok = true;
+    if (cap > c->dep_cap) {
+        retire(c, c->dep_pos);
+        retire(c, c->dep_rec);
+        c->dep_cap = 0;
+        ok = hipMalloc(&c->dep_pos, cap * sizeof(uint32_t)) == hipSuccess &&
+             hipMalloc(&c->dep_rec, cap * sizeof(qed::DepRecord)) == hipSuccess;
+        if (ok) c->dep_cap = cap;
+    }
+    if (ok && tiles > c->dep_tiles) {
+        retire(c, c->dep_count);
+        retire(c, c->dep_off);
+        retire(c, c->dep_part_off);
+        c->dep_tiles = 0;
+        ok = hipMalloc(&c->dep_count, tiles * sizeof(uint32_t)) == hipSuccess &&
+             hipMalloc(&c->dep_off, (tiles + 1) * sizeof(uint32_t)) == hipSuccess &&
+             hipMalloc(&c->dep_part_off, (tiles + 1) * sizeof(uint32_t)) == hipSuccess &&
+             hipMemset(c->dep_count, 0, tiles * sizeof(uint32_t)) == hipSuccess;   // the scan keeps it zero
+        if (ok) c->dep_tiles = tiles;
+    }
+    if (ok && parts > c->dep_parts) {
+        retire(c, c->dep_part_tile);
+        retire(c, c->dep_stage);
+        c->dep_parts = 0;
+        ok = hipMalloc(&c->dep_part_tile, parts * sizeof(uint32_t)) == hipSuccess &&
+             hipMalloc(&c->dep_stage, parts * qed::kDepStage * sizeof(double)) == hipSuccess;
+        if (ok) c->dep_parts = parts;
+    }
+    if (!ok) (void)hipGetLastError();   // an allocation failure is not kept as the stream's error
+    return ok;
 }
 
 bool tuning_ok(const qed_tuning &t) {
@@ -593,6 +638,7 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     c->tune.resolve_batch = 16;
     c->tune.prepass_finish = 1;
     c->tune.prepass_blocks_per_cu = 8;
+    c->tune.deposit_sort_min = 1u << 14;
     if (hipMalloc(&c->st, sizeof(qed::DevState)) != hipSuccess ||
         hipMemset(c->st, 0, sizeof(qed::DevState)) != hipSuccess ||
         hipMalloc(&c->model, sizeof(qed::MlpModel)) != hipSuccess ||
@@ -727,6 +773,39 @@ qed_status qed_deposit(qed_ctx *c, const qed_grid *grid, const qed_species *sp, 
     a.j[1] = jy;
     a.j[2] = jz;
     const int dtype = c->cfg.precision == QED_PREC_F64 ? 1 : 0;
+    const uint32_t te = qed::kDepTileEdge;
+    const u64 tiles[3] = {(grid->nx + te - 1) / te, (grid->ny + te - 1) / te, (grid->nz + te - 1) / te};
+    const u64 ntiles = tiles[0] * tiles[1] * tiles[2];
+    if (sp->capacity >= c->tune.deposit_sort_min && sp->capacity < (1ull << 32) && ntiles <= qed::kDepMaxTiles &&
+        ensure_deposit_scratch(c, sp->capacity, ntiles)) {
+        qed::DepSortArgs d;
+        d.n = a.n;
+        d.cap = sp->capacity;
+        d.x = a.x;
+        d.y = a.y;
+        d.z = a.z;
+        d.ux = a.ux;
+        d.uy = a.uy;
+        d.uz = a.uz;
+        d.w = a.w;
+        d.charge = charge;
+        for (int k = 0; k < 3; ++k) {
+            d.j[k] = a.j[k];
+            d.tiles[k] = (uint32_t)tiles[k];
+        }
+        d.ntiles = (uint32_t)ntiles;
+        d.max_parts = qed::dep_max_parts(sp->capacity, ntiles);
+        d.count = c->dep_count;
+        d.off = c->dep_off;
+        d.part_off = c->dep_part_off;
+        d.part_tile = c->dep_part_tile;
+        d.pos = c->dep_pos;
+        d.rec = c->dep_rec;
+        d.stage = c->dep_stage;
+        if (qed::launch_deposit_sorted(g, d, dtype, grid_for(sp->capacity, c->num_cu * 8), c->stream) != hipSuccess)
+            return QED_ERR_HIP;
+        return QED_OK;
+    }
     if (qed::launch_deposit(g, a, dtype, grid_for(sp->capacity, c->num_cu * 8), c->stream) != hipSuccess)
         return QED_ERR_HIP;
     return QED_OK;
@@ -1179,6 +1258,13 @@ void qed_finalize(qed_ctx *c) {
     release(c->pair_model);
     release(c->cell_buf);
     for (int s = 0; s < 3; ++s) release(c->cell_slot[s]);
+    release(c->dep_pos);
+    release(c->dep_rec);
+    release(c->dep_count);
+    release(c->dep_off);
+    release(c->dep_part_off);
+    release(c->dep_part_tile);
+    release(c->dep_stage);
     for (void *b : c->retired) (void)hipFree(b);
     delete c;
 }

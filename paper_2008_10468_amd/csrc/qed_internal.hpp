@@ -225,9 +225,45 @@ struct DepositArgs {
     double *j[3];                   // Jx, Jy, Jz on the E lattices
 };
 
+// Scratch and geometry of the tile-sorted deposition.
+constexpr uint32_t kDepTileEdge = 4;            // node cells per tile edge
+constexpr uint32_t kDepPart = 2048;             // particles of one tile summed by one block
+constexpr uint32_t kDepStage = 3 * 6 * 6 * 6;   // doubles staged per part
+constexpr uint32_t kBinLdsTiles = 4096;         // up to this many tiles counted in LDS
+constexpr uint32_t kDepMaxTiles = 1u << 18;     // beyond: the wave-run kernel
+// parts a deposit of cap slots over ntiles tiles can need
+inline u64 dep_max_parts(u64 cap, u64 ntiles) { return ntiles + (cap + kDepPart - 1) / kDepPart; }
+// One particle of the tile-sorted deposition: one cache line.
+struct alignas(64) DepRecord {
+    double ph[3];                   // fractions within the node cell along x, y, z
+    double cur[3];                  // current density components x, y, z
+    uint32_t local;                 // node within its tile (x + 4 y + 16 z)
+    uint32_t pad[3];
+};
+static_assert(sizeof(DepRecord) == 64, "one record per cache line");
+
+struct DepSortArgs {
+    const u64 *n;
+    u64 cap;                        // slots
+    const double *x, *y, *z;
+    const void *ux, *uy, *uz, *w;
+    double charge;
+    double *j[3];
+    uint32_t tiles[3], ntiles;      // tiles per axis, their product
+    u64 max_parts;                  // dep_max_parts(cap, ntiles): blocks of k_dep_accum
+    uint32_t *count;                // ntiles, zero on entry and on exit
+    uint32_t *off;                  // ntiles + 1: first record of each tile, total
+    uint32_t *part_off;             // ntiles + 1: first part of each tile, total
+    uint32_t *part_tile;            // max_parts: tile of each part
+    uint32_t *pos;                  // per slot: rank in its tile (~0u: off the grid)
+    DepRecord *rec;                 // cap records in tile order
+    double *stage;                  // kDepStage per part: the part's summed region
+};
+
 // dtype: 0 = float, 1 = double (the context's momentum and field type).
 hipError_t launch_gather(const GridDev &g, const GatherArgs &a, int dtype, int blocks, hipStream_t s);
 hipError_t launch_deposit(const GridDev &g, const DepositArgs &a, int dtype, int blocks, hipStream_t s);
+hipError_t launch_deposit_sorted(const GridDev &g, const DepSortArgs &a, int dtype, int blocks, hipStream_t s);
 
 // Enqueue the elementwise synchrotron kernel (dtype: 0 = float, 1 = double).
 hipError_t launch_synchrotron(const void *x, void *F, void *G, u64 n, int dtype, DevState *st,

@@ -65,24 +65,98 @@ def test_gather_matches_oracle(prec_name):
     gen.close()
 
 
-@pytest.mark.parametrize("prec_name", ["F64", "MIXED"])
-def test_deposit_matches_oracle(prec_name):
-    from paper_2008_10468_amd import qed
-    prec = getattr(qed, "QED_PREC_" + prec_name)
-    rng = np.random.default_rng(2)
-    gen = qed.Generator(precision=prec, capacity=(60000, 16, 16))
-    g, s, _ = _grid(qed, gen.real, rng, nx=11, ny=7, nz=5)
-    p = _particles(g, rng, 60000)
-    gen.sp[0].upload(p)
+SORT = {"sorted": 0, "wave": 0xFFFFFFFF}   # qed_tuning.deposit_sort_min: always / never
+
+
+def _deposit_mode(qed, gen, mode):
+    t = qed.qed_get_tuning(gen.ctx)
+    t.deposit_sort_min = SORT[mode]
+    assert qed.qed_set_tuning(gen.ctx, t) == qed.QED_OK
+
+
+def _deposit_check(qed, gen, g, s, charge=-1.0):
+    """qed_deposit of species 0 against the oracle on the stored values (1e-10 of the
+    largest current)."""
     q = gen.sp[0].download()                                     # momenta and weights as stored
     ncell = g["nx"] * g["ny"] * g["nz"]
     j = [torch.zeros(ncell, dtype=torch.float64, device="cuda") for _ in range(3)]
-    assert qed.qed_deposit(gen.ctx, s, gen.sp[0].struct(), -1.0, *[t.data_ptr() for t in j]) == qed.QED_OK
+    assert qed.qed_deposit(gen.ctx, s, gen.sp[0].struct(), charge, *[t.data_ptr() for t in j]) == qed.QED_OK
     torch.cuda.synchronize()
-    ref = og.deposit(g, q["x"], q["y"], q["z"], q["ux"], q["uy"], q["uz"], q["w"], -1.0)
+    ref = og.deposit(g, q["x"], q["y"], q["z"], q["ux"], q["uy"], q["uz"], q["w"], charge)
     for t, r in zip(j, ref):
         got = t.cpu().numpy()
-        assert np.abs(got - r).max() <= 1e-10 * np.abs(r).max()
+        assert np.abs(got - r).max() <= 1e-10 * max(np.abs(r).max(), 1e-300)
+    return j
+
+
+@pytest.mark.parametrize("mode", ["sorted", "wave"])
+@pytest.mark.parametrize("prec_name", ["F64", "MIXED"])
+def test_deposit_matches_oracle(prec_name, mode):
+    from paper_2008_10468_amd import qed
+    prec = getattr(qed, "QED_PREC_" + prec_name)
+    rng = np.random.default_rng(2)
+    gen = qed.Generator(precision=prec, capacity=(70000, 16, 16))   # slots past the count ignored
+    _deposit_mode(qed, gen, mode)
+    g, s, _ = _grid(qed, gen.real, rng, nx=11, ny=7, nz=5)
+    gen.sp[0].upload(_particles(g, rng, 60000))
+    _deposit_check(qed, gen, g, s)
+    gen.close()
+
+
+def _clustered(g, rng, n, frac, lo, hi):
+    """Particles uniform over the box, a fraction of them inside the cell box [lo, hi)."""
+    p = _particles(g, rng, n)
+    k = int(n * frac)
+    d = {"x": "dx", "y": "dy", "z": "dz"}
+    for a, (l, h) in zip("xyz", zip(lo, hi)):
+        p[a][:k] = g[a + "0"] + rng.uniform(l, h, k) * g[d[a]]
+    perm = rng.permutation(n)
+    return {key: v[perm] for key, v in p.items()}
+
+
+@pytest.mark.parametrize("case", ["sparse", "many_tiles", "clustered", "tiny_grid", "cell_order", "one", "empty"])
+def test_deposit_sorted_cases(case):
+    """The tile-sorted deposition on each of its branches: tiles summed in LDS (dense),
+    particles added directly (tiles of fewer than 256), both within one chunk
+    (clustered), tiles counted with global atomics (more than 4096 tiles), grids of
+    fewer cells than a tile along an axis, particles in cell order (all lanes of a wave
+    on the same LDS points), a single particle and none."""
+    from paper_2008_10468_amd import qed
+    rng = np.random.default_rng(31)
+    shape, n = {"sparse": ((64, 32, 16), 20000), "many_tiles": ((84, 80, 52), 100000),
+                "clustered": ((32, 24, 20), 60000), "tiny_grid": ((1, 2, 3), 30000),
+                "cell_order": ((16, 12, 8), 50000), "one": ((9, 9, 9), 1), "empty": ((9, 9, 9), 0)}[case]
+    gen = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(max(n, 64) + 100, 16, 16))
+    _deposit_mode(qed, gen, "sorted")
+    g, s, _ = _grid(qed, gen.real, rng, nx=shape[0], ny=shape[1], nz=shape[2])
+    if case == "clustered":
+        p = _clustered(g, rng, n, 0.5, (4.0, 8.0, 0.0), (12.0, 12.0, 4.0))   # two tiles
+    else:
+        p = _particles(g, rng, n)
+    if case == "cell_order":
+        cell = ((np.floor((p["z"] - g["z0"]) / g["dz"]) % g["nz"]) * g["ny"] +
+                (np.floor((p["y"] - g["y0"]) / g["dy"]) % g["ny"])) * g["nx"] + \
+            (np.floor((p["x"] - g["x0"]) / g["dx"]) % g["nx"])
+        order = np.argsort(cell, kind="stable")
+        p = {k: v[order] for k, v in p.items()}
+    gen.sp[0].upload(p)
+    j = _deposit_check(qed, gen, g, s, charge=1.0)
+    if n == 0:
+        assert all(float(t.abs().max()) == 0.0 for t in j)
+    gen.close()
+
+
+def test_deposit_sorted_changing_grids():
+    """One context, grids of 12, 5460 and again 12 tiles (the scratch grows; the tile
+    counts start from zero on every call) and a species that shrinks between calls."""
+    from paper_2008_10468_amd import qed
+    rng = np.random.default_rng(32)
+    gen = qed.Generator(precision=qed.QED_PREC_F64, capacity=(80000, 16, 16))
+    _deposit_mode(qed, gen, "sorted")
+    for (nx, ny, nz), n in (((11, 7, 5), 80000), ((84, 80, 52), 50000), ((11, 7, 5), 30000)):
+        g, s, _ = _grid(qed, gen.real, rng, nx=nx, ny=ny, nz=nz)
+        gen.sp[0].upload(_particles(g, rng, n))
+        _deposit_check(qed, gen, g, s)
     gen.close()
 
 
@@ -152,12 +226,14 @@ def test_grid_rejects_bad_arguments():
     gen.close()
 
 
-def test_non_finite_positions():
+@pytest.mark.parametrize("mode", ["sorted", "wave"])
+def test_non_finite_positions(mode):
     """A particle whose position is not finite gets NaN fields and deposits nothing;
     the others are unaffected (against the oracle on the finite particles)."""
     from paper_2008_10468_amd import qed
     rng = np.random.default_rng(6)
     gen = qed.Generator(precision=qed.QED_PREC_F64, capacity=(4096, 16, 16))
+    _deposit_mode(qed, gen, mode)
     g, s, _ = _grid(qed, gen.real, rng, nx=9, ny=6, nz=5)
     p = _particles(g, rng, 4000)
     bad = np.zeros(4000, bool)
