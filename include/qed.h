@@ -295,6 +295,9 @@ typedef struct qed_tuning {
                                       particles whose step is a single sub-step without an
                                       event, instead of the light pass reading them again
                                       (results do not depend on it) */
+    uint32_t scatter_blocks_per_cu; /* binned scheduler: grid of the pass that places the heavy
+                                      particles into their bins (1..1024; each block reserves
+                                      its share of every bin it holds with one atomic add) */
     uint32_t deposit_sort_min;     /* qed_deposit sorts the particles by grid tile (4^3 cells)
                                       and sums dense tiles in LDS when the species' capacity
                                       is at least this (0: always; 0xffffffff: never, every

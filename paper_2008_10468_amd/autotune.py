@@ -41,11 +41,12 @@ SPACE = {
     "resolve_batch": (4, 8, 12, 16, 24, 32, 48, 64),
     "prepass_blocks_per_cu": (4, 8, 16, 32, 64, 128, 256, 512),
     "prepass_finish": (0, 1),
+    "scatter_blocks_per_cu": (1, 2, 4, 8, 16),
 }
 NAIVE_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu")
 MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "sampler_gfx950.npz")
 BINNED_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu", "heavy_blocks_per_cu", "light_max", "chunk",
-               "prepass_blocks_per_cu", "prepass_finish")
+               "prepass_blocks_per_cu", "prepass_finish", "scatter_blocks_per_cu")
 SURROGATE_KEYS = ("resolve_batch",)   # added for workloads on the lepton optical-depth path
 
 

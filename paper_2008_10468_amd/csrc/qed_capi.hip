@@ -276,7 +276,8 @@ bool tuning_ok(const qed_tuning &t) {
            t.heavy_blocks_per_cu <= 64 && t.photon_blocks_per_cu >= 1 && t.photon_blocks_per_cu <= 1024 &&
            t.chunk >= 64 && t.chunk % 64 == 0 && t.chunk <= (1u << 20) &&
            t.resolve_batch >= 1 && t.resolve_batch <= 64 && t.prepass_finish <= 1 &&
-           t.prepass_blocks_per_cu >= 1 && t.prepass_blocks_per_cu <= 1024;
+           t.prepass_blocks_per_cu >= 1 && t.prepass_blocks_per_cu <= 1024 && t.scatter_blocks_per_cu >= 1 &&
+           t.scatter_blocks_per_cu <= 1024;
 }
 
 const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_prepass",
@@ -507,7 +508,8 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
         if (r == hipSuccess)
             r = launch(c, qed::K_PREPASS, a, prec, grid_for(lep_cap, c->num_cu * (int)c->tune.prepass_blocks_per_cu));
         if (r == hipSuccess) r = launch(c, qed::K_SCAN, a, prec, 1);
-        if (r == hipSuccess) r = launch(c, qed::K_SCATTER, a, prec, lepton_blocks);
+        if (r == hipSuccess)
+            r = launch(c, qed::K_SCATTER, a, prec, grid_for(lep_cap, c->num_cu * (int)c->tune.scatter_blocks_per_cu));
         if (r == hipSuccess && a.light_max > 0) r = launch(c, qed::K_LIGHT, a, prec, lepton_blocks);
         if (r == hipSuccess) r = launch(c, qed::K_HEAVY, a, prec, heavy_blocks);
     }
@@ -638,6 +640,7 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     c->tune.resolve_batch = 16;
     c->tune.prepass_finish = 1;
     c->tune.prepass_blocks_per_cu = 8;
+    c->tune.scatter_blocks_per_cu = 2;
     c->tune.deposit_sort_min = 1u << 14;
     if (hipMalloc(&c->st, sizeof(qed::DevState)) != hipSuccess ||
         hipMemset(c->st, 0, sizeof(qed::DevState)) != hipSuccess ||

@@ -241,7 +241,13 @@ __device__ __forceinline__ double rsqrt_(double v) { return 1.0 / sqrt(v); }
 // FK selects a specialisation that gives the same result as the general form for
 // the field it is used with: 0 general, 1 pure electric field (B = 0: the rotation
 // is the identity and u <- (u + hE) + hE), 2 pure magnetic field (E = 0: the
-// half kicks vanish exactly).
+// half kicks vanish exactly; see also Rot below).
+template <class R>
+__device__ __forceinline__ R inv_gamma(R ux, R uy, R uz, R &u2) {
+    u2 = ux * ux + uy * uy + uz * uz;
+    return rsqrt_(R(1) + u2);
+}
+
 template <class R, int FK = 0>
 __device__ __forceinline__ void boris(R &ux, R &uy, R &uz, R hex, R hey, R hez, R hq, R bx, R by,
                                       R bz) {
@@ -269,6 +275,45 @@ __device__ __forceinline__ void boris(R &ux, R &uy, R &uz, R hex, R hey, R hez, 
         uy = my + (pz * sx - px * sz) + hey;
         uz = mz + (px * sy - py * sx) + hez;
     }
+}
+
+// Pure magnetic field: the Boris rotation is exact, so |u|, hence gamma, the
+// rotation vectors t = hq B / gamma and s = 2 t / (1 + t^2) and the move per
+// sub-step u st / gamma keep their values from one sub-step to the next.  They are
+// set from u where gamma changes: at the start and after each emission's recoil.
+template <class R>
+struct Rot {
+    R ig, g, tx, ty, tz, sx, sy, sz, vs;
+};
+
+template <class R>
+__device__ __forceinline__ Rot<R> rot_of(R ux, R uy, R uz, R hq, R bx, R by, R bz, R str) {
+    Rot<R> r;
+    R u2;
+    r.ig = inv_gamma(ux, uy, uz, u2);
+    r.g = (R(1) + u2) * r.ig;
+    const R f = hq * r.ig;
+    r.tx = f * bx;
+    r.ty = f * by;
+    r.tz = f * bz;
+    const R s = R(2) * rcp(R(1) + r.tx * r.tx + r.ty * r.ty + r.tz * r.tz);
+    r.sx = s * r.tx;
+    r.sy = s * r.ty;
+    r.sz = s * r.tz;
+    r.vs = str * r.ig;
+    return r;
+}
+
+// The rotation of a Boris step in a pure magnetic field with the vectors of r.
+template <class R>
+__device__ __forceinline__ void rotate(R &ux, R &uy, R &uz, const Rot<R> &r) {
+    const R px = ux + (uy * r.tz - uz * r.ty);
+    const R py = uy + (uz * r.tx - ux * r.tz);
+    const R pz = uz + (ux * r.ty - uy * r.tx);
+    const R mx = ux, my = uy, mz = uz;
+    ux = mx + (py * r.sz - pz * r.sy);
+    uy = my + (pz * r.sx - px * r.sz);
+    uz = mz + (px * r.sy - py * r.sx);
 }
 
 }  // namespace qed

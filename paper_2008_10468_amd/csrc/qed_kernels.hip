@@ -16,7 +16,7 @@
 //   density eq. (1), recoil, photons appended), scheduled one of three ways:
 //     naive:   k_lepton, one lane per particle in buffer order;
 //     binned:  k_prepass computes each particle's sub-step count N and a histogram
-//              over quarter-octave bins of N; k_scan and k_scatter build a work
+//              over 1/16-octave bins of N; k_scan and k_scatter build a work
 //              queue of the heavy particles (N > light_max) sorted by bin, heaviest
 //              first; k_light runs the light particles in tiles sorted by N; k_heavy
 //              is a persistent kernel whose waves claim chunks of the queue, so the
@@ -432,14 +432,24 @@ template <class R, int FK>
 __device__ __forceinline__ SubStep<R, FK> substep(const Lepton<R> &p, R hex, R hey, R hez, R hq, R e2, R str, R kcb,
                                                   uint32_t k, uint32_t idlo, uint32_t idhi, uint32_t step,
                                                   uint32_t klo, uint32_t khi, Draw<R> &draw, const SynTable<R> &tab,
-                                                  R &ux, R &uy, R &uz, R &dx, R &dy, R &dz, uint32_t &guard) {
+                                                  R &ux, R &uy, R &uz, R &dx, R &dy, R &dz, const Rot<R> &rs,
+                                                  uint32_t &guard) {
     SubStep<R, FK> o;
-    // push: Boris rotation and move
-    boris<R, FK>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
-    o.u2 = ux * ux + uy * uy + uz * uz;
-    const R ig = rsqrt_(R(1) + o.u2);
-    o.g = (R(1) + o.u2) * ig;
-    const R vs = str * ig;
+    // push: Boris rotation and move (pure magnetic field: with the held rotation;
+    // o.u2 is then not set, an emission takes |u|^2 itself)
+    R ig, vs;
+    if constexpr (FK == 2) {
+        rotate(ux, uy, uz, rs);
+        ig = rs.ig;
+        o.g = rs.g;
+        o.u2 = R(0);
+        vs = rs.vs;
+    } else {
+        boris<R, FK>(ux, uy, uz, hex, hey, hez, hq, p.bx, p.by, p.bz);
+        ig = inv_gamma(ux, uy, uz, o.u2);
+        o.g = (R(1) + o.u2) * ig;
+        vs = str * ig;
+    }
     dx += ux * vs;
     dy += uy * vs;
     dz += uz * vs;
@@ -496,18 +506,23 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
     R dx = 0, dy = 0, dz = 0;
     uint32_t nev = 0;
     uint32_t last = 0;  // sub-steps done at this particle's previous event
+    Rot<R> rs{};
+    if constexpr (FK == 2) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);
     Draw<R> draw;
     for (uint32_t k = 0; k < N; ++k) {
         const SubStep<R, FK> o = substep<R, FK>(p, c.hex, c.hey, c.hez, c.hq, c.e2, c.str, c.kcb, k, idlo, idhi, step,
-                                                klo, khi, draw, tab, ux, uy, uz, dx, dy, dz, tl.guard);
+                                                klo, khi, draw, tab, ux, uy, uz, dx, dy, dz, rs, tl.guard);
         tl.max_p = fmax(tl.max_p, o.pm);
         tl.clips += o.pm > R(1);
         const bool acc = o.y < o.pm;
         // emission: stage the photon in the wave's LDS buffer, recoil on the parent
         const u64 m = __ballot(acc);
         if (m) {
-            stage_emission<R>(a, sp, i, pid, k, k, acc, m, o.x3, o.omx3, o.g, o.u2, dx, dy, dz, ux, uy, uz, cb, nev,
+            const R u2 = FK == 2 ? ux * ux + uy * uy + uz * uz : o.u2;
+            stage_emission<R>(a, sp, i, pid, k, k, acc, m, o.x3, o.omx3, o.g, u2, dx, dy, dz, ux, uy, uz, cb, nev,
                               t0, st, step);
+            if constexpr (FK == 2)
+                if (acc) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);   // after the recoil
             if (acc && a.gap_hist) {
                 count_gap(a, 0, k + 1 - last);
                 last = k + 1;
@@ -593,13 +608,22 @@ __device__ __forceinline__ float surr_reject(float chi, const SurrLds &S, const 
 template <int FK>
 __device__ __forceinline__ void substep_surr(const Lepton<float> &p, const PushConst<float> &c, float wk,
                                              const RateTable &rate, float &ux, float &uy, float &uz, float &dx,
-                                             float &dy, float &dz, double &tau, uint32_t &guard) {
+                                             float &dy, float &dz, const Rot<float> &rs, double &tau,
+                                             uint32_t &guard) {
     using R = float;
-    boris<R, FK>(ux, uy, uz, c.hex, c.hey, c.hez, c.hq, p.bx, p.by, p.bz);
-    const R u2 = ux * ux + uy * uy + uz * uz;
-    const R ig = rsqrt_(R(1) + u2);
-    const R g = (R(1) + u2) * ig;
-    const R vs = c.str * ig;
+    R ig, g, vs;
+    if constexpr (FK == 2) {
+        rotate(ux, uy, uz, rs);
+        ig = rs.ig;
+        g = rs.g;
+        vs = rs.vs;
+    } else {
+        boris<R, FK>(ux, uy, uz, c.hex, c.hey, c.hez, c.hq, p.bx, p.by, p.bz);
+        R u2;
+        ig = inv_gamma(ux, uy, uz, u2);
+        g = (R(1) + u2) * ig;
+        vs = c.str * ig;
+    }
     dx += ux * vs;
     dy += uy * vs;
     dz += uz * vs;
@@ -646,6 +670,8 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
     }
     R ux = p.ux, uy = p.uy, uz = p.uz;
     R dx = 0, dy = 0, dz = 0;
+    Rot<R> rs{};
+    if constexpr (FK == 2) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);
     uint32_t nev = 0;
     uint32_t k = 0;     // next sub-step of this lane
     bool pend = false;  // an emission waits for its energy
@@ -655,7 +681,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
     // holds the overshoot (<= 0) of the sub-step that crossed.
     for (;;) {
         if (k < N && !pend) {
-            substep_surr<FK>(p, c, wk, S.rate, ux, uy, uz, dx, dy, dz, tau, tl.guard);
+            substep_surr<FK>(p, c, wk, S.rate, ux, uy, uz, dx, dy, dz, rs, tau, tl.guard);
             pend = tau <= 0.0;
             pk = k;
             ++k;
@@ -709,8 +735,9 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
         // recoil.  If that crosses it again, the lane waits for another emission
         // before moving on.
         if (pend) {
-            const R u2 = ux * ux + uy * uy + uz * uz;
-            const R ig = rsqrt_(R(1) + u2);
+            if constexpr (FK == 2) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);   // after the recoil
+            R u2;
+            const R ig = inv_gamma(ux, uy, uz, u2);
             const R g = (R(1) + u2) * ig;
             const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
             const R rw = rate_chi_q(chi, S.rate) * ig;
@@ -891,7 +918,7 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
 // Bin of a sub-step count (see kBins).
 __device__ __forceinline__ int nbin(uint32_t N, uint32_t light_max) {
     if (N <= light_max) return 0;
-    const int b = 1 + (int)floorf(4.0f * __log2f((float)N));
+    const int b = 1 + (int)floorf((float)kBinsPerOctave * __log2f((float)N));
     return b < kBins - 1 ? b : kBins - 1;
 }
 
@@ -1014,11 +1041,13 @@ __device__ __forceinline__ bool finish_single_fk(const StepArgs &a, int s, u64 i
     const PushConst<R> c = push_const(p, s, st);
     R ux = p.ux, uy = p.uy, uz = p.uz;
     R dx = 0, dy = 0, dz = 0;
+    Rot<R> rs{};
+    if constexpr (FK == 2) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);
     uint32_t guard = 0;
     Draw<R> draw;
     const SubStep<R, FK> o = substep<R, FK>(p, c.hex, c.hey, c.hez, c.hq, c.e2, c.str, c.kcb, 0u, (uint32_t)pid,
                                             (uint32_t)(pid >> 32), step_of(a), (uint32_t)a.seed,
-                                            (uint32_t)(a.seed >> 32), draw, tab, ux, uy, uz, dx, dy, dz, guard);
+                                            (uint32_t)(a.seed >> 32), draw, tab, ux, uy, uz, dx, dy, dz, rs, guard);
     if (o.y < o.pm) return false;
     tl.max_p = fmax(tl.max_p, o.pm);
     tl.clips += o.pm > R(1);
@@ -1050,8 +1079,10 @@ __device__ __forceinline__ bool finish_single_surr_fk(const StepArgs &a, int s, 
     }
     float ux = p.ux, uy = p.uy, uz = p.uz;
     float dx = 0, dy = 0, dz = 0;
+    Rot<float> rs{};
+    if constexpr (FK == 2) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);
     uint32_t guard = 0;
-    substep_surr<FK>(p, c, wk, rate, ux, uy, uz, dx, dy, dz, tau, guard);
+    substep_surr<FK>(p, c, wk, rate, ux, uy, uz, dx, dy, dz, rs, tau, guard);
     if (tau <= 0.0) return false;
     tl.guard += guard;
     ((float *)sp.ux)[i] = ux;
@@ -1136,17 +1167,33 @@ __global__ __launch_bounds__(kBlock) void k_prepass(StepArgs a) {
     flush_tally(t, a.st, s);
 }
 
-// One block: heavy bins laid out heaviest first.
-__global__ void k_scan(StepArgs a) {
-    if (threadIdx.x < 2) {
-        const int s = threadIdx.x;
-        uint32_t off = 0;
-        for (int b = kBins - 1; b >= 1; --b) {
-            a.st->offset[s][b] = off;
-            a.st->cursor[s][b] = 0;
-            off += a.st->hist[s][b];
-        }
-        a.st->heavy[s] = off;
+// One block of kBins threads per species (y): heavy bins laid out heaviest first
+// (offset of bin b: the counts of the bins above it).
+__global__ __launch_bounds__(kBins) void k_scan(StepArgs a) {
+    __shared__ uint32_t wsum[kBins / 64];
+    const int s = blockIdx.y;
+    const int b = kBins - 1 - (int)threadIdx.x;   // thread 0 takes the heaviest bin
+    const uint32_t lane = __lane_id(), wv = threadIdx.x / 64;
+    const uint32_t v = b >= 1 ? a.st->hist[s][b] : 0u;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o);
+        if ((int)lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (uint32_t w = 0; w < kBins / 64; ++w) {
+        before += w < wv ? wsum[w] : 0u;
+        total += wsum[w];
+    }
+    if (b >= 1) {
+        a.st->offset[s][b] = before + incl - v;
+        a.st->cursor[s][b] = 0;
+    }
+    if (threadIdx.x == 0) {
+        a.st->heavy[s] = total;
         a.st->queue[s] = 0;
     }
 }
@@ -1164,10 +1211,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepArgs a) {
     const u64 hi = lo + per < n ? lo + per : n;
     for (int b = threadIdx.x; b < kBins; b += kBlock) cnt[b] = 0;
     __syncthreads();
-    for (u64 i = lo + threadIdx.x; i < hi; i += kBlock) {
-        const uint32_t N = a.nsub[s][i];
-        const int bin = N ? nbin(N, a.light_max) : 0;
-        if (bin) atomicAdd(&cnt[bin], 1u);
+    // kScatterBatch counts loaded before their bins are counted, so that the loads
+    // of one thread overlap
+    constexpr int kScatterBatch = 8;
+    for (u64 i0 = lo + threadIdx.x; i0 < hi; i0 += (u64)kBlock * kScatterBatch) {
+        uint32_t N[kScatterBatch];
+#pragma unroll
+        for (int k = 0; k < kScatterBatch; ++k) {
+            const u64 i = i0 + (u64)k * kBlock;
+            N[k] = i < hi ? a.nsub[s][i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kScatterBatch; ++k)
+            if (N[k]) {
+                const int bin = nbin(N[k], a.light_max);
+                if (bin) atomicAdd(&cnt[bin], 1u);
+            }
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kBins; b += kBlock) {
@@ -1175,10 +1234,19 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepArgs a) {
         cnt[b] = 0;
     }
     __syncthreads();
-    for (u64 i = lo + threadIdx.x; i < hi; i += kBlock) {
-        const uint32_t N = a.nsub[s][i];
-        const int bin = N ? nbin(N, a.light_max) : 0;
-        if (bin) a.queue[s][base[bin] + atomicAdd(&cnt[bin], 1u)] = (uint32_t)i;
+    for (u64 i0 = lo + threadIdx.x; i0 < hi; i0 += (u64)kBlock * kScatterBatch) {
+        uint32_t N[kScatterBatch];
+#pragma unroll
+        for (int k = 0; k < kScatterBatch; ++k) {
+            const u64 i = i0 + (u64)k * kBlock;
+            N[k] = i < hi ? a.nsub[s][i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kScatterBatch; ++k)
+            if (N[k]) {
+                const int bin = nbin(N[k], a.light_max);
+                if (bin) a.queue[s][base[bin] + atomicAdd(&cnt[bin], 1u)] = (uint32_t)(i0 + (u64)k * kBlock);
+            }
     }
 }
 
@@ -1976,7 +2044,7 @@ hipError_t launch_t(int id, const StepArgs &a, int blocks, hipStream_t s) {
                 }
             hipLaunchKernelGGL((k_prepass<R, false>), g2, blk, 0, s, a);
             break;
-        case K_SCAN: hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, a); break;
+        case K_SCAN: hipLaunchKernelGGL(k_scan, dim3(1, 2), dim3(kBins), 0, s, a); break;
         case K_SCATTER: hipLaunchKernelGGL(k_scatter, g2, blk, 0, s, a); break;
         case K_LIGHT:
             if constexpr (std::is_same<R, float>::value)

@@ -76,7 +76,8 @@ class qed_tuning(C.Structure):
     _fields_ = [("lepton_blocks_per_cu", C.c_uint32), ("heavy_blocks_per_cu", C.c_uint32),
                 ("photon_blocks_per_cu", C.c_uint32), ("light_max", C.c_uint32), ("chunk", C.c_uint32),
                 ("resolve_batch", C.c_uint32), ("prepass_blocks_per_cu", C.c_uint32),
-                ("prepass_finish", C.c_uint32), ("deposit_sort_min", C.c_uint32)]
+                ("prepass_finish", C.c_uint32), ("scatter_blocks_per_cu", C.c_uint32),
+                ("deposit_sort_min", C.c_uint32)]
 
 
 class qed_sampler_model(C.Structure):

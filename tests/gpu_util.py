@@ -169,3 +169,25 @@ def check_step(g, fields, dt, seed, step, precision, emission=True, pairs=True, 
                                     max_missing)
         out["photons_matched"] = nc
     return out, after, res
+
+
+def amplified_tol(start, fields, dt, seed, step, charge=-1.0, ulp=6e-8):
+    """Per-particle bound on the float path's momentum deviation from the oracle after
+    one step.  A float rounding of u changes |u|, hence the gyration frequency, so the
+    phase error it causes grows with the rotation that follows (and near the light-like
+    limit a perturbation grows along the orbit).  The oracle runs the step from the
+    start state and from it with |u| ulp * (a random direction) added; the float path
+    rounds at each of its N sub-steps, so its deviation stays below about 4 N ulp times
+    that amplification (at least 1).  Returns (bound, N)."""
+    a = {k: np.array(start[k], copy=True) for k in ("x", "y", "z", "ux", "uy", "uz", "w", "id")}
+    b = {k: v.copy() for k, v in a.items()}
+    m = np.sqrt(a["ux"] ** 2 + a["uy"] ** 2 + a["uz"] ** 2)
+    d = np.random.default_rng(step).standard_normal((3, m.size))
+    d /= np.linalg.norm(d, axis=0)
+    for j, k in enumerate(("ux", "uy", "uz")):
+        b[k] = b[k] + ulp * m * d[j]
+    _, ns, _, _ = oracle.lepton_step(a, fields, charge, dt, seed, step, rng_bits=24)
+    oracle.lepton_step(b, fields, charge, dt, seed, step, rng_bits=24)
+    du = np.sqrt(sum((a[k] - b[k]) ** 2 for k in ("ux", "uy", "uz")))
+    amp = du / np.maximum(np.sqrt(a["ux"] ** 2 + a["uy"] ** 2 + a["uz"] ** 2), 1.0) / ulp
+    return 4.0 * ulp * ns * np.maximum(amp, 1.0), ns

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import workloads
-from gpu_util import as_precision
+from gpu_util import amplified_tol, as_precision
 
 pytestmark = pytest.mark.gpu
 
@@ -61,8 +61,10 @@ def test_c1_full_size_fp64_identical_events():
 def test_c3_full_size_sampled_against_oracle():
     """C3 at 16,777,216 electrons (10% in the hot spot), binned with the tuned launch
     shapes, two steps; a stratified sample of 2^16 electrons (2^15 from the hot spot,
-    2^15 from the weak field) checked by the oracle at each step from the GPU's
-    state at that step's start: identical event counts on >= 99.99% of them."""
+    state at that step's start: identical event counts on >= 99.99% of them, and the
+    momenta of those within the float path's bound (gpu_util.amplified_tol: the hot
+    spot turns a particle through many gyrations in a step, over which a rounding of
+    |u| becomes a phase error)."""
     from paper_2008_10468_amd import qed
     print("C3 full size: building the population", flush=True)
     w = workloads.c3()
@@ -96,7 +98,9 @@ def test_c3_full_size_sampled_against_oracle():
               flush=True)
         assert np.mean(same) >= 0.9999, np.mean(same)
         du = np.linalg.norm(ug - _mom(sub), axis=0) / np.linalg.norm(_mom(sub), axis=0)
-        assert np.all(du[same] <= 2e-5 + 2e-7 * nsub[same])
+        bound = 2e-5 + amplified_tol(sub, fh, w["dt"], w["seed"], step)[0]
+        print("C3 full size: step", step, "largest deviation / bound", float(np.max((du / bound)[same])), flush=True)
+        assert np.all(du[same] <= bound[same])
     st = g.stats()
     g.close()
     assert st.heavy_particles > 0 and st.emissions > 0

@@ -15,9 +15,8 @@ least 99.99% of particles; the same under the naive, binned and tiled schedulers
 import numpy as np
 import pytest
 
-import oracle
 import workloads
-from gpu_util import as_precision, check_step
+from gpu_util import amplified_tol, as_precision, check_step
 
 pytestmark = pytest.mark.gpu
 
@@ -80,25 +79,9 @@ def test_general_fields_match_oracle(prec, sched):
     g.close()
 
 
-def _amplified(start, w, step, ulp=6e-8):
-    """Per-particle momentum tolerance from the dynamics: near the light-like limit a
-    perturbation of u grows along the orbit (by up to ~200 times over one step here).
-    The oracle runs the step from the start state and from it with |u| ulp * (random
-    direction) added; the float path rounds at every one of its N sub-steps, so its
-    deviation is bounded by about 4 N ulp times that amplification."""
-    fl = as_precision(w["fields"], 1)
-    a = {k: start[k].copy() for k in ("x", "y", "z", "ux", "uy", "uz", "w", "id")}
-    b = {k: v.copy() for k, v in a.items()}
-    m = np.sqrt(a["ux"] ** 2 + a["uy"] ** 2 + a["uz"] ** 2)
-    d = np.random.default_rng(step).standard_normal((3, m.size))
-    d /= np.linalg.norm(d, axis=0)
-    for j, k in enumerate(("ux", "uy", "uz")):
-        b[k] = b[k] + ulp * m * d[j]
-    _, ns, _, _ = oracle.lepton_step(a, fl, -1.0, w["dt"], w["seed"], step, rng_bits=24)
-    oracle.lepton_step(b, fl, -1.0, w["dt"], w["seed"], step, rng_bits=24)
-    du = np.sqrt(sum((a[k] - b[k]) ** 2 for k in ("ux", "uy", "uz")))
-    amp = du / np.maximum(np.sqrt(a["ux"] ** 2 + a["uy"] ** 2 + a["uz"] ** 2), 1.0) / ulp
-    return 4.0 * ulp * ns * np.maximum(amp, 1.0)
+def _amplified(start, w, step):
+    """The amplification bound of gpu_util.amplified_tol for the crossed-field workload."""
+    return amplified_tol(start, as_precision(w["fields"], 1), w["dt"], w["seed"], step)[0]
 
 
 @pytest.mark.parametrize("sched", SCHEDS)
