@@ -48,6 +48,13 @@ FLOPS_MOVE = 15
 FLOPS_PLAIN_TEST = 14 + 37 + 12
 FLOPS_SURR_RATE = 17 + 1 + 2
 FLOPS_MLP_PER_EVENT = 2 * (2 * 64 + 64 * 64 + 64 * 64 + 64)   # matrix cores (bf16), reported apart
+# per emission on the optical-depth path (vector unit): gamma, chi and the rate fit at the
+# crossing and again after the recoil (2 x 44), the next optical depth's logarithm (25,
+# double), x from the sample and the photon and recoil (35), the held rotation (20)
+FLOPS_SURR_EVENT = 2 * 44 + 25 + 35 + 20
+# per learned emission: the network's float layers (layer 1: 64 x (2 fma + activation 4);
+# the hidden activations: 64 x (bias + 4); output: 64 x (bias + 4 + fma 2) + 2)
+FLOPS_MLP_VALU_PER_EVENT = 64 * 8 + 64 * 5 + 64 * 7 + 2
 FLOPS_PER_PHOTON_SUBSTEP = 62       # move 6, candidate 6, F and G 37, acceptance 13
 BYTES_PER_LEPTON_STEP = 80          # read u 12 + id 8 + position 24; write u 12 + position 24
 BYTES_FIELD_PER_PARTICLE = 24       # six float field values, per-particle (stride 1) fields only
@@ -156,38 +163,43 @@ def cpu_baseline(workloads, budget_s):
 
 
 def kernel_source_hash():
-    """SHA-256 over the kernel sources, in name order (identifies the kernels a counter
-    summary was taken from)."""
+    """SHA-256 over the sources of the generator's kernels (qed_kernels.hip and the
+    headers and tables it includes), in name order: identifies the kernels a counter
+    summary was taken from."""
     import hashlib
     d = os.path.join(ROOT, "paper_2008_10468_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".inc")):
+        if f == "qed_kernels.hip" or f.endswith((".hpp", ".inc")):
             h.update(f.encode())
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload):
-    """Calibrated HBM bytes per launch of `kernel` from the committed counter summary of
-    this workload, or None if there is none or the kernels changed since it was taken."""
+def measured_traffic(kernel, workload, run="-", steps=None):
+    """Calibrated HBM bytes per launch of `kernel` in `run` of this workload from the
+    committed counter summary, or None if there is none, it was taken over another
+    number of steps, or the kernels changed since it was taken.  The summary's lines
+    read `source_sha256: <hash>`, `steps: <K>` and `traffic <run> <kernel> <bytes>`."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
     if not os.path.exists(path):
         return None
-    sha, val = None, None
+    sha, val, k = None, None, None
     for line in open(path):
         if line.startswith("source_sha256:"):
             sha = line.split(":", 1)[1].strip()
+        elif line.startswith("steps:"):
+            k = int(line.split(":", 1)[1])
         parts = line.split()
-        if len(parts) == 3 and parts[0] == "traffic" and parts[1] == kernel:
-            val = float(parts[2])
-    if sha != kernel_source_hash():
+        if len(parts) == 4 and parts[0] == "traffic" and parts[1] == run and parts[2] == kernel:
+            val = float(parts[3])
+    if sha != kernel_source_hash() or (steps is not None and k != steps):
         return None
     return val
 
 
 def roofline(kt, st, K, workload, field_kind="general", surrogate=False, field_bytes=0, peaks=None,
-             kernel=None):
+             kernel=None, run="-"):
     """Roofline of the kernel with the largest share of the profiled time (or `kernel`):
     its algorithmic bytes and flops per launch from the device counters and the unit
     costs above, against 8 TB/s or the FP32 vector peak (and the measured peaks, if
@@ -230,6 +242,11 @@ def roofline(kt, st, K, workload, field_kind="general", surrogate=False, field_b
         flops = FLOPS_PER_PHOTON_MOVE * (sub - st.sampled_substeps) + FLOPS_PER_PHOTON_SUBSTEP * st.sampled_substeps
     if surrogate:
         mfma = FLOPS_MLP_PER_EVENT * learned
+        # the emissions' own work: every event, the network's float layers for the learned
+        # ones, a candidate test per rejection draw for the others
+        if name != "k_photon":
+            draws = st.fallback_draws * (em / max(st.emissions, 1))
+            flops += FLOPS_SURR_EVENT * em + FLOPS_MLP_VALU_PER_EVENT * learned + FLOPS_PLAIN_TEST * draws
     byts /= max(nl, 1)
     flops /= max(nl, 1)
     mfma /= max(nl, 1)
@@ -246,7 +263,7 @@ def roofline(kt, st, K, workload, field_kind="general", surrogate=False, field_b
     if meas:
         roof["measured_peak"] = meas
         roof["frac_of_measured_peak"] = roof["achieved"] / meas
-    roof["traffic"] = measured_traffic(name, workload)
+    roof["traffic"] = measured_traffic(name, workload, run, K)
     roof["kernel"] = name
     roof["avg_launch_us"] = avg_s * 1e6
     roof["per_launch"] = {"particles": part / max(nl, 1), "substeps": sub / max(nl, 1),
@@ -479,7 +496,7 @@ def bench_hotspot(args, torch, qed, workloads):
                       "kernel_us": {k: v[1] * 1e3 / max(v[0], 1) for k, v in kt.items()},
                       "launch": "one HIP graph of all timed steps" if graphed else "eager"}
         rooflines[name] = roofline(kt, stats_p, K, "hotspot", field_kind="pure_b", surrogate=surr,
-                                   field_bytes=BYTES_FIELD_PER_PARTICLE, peaks=peaks, kernel="k_heavy")
+                                   field_bytes=BYTES_FIELD_PER_PARTICLE, peaks=peaks, kernel="k_heavy", run=name)
         g.close()
         del g
         torch.cuda.empty_cache()

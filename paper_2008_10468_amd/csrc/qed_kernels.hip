@@ -379,8 +379,21 @@ __device__ __forceinline__ uint32_t lepton_nsub(const StepArgs &a, int s, u64 i,
 // the sub-step loop.  k: the sub-step (birth time t0 + (k + 1) st); ctr: the
 // counter of the photon's id (the sub-step in Algorithm 1, the emission's index in
 // the step for the surrogate, which can emit more than once in a sub-step).
+// A lepton's position and weight at the start of the step, held for its emissions
+// and its end-of-step position (the step does not change them in memory).
+template <class R>
+struct Origin {
+    double x, y, z;
+    R w;
+};
+
+template <class R>
+__device__ __forceinline__ Origin<R> origin_of(const SpeciesDev &sp, u64 i) {
+    return Origin<R>{sp.x[i], sp.y[i], sp.z[i], ((const R *)sp.w)[i]};
+}
+
 template <class R, bool TB>
-__device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesDev &sp, u64 i, uint64_t pid,
+__device__ __forceinline__ void stage_emission(const StepArgs &a, const Origin<R> &org, uint64_t pid,
                                                uint32_t ctr, uint32_t k, bool acc, u64 m, R x3, R omx3, R g,
                                                R u2, R dx,
                                                R dy, R dz, R &ux, R &uy, R &uz, ChildBuf<R, TB> &cb,
@@ -394,13 +407,13 @@ __device__ __forceinline__ void stage_emission(const StepArgs &a, const SpeciesD
         const R umag = sqrt_(u2);
         const R inv = umag > R(0) ? rcp(umag) : R(0);
         const R eph = x3 * g * inv;
-        cb.x[e] = sp.x[i] + (double)dx;
-        cb.y[e] = sp.y[i] + (double)dy;
-        cb.z[e] = sp.z[i] + (double)dz;
+        cb.x[e] = org.x + (double)dx;
+        cb.y[e] = org.y + (double)dy;
+        cb.z[e] = org.z + (double)dz;
         cb.px[e] = ux * eph;
         cb.py[e] = uy * eph;
         cb.pz[e] = uz * eph;
-        cb.w[e] = ((const R *)sp.w)[i];
+        cb.w[e] = org.w;
         cb.ctr[e] = ctr;
         cb.parent[e] = pid;
         if constexpr (TB) cb.tb[e] = t0 + (double)(k + 1) * st;
@@ -497,6 +510,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
                                             const SynTable<R> &tab, ChildBuf<R> &cb, Tally<R> &tl, double t0) {
     const SpeciesDev &sp = a.sp[s];
     const uint64_t pid = sp.id[i];
+    const Origin<R> org = origin_of<R>(sp, i);
     const double st = (a.dt - t0) / (double)N;
     const PushConst<R> c = push_const(p, s, st);
     const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
@@ -519,7 +533,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
         const u64 m = __ballot(acc);
         if (m) {
             const R u2 = FK == 2 ? ux * ux + uy * uy + uz * uz : o.u2;
-            stage_emission<R>(a, sp, i, pid, k, k, acc, m, o.x3, o.omx3, o.g, u2, dx, dy, dz, ux, uy, uz, cb, nev,
+            stage_emission<R>(a, org, pid, k, k, acc, m, o.x3, o.omx3, o.g, u2, dx, dy, dz, ux, uy, uz, cb, nev,
                               t0, st, step);
             if constexpr (FK == 2)
                 if (acc) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);   // after the recoil
@@ -532,9 +546,9 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
     ((R *)sp.ux)[i] = ux;
     ((R *)sp.uy)[i] = uy;
     ((R *)sp.uz)[i] = uz;
-    sp.x[i] += (double)dx;
-    sp.y[i] += (double)dy;
-    sp.z[i] += (double)dz;
+    sp.x[i] = org.x + (double)dx;
+    sp.y[i] = org.y + (double)dy;
+    sp.z[i] = org.z + (double)dz;
     if (sp.events) sp.events[i] = nev;
     tl.substeps += N;
     tl.events += nev;
@@ -652,6 +666,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
     const SpeciesDev &sp = a.sp[s];
     const bool has = N > 0;
     const uint64_t pid = has ? sp.id[i] : 0ull;
+    const Origin<R> org = has ? origin_of<R>(sp, i) : Origin<R>{0.0, 0.0, 0.0, R(0)};
     const double st = has ? a.dt / (double)N : 0.0;
     const PushConst<R> c = push_const(p, s, st);
     const R e2 = c.e2;
@@ -728,7 +743,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
             x3 = x2 * x;
             omx3 = (R(1) - x) * (R(1) + x + x2);
         }
-        stage_emission<R>(a, sp, i, pid, nev, pk, pend, mp, x3, omx3, cg, cu2, dx, dy, dz, ux, uy, uz, cb, nev,
+        stage_emission<R>(a, org, pid, nev, pk, pend, mp, x3, omx3, cg, cu2, dx, dy, dz, ux, uy, uz, cb, nev,
                           0.0, st, step);
         // The part of the sub-step after the crossing (the overshoot, at the rate before
         // the emission) counts against the new optical depth at the rate after the
@@ -749,9 +764,9 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
         ((R *)sp.ux)[i] = ux;
         ((R *)sp.uy)[i] = uy;
         ((R *)sp.uz)[i] = uz;
-        sp.x[i] += (double)dx;
-        sp.y[i] += (double)dy;
-        sp.z[i] += (double)dz;
+        sp.x[i] = org.x + (double)dx;
+        sp.y[i] = org.y + (double)dy;
+        sp.z[i] = org.z + (double)dz;
         sp.tau[i] = tau;
         if (sp.events) sp.events[i] = nev;
         tl.substeps += N;
