@@ -111,8 +111,8 @@ def test_bad_configurations_are_rejected_before_device_work(qed):
 
 
 def test_bench_reads_traffic_only_for_the_kernels_as_they_stand(tmp_path, monkeypatch):
-    """bench.py reports a measured traffic figure only while the kernel sources hash to
-    the value recorded beside it."""
+    """bench.py reports a measured traffic figure only for the run and step count it was
+    taken over, and only while the kernel sources hash to the value recorded beside it."""
     import bench
     sha = bench.kernel_source_hash()
     assert re.fullmatch(r"[0-9a-f]{64}", sha) and sha == bench.kernel_source_hash()
@@ -120,9 +120,13 @@ def test_bench_reads_traffic_only_for_the_kernels_as_they_stand(tmp_path, monkey
     prof.mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: sha)
-    (prof / "hbm_traffic_c2.md").write_text(f"source_sha256: {sha}\ntraffic k_photon 123456\n")
-    assert bench.measured_traffic("k_photon", "c2") == 123456.0
-    assert bench.measured_traffic("k_lepton", "c2") is None
-    assert bench.measured_traffic("k_photon", "c3") is None
-    (prof / "hbm_traffic_c2.md").write_text("source_sha256: " + "0" * 64 + "\ntraffic k_photon 123456\n")
-    assert bench.measured_traffic("k_photon", "c2") is None
+    (prof / "hbm_traffic_hotspot.md").write_text(
+        f"source_sha256: {sha}\nsteps: 20\ntraffic plain_binned k_heavy 123456\ntraffic surrogate_binned k_heavy 654321\n")
+    assert bench.measured_traffic("k_heavy", "hotspot", "plain_binned", 20) == 123456.0
+    assert bench.measured_traffic("k_heavy", "hotspot", "surrogate_binned", 20) == 654321.0
+    assert bench.measured_traffic("k_heavy", "hotspot", "plain_binned", 8) is None     # other step count
+    assert bench.measured_traffic("k_lepton", "hotspot", "plain_binned", 20) is None
+    assert bench.measured_traffic("k_heavy", "c3", "plain_binned", 20) is None
+    (prof / "hbm_traffic_hotspot.md").write_text("source_sha256: " + "0" * 64 + "\nsteps: 20\n"
+                                                 "traffic plain_binned k_heavy 123456\n")
+    assert bench.measured_traffic("k_heavy", "hotspot", "plain_binned", 20) is None
