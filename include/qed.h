@@ -298,6 +298,13 @@ typedef struct qed_tuning {
     uint32_t scatter_blocks_per_cu; /* binned scheduler: grid of the pass that places the heavy
                                       particles into their bins (1..1024; each block reserves
                                       its share of every bin it holds with one atomic add) */
+    uint32_t bins_per_octave;      /* binned scheduler: sub-step-count bins per octave of N
+                                      (4..32; the heavy queue is ordered by bin, so finer bins
+                                      give the lanes of a wave closer counts) */
+    uint32_t light_tile;           /* binned scheduler: slots per wave tile of the light pass
+                                      (64..512, a multiple of 64) */
+    uint32_t tiled_slots;          /* tiled scheduler: slots per wave tile (64..256, a multiple
+                                      of 64) */
     uint32_t deposit_sort_min;     /* qed_deposit sorts the particles by grid tile (4^3 cells)
                                       and sums dense tiles in LDS when the species' capacity
                                       is at least this (0: always; 0xffffffff: never, every

@@ -7,8 +7,10 @@ handled by the light pass of the binned scheduler, and the number of queue
 entries a wave claims at a time in its persistent heavy pass.
 
 The surrogate path adds the number of emissions a wave lets wait before
-resolving them together, and the binned scheduler whether its pre-pass finishes
-particles of one quiet sub-step.
+resolving them together; the binned scheduler whether its pre-pass finishes
+particles of one quiet sub-step, the grid of its placement pass, the number of
+sub-step-count bins per octave (how close the counts in one wave of the heavy
+queue are) and the tile of its light pass; the tile-sorted scheduler its tile.
 
 `tune` measures candidate settings on the real workload and device with
 coordinate descent: starting from the library's defaults, it sweeps one
@@ -42,11 +44,15 @@ SPACE = {
     "prepass_blocks_per_cu": (4, 8, 16, 32, 64, 128, 256, 512),
     "prepass_finish": (0, 1),
     "scatter_blocks_per_cu": (1, 2, 4, 8, 16),
+    "bins_per_octave": (4, 8, 16, 32),
+    "light_tile": (128, 256, 512),
+    "tiled_slots": (64, 128, 256),
 }
 NAIVE_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu")
 MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "sampler_gfx950.npz")
 BINNED_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu", "heavy_blocks_per_cu", "light_max", "chunk",
-               "prepass_blocks_per_cu", "prepass_finish", "scatter_blocks_per_cu")
+               "prepass_blocks_per_cu", "prepass_finish", "scatter_blocks_per_cu", "bins_per_octave", "light_tile")
+TILED_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu", "tiled_slots")
 SURROGATE_KEYS = ("resolve_batch",)   # added for workloads on the lepton optical-depth path
 
 
@@ -225,7 +231,7 @@ def main(argv=None):
             sched = {"naive": qed.QED_SCHED_NAIVE, "binned": qed.QED_SCHED_BINNED, "tiled": qed.QED_SCHED_TILED}[sn]
             stream = torch.cuda.Stream()
             g, w, fields = _workload(wl, torch, workloads, sched, stream, args.steps)
-            keys = BINNED_KEYS if sn == "binned" else NAIVE_KEYS
+            keys = {"binned": BINNED_KEYS, "tiled": TILED_KEYS}.get(sn, NAIVE_KEYS)
             if wl in ("c2s", "c5"):
                 keys = keys + SURROGATE_KEYS
             best, ms, ms0, hist = tune(torch, g, stream, w, fields, w["dt"], w["seed"], args.steps, keys,

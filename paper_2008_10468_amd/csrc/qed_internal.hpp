@@ -13,11 +13,13 @@ namespace qed {
 typedef unsigned long long u64;
 
 // Sub-step-count bins of the binned scheduler: bin 0 holds the light particles
-// (N <= light_max), bin j >= 1 the heavy ones with floor(16 log2 N) = j - 1
-// (sixteen bins per octave, so the counts in one bin differ by less than 4.4% and a
-// wave of one bin idles little at the end of its loop).
-constexpr int kBins = 512;
-constexpr int kBinsPerOctave = 16;
+// (N <= light_max), bin j >= 1 the heavy ones with floor(B log2 N) = j - 1, B bins per
+// octave (the tuning's bins_per_octave, at most kMaxBinsPerOctave; at 16 the counts in
+// one bin differ by less than 4.4%, so a wave of one bin idles little at the end of
+// its loop).  kBins covers N up to 2^31 at the finest binning.
+constexpr int kMaxBinsPerOctave = 32;
+constexpr int kBins = 1024;
+static_assert(1 + 31 * kMaxBinsPerOctave < kBins, "bins cover every sub-step count");
 
 // Per-context device state: step bookkeeping and cumulative counters.
 struct DevState {
@@ -101,6 +103,9 @@ struct StepArgs {
     uint32_t chunk;        // binned scheduler: queue entries claimed per wave (multiple of 64)
     uint32_t resolve_batch;  // surrogate: waiting emissions that trigger a batched resolve (1..64)
     uint32_t prepass_finish; // binned: the pre-pass finishes particles of one quiet sub-step
+    uint32_t bins_per_octave; // binned: sub-step-count bins per octave (4..kMaxBinsPerOctave)
+    uint32_t light_tile;     // binned: slots per wave tile of the light pass (64..512, a multiple of 64)
+    uint32_t tiled_slots;    // tiled: slots per wave tile (64..256, a multiple of 64)
     uint8_t *alive;        // photon flags, one per slot: 0 decayed, 1 alive
     u64 *dead_idx;         // slots of the photons that decayed this step
     u64 *hole_idx;         // compaction lists

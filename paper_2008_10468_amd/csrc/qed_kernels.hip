@@ -931,9 +931,9 @@ __device__ __forceinline__ void photon_sample(const StepArgs &a, u64 i, R kx, R 
 }
 
 // Bin of a sub-step count (see kBins).
-__device__ __forceinline__ int nbin(uint32_t N, uint32_t light_max) {
+__device__ __forceinline__ int nbin(uint32_t N, uint32_t light_max, uint32_t per_octave) {
     if (N <= light_max) return 0;
-    const int b = 1 + (int)floorf((float)kBinsPerOctave * __log2f((float)N));
+    const int b = 1 + (int)floorf((float)per_octave * __log2f((float)N));
     return b < kBins - 1 ? b : kBins - 1;
 }
 
@@ -1171,7 +1171,7 @@ __global__ __launch_bounds__(kBlock) void k_prepass(StepArgs a) {
         if (done) N = 0;
         a.nsub[s][i] = N;
         if (N)
-            atomicAdd(&h[nbin(N, a.light_max)], 1u);
+            atomicAdd(&h[nbin(N, a.light_max, a.bins_per_octave)], 1u);
         else if (!done && a.sp[s].events)
             a.sp[s].events[i] = 0;
     }
@@ -1239,7 +1239,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepArgs a) {
 #pragma unroll
         for (int k = 0; k < kScatterBatch; ++k)
             if (N[k]) {
-                const int bin = nbin(N[k], a.light_max);
+                const int bin = nbin(N[k], a.light_max, a.bins_per_octave);
                 if (bin) atomicAdd(&cnt[bin], 1u);
             }
     }
@@ -1259,18 +1259,18 @@ __global__ __launch_bounds__(kBlock) void k_scatter(StepArgs a) {
 #pragma unroll
         for (int k = 0; k < kScatterBatch; ++k)
             if (N[k]) {
-                const int bin = nbin(N[k], a.light_max);
+                const int bin = nbin(N[k], a.light_max, a.bins_per_octave);
                 if (bin) a.queue[s][base[bin] + atomicAdd(&cnt[bin], 1u)] = (uint32_t)(i0 + (u64)k * kBlock);
             }
     }
 }
 
-// Light pass: each wave takes tiles of kTile consecutive slots; inside a tile the
-// light particles (1 <= N <= light_max) are counting-sorted by N in the wave's
-// LDS, heaviest first, and run 64 at a time in that order, so the lanes of a
-// wave carry nearly the same N.  Waves never wait for each other, and the
-// particle data stay in the tile's address window.
-constexpr int kTile = 512;     // slots per wave tile (8 per lane)
+// Light pass: each wave takes tiles of a.light_tile consecutive slots (at most kTile);
+// inside a tile the light particles (1 <= N <= light_max) are counting-sorted by N
+// in the wave's LDS, heaviest first, and run 64 at a time in that order, so the
+// lanes of a wave carry nearly the same N.  Waves never wait for each other, and
+// the particle data stay in the tile's address window.
+constexpr int kTile = 512;     // largest tile (8 slots per lane)
 constexpr int kTileKeys = 64;  // N >= 63 share the heaviest key
 
 template <class R, bool SURR>
@@ -1287,15 +1287,16 @@ __global__ __launch_bounds__(kBlock) void k_light(StepArgs a) {
     uint32_t *hist = hist_sh[wv];
     uint16_t *order = order_sh[wv];
     const u64 nwaves = (u64)gridDim.x * (kBlock / 64);
+    const uint32_t tile = a.light_tile, qn = tile / 64;
     Tally<R> t;
-    for (u64 t0 = ((u64)blockIdx.x * (kBlock / 64) + wv) * kTile; t0 < n; t0 += nwaves * kTile) {
+    for (u64 t0 = ((u64)blockIdx.x * (kBlock / 64) + wv) * tile; t0 < n; t0 += nwaves * tile) {
         hist[lane] = 0;
         __syncwarp();
         uint32_t kr[kTile / 64];  // key << 16 | rank
 #pragma unroll
         for (int q = 0; q < kTile / 64; ++q) {
             const u64 i = t0 + q * 64 + lane;
-            const uint32_t N = i < n ? a.nsub[s][i] : 0u;
+            const uint32_t N = (uint32_t)q < qn && i < n ? a.nsub[s][i] : 0u;
             const uint32_t key = (N >= 1 && N <= lmax) ? kTileKeys - (N < kTileKeys - 1 ? N : kTileKeys - 1) : 0u;
             kr[q] = key ? (key << 16) | atomicAdd(&hist[key], 1u) : 0u;
         }
@@ -1334,8 +1335,9 @@ __global__ __launch_bounds__(kBlock) void k_light(StepArgs a) {
 // consecutive slots, computes every particle's sub-step count, counting-sorts the
 // tile by it in LDS (heaviest first) and runs the tile 64 particles at a time in
 // that order, so the lanes of a wave carry nearly the same N.  The particle
-// records are read twice, the second time from the cache.
-constexpr int kTiledSlots = 256;  // slots per wave tile of the tile-sorted scheduler (4 per lane)
+// records are read twice, the second time from the cache.  Tiles hold a.tiled_slots
+// slots, at most kTiledSlots.
+constexpr int kTiledSlots = 256;  // largest wave tile of the tile-sorted scheduler (4 slots per lane)
 
 template <class R, bool SURR>
 __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
@@ -1352,17 +1354,19 @@ __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
     uint16_t *order = order_sh[wv];
     uint32_t *nsub = nsub_sh[wv];
     const u64 nwaves = (u64)gridDim.x * (kBlock / 64);
+    const uint32_t tile = a.tiled_slots, qn = tile / 64;
     Tally<R> t;
-    for (u64 t0 = ((u64)blockIdx.x * (kBlock / 64) + wv) * kTiledSlots; t0 < n; t0 += nwaves * kTiledSlots) {
+    for (u64 t0 = ((u64)blockIdx.x * (kBlock / 64) + wv) * tile; t0 < n; t0 += nwaves * tile) {
         hist[lane] = 0;
         __syncwarp();
         uint32_t kr[kTiledSlots / 64];  // key << 16 | rank
 #pragma unroll
         for (int q = 0; q < kTiledSlots / 64; ++q) {
             const u64 i = t0 + q * 64 + lane;
+            const bool in = (uint32_t)q < qn && i < n;
             Lepton<R> p;
-            const uint32_t N = lepton_fetch(a, s, i, i < n, p, t, a.dt);
-            if (i < n && N == 0 && a.sp[s].events) a.sp[s].events[i] = 0;
+            const uint32_t N = lepton_fetch(a, s, i, in, p, t, a.dt);
+            if (in && N == 0 && a.sp[s].events) a.sp[s].events[i] = 0;
             nsub[q * 64 + lane] = N;
             const uint32_t key = N ? kTileKeys - (N < kTileKeys - 1 ? N : kTileKeys - 1) : 0u;
             kr[q] = key ? (key << 16) | atomicAdd(&hist[key], 1u) : 0u;

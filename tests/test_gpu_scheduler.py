@@ -46,7 +46,10 @@ def _run(w, sched, tuning=None, steps=3, precision=None, fields_fn=None, per_spe
                                     {"light_max": 6, "chunk": 1024, "lepton_blocks_per_cu": 2,
                                      "photon_blocks_per_cu": 1},
                                     {"light_max": 0, "prepass_finish": 1, "prepass_blocks_per_cu": 1},
-                                    {"light_max": 0, "prepass_finish": 0, "chunk": 128}])
+                                    {"light_max": 0, "prepass_finish": 0, "chunk": 128},
+                                    {"light_max": 6, "light_tile": 128, "bins_per_octave": 4,
+                                     "scatter_blocks_per_cu": 1},
+                                    {"light_max": 0, "bins_per_octave": 32, "scatter_blocks_per_cu": 16}])
 def test_binned_equals_naive_c2(tuning):
     from paper_2008_10468_amd import qed
     w = workloads.c2(n_e=20000, n_g=5000, seed=3)
@@ -57,6 +60,60 @@ def test_binned_equals_naive_c2(tuning):
         for k in ("id", "ux", "uy", "uz", "x", "y", "z", "w"):
             assert np.array_equal(a[s][k], b[s][k]), (s, k)
     assert list(sa.substeps) == list(sb.substeps) and sa.emissions == sb.emissions
+
+
+@pytest.mark.parametrize("slots", [64, 128, 256])
+def test_tiled_equals_naive_c2(slots):
+    """The tile-sorted scheduler at each tile size gives the naive kernel's results bit for bit."""
+    from paper_2008_10468_amd import qed
+    w = workloads.c2(n_e=20000, n_g=5000, seed=4)
+    a, sa = _run(w, qed.QED_SCHED_NAIVE, fields_fn=workloads.c2_field)
+    b, sb = _run(w, qed.QED_SCHED_TILED, tuning={"tiled_slots": slots}, fields_fn=workloads.c2_field)
+    for s in range(3):
+        for k in ("id", "ux", "uy", "uz", "x", "y", "z", "w"):
+            assert np.array_equal(a[s][k], b[s][k]), (slots, s, k)
+    assert list(sa.substeps) == list(sb.substeps) and sa.emissions == sb.emissions
+
+
+@pytest.mark.parametrize("key", ["c3/binned", "c5/binned"])
+def test_recorded_tuning_binned_equals_naive(key):
+    """The launch shapes and scheduler parameters the autotuner recorded for the hot spot
+    (plain: c3; optical-depth path with the shipped network: c5) give the naive
+    scheduler's results bit for bit on a 2^15-electron hot spot over two steps."""
+    import json
+    import os
+    from paper_2008_10468_amd import qed
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    tuning = json.load(open(os.path.join(root, "paper_2008_10468_amd", "tuning_gfx950.json")))[key]["tuning"]
+    surr = key.startswith("c5")
+    m = np.load(os.path.join(root, "paper_2008_10468_amd", "models", "sampler_gfx950.npz")) if surr else None
+    w = workloads.c3(n=1 << 15, hot_fraction=0.2, seed=12)
+    zero = {k: np.zeros(1) for k in ("ex", "ey", "ez", "bx", "by", "bz")}
+    res = []
+    for sched, tu in ((qed.QED_SCHED_NAIVE, None), (qed.QED_SCHED_BINNED, tuning)):
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 15, 16, 1 << 19), pairs=False,
+                          scheduler=sched, sampler=qed.QED_SAMPLER_SURROGATE if surr else qed.QED_SAMPLER_REJECTION)
+        if surr:
+            assert qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
+                                       float(m["log10_chi_hi"])) == qed.QED_OK
+        if tu:
+            t = qed.qed_get_tuning(g.ctx)
+            for k, v in tu.items():
+                setattr(t, k, int(v))
+            assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
+        g.load_state(w)
+        g.set_fields(None, per_species=[w["fields"], zero, zero])
+        for step in range(2):
+            g.step(w["dt"], 7, step)
+            assert g.sync()[0] == qed.QED_OK
+        res.append(([_sorted(g.sp[k].download()) for k in (0, 2)], g.stats()))
+        g.close()
+    (a, sa), (b, sb) = res
+    for s in range(2):
+        for k in a[s]:
+            assert np.array_equal(a[s][k], b[s][k]), (key, s, k)
+    assert list(sa.substeps) == list(sb.substeps) and sa.emissions == sb.emissions and sa.emissions > 1000
+    assert sb.heavy_particles > 0
 
 
 def test_binned_hot_spot_matches_oracle():
@@ -122,4 +179,11 @@ def test_tuning_validation():
     assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
     t.light_max = 3
     assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
+    for field, bad, good in (("bins_per_octave", 3, 16), ("bins_per_octave", 33, 16), ("light_tile", 96, 512),
+                             ("light_tile", 1024, 512), ("tiled_slots", 512, 256), ("tiled_slots", 0, 256),
+                             ("scatter_blocks_per_cu", 0, 2)):
+        setattr(t, field, bad)
+        assert qed.qed_set_tuning(g.ctx, t) == qed.QED_ERR_INVALID_ARG, (field, bad)
+        setattr(t, field, good)
+        assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
     g.close()
