@@ -881,7 +881,9 @@ def bench_grid(args, torch, qed, workloads):
     out["random_order_us"] = {"gather": times["random"][0] * 1e3, "deposit": times["random"][1] * 1e3}
     out["deposit_without_tile_sort_us"] = {o: v * 1e3 for o, v in wave.items()}
     dom = "gather" if ms_g >= ms_d else "deposit"
-    out["roofline"] = dict(out[dom], kernel=f"k_{dom}")
+    # the deposit is one call of five kernels (tile sort, LDS sums, reduction); its figure is per call
+    out["roofline"] = dict(out[dom], kernel="k_gather" if dom == "gather" else
+                           "qed_deposit (k_dep_bin, k_dep_scan, k_dep_scatter, k_dep_accum, k_dep_reduce)")
     g.close()
     return out
 
