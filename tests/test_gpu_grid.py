@@ -146,6 +146,29 @@ def test_deposit_sorted_cases(case):
     gen.close()
 
 
+@pytest.mark.parametrize("order", ["random", "cell"])
+def test_deposit_benchmark_size(order):
+    """The grid benchmark's configuration: the 1,048,576 C2 electrons in a periodic box of
+    32^3 cells (32 per cell), mixed precision, the default (tile-sorted) deposit, in the
+    order the benchmark times: against the oracle to 1e-10 of the largest current."""
+    from paper_2008_10468_amd import qed
+    n = 1 << 20
+    w = workloads.c2(n_e=n, n_g=16)
+    geom = workloads.cell_box(32)
+    e = w["electrons"]
+    if order == "cell":
+        cell = ((np.floor((e["z"] - geom["z0"]) / geom["dz"]).astype(np.int64) % 32) * 32 +
+                (np.floor((e["y"] - geom["y0"]) / geom["dy"]).astype(np.int64) % 32)) * 32 + \
+            (np.floor((e["x"] - geom["x0"]) / geom["dx"]).astype(np.int64) % 32)
+        e = workloads.subset(e, np.argsort(cell, kind="stable"))
+    gen = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, 16), parent=False, events=False)
+    gen.sp[0].upload(e)
+    g = dict(geom)
+    print("deposit at the benchmark's size,", order, "order", flush=True)
+    _deposit_check(qed, gen, g, qed.cell_geometry(geom))
+    gen.close()
+
+
 def test_deposit_sorted_changing_grids():
     """One context, grids of 12, 5460 and again 12 tiles (the scratch grows; the tile
     counts start from zero on every call) and a species that shrinks between calls."""
