@@ -279,11 +279,15 @@ __device__ __forceinline__ void boris(R &ux, R &uy, R &uz, R hex, R hey, R hez, 
 
 // Pure magnetic field: the Boris rotation is exact, so |u|, hence gamma, the
 // rotation vectors t = hq B / gamma and s = 2 t / (1 + t^2) and the move per
-// sub-step u st / gamma keep their values from one sub-step to the next.  They are
-// set from u where gamma changes: at the start and after each emission's recoil.
+// sub-step u st / gamma keep their values from one sub-step to the next, and so do
+// u . B and therefore chi = |u x B| (and the optical-depth rate, a function of chi
+// and gamma).  They are set from u where gamma changes: at the start and after each
+// emission's recoil (rot_of here; chi and rw by the lepton loops, which own the
+// chi and rate code).
 template <class R>
 struct Rot {
     R ig, g, tx, ty, tz, sx, sy, sz, vs;
+    R chi, rw;  // chi; rate of the optical depth per unit step, chi q(chi) / gamma (its path only)
 };
 
 template <class R>
@@ -301,6 +305,8 @@ __device__ __forceinline__ Rot<R> rot_of(R ux, R uy, R uz, R hq, R bx, R by, R b
     r.sy = s * r.ty;
     r.sz = s * r.tz;
     r.vs = str * r.ig;
+    r.chi = R(0);
+    r.rw = R(0);
     return r;
 }
 

@@ -466,8 +466,12 @@ __device__ __forceinline__ SubStep<R, FK> substep(const Lepton<R> &p, R hex, R h
     dx += ux * vs;
     dy += uy * vs;
     dz += uz * vs;
-    // quantum parameter after the push
-    const R chi = chi_sub<FK>(ux, uy, uz, o.g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, guard);
+    // quantum parameter after the push (pure magnetic field: held, the rotation keeps it)
+    R chi;
+    if constexpr (FK == 2)
+        chi = rs.chi;
+    else
+        chi = chi_sub<FK>(ux, uy, uz, o.g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, guard);
     // candidate x and test value y
     R x;
     draw.get(k, idlo, idhi, step, klo, khi, x, o.y);
@@ -502,6 +506,15 @@ __device__ __forceinline__ PushConst<R> push_const(const Lepton<R> &p, int s, do
     return c;
 }
 
+// The held state of a pure-magnetic-field lepton (Rot) with its chi, from u.
+template <class R>
+__device__ __forceinline__ Rot<R> rot_chi(const Lepton<R> &p, const PushConst<R> &c, R ux, R uy, R uz) {
+    Rot<R> r = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);
+    uint32_t none = 0;  // no cross term in a pure magnetic field: the double recomputation never runs
+    r.chi = chi_sub<2>(ux, uy, uz, r.g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, c.e2, none);
+    return r;
+}
+
 // Algorithm 1's sub-step loop for one electron (s = 0, q = -1) or positron (s = 1,
 // q = +1) with N >= 1 sub-steps.  s is uniform across the wave.  FK: field kind
 // (0 general, 1 pure E, 2 pure B), see boris().
@@ -521,7 +534,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
     uint32_t nev = 0;
     uint32_t last = 0;  // sub-steps done at this particle's previous event
     Rot<R> rs{};
-    if constexpr (FK == 2) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);
+    if constexpr (FK == 2) rs = rot_chi(p, c, ux, uy, uz);
     Draw<R> draw;
     for (uint32_t k = 0; k < N; ++k) {
         const SubStep<R, FK> o = substep<R, FK>(p, c.hex, c.hey, c.hez, c.hq, c.e2, c.str, c.kcb, k, idlo, idhi, step,
@@ -536,7 +549,7 @@ __device__ __forceinline__ void lepton_loop(const StepArgs &a, int s, u64 i, uin
             stage_emission<R>(a, org, pid, k, k, acc, m, o.x3, o.omx3, o.g, u2, dx, dy, dz, ux, uy, uz, cb, nev,
                               t0, st, step);
             if constexpr (FK == 2)
-                if (acc) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);   // after the recoil
+                if (acc) rs = rot_chi(p, c, ux, uy, uz);   // after the recoil
             if (acc && a.gap_hist) {
                 count_gap(a, 0, k + 1 - last);
                 last = k + 1;
@@ -641,8 +654,13 @@ __device__ __forceinline__ void substep_surr(const Lepton<float> &p, const PushC
     dx += ux * vs;
     dy += uy * vs;
     dz += uz * vs;
-    const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, c.e2, guard);
-    const R rw = rate_chi_q(chi, rate) * ig;
+    R rw;
+    if constexpr (FK == 2) {
+        rw = rs.rw;   // chi and gamma are held, so is the rate
+    } else {
+        const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, c.e2, guard);
+        rw = rate_chi_q(chi, rate) * ig;
+    }
     tau -= (double)(wk * rw);
 }
 
@@ -686,7 +704,10 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
     R ux = p.ux, uy = p.uy, uz = p.uz;
     R dx = 0, dy = 0, dz = 0;
     Rot<R> rs{};
-    if constexpr (FK == 2) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);
+    if constexpr (FK == 2) {
+        rs = rot_chi(p, c, ux, uy, uz);
+        rs.rw = rate_chi_q(rs.chi, S.rate) * rs.ig;
+    }
     uint32_t nev = 0;
     uint32_t k = 0;     // next sub-step of this lane
     bool pend = false;  // an emission waits for its energy
@@ -750,7 +771,10 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
         // recoil.  If that crosses it again, the lane waits for another emission
         // before moving on.
         if (pend) {
-            if constexpr (FK == 2) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);   // after the recoil
+            if constexpr (FK == 2) {   // after the recoil
+                rs = rot_chi(p, c, ux, uy, uz);
+                rs.rw = rate_chi_q(rs.chi, S.rate) * rs.ig;
+            }
             R u2;
             const R ig = inv_gamma(ux, uy, uz, u2);
             const R g = (R(1) + u2) * ig;
@@ -1057,7 +1081,7 @@ __device__ __forceinline__ bool finish_single_fk(const StepArgs &a, int s, u64 i
     R ux = p.ux, uy = p.uy, uz = p.uz;
     R dx = 0, dy = 0, dz = 0;
     Rot<R> rs{};
-    if constexpr (FK == 2) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);
+    if constexpr (FK == 2) rs = rot_chi(p, c, ux, uy, uz);
     uint32_t guard = 0;
     Draw<R> draw;
     const SubStep<R, FK> o = substep<R, FK>(p, c.hex, c.hey, c.hez, c.hq, c.e2, c.str, c.kcb, 0u, (uint32_t)pid,
@@ -1095,7 +1119,10 @@ __device__ __forceinline__ bool finish_single_surr_fk(const StepArgs &a, int s, 
     float ux = p.ux, uy = p.uy, uz = p.uz;
     float dx = 0, dy = 0, dz = 0;
     Rot<float> rs{};
-    if constexpr (FK == 2) rs = rot_of(ux, uy, uz, c.hq, p.bx, p.by, p.bz, c.str);
+    if constexpr (FK == 2) {
+        rs = rot_chi(p, c, ux, uy, uz);
+        rs.rw = rate_chi_q(rs.chi, rate) * rs.ig;
+    }
     uint32_t guard = 0;
     substep_surr<FK>(p, c, wk, rate, ux, uy, uz, dx, dy, dz, rs, tau, guard);
     if (tau <= 0.0) return false;
@@ -1147,9 +1174,10 @@ __device__ __forceinline__ bool finish_single(const StepArgs &a, int s, u64 i, c
 // Pre-pass of the binned scheduler: every lepton's sub-step count N (the bound of
 // Sec. 3.1.1 in double) and the histogram of the bins.  With a.prepass_finish,
 // particles of a single quiet sub-step are finished here (N recorded as 0, like a
-// skipped particle), so the light pass does not read them again.
+// skipped particle), so the light pass does not read them again.  A streaming pass:
+// the float instances are held to 128 VGPRs so that 4 waves per SIMD hide its loads.
 template <class R, bool SURR>
-__global__ __launch_bounds__(kBlock) void k_prepass(StepArgs a) {
+__global__ __launch_bounds__(kBlock, sizeof(R) == 4 ? 4 : 3) void k_prepass(StepArgs a) {
     __shared__ PrepassLds<R, SURR> L;
     uint32_t *h = L.h;
     const int s = blockIdx.y;
