@@ -735,10 +735,16 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
             pu = u24(w.x);
             ptau = neg_ln(u53(w.z, w.w));
             cu2 = ux * ux + uy * uy + uz * uz;
-            const R ig = rsqrt_(R(1) + cu2);
-            cg = (R(1) + cu2) * ig;
-            cchi = chi_sub<FK>(ux, uy, uz, cg, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
-            crw = rate_chi_q(cchi, S.rate) * ig;
+            if constexpr (FK == 2) {   // the held state is the state at the crossing
+                cg = rs.g;
+                cchi = rs.chi;
+                crw = rs.rw;
+            } else {
+                const R ig = rsqrt_(R(1) + cu2);
+                cg = (R(1) + cu2) * ig;
+                cchi = chi_sub<FK>(ux, uy, uz, cg, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
+                crw = rate_chi_q(cchi, S.rate) * ig;
+            }
         }
         bool use_net = false;
         R sin = 0.0f;
@@ -771,15 +777,18 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
         // recoil.  If that crosses it again, the lane waits for another emission
         // before moving on.
         if (pend) {
-            if constexpr (FK == 2) {   // after the recoil
+            R rw;
+            if constexpr (FK == 2) {   // the held state after the recoil
                 rs = rot_chi(p, c, ux, uy, uz);
                 rs.rw = rate_chi_q(rs.chi, S.rate) * rs.ig;
+                rw = rs.rw;
+            } else {
+                R u2;
+                const R ig = inv_gamma(ux, uy, uz, u2);
+                const R g = (R(1) + u2) * ig;
+                const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
+                rw = rate_chi_q(chi, S.rate) * ig;
             }
-            R u2;
-            const R ig = inv_gamma(ux, uy, uz, u2);
-            const R g = (R(1) + u2) * ig;
-            const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
-            const R rw = rate_chi_q(chi, S.rate) * ig;
             tau = ptau + tau * (double)(rw / crw);
             pend = tau <= 0.0;
         }
