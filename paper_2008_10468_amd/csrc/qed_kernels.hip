@@ -2036,7 +2036,7 @@ __global__ __launch_bounds__(kBlock) void k_synchrotron(const R *__restrict__ x,
     using Vec = typename std::conditional<sizeof(R) == 4, float4, double2>::type;
     uint32_t bad = 0;
     const u64 stride = (u64)gridDim.x * kBlock;
-    const u64 nv = n / V;
+    const u64 nv = VEC ? n / V : 0;   // whole vectors (none without the vector loop)
     auto one = [&](R z, R &f, R &g) {
         if (z >= R(0)) {
             syn_eval(z, tab, f, g);

@@ -61,6 +61,33 @@ def test_ragged_sizes_and_null_outputs(ctx, n):
     assert np.max(np.abs(F.double().cpu().numpy() / Fo - 1)) <= 2e-6
 
 
+@pytest.mark.parametrize("dtype,tol", [("float32", 2e-6), ("float64", 1e-12)])
+@pytest.mark.parametrize("n", [1, 3, 1001, 65537])
+def test_unaligned_pointers_and_tails(ctx, dtype, tol, n):
+    """Arrays that start one element past a 16-byte boundary take the one-element-per-lane
+    kernel; aligned arrays of a length that is not a whole number of vectors take the
+    vector kernel and its tail.  Both against the oracle, in float and double."""
+    from paper_2008_10468_amd import qed
+    td = getattr(torch, dtype)
+    code = qed.QED_F32 if dtype == "float32" else qed.QED_F64
+    xs = workloads.c4_host(n, seed=n + 7)
+    Fo, Go = oracle.synchrotron(np.asarray(torch.from_numpy(xs).to(td).double().numpy()))
+    for off in (0, 1):
+        x = torch.zeros(n + 1, dtype=td, device="cuda")
+        x[off:off + n] = torch.from_numpy(xs).to(td).cuda()
+        F = torch.full((n + 1,), -1.0, dtype=td, device="cuda")
+        G = torch.full((n + 1,), -1.0, dtype=td, device="cuda")
+        es = x.element_size() * off
+        assert ((x.data_ptr() + es) % 16 != 0) == (off == 1)
+        assert qed.qed_synchrotron(ctx, x.data_ptr() + es, F.data_ptr() + es, G.data_ptr() + es, n, code) == qed.QED_OK
+        assert qed.qed_sync(ctx)[0] == qed.QED_OK
+        f = F.double().cpu().numpy()
+        g = G.double().cpu().numpy()
+        assert np.max(np.abs(f[off:off + n] / Fo - 1)) <= tol and np.max(np.abs(g[off:off + n] / Go - 1)) <= tol
+        rest = np.concatenate([f[:off], f[off + n:]])
+        assert np.all(rest == -1.0)                     # nothing written outside the n outputs
+
+
 def test_edge_values(ctx):
     from paper_2008_10468_amd import qed
     for td in (torch.float32, torch.float64):
