@@ -39,6 +39,30 @@ def test_split_network_trains(pair_trained):
     assert err.max() < 5 * cfg.tolerance, err
 
 
+def test_split_infer_ragged_sizes(pair_trained):
+    """qed_pair_sampler_infer on 1, 17 and 333 inputs: every row gives the value it gives
+    inside a full batch, bit for bit, and nothing is written past n."""
+    from paper_2008_10468_amd import qed
+    cfg, params, loss, err, fb = pair_trained
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(16, 16, 16))
+    assert qed.qed_pair_sampler_set(g.ctx, params, fb, LO, HI) == qed.QED_OK
+    rng = np.random.default_rng(17)
+    n = 333
+    tc = torch.from_numpy((10.0 ** rng.uniform(LO, HI, n)).astype(np.float32)).cuda()
+    tu = torch.from_numpy(rng.uniform(0, 1, n).astype(np.float32)).cuda()
+    full = torch.full_like(tc, -7.0)
+    assert qed.qed_pair_sampler_infer(g.ctx, tc.data_ptr(), tu.data_ptr(), full.data_ptr(), n) == qed.QED_OK
+    for k in (1, 17, 333):
+        part = torch.full_like(tc, -7.0)
+        assert qed.qed_pair_sampler_infer(g.ctx, tc[-k:].data_ptr(), tu[-k:].data_ptr(), part.data_ptr(),
+                                          k) == qed.QED_OK
+        torch.cuda.synchronize()
+        a, b = full[-k:].cpu().numpy(), part[:k].cpu().numpy()
+        assert np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(a[~np.isnan(a)], b[~np.isnan(b)]), k
+        assert np.all(part[k:].cpu().numpy() == -7.0)
+    g.close()
+
+
 def test_split_network_against_oracle(pair_trained):
     """Where the network is used: the oracle's CDF at the drawn d equals u to 3e-3."""
     from paper_2008_10468_amd import qed

@@ -272,6 +272,31 @@ def test_surrogate_event_count_matches_plain_with_recoil(p_s):
     assert abs(ms - mp) <= 4 * sig, (p_s, ms, mp, sig)
 
 
+def test_sampler_infer_ragged_sizes(trained):
+    """qed_sampler_infer on 1, 17 and 333 inputs (partial 16-row passes and a partial
+    wave): every row gives the value it gives inside a full batch, bit for bit."""
+    from paper_2008_10468_amd import qed
+    cfg, params, loss, err, fb = trained
+    ctx = qed.qed_init(qed.qed_config_default())
+    assert qed.qed_sampler_set(ctx, params, fb, cfg.log10_chi_lo, cfg.log10_chi_hi) == qed.QED_OK
+    rng = np.random.default_rng(13)
+    n = 333
+    chi = (10.0 ** rng.uniform(cfg.log10_chi_lo, cfg.log10_chi_hi, n)).astype(np.float32)
+    u = rng.uniform(0, 1, n).astype(np.float32)
+    dc, du = torch.from_numpy(chi).cuda(), torch.from_numpy(u).cuda()
+    full = torch.full_like(dc, -7.0)
+    assert qed.qed_sampler_infer(ctx, dc.data_ptr(), du.data_ptr(), full.data_ptr(), n) == qed.QED_OK
+    for k in (1, 17, 333):
+        part = torch.full_like(dc, -7.0)
+        assert qed.qed_sampler_infer(ctx, dc[-k:].data_ptr(), du[-k:].data_ptr(), part.data_ptr(), k) == qed.QED_OK
+        torch.cuda.synchronize()
+        a = full[-k:].cpu().numpy()
+        b = part[:k].cpu().numpy()
+        assert np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(a[~np.isnan(a)], b[~np.isnan(b)]), k
+        assert np.all(part[k:].cpu().numpy() == -7.0)        # nothing written past n
+    qed.qed_finalize(ctx)
+
+
 def test_surrogate_binned_equals_naive(trained):
     from paper_2008_10468_amd import qed
     cfg, params, loss, err, fb = trained
