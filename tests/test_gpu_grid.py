@@ -89,6 +89,38 @@ def _deposit_check(qed, gen, g, s, charge=-1.0):
     return j
 
 
+def test_gather_benchmark_size():
+    """The grid benchmark's gather: the 1,048,576 C2 electrons in random order, a 32^3 grid
+    of float fields, against the oracle on a sample of 2^16 particles (2e-6 of the largest
+    field value)."""
+    from paper_2008_10468_amd import qed
+    n = 1 << 20
+    w = workloads.c2(n_e=n, n_g=16)
+    geom = workloads.cell_box(32)
+    gen = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, 16), parent=False, events=False)
+    gen.sp[0].upload(w["electrons"])
+    rng = np.random.default_rng(5)
+    g = dict(geom)
+    dev = {}
+    for c in COMP:
+        v = rng.normal(size=(32, 32, 32)) * 1e-3
+        dev[c] = torch.from_numpy(v).float().cuda()
+        g[c] = dev[c].double().cpu().numpy()
+    s = qed.cell_geometry(geom)
+    for c in COMP:
+        setattr(s, c, dev[c].data_ptr())
+    out = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in COMP]
+    assert qed.qed_gather(gen.ctx, s, gen.sp[0].struct(), [t.data_ptr() for t in out]) == qed.QED_OK
+    torch.cuda.synchronize()
+    e = gen.sp[0].download()
+    idx = np.sort(rng.choice(n, 1 << 16, replace=False))
+    ref = og.gather(g, e["x"][idx], e["y"][idx], e["z"][idx])
+    for c, t in zip(COMP, out):
+        got = t.double().cpu().numpy()[idx]
+        assert np.abs(got - ref[c]).max() <= 2e-6 * np.abs(g[c]).max(), c
+    gen.close()
+
+
 @pytest.mark.parametrize("mode", ["sorted", "wave"])
 @pytest.mark.parametrize("prec_name", ["F64", "MIXED"])
 def test_deposit_matches_oracle(prec_name, mode):
@@ -166,6 +198,47 @@ def test_deposit_benchmark_size(order):
     g = dict(geom)
     print("deposit at the benchmark's size,", order, "order", flush=True)
     _deposit_check(qed, gen, g, qed.cell_geometry(geom))
+    gen.close()
+
+
+def test_deposit_in_a_recorded_graph():
+    """qed_deposit recorded into a HIP graph: on a fresh context (no scratch yet, and none
+    may be allocated while recording) it records the per-wave kernel; once the sorted
+    deposit's scratch exists it records the sorted kernels.  Both graphs, replayed three
+    times with eager work and a cleared current between the replays, give the oracle's
+    current each time."""
+    from paper_2008_10468_amd import qed
+    rng = np.random.default_rng(41)
+    stream = torch.cuda.Stream()
+    gen = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(70000, 16, 16), stream=stream.cuda_stream)
+    _deposit_mode(qed, gen, "sorted")
+    g, s, _ = _grid(qed, gen.real, rng, nx=13, ny=9, nz=7)
+    gen.sp[0].upload(_particles(g, rng, 60000))
+    torch.cuda.synchronize()
+    q = gen.sp[0].download()
+    ref = og.deposit(g, q["x"], q["y"], q["z"], q["ux"], q["uy"], q["uz"], q["w"], -1.0)
+    ncell = g["nx"] * g["ny"] * g["nz"]
+    j = [torch.zeros(ncell, dtype=torch.float64, device="cuda") for _ in range(3)]
+    ptrs = [t.data_ptr() for t in j]
+    for case in ("fresh", "with_scratch"):
+        if case == "with_scratch":     # an eager call outside the graph allocates the scratch
+            assert qed.qed_deposit(gen.ctx, s, gen.sp[0].struct(), -1.0, *ptrs) == qed.QED_OK
+            assert gen.sync()[0] == qed.QED_OK
+        assert qed.qed_graph_begin(gen.ctx) == qed.QED_OK
+        assert qed.qed_deposit(gen.ctx, s, gen.sp[0].struct(), -1.0, *ptrs) == qed.QED_OK
+        st, graph = qed.qed_graph_end(gen.ctx)
+        assert st == qed.QED_OK
+        for rep in range(3):
+            for t in j:
+                t.zero_()
+            junk = torch.randn(1 << 18, device="cuda").sum().item()
+            torch.cuda.synchronize()
+            assert qed.qed_graph_launch(gen.ctx, graph) == qed.QED_OK
+            assert gen.sync()[0] == qed.QED_OK
+            torch.cuda.synchronize()
+            for t, r in zip(j, ref):
+                assert np.abs(t.cpu().numpy() - r).max() <= 1e-10 * np.abs(r).max(), (case, rep)
+        qed.qed_graph_destroy(graph)
     gen.close()
 
 
