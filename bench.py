@@ -276,11 +276,13 @@ def roofline(kt, st, K, workload, field_kind="general", surrogate=False, field_b
 
 
 def load_tuning(qed, g, key, path):
-    """Apply the autotuner's choice for this workload and scheduler, if recorded."""
+    """Apply the autotuner's choice for this workload and scheduler, if recorded (key: one
+    "<workload>/<scheduler>" or a list of them, the first recorded one applies)."""
     if not path or not os.path.exists(path):
         return None
     table = json.load(open(path))
-    choice = table.get(key)
+    keys = [key] if isinstance(key, str) else list(key)
+    choice = next((table[k] for k in keys if table.get(k)), None)
     if not choice:
         return None
     t = qed.qed_get_tuning(g.ctx)
@@ -450,6 +452,15 @@ def cpu_baseline_hotspot(workloads, budget_s, n_sample=1 << 16):
     return out
 
 
+def hotspot_tuning_keys(surrogate, net, sched):
+    """Tuning table keys of a hot-spot run: c3 (plain generator), c5 (optical-depth path
+    with the network), c5r (optical-depth path with rejection energies; each sampler at
+    the launch shapes and resolve batch tuned for it, c5's if c5r is not recorded)."""
+    if not surrogate:
+        return [f"c3/{sched}"]
+    return [f"c5/{sched}"] if net else [f"c5r/{sched}", f"c5/{sched}"]
+
+
 def bench_hotspot(args, torch, qed, workloads):
     """The hot-spot workload (16.8M electrons, 10% hot), four runs on the same population:
     plain naive, plain binned, surrogate binned with rejection energies, surrogate binned
@@ -479,7 +490,7 @@ def bench_hotspot(args, torch, qed, workloads):
             assert qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
                                        float(m["log10_chi_hi"])) == qed.QED_OK
         sname = "naive" if sched == qed.QED_SCHED_NAIVE else "binned"
-        tuned = load_tuning(qed, g, f"{'c5' if sampler == sur else 'c3'}/{sname}", args.tuning)
+        tuned = load_tuning(qed, g, hotspot_tuning_keys(sampler == sur, net, sname), args.tuning)
         g.set_fields(None, per_species=[w["fields"], zero, zero])
         fl = [f.struct() for f in g.fields]
         fields = lambda s: (qed.qed_field * 3)(*fl)
@@ -724,7 +735,7 @@ def bench_c5(args, torch, qed, workloads):
         if net:
             assert qed.qed_sampler_set(g.ctx, params, fb, tc.log10_chi_lo, tc.log10_chi_hi) == qed.QED_OK
         sname = "naive" if sched == qed.QED_SCHED_NAIVE else "binned"
-        tuned = load_tuning(qed, g, f"{'c5' if sampler == sur else 'c3'}/{sname}", args.tuning)
+        tuned = load_tuning(qed, g, hotspot_tuning_keys(sampler == sur, net, sname), args.tuning)
         g.set_fields(None, per_species=[w["fields"], zero, zero])
         fl = [f.struct() for f in g.fields]
         fields = lambda s: (qed.qed_field * 3)(*fl)

@@ -190,19 +190,21 @@ def _workload(name, torch, workloads, sched, stream, steps):
         g.set_fields(None, per_species=[w["fields"], zero, zero])
         fl = [f.struct() for f in g.fields]
         return g, w, lambda s: (qed.qed_field * 3)(*fl)
-    if name == "c5":
+    if name in ("c5", "c5r"):
         # the hot-spot workload on the surrogate path, with the network shipped for gfx950
+        # (c5) or with rejection energies (c5r)
         import numpy as np
         w = workloads.c3()
         n = w["electrons"]["id"].size
         g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, int(0.65 * n * steps) + (1 << 23)),
                           pairs=False, parent=False, events=False, scheduler=sched,
                           stream=stream.cuda_stream, sampler=qed.QED_SAMPLER_SURROGATE)
-        m = np.load(MODEL)
-        st = qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
-                                 float(m["log10_chi_hi"]))
-        if st != qed.QED_OK:
-            raise qed.QedError(st, "qed_sampler_set")
+        if name == "c5":
+            m = np.load(MODEL)
+            st = qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
+                                     float(m["log10_chi_hi"]))
+            if st != qed.QED_OK:
+                raise qed.QedError(st, "qed_sampler_set")
         zero = workloads.uniform_field()
         g.set_fields(None, per_species=[w["fields"], zero, zero])
         fl = [f.struct() for f in g.fields]
@@ -212,7 +214,7 @@ def _workload(name, torch, workloads, sched, stream, steps):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Tune launch shapes of the QED generator on this GPU")
-    ap.add_argument("--workload", choices=("c2", "c2s", "c3", "c5"), action="append")
+    ap.add_argument("--workload", choices=("c2", "c2s", "c3", "c5", "c5r"), action="append")
     ap.add_argument("--scheduler", choices=("naive", "binned", "tiled"), action="append")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--passes", type=int, default=2)
@@ -232,7 +234,7 @@ def main(argv=None):
             stream = torch.cuda.Stream()
             g, w, fields = _workload(wl, torch, workloads, sched, stream, args.steps)
             keys = {"binned": BINNED_KEYS, "tiled": TILED_KEYS}.get(sn, NAIVE_KEYS)
-            if wl in ("c2s", "c5"):
+            if wl in ("c2s", "c5", "c5r"):
                 keys = keys + SURROGATE_KEYS
             best, ms, ms0, hist = tune(torch, g, stream, w, fields, w["dt"], w["seed"], args.steps, keys,
                                        passes=args.passes, log=lambda *a: print(*a, flush=True))

@@ -193,14 +193,20 @@ __device__ __forceinline__ void flush_tally(const Tally<R> &t, DevState *st, int
 // A child's id (a Philox block of its parent's id and counter) is formed when the
 // buffer is written out, by all the flushing lanes together, rather than by the
 // few lanes that emit in one sub-step.
-// TB: with birth times (the surrogate path, which runs no cascades, saves the LDS).
+// Every flush is an atomic on the one counter of the species that all waves of the
+// chip share.  TB: with birth times.  The optical-depth path (TB false: it runs no
+// cascades) emits its photons about twice as fast as Algorithm 1's loop in a hot
+// spot, and waits on those atomics, so its buffer holds 128 children (each atomic
+// then covers twice the writes; 52 bytes of LDS per entry); the plain path's 64
+// entries keep its LDS small at no measurable cost.
 template <class R, bool TB = true>
 struct ChildBuf {
-    double x[64], y[64], z[64];
-    R px[64], py[64], pz[64], w[64];
-    uint64_t parent[64];
-    uint32_t ctr[64];        // the id's counter word (the event's index)
-    double tb[TB ? 64 : 1];  // birth time within the step
+    static constexpr uint32_t kCap = TB ? 64 : 128;
+    double x[kCap], y[kCap], z[kCap];
+    R px[kCap], py[kCap], pz[kCap], w[kCap];
+    uint64_t parent[kCap];
+    uint32_t ctr[kCap];        // the id's counter word (the event's index)
+    double tb[TB ? kCap : 1];  // birth time within the step
     uint32_t count;
 };
 
@@ -400,7 +406,7 @@ __device__ __forceinline__ void stage_emission(const StepArgs &a, const Origin<R
                                                uint32_t &nev, double t0, double st, uint32_t step) {
     const uint32_t c = (uint32_t)__popcll(m);
     __syncwarp();
-    if (cb.count + c > 64) flush_children(cb, a.sp[2], a.seed, step);
+    if (cb.count + c > ChildBuf<R, TB>::kCap) flush_children(cb, a.sp[2], a.seed, step);
     const uint32_t n0 = cb.count;
     if (acc) {
         const uint32_t e = n0 + (uint32_t)__popcll(m & lanemask_lt());
@@ -675,8 +681,10 @@ __device__ __forceinline__ void substep_surr(const Lepton<float> &p, const PushC
 // A lane's own sequence of operations and draws does not depend on when its
 // emission is resolved, so the result is the same for any batch size and any
 // scheduler.  N: this lane's sub-steps (0 for a lane without a particle).  All
-// 64 lanes of the wave call it.
-template <int FK>
+// 64 lanes of the wave call it.  DUAL: network passes of up to 32 rows (two
+// groups sharing their weight reads; the heavy queue, whose register budget has
+// room for them), else 16.
+template <int FK, bool DUAL>
 __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i, uint32_t N,
                                                  const Lepton<float> &p, const SynTable<float> &tab, SurrLds &S,
                                                  ChildBuf<float, false> &cb, Tally<float> &tl) {
@@ -755,7 +763,7 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
             use_net = in_range && !S.mlp.fallback[bin];
         }
         R yv = 0.0f;
-        if (__ballot(use_net)) yv = mlp_infer_wave(S.mlp, ws, use_net, sin, mlp_input_v(pu));
+        if (__ballot(use_net)) yv = mlp_infer_wave<DUAL>(S.mlp, ws, use_net, sin, mlp_input_v(pu));
         R x3 = 0, omx3 = 1;
         if (pend) {
             R x;
@@ -813,7 +821,7 @@ struct LeptonRunner;
 
 template <class R>
 struct LeptonRunner<R, false> {
-    template <class L>
+    template <bool DUAL = false, class L>
     __device__ static void run(const StepArgs &a, int s, u64 i, uint32_t N, const Lepton<R> &p, L &lds,
                                ChildBuf<R> &cb, Tally<R> &t, double t0 = 0.0) {
         if (N) lepton_run<R>(a, s, i, N, p, lds.tab, cb, t, t0);
@@ -822,7 +830,7 @@ struct LeptonRunner<R, false> {
 
 template <>
 struct LeptonRunner<float, true> {
-    template <class L>
+    template <bool DUAL = false, class L>
     __device__ static void run(const StepArgs &a, int s, u64 i, uint32_t n, const Lepton<float> &p, L &lds,
                                ChildBuf<float, false> &cb, Tally<float> &t, double = 0.0) {
         if (__ballot(n != 0) == 0) return;
@@ -831,11 +839,11 @@ struct LeptonRunner<float, true> {
         const bool noE = p.ex == 0.0f && p.ey == 0.0f && p.ez == 0.0f;
         const u64 live = __ballot(n != 0);
         if ((__ballot(n != 0 && noB) == live))
-            lepton_loop_surr<1>(a, s, i, n, p, lds.tab, lds.surr, cb, t);
+            lepton_loop_surr<1, DUAL>(a, s, i, n, p, lds.tab, lds.surr, cb, t);
         else if ((__ballot(n != 0 && noE) == live))
-            lepton_loop_surr<2>(a, s, i, n, p, lds.tab, lds.surr, cb, t);
+            lepton_loop_surr<2, DUAL>(a, s, i, n, p, lds.tab, lds.surr, cb, t);
         else
-            lepton_loop_surr<0>(a, s, i, n, p, lds.tab, lds.surr, cb, t);
+            lepton_loop_surr<0, DUAL>(a, s, i, n, p, lds.tab, lds.surr, cb, t);
     }
 };
 
@@ -1439,9 +1447,12 @@ __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
     flush_tally(t, a.st, s);
 }
 
-// Persistent: each wave claims chunk consecutive queue entries at a time.
+// Persistent: each wave claims chunk consecutive queue entries at a time.  The
+// optical-depth instance's LDS (the network, the rate table, the larger child
+// buffers) fits two blocks per compute unit, so it is compiled for two waves per
+// SIMD and may use the registers that allows.
 template <class R, bool SURR>
-__global__ __launch_bounds__(kBlock, 3) void k_heavy(StepArgs a) {
+__global__ __launch_bounds__(kBlock, SURR ? 2 : 3) void k_heavy(StepArgs a) {
     __shared__ LeptonLds<R, SURR> L;
     auto &cb = lepton_lds_init<R, SURR>(a, L);
     const int s = blockIdx.y;
@@ -1461,7 +1472,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_heavy(StepArgs a) {
             const u64 i = has ? a.queue[s][j] : 0;
             const uint32_t N = has ? a.nsub[s][i] : 0u;
             const Lepton<R> q = has ? load_lepton<R>(a, s, i) : Lepton<R>{0, 0, 0, 0, 0, 0, 0, 0, 0};
-            LeptonRunner<R, SURR>::run(a, s, i, N, q, L, cb, t);
+            LeptonRunner<R, SURR>::template run<SURR>(a, s, i, N, q, L, cb, t);
             t.particles += has;
         }
         u64 nb = 0;

@@ -126,9 +126,10 @@ __device__ __forceinline__ void mlp_stage(const MlpModel *__restrict__ src, MlpL
     __syncthreads();
 }
 
-// Per-wave scratch of the batched evaluation: the rows' inputs and outputs.
+// Per-wave scratch of the batched evaluation: the rows' inputs and outputs (up to
+// two 16-row groups per pass).
 struct MlpWave {
-    float in_s[16], in_v[16], y[16];
+    float in_s[32], in_v[32], y[32];
 };
 
 // Activations of one batch row as B-operand fragments (high parts and residuals).
@@ -159,6 +160,42 @@ __device__ __forceinline__ void mlp_layer(const BFrag &x, const uint4 (*wh)[2][6
     }
 }
 
+// The same products for two 16-row groups of one pass: each weight fragment is read
+// from LDS once for both (the reads, 16 KB per layer and pass, are what a lone group
+// waits on).  Every row goes through the same operations in the same order as in
+// mlp_layer, so its result does not depend on the group it is evaluated in.
+__device__ __forceinline__ void mlp_layer2(const BFrag &x, const BFrag &x2, const uint4 (*wh)[2][64],
+                                           const uint4 (*wl)[2][64], int lane, f32x4 *acc, f32x4 *acc2) {
+    const bf16x8 xh0 = as_bf8(make_uint4(x.h[0][0], x.h[0][1], x.h[0][2], x.h[0][3]));
+    const bf16x8 xh1 = as_bf8(make_uint4(x.h[1][0], x.h[1][1], x.h[1][2], x.h[1][3]));
+    const bf16x8 xl0 = as_bf8(make_uint4(x.l[0][0], x.l[0][1], x.l[0][2], x.l[0][3]));
+    const bf16x8 xl1 = as_bf8(make_uint4(x.l[1][0], x.l[1][1], x.l[1][2], x.l[1][3]));
+    const bf16x8 yh0 = as_bf8(make_uint4(x2.h[0][0], x2.h[0][1], x2.h[0][2], x2.h[0][3]));
+    const bf16x8 yh1 = as_bf8(make_uint4(x2.h[1][0], x2.h[1][1], x2.h[1][2], x2.h[1][3]));
+    const bf16x8 yl0 = as_bf8(make_uint4(x2.l[0][0], x2.l[0][1], x2.l[0][2], x2.l[0][3]));
+    const bf16x8 yl1 = as_bf8(make_uint4(x2.l[1][0], x2.l[1][1], x2.l[1][2], x2.l[1][3]));
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const bf16x8 a0 = as_bf8(wh[n][0][lane]), a1 = as_bf8(wh[n][1][lane]);
+        const bf16x8 c0 = as_bf8(wl[n][0][lane]), c1 = as_bf8(wl[n][1][lane]);
+        f32x4 c = f32x4{0.0f, 0.0f, 0.0f, 0.0f}, d = c;
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, xl0, c, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, yl0, d, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, xl1, c, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, yl1, d, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c0, xh0, c, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c0, yh0, d, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c1, xh1, c, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c1, yh1, d, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, xh0, c, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, yh0, d, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, xh1, c, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, yh1, d, 0, 0, 0);
+        acc[n] = c;
+        acc2[n] = d;
+    }
+}
+
 // a(z + b) of a layer's result, written as the next layer's B fragments.
 __device__ __forceinline__ BFrag mlp_activate(const f32x4 *acc, const float *bias, int g) {
     BFrag x;
@@ -176,19 +213,55 @@ __device__ __forceinline__ BFrag mlp_activate(const f32x4 *acc, const float *bia
     return x;
 }
 
+// Layer 1 (float) of batch row (s, v), straight into the B layout of layer 2.
+__device__ __forceinline__ BFrag mlp_first(const MlpLds &M, float si, float vi, int g) {
+    BFrag x;
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+            const int u0 = unit_of(kk, g, j), u1 = unit_of(kk, g, j + 1);
+            const float h0 = mlp_act(fmaf(M.w1[u0][0], si, fmaf(M.w1[u0][1], vi, M.b1[u0])));
+            const float h1 = mlp_act(fmaf(M.w1[u1][0], si, fmaf(M.w1[u1][1], vi, M.b1[u1])));
+            x.h[kk][j / 2] = pack2(h0, h1);
+            x.l[kk][j / 2] = pack2_lo(h0, h1);
+        }
+    return x;
+}
+
+// Output layer: the row's value summed over the four lane groups (every lane gets it).
+__device__ __forceinline__ float mlp_last(const MlpLds &M, const f32x4 *acc, int g) {
+    float part = 0.0f;
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int u = 16 * n + 4 * g + q;
+            part = fmaf(M.w4[u], mlp_act(acc[n][q] + M.b3[u]), part);
+        }
+    part += __shfl_xor(part, 16);
+    part += __shfl_xor(part, 32);
+    return part + M.b4;
+}
+
 // y for every lane with act set.  Called by the whole wave in uniform control
 // flow (all 64 lanes active); lanes without act get 0.  The active lanes are
-// taken 16 at a time as the columns (batch rows) of one matrix-core pass; each
-// row's result is independent of the other rows.
+// taken 16 at a time as the columns (batch rows) of one matrix-core pass; with
+// DUAL, 32 at a time in two 16-row groups that share their weight reads while
+// more than 16 wait (more registers: for kernels that have them to spare).  Each
+// row's result is independent of the other rows and of its group.
+template <bool DUAL = false>
 __device__ __forceinline__ float mlp_infer_wave(const MlpLds &M, MlpWave &W, bool act, float s, float v) {
     const int lane = __lane_id(), r = lane & 15, g = lane >> 4;
     float out = 0.0f;
     uint64_t m = __ballot(act);
     while (m) {
+        const bool two = DUAL && __popcll(m) > 16;   // uniform across the wave
+        const uint32_t rows = two ? 32u : 16u;
         const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        const bool mine = ((m >> lane) & 1ull) && rank < 16;
+        const bool mine = ((m >> lane) & 1ull) && rank < rows;
         __syncwarp();
-        if (lane < 16) {
+        if (lane < 32) {
             W.in_s[lane] = 0.0f;
             W.in_v[lane] = 0.0f;
         }
@@ -198,35 +271,27 @@ __device__ __forceinline__ float mlp_infer_wave(const MlpLds &M, MlpWave &W, boo
             W.in_v[rank] = v;
         }
         __syncwarp();
-        // layer 1 (float), straight into the B layout of layer 2
-        const float si = W.in_s[r], vi = W.in_v[r];
-        BFrag x;
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-            for (int j = 0; j < 8; j += 2) {
-                const int u0 = unit_of(kk, g, j), u1 = unit_of(kk, g, j + 1);
-                const float h0 = mlp_act(fmaf(M.w1[u0][0], si, fmaf(M.w1[u0][1], vi, M.b1[u0])));
-                const float h1 = mlp_act(fmaf(M.w1[u1][0], si, fmaf(M.w1[u1][1], vi, M.b1[u1])));
-                x.h[kk][j / 2] = pack2(h0, h1);
-                x.l[kk][j / 2] = pack2_lo(h0, h1);
-            }
         f32x4 acc[4];
-        mlp_layer(x, M.wf2, M.wl2, lane, acc);
-        x = mlp_activate(acc, M.b2, g);
-        mlp_layer(x, M.wf3, M.wl3, lane, acc);
-        // output layer: this lane's 16 units, then the sum over the four lane groups
-        float part = 0.0f;
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int u = 16 * n + 4 * g + q;
-                part = fmaf(M.w4[u], mlp_act(acc[n][q] + M.b3[u]), part);
+        BFrag x = mlp_first(M, W.in_s[r], W.in_v[r], g);
+        if (two) {
+            f32x4 acc2[4];
+            BFrag x2 = mlp_first(M, W.in_s[16 + r], W.in_v[16 + r], g);
+            mlp_layer2(x, x2, M.wf2, M.wl2, lane, acc, acc2);
+            x = mlp_activate(acc, M.b2, g);
+            x2 = mlp_activate(acc2, M.b2, g);
+            mlp_layer2(x, x2, M.wf3, M.wl3, lane, acc, acc2);
+            const float y0 = mlp_last(M, acc, g), y1 = mlp_last(M, acc2, g);
+            if (g == 0) {
+                W.y[r] = y0;
+                W.y[16 + r] = y1;
             }
-        part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
-        if (g == 0) W.y[r] = part + M.b4;
+        } else {
+            mlp_layer(x, M.wf2, M.wl2, lane, acc);
+            x = mlp_activate(acc, M.b2, g);
+            mlp_layer(x, M.wf3, M.wl3, lane, acc);
+            const float y0 = mlp_last(M, acc, g);
+            if (g == 0) W.y[r] = y0;
+        }
         __syncwarp();
         if (mine) out = W.y[rank];
         m &= ~__ballot(mine);

@@ -75,25 +75,28 @@ def test_tiled_equals_naive_c2(slots):
     assert list(sa.substeps) == list(sb.substeps) and sa.emissions == sb.emissions
 
 
-@pytest.mark.parametrize("key", ["c3/binned", "c5/binned"])
+@pytest.mark.parametrize("key", ["c3/binned", "c5/binned", "c5r/binned"])
 def test_recorded_tuning_binned_equals_naive(key):
     """The launch shapes and scheduler parameters the autotuner recorded for the hot spot
-    (plain: c3; optical-depth path with the shipped network: c5) give the naive
-    scheduler's results bit for bit on a 2^15-electron hot spot over two steps."""
+    (plain: c3; optical-depth path with the shipped network: c5, with rejection energies:
+    c5r) give the naive scheduler's results bit for bit on a 2^15-electron hot spot over
+    two steps (c5: the heavy queue's two-group network passes against the naive pass's
+    single-group ones)."""
     import json
     import os
     from paper_2008_10468_amd import qed
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     tuning = json.load(open(os.path.join(root, "paper_2008_10468_amd", "tuning_gfx950.json")))[key]["tuning"]
     surr = key.startswith("c5")
-    m = np.load(os.path.join(root, "paper_2008_10468_amd", "models", "sampler_gfx950.npz")) if surr else None
+    net = key.startswith("c5/")
+    m = np.load(os.path.join(root, "paper_2008_10468_amd", "models", "sampler_gfx950.npz")) if net else None
     w = workloads.c3(n=1 << 15, hot_fraction=0.2, seed=12)
     zero = {k: np.zeros(1) for k in ("ex", "ey", "ez", "bx", "by", "bz")}
     res = []
     for sched, tu in ((qed.QED_SCHED_NAIVE, None), (qed.QED_SCHED_BINNED, tuning)):
         g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(1 << 15, 16, 1 << 19), pairs=False,
                           scheduler=sched, sampler=qed.QED_SAMPLER_SURROGATE if surr else qed.QED_SAMPLER_REJECTION)
-        if surr:
+        if net:
             assert qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
                                        float(m["log10_chi_hi"])) == qed.QED_OK
         if tu:
