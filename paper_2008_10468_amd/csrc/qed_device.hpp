@@ -322,4 +322,61 @@ __device__ __forceinline__ void rotate(R &ux, R &uy, R &uz, const Rot<R> &r) {
     uz = mz + (px * r.sy - py * r.sx);
 }
 
+// m sub-steps of the held rotation at once: u <- R^m u and d <- d + vs sum_{j=1..m} R^j u,
+// the result of m calls of rotate() with their moves, in closed form.  R turns u about
+// n = t / |t| by theta, cos theta = (1 - t^2) / (1 + t^2), sin theta = 2 |t| / (1 + t^2): on the
+// plane normal to n it multiplies u_perp + i w (w = u_perp x n) by z = e^{i theta}.  z^m = 1 + e
+// comes from binary powering in that form ((1 + a)(1 + b) = 1 + a + b + ab), in double from the
+// float t, so the turn m theta carries only the rounding of t itself (as m calls of rotate() do);
+// then R^m u = u + Re(e) u_perp + Im(e) w and sum_{j=1..m} z^j = z e / (z - 1) with
+// 1 / (z - 1) = -(1 + i / |t|) / 2 exactly.
+__device__ __forceinline__ void rotate_many(float &ux, float &uy, float &uz, float &dx, float &dy, float &dz,
+                                            const Rot<float> &r, uint32_t m) {
+    const double tx = r.tx, ty = r.ty, tz = r.tz;
+    const double t2 = tx * tx + ty * ty + tz * tz;
+    const float fm = (float)m;
+    if (!(t2 > 1e-60)) {   // no measurable turn: a straight line
+        dx += fm * (ux * r.vs);
+        dy += fm * (uy * r.vs);
+        dz += fm * (uz * r.vs);
+        return;
+    }
+    const double tn = sqrt(t2), it = 1.0 / tn;
+    // z - 1 = h (-t^2 + i |t|), h = 2 / (1 + t^2)
+    const double h = 2.0 / (1.0 + t2);
+    const double cr = -t2 * h, ci = tn * h;
+    double er = 0.0, ei = 0.0, br = cr, bi = ci;
+    for (uint32_t q = m;;) {
+        if (q & 1u) {
+            const double nr = er + br + (er * br - ei * bi);
+            const double ni = ei + bi + (er * bi + ei * br);
+            er = nr;
+            ei = ni;
+        }
+        q >>= 1;
+        if (q == 0u) break;
+        const double nr = br * (br + 2.0) - bi * bi;
+        const double ni = 2.0 * bi * (br + 1.0);
+        br = nr;
+        bi = ni;
+    }
+    // z e, then times -(1 + i / |t|) / 2
+    const double zr = 1.0 + cr, zi = ci;
+    const double ar = zr * er - zi * ei, ai = zr * ei + zi * er;
+    const float sr = (float)(-0.5 * (ar - ai * it)), si = (float)(-0.5 * (ai + ar * it));
+    const float fer = (float)er, fei = (float)ei;
+    const float fit = (float)it;
+    const float nx = r.tx * fit, ny = r.ty * fit, nz = r.tz * fit;
+    const float up = ux * nx + uy * ny + uz * nz;
+    const float px = ux - up * nx, py = uy - up * ny, pz = uz - up * nz;
+    const float wx = py * nz - pz * ny, wy = pz * nx - px * nz, wz = px * ny - py * nx;
+    const float ms = fm * up;
+    dx += r.vs * (ms * nx + sr * px + si * wx);
+    dy += r.vs * (ms * ny + sr * py + si * wy);
+    dz += r.vs * (ms * nz + sr * pz + si * wz);
+    ux += fer * px + fei * wx;
+    uy += fer * py + fei * wy;
+    uz += fer * pz + fei * wz;
+}
+
 }  // namespace qed

@@ -725,10 +725,34 @@ __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i
     // holds the overshoot (<= 0) of the sub-step that crossed.
     for (;;) {
         if (k < N && !pend) {
-            substep_surr<FK>(p, c, wk, S.rate, ux, uy, uz, dx, dy, dz, rs, tau, tl.guard);
-            pend = tau <= 0.0;
-            pk = k;
-            ++k;
+            if constexpr (FK == 2) {
+                // The held rate does not change until the next emission, so the optical
+                // depth falls by the same d every sub-step: go straight to the sub-step
+                // where it crosses zero, or to the end of the step.  One sub-step runs as
+                // the loop body (bit for bit what the pre-pass runs); more run in closed
+                // form (rotate_many), with tau - m d in one rounding.  Every lane that can
+                // move then reaches its crossing at once, and the resolves take them all.
+                const double d = (double)(wk * rs.rw);
+                uint32_t m = N - k;
+                if (d > 0.0) {
+                    const double q = ceil(tau / d);
+                    if (q < (double)m) m = q < 1.0 ? 1u : (uint32_t)q;
+                }
+                if (m == 1u) {
+                    substep_surr<2>(p, c, wk, S.rate, ux, uy, uz, dx, dy, dz, rs, tau, tl.guard);
+                } else {
+                    rotate_many(ux, uy, uz, dx, dy, dz, rs, m);
+                    tau = fma(-(double)m, d, tau);
+                }
+                pend = tau <= 0.0;
+                pk = k + m - 1u;
+                k += m;
+            } else {
+                substep_surr<FK>(p, c, wk, S.rate, ux, uy, uz, dx, dy, dz, rs, tau, tl.guard);
+                pend = tau <= 0.0;
+                pk = k;
+                ++k;
+            }
         }
         const u64 mp = __ballot(pend);
         const u64 mr = __ballot(k < N && !pend);
