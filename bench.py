@@ -56,6 +56,12 @@ FLOPS_SURR_EVENT = 2 * 44 + 25 + 35 + 20
 # the hidden activations: 64 x (bias + 4); output: 64 x (bias + 4 + fma 2) + 2)
 FLOPS_MLP_VALU_PER_EVENT = 64 * 8 + 64 * 5 + 64 * 7 + 2
 FLOPS_PER_PHOTON_SUBSTEP = 62       # move 6, candidate 6, F and G 37, acceptance 13
+# optical-depth path in a pure magnetic field: the sub-steps up to each crossing (and up to
+# the end of the step) are taken in closed form, one advance each: float 57 (axis, the
+# parallel and normal parts, the turned momentum and the summed move) and double about 145
+# (|t|, the turn's complex step, binary powering over about six bits of m at 20 each, the
+# geometric sum, the crossing sub-step tau / d)
+FLOPS_SURR_ADVANCE_PURE_B = 57 + 145
 BYTES_PER_LEPTON_STEP = 80          # read u 12 + id 8 + position 24; write u 12 + position 24
 BYTES_FIELD_PER_PARTICLE = 24       # six float field values, per-particle (stride 1) fields only
 BYTES_TAU = 16                      # optical depth read and written (double)
@@ -226,6 +232,9 @@ def roofline(kt, st, K, workload, field_kind="general", surrogate=False, field_b
         learned = st.learned_events * share
         byts = (rec + BYTES_PER_BINNED_EXTRA) * part + BYTES_PER_EMISSION * em
         flops = f_sub * sub
+        if surrogate and field_kind == "pure_b":
+            # one closed-form advance per crossing and one to the end of the step
+            flops = FLOPS_SURR_ADVANCE_PURE_B * (part + em)
     elif name == "k_light":
         sub, part = lep_sub - st.heavy_substeps, lep_part - st.heavy_particles
         share = sub / max(lep_sub, 1)
