@@ -461,13 +461,17 @@ def cpu_baseline_hotspot(workloads, budget_s, n_sample=1 << 16):
     return out
 
 
-def hotspot_tuning_keys(surrogate, net, sched):
+def hotspot_tuning_keys(surrogate, net, sched, weak=False):
     """Tuning table keys of a hot-spot run: c3 (plain generator), c5 (optical-depth path
     with the network), c5r (optical-depth path with rejection energies; each sampler at
-    the launch shapes and resolve batch tuned for it, c5's if c5r is not recorded)."""
+    the launch shapes and resolve batch tuned for it, c5's if c5r is not recorded); for
+    the weak uniform field w5 and w5r first."""
     if not surrogate:
         return [f"c3/{sched}"]
-    return [f"c5/{sched}"] if net else [f"c5r/{sched}", f"c5/{sched}"]
+    keys = [f"c5/{sched}"] if net else [f"c5r/{sched}", f"c5/{sched}"]
+    if weak:
+        keys = ([f"w5/{sched}"] if net else [f"w5r/{sched}", f"w5/{sched}"]) + keys
+    return keys
 
 
 def bench_hotspot(args, torch, qed, workloads):
@@ -571,6 +575,61 @@ def bench_c2(args, torch, qed, workloads):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(workloads, args.cpu_seconds)
     g.close()
+    return out
+
+
+def bench_weak(args, torch, qed, workloads):
+    """The learned sampler where rejection is expensive: 16.8M electrons in one weak
+    uniform field (chi 1e-3 to 1e-2), the optical-depth path with the shipped network
+    against the same path with rejection energies, the plain generator (binned) beside."""
+    K, W = (args.steps if args.steps_given else 20), args.warmup
+    n = int(args.c3_particles)
+    m = np.load(os.path.join(ROOT, "paper_2008_10468_amd", "models", "sampler_gfx950.npz"))
+    w = workloads.weak(n=n)
+    zero = workloads.uniform_field()
+    cap_ph = int(min(1.0 * n * max(K, W) + (1 << 23), 1 << 31))
+    p_s = args.surrogate_p_max
+    rej, sur = qed.QED_SAMPLER_REJECTION, qed.QED_SAMPLER_SURROGATE
+    stream = torch.cuda.Stream()
+    runs = {}
+    for name, sampler, net in (("plain_binned", rej, False), ("surrogate_rejection_binned", sur, False),
+                               ("surrogate_binned", sur, True)):
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, cap_ph), pairs=False, parent=False,
+                          events=False, scheduler=qed.QED_SCHED_BINNED, stream=stream.cuda_stream, sampler=sampler,
+                          surrogate_p_max=p_s)
+        if net:
+            assert qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
+                                       float(m["log10_chi_hi"])) == qed.QED_OK
+        tuned = load_tuning(qed, g, hotspot_tuning_keys(sampler == sur, net, "binned", weak=True), args.tuning)
+        g.set_fields(None, per_species=[w["fields"], zero, zero])
+        fl = [f.struct() for f in g.fields]
+        fields = lambda s: (qed.qed_field * 3)(*fl)
+        log(f"bench: weak field, {name}, {n} e-, steps={K}, warmup={W}, tuning={tuned}")
+        ms, stats, stats_p, kt, graphed = stepped(torch, qed, g, stream, fields, w, w["dt"], w["seed"], K, W,
+                                                  not args.no_graph)
+        runs[name] = {"ms_per_step": ms / K, "substeps_per_step": sum(stats.substeps) / K,
+                      "emissions_per_step": stats.emissions / K, "events_per_s": stats.emissions / (ms * 1e-3),
+                      "learned_events": stats.learned_events, "fallback_events": stats.fallback_events,
+                      "fallback_draws": stats.fallback_draws, "tuning": tuned,
+                      "kernel_us": {k: v[1] * 1e3 / max(v[0], 1) for k, v in kt.items()}}
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    best = runs["surrogate_binned"]
+    value = runs["plain_binned"]["substeps_per_step"] / (best["ms_per_step"] * 1e-3)
+    out = header(args, value, best["ms_per_step"] * K, K, W, "f32+bf16", {
+        "workload": f"weak field: {n} electrons, gamma log-uniform [1e3, 1e4], isotropic, uniform B = 1e-6 E_S "
+                    f"(chi 1e-3 to 1e-2), emission only, mixed precision; optical-depth path with the learned "
+                    f"sampler (sub-step target {p_s}), binned scheduler",
+        "value_counts": "the particle-sub-steps Algorithm 1 takes for this population at P_max = 0.01 per "
+                        "second of the optical-depth path's step time",
+        "steps": K, "dt_hbar_over_mc2": w["dt"], "seed": w["seed"], "scheduler": "binned"})
+    out["runs"] = runs
+    speed = lambda a, b: runs[b]["ms_per_step"] / runs[a]["ms_per_step"]
+    out["network_gain_vs_rejection"] = speed("surrogate_binned", "surrogate_rejection_binned")
+    out["step_speedup_vs_plain_binned"] = speed("surrogate_binned", "plain_binned")
+    rj = runs["surrogate_rejection_binned"]
+    out["rejection_draws_per_energy"] = rj["fallback_draws"] / max(rj["fallback_events"], 1)
     return out
 
 
@@ -913,7 +972,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=("hotspot", "c2", "c1", "c3", "c4", "c5", "c2s", "shower", "grid"),
+    ap.add_argument("--workload", choices=("hotspot", "c2", "c1", "c3", "c4", "c5", "c2s", "shower", "grid", "weak"),
                     default="hotspot")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -944,6 +1003,7 @@ def main():
 
     torch.cuda.set_device(0)
     fn = {"hotspot": bench_hotspot, "c2": bench_c2, "c1": bench_c1, "c3": bench_c3, "c4": bench_c4, "c5": bench_c5,
+          "weak": bench_weak,
           "c2s": bench_c2s, "shower": bench_shower, "grid": bench_grid}[args.workload]
     out = fn(args, torch, qed, workloads)
     if args.copy_probe:

@@ -47,13 +47,14 @@ SPACE = {
     "bins_per_octave": (4, 8, 16, 32),
     "light_tile": (128, 256, 512),
     "tiled_slots": (64, 128, 256),
+    "heavy_refill": (0, 1),
 }
 NAIVE_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu")
 MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "sampler_gfx950.npz")
 BINNED_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu", "heavy_blocks_per_cu", "light_max", "chunk",
                "prepass_blocks_per_cu", "prepass_finish", "scatter_blocks_per_cu", "bins_per_octave", "light_tile")
 TILED_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu", "tiled_slots")
-SURROGATE_KEYS = ("resolve_batch",)   # added for workloads on the lepton optical-depth path
+SURROGATE_KEYS = ("resolve_batch", "heavy_refill")   # added for workloads on the lepton optical-depth path
 
 
 def _settings(g):
@@ -190,16 +191,17 @@ def _workload(name, torch, workloads, sched, stream, steps):
         g.set_fields(None, per_species=[w["fields"], zero, zero])
         fl = [f.struct() for f in g.fields]
         return g, w, lambda s: (qed.qed_field * 3)(*fl)
-    if name in ("c5", "c5r"):
-        # the hot-spot workload on the surrogate path, with the network shipped for gfx950
-        # (c5) or with rejection energies (c5r)
+    if name in ("c5", "c5r", "w5", "w5r"):
+        # the hot-spot workload (c5) or the weak uniform field (w5) on the surrogate path,
+        # with the network shipped for gfx950 or with rejection energies (c5r, w5r)
         import numpy as np
-        w = workloads.c3()
+        w = workloads.c3() if name.startswith("c") else workloads.weak()
         n = w["electrons"]["id"].size
-        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, int(0.65 * n * steps) + (1 << 23)),
+        per = 0.65 if name.startswith("c") else 1.0   # photons per electron and step, about
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, int(per * n * steps) + (1 << 23)),
                           pairs=False, parent=False, events=False, scheduler=sched,
                           stream=stream.cuda_stream, sampler=qed.QED_SAMPLER_SURROGATE)
-        if name == "c5":
+        if name in ("c5", "w5"):
             m = np.load(MODEL)
             st = qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
                                      float(m["log10_chi_hi"]))
@@ -214,7 +216,7 @@ def _workload(name, torch, workloads, sched, stream, steps):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Tune launch shapes of the QED generator on this GPU")
-    ap.add_argument("--workload", choices=("c2", "c2s", "c3", "c5", "c5r"), action="append")
+    ap.add_argument("--workload", choices=("c2", "c2s", "c3", "c5", "c5r", "w5", "w5r"), action="append")
     ap.add_argument("--scheduler", choices=("naive", "binned", "tiled"), action="append")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--passes", type=int, default=2)
@@ -234,7 +236,7 @@ def main(argv=None):
             stream = torch.cuda.Stream()
             g, w, fields = _workload(wl, torch, workloads, sched, stream, args.steps)
             keys = {"binned": BINNED_KEYS, "tiled": TILED_KEYS}.get(sn, NAIVE_KEYS)
-            if wl in ("c2s", "c5", "c5r"):
+            if wl in ("c2s", "c5", "c5r", "w5", "w5r"):
                 keys = keys + SURROGATE_KEYS
             best, ms, ms0, hist = tune(torch, g, stream, w, fields, w["dt"], w["seed"], args.steps, keys,
                                        passes=args.passes, log=lambda *a: print(*a, flush=True))

@@ -190,3 +190,56 @@ def test_tuning_validation():
         setattr(t, field, good)
         assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
     g.close()
+
+
+@pytest.mark.parametrize("pop", ["hot", "weak"])
+@pytest.mark.parametrize("batch", [1, 24, 64])
+def test_refilled_heavy_queue_equals_naive(pop, batch):
+    """heavy_refill: in a pure magnetic field the optical-depth heavy queue hands the
+    next queue entry to each lane whose lepton has finished (refilling after `batch`
+    lanes are idle); every lepton, its photons and the counters are the naive
+    scheduler's bit for bit, with the shipped network (hot spot, 2^15 electrons, 20%
+    hot; and the weak uniform field, where most leptons emit once or not at all)."""
+    import os
+    from paper_2008_10468_amd import qed
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    m = np.load(os.path.join(root, "paper_2008_10468_amd", "models", "sampler_gfx950.npz"))
+    n = 1 << 15
+    w = workloads.c3(n=n, hot_fraction=0.2, seed=12) if pop == "hot" else workloads.weak(n=n, seed=13)
+    zero = {k: np.zeros(1) for k in ("ex", "ey", "ez", "bx", "by", "bz")}
+    tuning = {"light_max": 0, "heavy_refill": 1, "resolve_batch": batch, "chunk": 256}
+    res = []
+    for sched, tu in ((qed.QED_SCHED_NAIVE, None), (qed.QED_SCHED_BINNED, tuning)):
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, 1 << 19), pairs=False, scheduler=sched,
+                          sampler=qed.QED_SAMPLER_SURROGATE)
+        assert qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
+                                   float(m["log10_chi_hi"])) == qed.QED_OK
+        if tu:
+            t = qed.qed_get_tuning(g.ctx)
+            for k, v in tu.items():
+                setattr(t, k, int(v))
+            assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
+        g.load_state(w)
+        g.set_fields(None, per_species=[w["fields"], zero, zero])
+        for step in range(2):
+            g.step(w["dt"], 7, step)
+            assert g.sync()[0] == qed.QED_OK
+        res.append(([_sorted(g.sp[k].download()) for k in (0, 2)], g.stats()))
+        g.close()
+    (a, sa), (b, sb) = res
+    for s in range(2):
+        for k in a[s]:
+            assert np.array_equal(a[s][k], b[s][k]), (pop, batch, s, k)
+    assert list(sa.substeps) == list(sb.substeps) and sa.emissions == sb.emissions and sa.emissions > 1000
+    assert list(sa.particles) == list(sb.particles)
+    assert sb.heavy_particles > 0
+
+
+def test_refill_is_validated():
+    from paper_2008_10468_amd import qed
+    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(16, 16, 16))
+    t = qed.qed_get_tuning(g.ctx)
+    assert t.heavy_refill == 0
+    t.heavy_refill = 2
+    assert qed.qed_set_tuning(g.ctx, t) == qed.QED_ERR_INVALID_ARG
+    g.close()

@@ -162,6 +162,24 @@ def c3(n=16777216, seed=3, hot_fraction=0.1, shuffle=True):
             "hot": hot, "dt": DT_C3, "steps": 50, "seed": 1, "p_max": P_MAX}
 
 
+DT_WEAK = 1.0e8        # weak uniform field: about 0.8 emissions per electron and step
+B_WEAK = 1.0e-6
+
+
+def weak(n=16777216, seed=8):
+    """Every electron in one weak uniform field (chi 1e-3 to 1e-2, about 90 sub-steps of
+    Algorithm 1 at P_max = 0.01): the emission spectrum is concentrated at small x, where
+    the rejection sampler's flat envelope accepts one candidate in five to ten."""
+    rng = np.random.default_rng(seed)
+    e = _species(n, 0, rng)
+    gamma = 10.0 ** rng.uniform(3.0, 4.0, n)
+    u = np.sqrt(gamma * gamma - 1.0)
+    dx, dy, dz = _isotropic(rng, n)
+    e["ux"], e["uy"], e["uz"] = u * dx, u * dy, u * dz
+    return {"electrons": e, "positrons": _empty(), "photons": _empty(), "fields": uniform_field(bz=B_WEAK),
+            "dt": DT_WEAK, "steps": 20, "seed": 1, "p_max": P_MAX}
+
+
 def c4_host(n, seed=4):
     """log-uniform x in [1e-4, 50] (host, float64)."""
     rng = np.random.default_rng(seed)
