@@ -310,12 +310,6 @@ typedef struct qed_tuning {
                                       is at least this (0: always; 0xffffffff: never, every
                                       call adds per wave of 64 particles); results agree up to
                                       the order of the additions */
-    uint32_t heavy_refill;         /* binned scheduler, optical-depth path, 0 or 1: in a pure
-                                      magnetic field a heavy-queue lane whose lepton has
-                                      finished its step takes the next queue entry (lanes are
-                                      refilled together once resolve_batch of them are idle),
-                                      so resolves keep their lanes busy when leptons emit few
-                                      times each (results do not depend on it) */
 } qed_tuning;
 
 /* Read / replace the context's launch shape; INVALID_ARG if a field is out of range. */

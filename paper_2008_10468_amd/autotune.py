@@ -47,14 +47,13 @@ SPACE = {
     "bins_per_octave": (4, 8, 16, 32),
     "light_tile": (128, 256, 512),
     "tiled_slots": (64, 128, 256),
-    "heavy_refill": (0, 1),
 }
 NAIVE_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu")
 MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "sampler_gfx950.npz")
 BINNED_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu", "heavy_blocks_per_cu", "light_max", "chunk",
                "prepass_blocks_per_cu", "prepass_finish", "scatter_blocks_per_cu", "bins_per_octave", "light_tile")
 TILED_KEYS = ("lepton_blocks_per_cu", "photon_blocks_per_cu", "tiled_slots")
-SURROGATE_KEYS = ("resolve_batch", "heavy_refill")   # added for workloads on the lepton optical-depth path
+SURROGATE_KEYS = ("resolve_batch",)   # added for workloads on the lepton optical-depth path
 
 
 def _settings(g):

@@ -279,8 +279,7 @@ bool tuning_ok(const qed_tuning &t) {
            t.prepass_blocks_per_cu >= 1 && t.prepass_blocks_per_cu <= 1024 && t.scatter_blocks_per_cu >= 1 &&
            t.scatter_blocks_per_cu <= 1024 && t.bins_per_octave >= 4 &&
            t.bins_per_octave <= (uint32_t)qed::kMaxBinsPerOctave && t.light_tile >= 64 && t.light_tile <= 512 &&
-           t.light_tile % 64 == 0 && t.tiled_slots >= 64 && t.tiled_slots <= 256 && t.tiled_slots % 64 == 0 &&
-           t.heavy_refill <= 1;
+           t.light_tile % 64 == 0 && t.tiled_slots >= 64 && t.tiled_slots <= 256 && t.tiled_slots % 64 == 0;
 }
 
 const char *kKernelName[qed::K_COUNT] = {"k_begin", "k_photon", "k_lepton", "k_prepass",
@@ -478,7 +477,6 @@ qed_status step_impl(qed_ctx *c, qed_particles *p, const qed_field fields[3], do
     a.bins_per_octave = c->tune.bins_per_octave;
     a.light_tile = c->tune.light_tile;
     a.tiled_slots = c->tune.tiled_slots;
-    a.heavy_refill = c->tune.heavy_refill;
     a.alive = x.alive;
     a.dead_idx = x.dead_idx;
     a.hole_idx = x.hole_idx;
@@ -652,7 +650,6 @@ qed_status qed_init(qed_ctx **out, const qed_config *cfg) {
     c->tune.light_tile = 512;
     c->tune.tiled_slots = 256;
     c->tune.deposit_sort_min = 1u << 14;
-    c->tune.heavy_refill = 0;
     if (hipMalloc(&c->st, sizeof(qed::DevState)) != hipSuccess ||
         hipMemset(c->st, 0, sizeof(qed::DevState)) != hipSuccess ||
         hipMalloc(&c->model, sizeof(qed::MlpModel)) != hipSuccess ||

@@ -106,7 +106,6 @@ struct StepArgs {
     uint32_t bins_per_octave; // binned: sub-step-count bins per octave (4..kMaxBinsPerOctave)
     uint32_t light_tile;     // binned: slots per wave tile of the light pass (64..512, a multiple of 64)
     uint32_t tiled_slots;    // tiled: slots per wave tile (64..256, a multiple of 64)
-    uint32_t heavy_refill;   // binned, optical-depth path: refill finished heavy-queue lanes
     uint8_t *alive;        // photon flags, one per slot: 0 decayed, 1 alive
     u64 *dead_idx;         // slots of the photons that decayed this step
     u64 *hole_idx;         // compaction lists

@@ -680,266 +680,162 @@ __device__ __forceinline__ void substep_surr(const Lepton<float> &p, const PushC
 // with the waiting lanes together instead of stalling the wave at every crossing.
 // A lane's own sequence of operations and draws does not depend on when its
 // emission is resolved, so the result is the same for any batch size and any
-// scheduler.
-//
-// The state of one lane's lepton on this path (N = 0: no particle).  A waiting lane
-// keeps its momentum at the crossing, so chi, gamma and the rate there are
-// recomputed when the emission is resolved instead of held; tau then holds the
-// overshoot (<= 0) of the sub-step that crossed.
-struct SurrLane {
-    Lepton<float> p;
-    Origin<float> org;
-    PushConst<float> c;
-    Rot<float> rs;
-    double st, tau;
-    u64 i;
-    uint64_t pid;
-    float wk, ux, uy, uz, dx, dy, dz;
-    uint32_t N, k, pk, j, nev;   // sub-steps, next sub-step, the waiting one, draws, events
-    bool pend;                   // an emission waits for its energy
-};
-
-// Take up lepton i of species s with N >= 1 sub-steps (N = 0: an empty lane).
-template <int FK>
-__device__ __forceinline__ void surr_begin(const StepArgs &a, int s, u64 i, uint32_t N, const Lepton<float> &p,
-                                           const SurrLds &S, SurrLane &L) {
-    const SpeciesDev &sp = a.sp[s];
-    const bool has = N > 0;
-    L.p = p;
-    L.i = i;
-    L.N = N;
-    L.pid = has ? sp.id[i] : 0ull;
-    L.org = has ? origin_of<float>(sp, i) : Origin<float>{0.0, 0.0, 0.0, 0.0f};
-    L.st = has ? a.dt / (double)N : 0.0;
-    L.c = push_const(p, s, L.st);
-    // W sub_t = alpha sub_t chi q(chi) / gamma
-    L.wk = (float)(kAlpha * L.st);
-    L.j = 0;
-    L.tau = has ? sp.tau[i] : 1.0;
-    if (has && !(L.tau > 0.0)) {
-        const u32x4 w = philox10((uint32_t)L.pid, (uint32_t)(L.pid >> 32), step_of(a), L.j++,
-                                 (uint32_t)a.seed ^ kSurrTagLo, (uint32_t)(a.seed >> 32) ^ kSurrTagHi);
-        L.tau = neg_ln(u53(w.x, w.y));
-    }
-    L.ux = p.ux;
-    L.uy = p.uy;
-    L.uz = p.uz;
-    L.dx = L.dy = L.dz = 0.0f;
-    L.rs = Rot<float>{};
-    if constexpr (FK == 2) {
-        L.rs = rot_chi(p, L.c, L.ux, L.uy, L.uz);
-        L.rs.rw = rate_chi_q(L.rs.chi, S.rate) * L.rs.ig;
-    }
-    L.nev = 0;
-    L.k = 0;
-    L.pk = 0;
-    L.pend = false;
-}
-
-// Advance a lane that can move (k < N, nothing waiting) to its next crossing.
-template <int FK>
-__device__ __forceinline__ void surr_advance(SurrLane &L, const RateTable &rate, Tally<float> &tl) {
-    if constexpr (FK == 2) {
-        // The held rate does not change until the next emission, so the optical
-        // depth falls by the same d every sub-step: go straight to the sub-step
-        // where it crosses zero, or to the end of the step.  One sub-step runs as
-        // the loop body (bit for bit what the pre-pass runs); more run in closed
-        // form (rotate_many), with tau - m d in one rounding.  Every lane that can
-        // move then reaches its crossing at once, and the resolves take them all.
-        const double d = (double)(L.wk * L.rs.rw);
-        uint32_t m = L.N - L.k;
-        if (d > 0.0) {
-            const double q = ceil(L.tau / d);
-            if (q < (double)m) m = q < 1.0 ? 1u : (uint32_t)q;
-        }
-        if (m == 1u) {
-            substep_surr<2>(L.p, L.c, L.wk, rate, L.ux, L.uy, L.uz, L.dx, L.dy, L.dz, L.rs, L.tau, tl.guard);
-        } else {
-            rotate_many(L.ux, L.uy, L.uz, L.dx, L.dy, L.dz, L.rs, m);
-            L.tau = fma(-(double)m, d, L.tau);
-        }
-        L.pend = L.tau <= 0.0;
-        L.pk = L.k + m - 1u;
-        L.k += m;
-    } else {
-        substep_surr<FK>(L.p, L.c, L.wk, rate, L.ux, L.uy, L.uz, L.dx, L.dy, L.dz, L.rs, L.tau, tl.guard);
-        L.pend = L.tau <= 0.0;
-        L.pk = L.k;
-        ++L.k;
-    }
-}
-
-// Resolve the emissions of the waiting lanes (mp: their ballot).  All 64 lanes of
-// the wave call it.
-template <int FK, bool DUAL>
-__device__ __forceinline__ void surr_resolve(const StepArgs &a, u64 mp, const SynTable<float> &tab, SurrLds &S,
-                                             ChildBuf<float, false> &cb, SurrLane &L, Tally<float> &tl) {
-    using R = float;
-    const uint32_t klo = (uint32_t)a.seed ^ kSurrTagLo, khi = (uint32_t)(a.seed >> 32) ^ kSurrTagHi;
-    const uint32_t step = step_of(a);
-    const uint32_t idlo = (uint32_t)L.pid, idhi = (uint32_t)(L.pid >> 32);
-    const Lepton<R> &p = L.p;
-    // The waiting lanes: the uniform of the energy and the next optical depth,
-    // then their state at the crossing.
-    R pu = 0.5f, cu2 = 0, cg = 1, cchi = 0, crw = 1;
-    double ptau = 1.0;
-    if (L.pend) {
-        const u32x4 w = philox10(idlo, idhi, step, L.j++, klo, khi);
-        pu = u24(w.x);
-        ptau = neg_ln(u53(w.z, w.w));
-        cu2 = L.ux * L.ux + L.uy * L.uy + L.uz * L.uz;
-        if constexpr (FK == 2) {   // the held state is the state at the crossing
-            cg = L.rs.g;
-            cchi = L.rs.chi;
-            crw = L.rs.rw;
-        } else {
-            const R ig = rsqrt_(R(1) + cu2);
-            cg = (R(1) + cu2) * ig;
-            cchi = chi_sub<FK>(L.ux, L.uy, L.uz, cg, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, L.c.e2, tl.guard);
-            crw = rate_chi_q(cchi, S.rate) * ig;
-        }
-    }
-    bool use_net = false;
-    R sin = 0.0f;
-    if (L.pend && S.have_model) {
-        bool in_range;
-        int bin;
-        sin = mlp_input_s(S.mlp, cchi, in_range, bin);
-        use_net = in_range && !S.mlp.fallback[bin];
-    }
-    R yv = 0.0f;
-    if (__ballot(use_net)) yv = mlp_infer_wave<DUAL>(S.mlp, S.ws[threadIdx.x / 64], use_net, sin, mlp_input_v(pu));
-    R x3 = 0, omx3 = 1;
-    if (L.pend) {
-        R x;
-        if (use_net) {
-            x = mlp_x_of_y(yv, cchi);
-            tl.learned++;
-        } else {
-            x = surr_reject(cchi, S, tab, idlo, idhi, step, klo, khi, L.j, tl);
-            tl.fallback++;
-        }
-        const R x2 = x * x;
-        x3 = x2 * x;
-        omx3 = (R(1) - x) * (R(1) + x + x2);
-    }
-    stage_emission<R>(a, L.org, L.pid, L.nev, L.pk, L.pend, mp, x3, omx3, cg, cu2, L.dx, L.dy, L.dz, L.ux, L.uy,
-                      L.uz, cb, L.nev, 0.0, L.st, step);
-    // The part of the sub-step after the crossing (the overshoot, at the rate before
-    // the emission) counts against the new optical depth at the rate after the
-    // recoil.  If that crosses it again, the lane waits for another emission
-    // before moving on.
-    if (L.pend) {
-        R rw;
-        if constexpr (FK == 2) {   // the held state after the recoil
-            L.rs = rot_chi(p, L.c, L.ux, L.uy, L.uz);
-            L.rs.rw = rate_chi_q(L.rs.chi, S.rate) * L.rs.ig;
-            rw = L.rs.rw;
-        } else {
-            R u2;
-            const R ig = inv_gamma(L.ux, L.uy, L.uz, u2);
-            const R g = (R(1) + u2) * ig;
-            const R chi = chi_sub<FK>(L.ux, L.uy, L.uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, L.c.e2, tl.guard);
-            rw = rate_chi_q(chi, S.rate) * ig;
-        }
-        L.tau = ptau + L.tau * (double)(rw / crw);
-        L.pend = L.tau <= 0.0;
-    }
-}
-
-// Store a lane's lepton at the end of its step.
-__device__ __forceinline__ void surr_end(const StepArgs &a, int s, const SurrLane &L, Tally<float> &tl) {
-    const SpeciesDev &sp = a.sp[s];
-    const u64 i = L.i;
-    ((float *)sp.ux)[i] = L.ux;
-    ((float *)sp.uy)[i] = L.uy;
-    ((float *)sp.uz)[i] = L.uz;
-    sp.x[i] = L.org.x + (double)L.dx;
-    sp.y[i] = L.org.y + (double)L.dy;
-    sp.z[i] = L.org.z + (double)L.dz;
-    sp.tau[i] = L.tau;
-    if (sp.events) sp.events[i] = L.nev;
-    tl.substeps += L.N;
-    tl.events += L.nev;
-}
-
-// The optical-depth path for one lepton per lane (N: this lane's sub-steps, 0 for a
-// lane without a particle).  All 64 lanes of the wave call it.  DUAL: network passes
-// of up to 32 rows (two groups sharing their weight reads; the heavy queue, whose
-// register budget has room for them), else 16.
+// scheduler.  N: this lane's sub-steps (0 for a lane without a particle).  All
+// 64 lanes of the wave call it.  DUAL: network passes of up to 32 rows (two
+// groups sharing their weight reads; the heavy queue, whose register budget has
+// room for them), else 16.
 template <int FK, bool DUAL>
 __device__ __forceinline__ void lepton_loop_surr(const StepArgs &a, int s, u64 i, uint32_t N,
                                                  const Lepton<float> &p, const SynTable<float> &tab, SurrLds &S,
                                                  ChildBuf<float, false> &cb, Tally<float> &tl) {
-    SurrLane L;
-    surr_begin<FK>(a, s, i, N, p, S, L);
+    using R = float;
+    const SpeciesDev &sp = a.sp[s];
+    const bool has = N > 0;
+    const uint64_t pid = has ? sp.id[i] : 0ull;
+    const Origin<R> org = has ? origin_of<R>(sp, i) : Origin<R>{0.0, 0.0, 0.0, R(0)};
+    const double st = has ? a.dt / (double)N : 0.0;
+    const PushConst<R> c = push_const(p, s, st);
+    const R e2 = c.e2;
+    // W sub_t = alpha sub_t chi q(chi) / gamma
+    const R wk = (R)(kAlpha * st);
+    const uint32_t idlo = (uint32_t)pid, idhi = (uint32_t)(pid >> 32);
+    const uint32_t klo = (uint32_t)a.seed ^ kSurrTagLo, khi = (uint32_t)(a.seed >> 32) ^ kSurrTagHi;
+    const uint32_t step = step_of(a);
     const int batch = (int)a.resolve_batch;
+    MlpWave &ws = S.ws[threadIdx.x / 64];
+    uint32_t j = 0;
+    double tau = has ? sp.tau[i] : 1.0;
+    if (has && !(tau > 0.0)) {
+        const u32x4 w = philox10(idlo, idhi, step, j++, klo, khi);
+        tau = neg_ln(u53(w.x, w.y));
+    }
+    R ux = p.ux, uy = p.uy, uz = p.uz;
+    R dx = 0, dy = 0, dz = 0;
+    Rot<R> rs{};
+    if constexpr (FK == 2) {
+        rs = rot_chi(p, c, ux, uy, uz);
+        rs.rw = rate_chi_q(rs.chi, S.rate) * rs.ig;
+    }
+    uint32_t nev = 0;
+    uint32_t k = 0;     // next sub-step of this lane
+    bool pend = false;  // an emission waits for its energy
+    uint32_t pk = 0;    // its sub-step
+    // A waiting lane keeps its momentum at the crossing, so chi, gamma and the rate
+    // there are recomputed when the emission is resolved instead of held; tau then
+    // holds the overshoot (<= 0) of the sub-step that crossed.
     for (;;) {
-        if (L.k < L.N && !L.pend) surr_advance<FK>(L, S.rate, tl);
-        const u64 mp = __ballot(L.pend);
-        const u64 mr = __ballot(L.k < L.N && !L.pend);
+        if (k < N && !pend) {
+            if constexpr (FK == 2) {
+                // The held rate does not change until the next emission, so the optical
+                // depth falls by the same d every sub-step: go straight to the sub-step
+                // where it crosses zero, or to the end of the step.  One sub-step runs as
+                // the loop body (bit for bit what the pre-pass runs); more run in closed
+                // form (rotate_many), with tau - m d in one rounding.  Every lane that can
+                // move then reaches its crossing at once, and the resolves take them all.
+                const double d = (double)(wk * rs.rw);
+                uint32_t m = N - k;
+                if (d > 0.0) {
+                    const double q = ceil(tau / d);
+                    if (q < (double)m) m = q < 1.0 ? 1u : (uint32_t)q;
+                }
+                if (m == 1u) {
+                    substep_surr<2>(p, c, wk, S.rate, ux, uy, uz, dx, dy, dz, rs, tau, tl.guard);
+                } else {
+                    rotate_many(ux, uy, uz, dx, dy, dz, rs, m);
+                    tau = fma(-(double)m, d, tau);
+                }
+                pend = tau <= 0.0;
+                pk = k + m - 1u;
+                k += m;
+            } else {
+                substep_surr<FK>(p, c, wk, S.rate, ux, uy, uz, dx, dy, dz, rs, tau, tl.guard);
+                pend = tau <= 0.0;
+                pk = k;
+                ++k;
+            }
+        }
+        const u64 mp = __ballot(pend);
+        const u64 mr = __ballot(k < N && !pend);
         if (mp == 0 && mr == 0) break;
         if (mp == 0 || (__popcll(mp) < batch && mr != 0)) continue;
-        surr_resolve<FK, DUAL>(a, mp, tab, S, cb, L, tl);
-    }
-    if (N) surr_end(a, s, L, tl);
-}
-
-// True if no lepton among heavy-queue entries base..end of species s has an electric
-// field and at least one has a magnetic field: the field kind (pure B) the sub-step
-// loops choose for a wave of such particles.
-__device__ __forceinline__ bool queue_pure_b(const StepArgs &a, int s, u64 base, u64 end) {
-    const FieldDev &fl = a.fl[s];
-    bool e = false, b = false;
-    for (u64 q = base + __lane_id(); q < end; q += 64) {
-        const u64 f = (u64)a.queue[s][q] * fl.stride;
-        e = e || ((const float *)fl.ex)[f] != 0.0f || ((const float *)fl.ey)[f] != 0.0f ||
-            ((const float *)fl.ez)[f] != 0.0f;
-        b = b || ((const float *)fl.bx)[f] != 0.0f || ((const float *)fl.by)[f] != 0.0f ||
-            ((const float *)fl.bz)[f] != 0.0f;
-    }
-    return __ballot(e) == 0 && __ballot(b) != 0;
-}
-
-// Heavy-queue entries base..end in a pure magnetic field (queue_pure_b) on the
-// optical-depth path, with lanes refilled: a lane whose lepton has finished its
-// step stores it, and once a.resolve_batch lanes are idle (or none is busy) they take
-// the next entries together (each refill waits on the new leptons' loads, so it pays
-// to take several).  Resolves then run with most of the wave's lanes, not with the
-// fewer that a fixed set of 64 leptons has left, which matters when the leptons emit
-// a few times each.  Each lepton runs exactly as in lepton_loop_surr<2> (its result
-// does not depend on the lanes it shares a resolve with).  All 64 lanes call it.
-template <bool DUAL>
-__device__ __forceinline__ void lepton_queue_surr_b(const StepArgs &a, int s, u64 base, u64 end,
-                                                    const SynTable<float> &tab, SurrLds &S,
-                                                    ChildBuf<float, false> &cb, Tally<float> &tl) {
-    SurrLane L;
-    surr_begin<2>(a, s, 0, 0u, Lepton<float>{0, 0, 0, 0, 0, 0, 0, 0, 0}, S, L);   // an empty lane
-    u64 cur = base;   // the next entry to hand out (uniform across the wave)
-    const int batch = (int)a.resolve_batch;
-    for (;;) {
-        if (L.N != 0 && L.k >= L.N && !L.pend) {
-            surr_end(a, s, L, tl);
-            tl.particles++;
-            L.N = 0;
-        }
-        const bool idle = L.N == 0;
-        const u64 mi = __ballot(idle);
-        if (mi != 0 && cur < end && (__popcll(mi) >= batch || mi == ~0ull)) {
-            const u64 q = cur + (u64)__popcll(mi & lanemask_lt());
-            if (idle) {
-                const bool has = q < end;
-                const u64 i = has ? (u64)a.queue[s][q] : 0ull;
-                const uint32_t N = has ? a.nsub[s][i] : 0u;
-                const Lepton<float> p = has ? load_lepton<float>(a, s, i) : Lepton<float>{0, 0, 0, 0, 0, 0, 0, 0, 0};
-                surr_begin<2>(a, s, i, N, p, S, L);
+        // The waiting lanes: the uniform of the energy and the next optical depth,
+        // then their state at the crossing.
+        R pu = 0.5f, cu2 = 0, cg = 1, cchi = 0, crw = 1;
+        double ptau = 1.0;
+        if (pend) {
+            const u32x4 w = philox10(idlo, idhi, step, j++, klo, khi);
+            pu = u24(w.x);
+            ptau = neg_ln(u53(w.z, w.w));
+            cu2 = ux * ux + uy * uy + uz * uz;
+            if constexpr (FK == 2) {   // the held state is the state at the crossing
+                cg = rs.g;
+                cchi = rs.chi;
+                crw = rs.rw;
+            } else {
+                const R ig = rsqrt_(R(1) + cu2);
+                cg = (R(1) + cu2) * ig;
+                cchi = chi_sub<FK>(ux, uy, uz, cg, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
+                crw = rate_chi_q(cchi, S.rate) * ig;
             }
-            cur += (u64)__popcll(mi);
         }
-        if (__ballot(L.N != 0) == 0) break;
-        if (L.k < L.N && !L.pend) surr_advance<2>(L, S.rate, tl);
-        const u64 mp = __ballot(L.pend);
-        if (mp) surr_resolve<2, DUAL>(a, mp, tab, S, cb, L, tl);
+        bool use_net = false;
+        R sin = 0.0f;
+        if (pend && S.have_model) {
+            bool in_range;
+            int bin;
+            sin = mlp_input_s(S.mlp, cchi, in_range, bin);
+            use_net = in_range && !S.mlp.fallback[bin];
+        }
+        R yv = 0.0f;
+        if (__ballot(use_net)) yv = mlp_infer_wave<DUAL>(S.mlp, ws, use_net, sin, mlp_input_v(pu));
+        R x3 = 0, omx3 = 1;
+        if (pend) {
+            R x;
+            if (use_net) {
+                x = mlp_x_of_y(yv, cchi);
+                tl.learned++;
+            } else {
+                x = surr_reject(cchi, S, tab, idlo, idhi, step, klo, khi, j, tl);
+                tl.fallback++;
+            }
+            const R x2 = x * x;
+            x3 = x2 * x;
+            omx3 = (R(1) - x) * (R(1) + x + x2);
+        }
+        stage_emission<R>(a, org, pid, nev, pk, pend, mp, x3, omx3, cg, cu2, dx, dy, dz, ux, uy, uz, cb, nev,
+                          0.0, st, step);
+        // The part of the sub-step after the crossing (the overshoot, at the rate before
+        // the emission) counts against the new optical depth at the rate after the
+        // recoil.  If that crosses it again, the lane waits for another emission
+        // before moving on.
+        if (pend) {
+            R rw;
+            if constexpr (FK == 2) {   // the held state after the recoil
+                rs = rot_chi(p, c, ux, uy, uz);
+                rs.rw = rate_chi_q(rs.chi, S.rate) * rs.ig;
+                rw = rs.rw;
+            } else {
+                R u2;
+                const R ig = inv_gamma(ux, uy, uz, u2);
+                const R g = (R(1) + u2) * ig;
+                const R chi = chi_sub<FK>(ux, uy, uz, g, p.ex, p.ey, p.ez, p.bx, p.by, p.bz, e2, tl.guard);
+                rw = rate_chi_q(chi, S.rate) * ig;
+            }
+            tau = ptau + tau * (double)(rw / crw);
+            pend = tau <= 0.0;
+        }
+    }
+    if (has) {
+        ((R *)sp.ux)[i] = ux;
+        ((R *)sp.uy)[i] = uy;
+        ((R *)sp.uz)[i] = uz;
+        sp.x[i] = org.x + (double)dx;
+        sp.y[i] = org.y + (double)dy;
+        sp.z[i] = org.z + (double)dz;
+        sp.tau[i] = tau;
+        if (sp.events) sp.events[i] = nev;
+        tl.substeps += N;
+        tl.events += nev;
     }
 }
 
@@ -1575,9 +1471,7 @@ __global__ __launch_bounds__(kBlock) void k_tiled(StepArgs a) {
     flush_tally(t, a.st, s);
 }
 
-// Persistent: each wave claims chunk consecutive queue entries at a time (on the
-// optical-depth path with heavy_refill, a chunk in a pure magnetic field runs with
-// refilled lanes: lepton_queue_surr_b).  The
+// Persistent: each wave claims chunk consecutive queue entries at a time.  The
 // optical-depth instance's LDS (the network, the rate table, the larger child
 // buffers) fits two blocks per compute unit, so it is compiled for two waves per
 // SIMD and may use the registers that allows.
@@ -1596,14 +1490,7 @@ __global__ __launch_bounds__(kBlock, SURR ? 2 : 3) void k_heavy(StepArgs a) {
     for (;;) {
         if (base >= H) break;
         const u64 end = base + chunk < H ? base + chunk : H;
-        bool done = false;
-        if constexpr (SURR) {
-            if (a.heavy_refill && queue_pure_b(a, s, base, end)) {
-                lepton_queue_surr_b<true>(a, s, base, end, L.tab, L.surr, cb, t);
-                done = true;
-            }
-        }
-        for (u64 j0 = base; !done && j0 < end; j0 += 64) {
+        for (u64 j0 = base; j0 < end; j0 += 64) {
             const u64 j = j0 + __lane_id();
             const bool has = j < end;
             const u64 i = has ? a.queue[s][j] : 0;

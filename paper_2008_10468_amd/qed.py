@@ -78,7 +78,7 @@ class qed_tuning(C.Structure):
                 ("resolve_batch", C.c_uint32), ("prepass_blocks_per_cu", C.c_uint32),
                 ("prepass_finish", C.c_uint32), ("scatter_blocks_per_cu", C.c_uint32),
                 ("bins_per_octave", C.c_uint32), ("light_tile", C.c_uint32), ("tiled_slots", C.c_uint32),
-                ("deposit_sort_min", C.c_uint32), ("heavy_refill", C.c_uint32)]
+                ("deposit_sort_min", C.c_uint32)]
 
 
 class qed_sampler_model(C.Structure):

@@ -75,22 +75,25 @@ def test_tiled_equals_naive_c2(slots):
     assert list(sa.substeps) == list(sb.substeps) and sa.emissions == sb.emissions
 
 
-@pytest.mark.parametrize("key", ["c3/binned", "c5/binned", "c5r/binned"])
+@pytest.mark.parametrize("key", ["c3/binned", "c5/binned", "c5r/binned", "w5/binned", "w5r/binned"])
 def test_recorded_tuning_binned_equals_naive(key):
     """The launch shapes and scheduler parameters the autotuner recorded for the hot spot
     (plain: c3; optical-depth path with the shipped network: c5, with rejection energies:
-    c5r) give the naive scheduler's results bit for bit on a 2^15-electron hot spot over
-    two steps (c5: the heavy queue's two-group network passes against the naive pass's
-    single-group ones)."""
+    c5r) and for the weak uniform field (w5, w5r) give the naive scheduler's results bit
+    for bit on 2^15 electrons over two steps (c5, w5: the heavy queue's two-group network
+    passes against the naive pass's single-group ones)."""
     import json
     import os
     from paper_2008_10468_amd import qed
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     tuning = json.load(open(os.path.join(root, "paper_2008_10468_amd", "tuning_gfx950.json")))[key]["tuning"]
-    surr = key.startswith("c5")
-    net = key.startswith("c5/")
+    surr = key.startswith(("c5", "w5"))
+    net = key.startswith(("c5/", "w5/"))
     m = np.load(os.path.join(root, "paper_2008_10468_amd", "models", "sampler_gfx950.npz")) if net else None
-    w = workloads.c3(n=1 << 15, hot_fraction=0.2, seed=12)
+    if key.startswith("w5"):
+        w = workloads.weak(n=1 << 15, seed=13)
+    else:
+        w = workloads.c3(n=1 << 15, hot_fraction=0.2, seed=12)
     zero = {k: np.zeros(1) for k in ("ex", "ey", "ez", "bx", "by", "bz")}
     res = []
     for sched, tu in ((qed.QED_SCHED_NAIVE, None), (qed.QED_SCHED_BINNED, tuning)):
@@ -191,55 +194,3 @@ def test_tuning_validation():
         assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
     g.close()
 
-
-@pytest.mark.parametrize("pop", ["hot", "weak"])
-@pytest.mark.parametrize("batch", [1, 24, 64])
-def test_refilled_heavy_queue_equals_naive(pop, batch):
-    """heavy_refill: in a pure magnetic field the optical-depth heavy queue hands the
-    next queue entry to each lane whose lepton has finished (refilling after `batch`
-    lanes are idle); every lepton, its photons and the counters are the naive
-    scheduler's bit for bit, with the shipped network (hot spot, 2^15 electrons, 20%
-    hot; and the weak uniform field, where most leptons emit once or not at all)."""
-    import os
-    from paper_2008_10468_amd import qed
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    m = np.load(os.path.join(root, "paper_2008_10468_amd", "models", "sampler_gfx950.npz"))
-    n = 1 << 15
-    w = workloads.c3(n=n, hot_fraction=0.2, seed=12) if pop == "hot" else workloads.weak(n=n, seed=13)
-    zero = {k: np.zeros(1) for k in ("ex", "ey", "ez", "bx", "by", "bz")}
-    tuning = {"light_max": 0, "heavy_refill": 1, "resolve_batch": batch, "chunk": 256}
-    res = []
-    for sched, tu in ((qed.QED_SCHED_NAIVE, None), (qed.QED_SCHED_BINNED, tuning)):
-        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, 1 << 19), pairs=False, scheduler=sched,
-                          sampler=qed.QED_SAMPLER_SURROGATE)
-        assert qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
-                                   float(m["log10_chi_hi"])) == qed.QED_OK
-        if tu:
-            t = qed.qed_get_tuning(g.ctx)
-            for k, v in tu.items():
-                setattr(t, k, int(v))
-            assert qed.qed_set_tuning(g.ctx, t) == qed.QED_OK
-        g.load_state(w)
-        g.set_fields(None, per_species=[w["fields"], zero, zero])
-        for step in range(2):
-            g.step(w["dt"], 7, step)
-            assert g.sync()[0] == qed.QED_OK
-        res.append(([_sorted(g.sp[k].download()) for k in (0, 2)], g.stats()))
-        g.close()
-    (a, sa), (b, sb) = res
-    for s in range(2):
-        for k in a[s]:
-            assert np.array_equal(a[s][k], b[s][k]), (pop, batch, s, k)
-    assert list(sa.substeps) == list(sb.substeps) and sa.emissions == sb.emissions and sa.emissions > 1000
-    assert list(sa.particles) == list(sb.particles)
-    assert sb.heavy_particles > 0
-
-
-def test_refill_is_validated():
-    from paper_2008_10468_amd import qed
-    g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(16, 16, 16))
-    t = qed.qed_get_tuning(g.ctx)
-    assert t.heavy_refill == 0
-    t.heavy_refill = 2
-    assert qed.qed_set_tuning(g.ctx, t) == qed.QED_ERR_INVALID_ARG
-    g.close()
