@@ -233,6 +233,44 @@ def test_surrogate_emission_law(trained, chi, use_model):
         assert stats.learned_events == 0 and stats.fallback_events == stats.emissions
 
 
+@pytest.mark.parametrize("flagged", ["above", "at_and_below"])
+def test_fallback_flags_choose_the_sampler(trained, flagged):
+    """The per-bin fallback flags pick the sampler by the chi at the emission.  In a pure B
+    field chi stays constant between emissions and only falls at them (recoil).  With the
+    bins above the start chi flagged, every energy comes from the network.  With the start
+    chi's bin and all below flagged, every energy comes from rejection.  Either way the
+    first photons' energy fractions follow the normalised eq. (1)."""
+    from paper_2008_10468_amd import qed
+    cfg, params, loss, err, fb0 = trained
+    nb = int(np.asarray(fb0).size)
+    binw = (cfg.log10_chi_hi - cfg.log10_chi_lo) / nb
+    b0 = int((math.log10(0.7) - cfg.log10_chi_lo) / binw)
+    chi = 10.0 ** (cfg.log10_chi_lo + (b0 + 0.5) * binw)     # the middle of its bin
+    fb = np.zeros(nb, np.uint8)
+    if flagged == "above":
+        fb[b0 + 1:] = 1
+    else:
+        fb[:b0 + 1] = 1
+    gamma, n = 2000.0, 50_000
+    dt = 0.7 / oracle.emission_prob(chi, gamma, 1.0, False)
+    ev, ph, stats = _run_surrogate(qed, n, chi, gamma, dt, model=(cfg, params, fb))
+    assert stats.emissions == ph["id"].size and stats.emissions > 0.4 * n
+    if flagged == "above":
+        assert stats.learned_events == stats.emissions and stats.fallback_events == 0
+    else:
+        assert stats.learned_events == 0 and stats.fallback_events == stats.emissions
+        assert stats.fallback_draws >= stats.emissions
+    first = {}
+    for j in range(ph["id"].size):
+        first.setdefault(int(ph["parent"][j]), j)
+    sel = np.array(sorted(first.values()))
+    delta = np.sqrt(ph["ux"][sel] ** 2 + ph["uy"][sel] ** 2 + ph["uz"][sel] ** 2) / gamma
+    for q in (0.05, 0.2, 0.5, 0.8, 0.95):
+        c = oracle.emission_cdf(chi, np.quantile(delta, q))
+        s = math.sqrt(q * (1 - q) / delta.size)
+        assert abs(c - q) <= 4 * s + 2e-3, (flagged, q, c, s)
+
+
 @pytest.mark.parametrize("p_s", [0.01, 0.1, 0.3])
 def test_surrogate_event_count_is_poisson(p_s):
     """chi = 0.02 in a pure B field: the rate alpha chi q(chi) / gamma = alpha B q(chi) changes
