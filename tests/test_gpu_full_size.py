@@ -177,3 +177,64 @@ def test_c5_full_size_surrogate_against_plain():
     assert ls > 0.9 * es
     assert ss < 0.5 * sp_                        # the optical-depth path runs far fewer sub-steps
     assert sps.ks_2samp(kp, ks).pvalue > 1e-3
+
+
+def test_weak_field_network_against_rejection():
+    """What the trained network gains over the method without it.  The workload is the
+    16.8M-electron weak uniform field (chi 1e-3 to 1e-2), where the flat envelope accepts few
+    candidates.  The optical-depth path with the shipped network runs against the same path
+    with rejection energies, three steps each from the same state.  Both emit the same number
+    of photons within statistics, with the same spectrum (KS).  Rejection spends at least five
+    candidates per energy, each with its pair of synchrotron evaluations.  With the network,
+    most energies take one network evaluation and no candidate (those below its chi range fall
+    back), cutting the candidates per energy at least fourfold.  The step times are printed,
+    not asserted."""
+    from paper_2008_10468_amd import qed
+    from scipy import stats as sps
+    m = np.load(os.path.join(ROOT, "paper_2008_10468_amd", "models", "sampler_gfx950.npz"))
+    w = workloads.weak()
+    n = w["electrons"]["id"].size
+    zero = workloads.uniform_field()
+    K = 3
+    out = {}
+    for name, net, key in (("rejection", False, "w5r/binned"), ("network", True, "w5/binned")):
+        print("weak field:", name, flush=True)
+        g = qed.Generator(precision=qed.QED_PREC_MIXED, capacity=(n, 16, K * n + (1 << 23)), pairs=False,
+                          parent=False, events=False, scheduler=qed.QED_SCHED_BINNED,
+                          sampler=qed.QED_SAMPLER_SURROGATE, surrogate_p_max=0.1)
+        if net:
+            assert qed.qed_sampler_set(g.ctx, m["params"], m["fallback"], float(m["log10_chi_lo"]),
+                                       float(m["log10_chi_hi"])) == qed.QED_OK
+        _apply_tuning(qed, g, key)
+        g.set_fields(None, per_species=[w["fields"], zero, zero])
+        g.load_state(w)
+        g.step(w["dt"], w["seed"], 0)                 # warm-up
+        assert g.sync()[0] == qed.QED_OK
+        g.load_state(w)
+        qed.qed_reset_stats(g.ctx)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for s in range(K):
+            g.step(w["dt"], w["seed"], s)
+        e1.record()
+        assert g.sync()[0] == qed.QED_OK
+        ms = e0.elapsed_time(e1) / K
+        st = g.stats()
+        k = g.sp[2]
+        kk = torch.sqrt(k.ux[:k.count()].double() ** 2 + k.uy[:k.count()].double() ** 2 +
+                        k.uz[:k.count()].double() ** 2)
+        idx = torch.from_numpy(np.random.default_rng(5).choice(k.count(), 200000, replace=False)).cuda()
+        out[name] = (st.emissions, st.learned_events, st.fallback_events, st.fallback_draws, kk[idx].cpu().numpy())
+        print(f"weak field: {name}: {ms:.3f} ms per step, {st.emissions} emissions, {st.learned_events} learned, "
+              f"{st.fallback_draws / max(st.emissions, 1):.2f} candidates per energy", flush=True)
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    er, lr, fr, dr, kr = out["rejection"]
+    en, ln, fn, dn, kn = out["network"]
+    assert er > 1e7
+    assert abs(er - en) <= 4.5 * math.sqrt(er + en), (er, en)
+    assert lr == 0 and fr == er and dr >= 5 * er
+    assert ln + fn == en and ln >= 0.85 * en and dn >= fn
+    assert dn / en <= 0.25 * (dr / er)
+    assert sps.ks_2samp(kr, kn).pvalue > 1e-3
